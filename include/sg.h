@@ -1,0 +1,206 @@
+/*
+ * sg.h -- C ABI of the MI355X spin-glass Monte Carlo library (libsg.so).
+ *
+ * The library runs the data-parallel hot path of the probabilistic-computer
+ * solvers of arXiv:2503.10302 on one AMD Instinct MI355X (gfx950):
+ *   - graph-coloured p-bit (Gibbs) sweeps, Eqs. (5)-(6), over many replicas
+ *     and inverse temperatures (Methods, "Graph Coloring");
+ *   - replica-exchange swaps, Eq. (4), with the alternating pair schedule and
+ *     per-label chains of Methods, "APT details";
+ *   - Houdayer isoenergetic cluster moves, Algorithm S2 (ICMop);
+ *   - discrete-time simulated quantum annealing, Supplementary Eqs. S.1-S.3
+ *     and Algorithm S1;
+ *   - the adaptive inverse-temperature ladder of Algorithm S2 and a learned
+ *     ladder predictor that replaces it (with the adaptive stage as fallback).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns sg_status: SG_OK (0) or a negative error code.
+ *     Nothing aborts or exits.  sg_last_error() gives a message.
+ *   - Host pointers only.  The caller owns every array it passes; sg_create
+ *     copies what it needs.  The context owns all device memory it allocates
+ *     and frees it in sg_destroy.
+ *   - All work of one context is ordered on one HIP stream (given in the
+ *     config, or created by the library when NULL).  Functions that write
+ *     host arrays synchronise that stream before returning.
+ *   - A context is not thread-safe; use one per thread.
+ *   - On SG_EINVAL / SG_EUNSUPPORTED the context is left unchanged.
+ *
+ * Data layout
+ *   - Site index j = x + Lx*(y + Ly*z), n = Lx*Ly*Lz <= 32767.
+ *   - J[3*j + a] (int8, -1, 0 or +1) is the coupling between site j and its
+ *     +a neighbour (a = 0,1,2 for x,y,z).  Along a periodic axis the last site
+ *     couples to the first; across an open boundary the stored value is
+ *     ignored.  0 means no bond.  h[j] (int8, |h| <= 31) or NULL.
+ *   - Spins are exchanged as int8 +1/-1.
+ *   - APT replica slot s = b*reps_per_beta + l: inverse temperature index b,
+ *     ICM label l.  DT-SQA slot (r, k): independent replica r, Trotter slice k.
+ *
+ * Random numbers: Philox4x32-10 keyed by the 64-bit seed; each update draws
+ * from a counter made of (site, sweep index, slot group, instance, purpose), so
+ * results do not depend on the launch configuration and checkpoints resume
+ * exactly.
+ */
+#ifndef SG_H
+#define SG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sg_status;
+#define SG_OK 0
+#define SG_EINVAL (-1)         /* invalid argument */
+#define SG_ENOMEM (-2)         /* device or host allocation failed */
+#define SG_EHIP (-3)           /* HIP runtime error (no device, launch failure) */
+#define SG_ESTATE (-4)         /* call does not fit the context's mode or state */
+#define SG_EUNSUPPORTED (-5)   /* valid input this implementation does not handle */
+
+#define SG_APT 1
+#define SG_SQA 2
+
+typedef struct sg_ctx sg_ctx;
+
+/* One problem instance (Eq. 1 with fields, Eq. 8). */
+typedef struct {
+    int32_t Lx, Ly, Lz;
+    uint32_t periodic;   /* bit0 = x, bit1 = y, bit2 = z */
+    const int8_t *J;     /* [Lz][Ly][Lx][3] */
+    const int8_t *h;     /* [n] or NULL */
+} sg_lattice;
+
+typedef struct {
+    int32_t mode;              /* SG_APT or SG_SQA */
+    int32_t n_inst;            /* >= 1; lattice sizes may differ (batched form) */
+    const sg_lattice *inst;    /* [n_inst] */
+    /* APT (Algorithm S2): */
+    int32_t n_beta;            /* >= 2 inverse temperatures per instance */
+    const double *beta;        /* [n_inst][n_beta], strictly ascending, >= 0 */
+    int32_t reps_per_beta;     /* ICM labels per temperature: 1, 2 or 4 */
+    /* DT-SQA (Algorithm S1): */
+    int32_t M;                 /* Trotter slices, even, 2..64 */
+    int32_t R;                 /* independent replicas per instance, 1..65535 */
+    double sqa_beta;           /* inverse temperature beta > 0 */
+    uint64_t seed;
+    void *hip_stream;          /* hipStream_t borrowed from the caller, or NULL */
+} sg_config;
+
+/* Validate, copy the instances, build colour classes and acceptance tables,
+ * allocate device memory and draw the random initial spins (Algorithm S1 and
+ * S2: "initialize all replicas to random states").  *out is NULL on error. */
+sg_status sg_create(const sg_config *cfg, sg_ctx **out);
+void sg_destroy(sg_ctx *ctx);
+const char *sg_last_error(const sg_ctx *ctx);
+
+/* APT: n_sweeps coloured Gibbs sweeps of every replica (Eqs. 5-6): for each
+ * colour, every p-bit of that colour in every slot is resampled at its slot's
+ * inverse temperature. */
+sg_status sg_sweep(sg_ctx *ctx, int32_t n_sweeps);
+
+/* APT: one ICMop per replica pair at every inverse temperature >= beta_cutoff
+ * (Algorithm S2; 2 labels -> one pair, 4 labels -> a random matching).
+ * info_host (nullable) [n_inst][n_beta][max(1, reps/2)][4] receives
+ * (m, seed site, cluster size, branch) per pair, -1 where not applied.
+ * SG_EUNSUPPORTED when an instance has a non-zero field (the whole-replica
+ * branch is isoenergetic only for h = 0). */
+sg_status sg_icm(sg_ctx *ctx, double beta_cutoff, int32_t *info_host);
+
+/* Energies (Eq. 8) of every slot.  E_host: APT [n_inst][n_beta*reps] in slot
+ * order, DT-SQA [n_inst][R][M] per slice under the original couplings. */
+sg_status sg_energy(sg_ctx *ctx, int64_t *E_host);
+
+/* APT: one replica-exchange attempt (Eq. 4).  Attempts are numbered from 1;
+ * odd attempts try temperature pairs (0,1),(2,3),..., even ones (1,2),...;
+ * each label decides on its own.  accepted_host (nullable)
+ * [n_inst][(n_beta-1)*reps]: 1 accepted, 0 rejected, -1 not attempted. */
+sg_status sg_swap(sg_ctx *ctx, int32_t *accepted_host);
+
+/* APT main loop (Algorithm S2), n_cycles times: sweeps_per_swap sweeps, one
+ * ICM call at beta >= icm_cutoff (pass +inf for none), energies, one swap
+ * attempt, running minimum energy per instance.  Runs as device-resident
+ * cycles replayed from a captured HIP graph.  best_trace (nullable)
+ * [n_inst][n_cycles / record_every] receives the running minimum. */
+sg_status sg_run_apt(sg_ctx *ctx, int64_t n_cycles, int32_t sweeps_per_swap, double icm_cutoff,
+                     int32_t record_every, int64_t *best_trace);
+
+/* APT: running minimum energy per instance since creation [n_inst]. */
+sg_status sg_best(sg_ctx *ctx, int64_t *best_host);
+
+/* APT: accepted-swap counts since creation [n_inst][(n_beta-1)*reps]. */
+sg_status sg_swap_counts(sg_ctx *ctx, int64_t *counts_host);
+
+/* DT-SQA (Algorithm S1): for t = 0..n_steps-1, J_perp follows gamma[t]
+ * (Supplementary Eq. S.3) and every slice of every replica gets one coloured
+ * sweep of the (d+1)-dimensional lattice.  Then the energy of every slice
+ * under the original couplings; best_E[n_inst] and best_state[n_inst][n_max]
+ * (nullable) receive the minimum and its slice (ties: lowest r*M + k). */
+sg_status sg_sqa_anneal(sg_ctx *ctx, const double *gamma, int32_t n_steps, int64_t *best_E,
+                        int8_t *best_state);
+
+/* Spins in logical order, +1/-1.  APT [n_inst][n_beta*reps][n_max];
+ * DT-SQA [n_inst][R][M][n_max]; n_max = largest n, unused tail zero. */
+sg_status sg_get_spins(sg_ctx *ctx, int8_t *spins_host);
+sg_status sg_set_spins(sg_ctx *ctx, const int8_t *spins_host);
+
+/* Counters {sweeps or SQA steps done, ICM calls, swap attempts}. */
+sg_status sg_get_counters(sg_ctx *ctx, uint32_t *counters3);
+
+/* Checkpoint: spins, counters and running minima in one opaque blob.
+ * sg_get_state with blob == NULL sets *len to the size needed. */
+sg_status sg_get_state(sg_ctx *ctx, void *blob, size_t *len);
+sg_status sg_set_state(sg_ctx *ctx, const void *blob, size_t len);
+
+/* Stream-ordered timing: record a HIP event on the context's stream now
+ * (sg_timer_start) and the elapsed milliseconds at the matching stop. */
+sg_status sg_timer_start(sg_ctx *ctx);
+sg_status sg_timer_stop(sg_ctx *ctx, float *ms);
+sg_status sg_synchronize(sg_ctx *ctx);
+
+/* ---- adaptive ladder (Algorithm S2 preprocessing; Methods "APT details") ----
+ * Chains start random at beta0; each step runs `sweeps` sweeps per chain at
+ * beta_t, takes each chain's sample standard deviation of the energy over the
+ * last `tail` sweeps (exact integer moments, FP64 on the host), averages it
+ * over chains (sigma_E), appends beta_t and stops once sigma_E < tol,
+ * otherwise beta_{t+1} = beta_t + alpha / sigma_E.  All instances run as one
+ * batch.  beta_out [n_inst][max_steps], sigma_out (nullable) same shape,
+ * len_out [n_inst]. */
+typedef struct {
+    double beta0, alpha, tol;
+    int32_t n_chains, sweeps, tail, max_steps;
+} sg_adaptive_params;
+sg_status sg_adaptive_ladder(const sg_lattice *inst, int32_t n_inst, const sg_adaptive_params *p,
+                             uint64_t seed, void *hip_stream, double *beta_out, double *sigma_out,
+                             int32_t *len_out);
+
+/* ---- learned ladder predictor (project component, not in the paper) ----
+ * Features per instance: cube root of n, mean and variance over sites of the
+ * absolute sum of the couplings at the site, and the frustrated-plaquette
+ * fraction.  Network 4 -> 64 -> 64 -> 33 (ReLU, FP32) on standardised
+ * features; outputs log beta_0, softplus increments of log beta_1..31, and
+ * the log ICM cutoff.  Parameters: W1[64][4] b1[64] W2[64][64] b2[64]
+ * W3[33][64] b3[33] (6625 floats) followed by the feature mean[4] and std[4]. */
+#define SG_MLP_NPARAM 6625
+typedef struct sg_mlp sg_mlp;
+sg_status sg_mlp_create(const float *params /* nullable: random init from seed */, uint64_t seed,
+                        void *hip_stream, sg_mlp **out);
+void sg_mlp_destroy(sg_mlp *m);
+sg_status sg_instance_features(const sg_lattice *inst, int32_t n_inst, double *features /*[n_inst][4]*/);
+sg_status sg_mlp_set_standardisation(sg_mlp *m, const float *mean4, const float *std4);
+/* Mean-squared-error loss and its gradient over a batch (raw features and
+ * targets [B][33] = log betas and log cutoff); FP32 kernels. */
+sg_status sg_mlp_loss_grad(sg_mlp *m, const float *x, const float *y, int32_t batch, float *loss,
+                           float *grad /* nullable [6625] */);
+/* Adam training: epochs over the data set in minibatches (lr, betas 0.9/0.999). */
+sg_status sg_mlp_train(sg_mlp *m, const float *x, const float *y, int32_t n, int32_t batch,
+                       int32_t epochs, float lr, float *loss_per_epoch);
+sg_status sg_mlp_get_params(sg_mlp *m, float *params /*[6625 + 8]*/);
+/* Predicted ladders: beta_out [n_inst][32] ascending, cutoff_out [n_inst]. */
+sg_status sg_ladder_predict(sg_mlp *m, const sg_lattice *inst, int32_t n_inst, double *beta_out,
+                            double *cutoff_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -77,9 +77,9 @@ def lib():
             "sgo_apt_swap": (None, [u32, i32, i32, P, u64, u32, i32, P, P, P]),
             "sgo_apt_run": (i32, [LP, u32, i32, i32, P, u64, i64, i32, dbl, i32, P, P, P, P,
                                   P, P]),
-            "sgo_sqa_init": (None, [LP, u32, i32, i32, u64, P]),
-            "sgo_sqa_step": (None, [LP, u32, i32, i32, dbl, dbl, u64, u32, P]),
-            "sgo_sqa_anneal": (None, [LP, u32, i32, i32, dbl, P, i32, u64, u32, P, P, P, P]),
+            "sgo_sqa_init": (None, [LP, u32, i32, i32, i32, u64, P]),
+            "sgo_sqa_step": (None, [LP, u32, i32, i32, i32, dbl, dbl, u64, u32, P]),
+            "sgo_sqa_anneal": (None, [LP, u32, i32, i32, i32, dbl, P, i32, u64, u32, P, P, P, P]),
             "sgo_adaptive_ladder": (i32, [LP, u32, C.POINTER(_AdaptiveParams), u64, P, P, P]),
             "sgo_sigma_from_moments": (dbl, [i64, i64, i64]),
             "sgo_instance_features": (None, [LP, P]),
@@ -209,24 +209,27 @@ def apt_run(lat, inst, beta, R_lab, seed, n_cycles, sweeps_per_swap, cutoff, rec
     return rc, trace[:ntr], accc
 
 
-def sqa_init(lat, inst, M, R, seed):
+def sqa_init(lat, inst, M, R, seed, r0=0):
+    """Replicas r0 .. r0+R-1 of one instance, spins [R, M, n]."""
     s = np.zeros((R, M, lat.n), np.int8)
-    lib().sgo_sqa_init(lat.c, inst, M, R, seed, _ptr(s))
+    lib().sgo_sqa_init(lat.c, inst, M, r0, R, seed, _ptr(s))
     return s
 
 
-def sqa_step(lat, inst, M, R, beta, gamma, seed, t, spins):
-    lib().sgo_sqa_step(lat.c, inst, M, R, float(beta), float(gamma), seed, t, _ptr(spins))
+def sqa_step(lat, inst, M, R, beta, gamma, seed, t, spins, r0=0):
+    assert spins.shape == (R, M, lat.n) and spins.dtype == np.int8 and spins.flags.c_contiguous
+    lib().sgo_sqa_step(lat.c, inst, M, r0, R, float(beta), float(gamma), seed, t, _ptr(spins))
     return spins
 
 
-def sqa_anneal(lat, inst, M, R, beta, gammas, seed, t0, spins):
+def sqa_anneal(lat, inst, M, R, beta, gammas, seed, t0, spins, r0=0):
+    assert spins.shape == (R, M, lat.n) and spins.dtype == np.int8 and spins.flags.c_contiguous
     g = np.ascontiguousarray(gammas, dtype=np.float64)
     sE = np.zeros((R, M), np.int64)
     bE = np.zeros(1, np.int64)
     bs = np.zeros(lat.n, np.int8)
-    lib().sgo_sqa_anneal(lat.c, inst, M, R, float(beta), _ptr(g), g.size, seed, t0, _ptr(spins),
-                         _ptr(sE), _ptr(bE), _ptr(bs))
+    lib().sgo_sqa_anneal(lat.c, inst, M, r0, R, float(beta), _ptr(g), g.size, seed, t0,
+                         _ptr(spins), _ptr(sE), _ptr(bE), _ptr(bs))
     return int(bE[0]), bs, sE
 
 

@@ -396,7 +396,7 @@ int32_t sgo_apt_run(const sgo_lattice *lat, uint32_t inst, int32_t n_beta, int32
 }
 
 /* ------------------------------------------------------------------------- */
-/* DT-SQA (Algorithm S1).  Spins [r][k][n]: replica r, Trotter slice k.      */
+/* DT-SQA (Algorithm S1).  Spins [r][k][n]: replica r0 + r, Trotter slice k.  */
 /* Slice k = 2 hh + p draws word (hh & 3) of the block with counter word 2   */
 /* equal to (r << 16) | (p << 15) | (hh >> 2).                               */
 /* ------------------------------------------------------------------------- */
@@ -406,14 +406,14 @@ static uint32_t sqa_c2(int32_t r, int32_t k)
     return ((uint32_t)r << 16) | (p << 15) | (hh >> 2);
 }
 
-void sgo_sqa_init(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t R, uint64_t seed,
-                  int8_t *spins)
+void sgo_sqa_init(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t r0, int32_t R,
+                  uint64_t seed, int8_t *spins)
 {
     int32_t n = sgo_n_sites(lat);
     for (int32_t r = 0; r < R; ++r)
         for (int32_t k = 0; k < M; ++k)
             for (int32_t j = 0; j < n; ++j) {
-                uint32_t w = sgo_word(seed, (uint32_t)j, 0u, sqa_c2(r, k), inst,
+                uint32_t w = sgo_word(seed, (uint32_t)j, 0u, sqa_c2(r0 + r, k), inst,
                                       SGO_TAG_SQA_INIT, (k >> 1) & 3);
                 spins[((int64_t)r * M + k) * n + j] = (w < 0x80000000u) ? 1 : -1;
             }
@@ -421,8 +421,8 @@ void sgo_sqa_init(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t R, u
 
 /* One annealing step: the transverse coupling follows Gamma, then one
  * coloured sweep of the (d+1)-dimensional lattice. */
-void sgo_sqa_step(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t R, double beta,
-                  double gamma, uint64_t seed, uint32_t t, int8_t *spins)
+void sgo_sqa_step(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t r0, int32_t R,
+                  double beta, double gamma, uint64_t seed, uint32_t t, int8_t *spins)
 {
     int32_t n = sgo_n_sites(lat);
     int32_t C = sgo_n_colours(lat, M);
@@ -436,7 +436,7 @@ void sgo_sqa_step(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t R, d
                     int8_t dn = spins[((int64_t)r * M + (k + 1) % M) * n + j];
                     int32_t s = sgo_local_field(lat, slice, j);
                     uint32_t T = sgo_sqa_threshold(beta, M, gamma, s, up + dn);
-                    uint32_t u = sgo_word(seed, (uint32_t)j, t, sqa_c2(r, k), inst,
+                    uint32_t u = sgo_word(seed, (uint32_t)j, t, sqa_c2(r0 + r, k), inst,
                                           SGO_TAG_SQA_SWEEP, (k >> 1) & 3);
                     slice[j] = (u < T) ? 1 : -1;
                 }
@@ -445,13 +445,13 @@ void sgo_sqa_step(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t R, d
 
 /* Algorithm S1 main loop, then the energy of every slice under the original
  * couplings and the minimum (ties -> lowest r*M + k). */
-void sgo_sqa_anneal(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t R, double beta,
-                    const double *gamma, int32_t n_steps, uint64_t seed, uint32_t t0,
+void sgo_sqa_anneal(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t r0, int32_t R,
+                    double beta, const double *gamma, int32_t n_steps, uint64_t seed, uint32_t t0,
                     int8_t *spins, int64_t *slice_E, int64_t *best_E, int8_t *best_state)
 {
     int32_t n = sgo_n_sites(lat);
     for (int32_t t = 0; t < n_steps; ++t)
-        sgo_sqa_step(lat, inst, M, R, beta, gamma[t], seed, t0 + (uint32_t)t, spins);
+        sgo_sqa_step(lat, inst, M, r0, R, beta, gamma[t], seed, t0 + (uint32_t)t, spins);
     int64_t best = 0;
     int64_t arg = -1;
     for (int64_t q = 0; q < (int64_t)R * M; ++q) {

@@ -84,13 +84,13 @@ int32_t sgo_apt_run(const sgo_lattice *lat, uint32_t inst, int32_t n_beta, int32
                     uint32_t *counters, int8_t *spins, int64_t *E, int64_t *best,
                     int64_t *best_trace, int64_t *accept_count);
 
-/* ---- DT-SQA (one instance, spins [R][M][n]) ---- */
-void sgo_sqa_init(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t R, uint64_t seed,
-                  int8_t *spins);
-void sgo_sqa_step(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t R, double beta,
-                  double gamma, uint64_t seed, uint32_t t, int8_t *spins);
-void sgo_sqa_anneal(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t R, double beta,
-                    const double *gamma, int32_t n_steps, uint64_t seed, uint32_t t0,
+/* ---- DT-SQA (one instance, replicas r0 .. r0+R-1, spins [R][M][n]) ---- */
+void sgo_sqa_init(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t r0, int32_t R,
+                  uint64_t seed, int8_t *spins);
+void sgo_sqa_step(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t r0, int32_t R,
+                  double beta, double gamma, uint64_t seed, uint32_t t, int8_t *spins);
+void sgo_sqa_anneal(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t r0, int32_t R,
+                    double beta, const double *gamma, int32_t n_steps, uint64_t seed, uint32_t t0,
                     int8_t *spins, int64_t *slice_E, int64_t *best_E, int8_t *best_state);
 
 /* ---- adaptive beta ladder (Algorithm S2, preprocessing loop) ---- */

@@ -1,0 +1,1293 @@
+// sg_api.cpp -- host side of libsg: validation, colour classes, FP64
+// acceptance tables, device memory, launches and the C ABI of include/sg.h.
+//
+// Threshold tables are built in FP64 and rounded to 32-bit integers here, on
+// the host, so that every spin decision on the device is an exact integer
+// comparison.  This file must be compiled with -ffp-contract=off.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sg.h"
+#include "sg_internal.h"
+
+using namespace sg;
+
+namespace {
+
+// ------------------------------------------------------------------ errors
+struct Failure {
+    sg_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(sg_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    throw Failure{code, buf};
+}
+
+void hip_check(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return;
+    if (e == hipErrorOutOfMemory) fail(SG_ENOMEM, "%s: out of device memory", what);
+    fail(SG_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void alloc(size_t count, const char *what)
+    {
+        release();
+        if (count == 0) count = 1;
+        hip_check(hipMalloc((void **)&p, count * sizeof(T)), what);
+        n = count;
+    }
+    void upload(const T *h, size_t count, hipStream_t s, const char *what)
+    {
+        if (count > n) alloc(count, what);
+        hip_check(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s), what);
+    }
+    void upload(const std::vector<T> &v, hipStream_t s, const char *what)
+    {
+        alloc(v.size(), what);
+        if (!v.empty())
+            hip_check(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s),
+                      what);
+    }
+    void download(T *h, size_t count, hipStream_t s, const char *what) const
+    {
+        hip_check(hipMemcpyAsync(h, p, count * sizeof(T), hipMemcpyDeviceToHost, s), what);
+    }
+};
+
+// ------------------------------------------------------------------ geometry
+struct Lat {
+    int Lx, Ly, Lz;
+    uint32_t periodic;
+    int n;
+    std::vector<int8_t> J;   // [n][3]
+    std::vector<int8_t> h;   // [n]
+    int len(int a) const { return a == 0 ? Lx : (a == 1 ? Ly : Lz); }
+    int coord(int j, int a) const
+    {
+        if (a == 0) return j % Lx;
+        if (a == 1) return (j / Lx) % Ly;
+        return j / (Lx * Ly);
+    }
+    int stride(int a) const { return a == 0 ? 1 : (a == 1 ? Lx : Lx * Ly); }
+    // neighbour of j along axis a (dir = +1/-1) or -1
+    int nbr(int j, int a, int dir) const
+    {
+        const int L = len(a);
+        if (L < 2) return -1;
+        const int c = coord(j, a);
+        int c2 = c + dir;
+        if (c2 < 0 || c2 >= L) {
+            if (!((periodic >> a) & 1u)) return -1;
+            c2 = (c2 + L) % L;
+        }
+        return j + (c2 - c) * stride(a);
+    }
+    int coupling(int j, int a, int dir) const
+    {
+        const int nb = nbr(j, a, dir);
+        if (nb < 0) return 0;
+        return dir > 0 ? J[3 * j + a] : J[3 * nb + a];
+    }
+    bool odd_ring(int a) const
+    {
+        const int L = len(a);
+        return ((periodic >> a) & 1u) && L >= 3 && (L & 1);
+    }
+    // Per-axis colour label: i mod 2, or 2 at the last site of an odd periodic axis
+    // (when three colours are in use).  Neighbours differ in exactly one label.
+    int label_sum(int j, bool three) const
+    {
+        int s = 0;
+        for (int a = 0; a < 3; ++a) {
+            const int c = coord(j, a);
+            s += (three && odd_ring(a) && c == len(a) - 1) ? 2 : (c & 1);
+        }
+        return s;
+    }
+    bool any_odd_ring() const { return odd_ring(0) || odd_ring(1) || odd_ring(2); }
+    int hmax() const
+    {
+        int m = 0;
+        for (int8_t v : h) m = std::max(m, std::abs((int)v));
+        return m;
+    }
+    bool has_field() const
+    {
+        for (int8_t v : h)
+            if (v) return true;
+        return false;
+    }
+    int64_t max_energy_gap() const
+    {
+        int64_t s = 0;
+        for (int j = 0; j < n; ++j) {
+            for (int a = 0; a < 3; ++a) s += std::abs(coupling(j, a, +1));
+            s += std::abs((int)h[j]);
+        }
+        return 2 * s;
+    }
+};
+
+Lat copy_lattice(const sg_lattice &L, int idx)
+{
+    if (L.Lx < 1 || L.Ly < 1 || L.Lz < 1) fail(SG_EINVAL, "instance %d: lattice size < 1", idx);
+    const int64_t n = (int64_t)L.Lx * L.Ly * L.Lz;
+    if (n > kMaxN) fail(SG_EINVAL, "instance %d: %lld sites exceed %d", idx, (long long)n, kMaxN);
+    if (L.periodic > 7u) fail(SG_EINVAL, "instance %d: periodic mask must be 0..7", idx);
+    if (!L.J) fail(SG_EINVAL, "instance %d: J is NULL", idx);
+    Lat t;
+    t.Lx = L.Lx; t.Ly = L.Ly; t.Lz = L.Lz;
+    t.periodic = L.periodic;
+    t.n = (int)n;
+    t.J.assign(L.J, L.J + 3 * n);
+    t.h.assign(n, 0);
+    if (L.h) t.h.assign(L.h, L.h + n);
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (t.J[i] < -1 || t.J[i] > 1) fail(SG_EINVAL, "instance %d: J must be -1, 0 or +1", idx);
+    for (int8_t v : t.h)
+        if (v < -kMaxH || v > kMaxH) fail(SG_EINVAL, "instance %d: |h| must be <= %d", idx, kMaxH);
+    // values stored across open boundaries are not bonds
+    for (int j = 0; j < t.n; ++j)
+        for (int a = 0; a < 3; ++a)
+            if (t.nbr(j, a, +1) < 0) t.J[3 * j + a] = 0;
+    return t;
+}
+
+// Site record, see sg_internal.h.
+uint4 make_record(const Lat &L, int j, uint32_t parity)
+{
+    uint32_t nb[6];
+    uint32_t jneg = 0, d = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int s = 0; s < 2; ++s) {
+            const int dir = s ? -1 : +1;
+            const int v = L.nbr(j, a, dir);
+            const int c = L.coupling(j, a, dir);
+            const int slot = 2 * a + s;
+            if (v < 0 || c == 0) {
+                nb[slot] = (uint32_t)L.n;
+            } else {
+                nb[slot] = (uint32_t)v;
+                ++d;
+                if (c < 0) jneg |= 1u << slot;
+            }
+        }
+    uint4 r;
+    r.x = (uint32_t)j | (d << 16) | (jneg << 19) | ((uint32_t)(L.h[j] + 32) << 25) | (parity << 31);
+    r.y = nb[0] | (nb[1] << 16);
+    r.z = nb[2] | (nb[3] << 16);
+    r.w = nb[4] | (nb[5] << 16);
+    return r;
+}
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// ------------------------------------------------------------------ thresholds (FP64)
+uint32_t to_threshold(double p)
+{
+    if (p >= 1.0) return 0xFFFFFFFFu;
+    return (uint32_t)(p * 4294967296.0);
+}
+
+// Eq. (6): P(s = +1 | I) = (1 + tanh(beta I)) / 2.
+uint32_t heat_bath_threshold(double beta, int I)
+{
+    const double x = beta * (double)I;
+    const double p = 0.5 * (1.0 + std::tanh(x));
+    return to_threshold(p);
+}
+
+// Supplementary Eq. S.3 with M slices: argument (beta/M) s + K tau,
+// K = beta J_perp = -(1/2) ln tanh(beta Gamma / M).
+uint32_t trotter_threshold(double beta, int M, double K, int s, int tau)
+{
+    const double x = (beta / (double)M) * (double)s + K * (double)tau;
+    const double p = 0.5 * (1.0 + std::tanh(x));
+    return to_threshold(p);
+}
+
+double trotter_K(double beta, int M, double gamma)
+{
+    return -0.5 * std::log(std::tanh(beta * gamma / (double)M));
+}
+
+// Eq. (4) for dE = -d < 0: accept iff u < floor(exp(dbeta * dE) * 2^32).
+uint32_t swap_threshold(double beta_lo, double beta_hi, int64_t d)
+{
+    const double x = (beta_hi - beta_lo) * (double)(-d);
+    const double e = std::exp(x) * 4294967296.0;
+    return (uint32_t)e;
+}
+
+// ------------------------------------------------------------------ timers
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
+}  // namespace
+
+// ====================================================================== context
+struct sg_ctx {
+    int mode = 0;
+    int n_inst = 0;
+    uint64_t seed = 0;
+    uint32_t key0 = 0, key1 = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    std::vector<Lat> lat;
+    std::vector<InstDev> idev;
+    int n_max = 0;
+    int hmax = 0;
+    DevBuf<InstDev> d_inst;
+    DevBuf<uint4> d_rec, d_recj;
+    DevBuf<uint32_t> d_ctr;      // {sweeps/steps, icm calls, swap attempts, cycles, done}
+    Timer timer;
+
+    // APT
+    int n_beta = 0, reps = 0, n_slots = 0, n_quads = 0, imax = 0, ni = 0;
+    std::vector<double> beta;    // [n_inst][n_beta]
+    DevBuf<uint8_t> d_spins;
+    DevBuf<int32_t> d_perm, d_E, d_slot_lut, d_tab_off, d_tab_len, d_icm_info;
+    DevBuf<uint32_t> d_lut, d_tab;
+    DevBuf<uint8_t> d_icm_on;
+    DevBuf<int64_t> d_best, d_acc_count, d_mom, d_trace;
+    DevBuf<int32_t> d_acc_out;
+    DevBuf<QuadDesc> d_desc;
+    int n_blocks = 0;
+    size_t quad_lds = 0;
+    double icm_cutoff_loaded = std::numeric_limits<double>::quiet_NaN();
+    // graph cache for APT cycles
+    hipGraphExec_t gexec = nullptr;
+    int g_sweeps = -1, g_icm = -1, g_record = -1, g_cycles = 0;
+    int64_t *g_trace = nullptr;
+    int g_trace_cap = 0;
+
+    // DT-SQA
+    int M = 0, R = 0, H = 0, smax = 0, nl = 0;
+    double sqa_beta = 0.0;
+    DevBuf<uint32_t> d_sqa, d_sqa_lut;
+    DevBuf<int32_t> d_slice_E;
+    size_t sqa_lds = 0;
+    uint32_t sqa_steps = 0;
+
+    ~sg_ctx()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (timer.a) (void)hipEventDestroy(timer.a);
+        if (timer.b) (void)hipEventDestroy(timer.b);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+namespace {
+
+void set_key(sg_ctx *c, uint64_t seed)
+{
+    c->seed = seed;
+    c->key0 = (uint32_t)seed;
+    c->key1 = (uint32_t)(seed >> 32);
+}
+
+void init_stream(sg_ctx *c, void *s)
+{
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(SG_EHIP, "no HIP device");
+    if (s) {
+        c->stream = (hipStream_t)s;
+    } else {
+        hip_check(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "hipStreamCreate");
+        c->own_stream = true;
+    }
+}
+
+// Colour classes of the spatial lattice (Methods, "Graph Coloring").
+void apt_records(const Lat &L, std::vector<uint4> &rec, std::vector<uint4> &recj, InstDev &I)
+{
+    const bool three = L.any_odd_ring();
+    const int C = three ? 3 : 2;
+    I.n_colours = C;
+    I.rec_off = (int64_t)rec.size();
+    I.recj_off = (int64_t)recj.size();
+    int off = 0;
+    for (int c = 0; c < 3; ++c) {
+        I.col_off[c] = off;
+        I.col_cnt[c] = 0;
+        if (c >= C) continue;
+        for (int j = 0; j < L.n; ++j)
+            if (L.label_sum(j, three) % C == c) {
+                rec.push_back(make_record(L, j, 0u));
+                ++I.col_cnt[c];
+            }
+        off += I.col_cnt[c];
+    }
+    for (int j = 0; j < L.n; ++j) recj.push_back(make_record(L, j, 0u));
+}
+
+// Phases of the (d+1)-dimensional lattice with an even periodic Trotter ring:
+// colour(j, k) = (spatial label sum + k) mod C, so in phase c site j updates
+// the slices of parity p = (c - label sum) mod C when p is 0 or 1.
+void sqa_records(const Lat &L, std::vector<uint4> &rec, std::vector<uint4> &recj, InstDev &I)
+{
+    const bool three = L.any_odd_ring();
+    const int C = three ? 3 : 2;
+    I.n_colours = C;
+    I.rec_off = (int64_t)rec.size();
+    I.recj_off = (int64_t)recj.size();
+    int off = 0;
+    for (int c = 0; c < 3; ++c) {
+        I.col_off[c] = off;
+        I.col_cnt[c] = 0;
+        if (c >= C) continue;
+        for (int j = 0; j < L.n; ++j) {
+            const int p = ((c - L.label_sum(j, three)) % C + C) % C;
+            if (p > 1) continue;
+            rec.push_back(make_record(L, j, (uint32_t)p));
+            ++I.col_cnt[c];
+        }
+        off += I.col_cnt[c];
+    }
+    for (int j = 0; j < L.n; ++j) recj.push_back(make_record(L, j, 0u));
+}
+
+// Work-group tasks, grouped so that all quads of an instance run on one
+// XCD (blocks are dispatched round-robin over the 8 XCDs; each XCD has its own
+// L2 holding that instance's records and tables).  Largest instances first.
+std::vector<QuadDesc> make_quad_descs(const std::vector<Lat> &lat, int n_quads)
+{
+    const int ni = (int)lat.size();
+    std::vector<int> order(ni);
+    for (int i = 0; i < ni; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lat[a].n > lat[b].n; });
+    std::vector<QuadDesc> out;
+    if (ni < 8) {
+        for (int i : order)
+            for (int q = 0; q < n_quads; ++q) out.push_back({i, q});
+        return out;
+    }
+    const int X = 8;
+    std::vector<std::vector<QuadDesc>> qs(X);
+    std::vector<int64_t> load(X, 0);
+    for (int i : order) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[x] += (int64_t)lat[i].n;
+        for (int q = 0; q < n_quads; ++q) qs[x].push_back({i, q});
+    }
+    size_t len = 0;
+    for (auto &v : qs) len = std::max(len, v.size());
+    out.assign(len * X, QuadDesc{-1, 0});
+    for (int x = 0; x < X; ++x)
+        for (size_t m = 0; m < qs[x].size(); ++m) out[m * X + x] = qs[x][m];
+    return out;
+}
+
+void build_common(sg_ctx *c, const sg_config *cfg)
+{
+    if (cfg->n_inst < 1) fail(SG_EINVAL, "n_inst must be >= 1");
+    if (!cfg->inst) fail(SG_EINVAL, "inst is NULL");
+    for (int i = 0; i < cfg->n_inst; ++i) c->lat.push_back(copy_lattice(cfg->inst[i], i));
+    c->n_inst = cfg->n_inst;
+    for (auto &L : c->lat) {
+        c->n_max = std::max(c->n_max, L.n);
+        c->hmax = std::max(c->hmax, L.hmax());
+    }
+    set_key(c, cfg->seed);
+}
+
+// --------------------------------------------------------------------- APT
+void create_apt(sg_ctx *c, const sg_config *cfg)
+{
+    if (cfg->n_beta < 2) fail(SG_EINVAL, "n_beta must be >= 2");
+    if (!cfg->beta) fail(SG_EINVAL, "beta is NULL");
+    if (cfg->reps_per_beta != 1 && cfg->reps_per_beta != 2 && cfg->reps_per_beta != 4)
+        fail(SG_EINVAL, "reps_per_beta must be 1, 2 or 4");
+    if ((int64_t)cfg->n_inst * cfg->n_beta * cfg->reps_per_beta > (1 << 26))
+        fail(SG_ENOMEM, "too many replicas");
+    c->n_beta = cfg->n_beta;
+    c->reps = cfg->reps_per_beta;
+    c->n_slots = c->n_beta * c->reps;
+    c->n_quads = (c->n_slots + 3) / 4;
+    c->beta.assign(cfg->beta, cfg->beta + (size_t)cfg->n_inst * cfg->n_beta);
+    for (int i = 0; i < cfg->n_inst; ++i)
+        for (int b = 0; b < c->n_beta; ++b) {
+            const double v = c->beta[(size_t)i * c->n_beta + b];
+            if (!std::isfinite(v) || v < 0.0) fail(SG_EINVAL, "beta must be finite and >= 0");
+            if (b > 0 && !(v > c->beta[(size_t)i * c->n_beta + b - 1]))
+                fail(SG_EINVAL, "beta must be strictly ascending");
+        }
+    build_common(c, cfg);
+    init_stream(c, cfg->hip_stream);
+    hipStream_t s = c->stream;
+    const int nb4 = 4 * c->n_quads;   // physical buffers per instance (slots padded to a quad)
+
+    std::vector<uint4> rec, recj;
+    std::vector<int32_t> perm, slot_lut, tab_off, tab_len;
+    std::vector<uint32_t> lut, tab;
+    int64_t spin_bytes = 0;
+    c->imax = 6 + c->hmax;
+    c->ni = 2 * c->imax + 1;
+    for (int i = 0; i < c->n_inst; ++i) {
+        const Lat &L = c->lat[i];
+        InstDev I{};
+        I.n = L.n;
+        I.npad = round_up(L.n, 16);
+        I.n_slots = c->n_slots;
+        apt_records(L, rec, recj, I);
+        I.spin_off = spin_bytes;
+        spin_bytes += (int64_t)nb4 * I.npad;
+        I.slot_off = i * nb4;
+        I.swap_off = i * (c->n_beta - 1);
+        I.info_off = i * c->n_beta * std::max(1, c->reps / 2);
+        for (int s2 = 0; s2 < nb4; ++s2) {
+            perm.push_back(s2);
+            slot_lut.push_back(i * c->n_beta + std::min(s2, c->n_slots - 1) / c->reps);
+        }
+        const double *bt = &c->beta[(size_t)i * c->n_beta];
+        for (int b = 0; b < c->n_beta; ++b)
+            for (int I2 = -c->imax; I2 <= c->imax; ++I2) lut.push_back(heat_bath_threshold(bt[b], I2));
+        const int64_t gap = L.max_energy_gap();
+        for (int b = 0; b + 1 < c->n_beta; ++b) {
+            tab_off.push_back((int32_t)tab.size());
+            tab.push_back(0xFFFFFFFFu);   // d = 0 is always accepted and never looked up
+            int64_t d = 1;
+            for (; d <= gap; ++d) {
+                const uint32_t T = swap_threshold(bt[b], bt[b + 1], d);
+                if (T == 0u) break;
+                tab.push_back(T);
+            }
+            tab_len.push_back((int32_t)d);
+            if (tab.size() > (size_t)1 << 30) fail(SG_ENOMEM, "swap tables too large");
+        }
+        c->idev.push_back(I);
+    }
+    c->d_inst.upload(c->idev, s, "instances");
+    c->d_rec.upload(rec, s, "records");
+    c->d_recj.upload(recj, s, "records");
+    c->d_perm.upload(perm, s, "perm");
+    c->d_slot_lut.upload(slot_lut, s, "slot tables");
+    c->d_lut.upload(lut, s, "thresholds");
+    c->d_tab.upload(tab, s, "swap thresholds");
+    c->d_tab_off.upload(tab_off, s, "swap offsets");
+    c->d_tab_len.upload(tab_len, s, "swap lengths");
+    c->d_spins.alloc((size_t)spin_bytes, "spins");
+    c->d_E.alloc((size_t)c->n_inst * nb4, "energies");
+    c->d_mom.alloc((size_t)c->n_inst * nb4 * 2, "moments");
+    c->d_best.alloc((size_t)c->n_inst, "best");
+    c->d_acc_count.alloc((size_t)c->n_inst * (c->n_beta - 1) * c->reps, "swap counts");
+    c->d_acc_out.alloc((size_t)c->n_inst * (c->n_beta - 1) * c->reps, "swap flags");
+    c->d_icm_info.alloc((size_t)c->n_inst * c->n_beta * std::max(1, c->reps / 2) * 4, "icm info");
+    c->d_icm_on.alloc((size_t)c->n_inst * c->n_beta, "icm flags");
+    c->d_ctr.alloc(8, "counters");
+    std::vector<QuadDesc> desc = make_quad_descs(c->lat, c->n_quads);
+    c->n_blocks = (int)desc.size();
+    c->d_desc.upload(desc, s, "tasks");
+    int npad_max = 0;
+    for (auto &I : c->idev) npad_max = std::max(npad_max, I.npad);
+    c->quad_lds = sizeof(uint32_t) * (size_t)(npad_max + 4 + 4 * c->ni + 32 + (npad_max + 31) / 32 + 1) +
+                  sizeof(uint16_t) * (size_t)npad_max + 16;
+    if (c->quad_lds > kMaxLds)
+        fail(SG_EUNSUPPORTED, "instance too large for one work-group's LDS (%zu bytes)", c->quad_lds);
+    hip_check(launch_fill_u32(c->d_ctr.p, 0u, 8, s), "init");
+    hip_check(launch_fill_i64(c->d_best.p, std::numeric_limits<int64_t>::max(), c->n_inst, s), "init");
+    hip_check(launch_fill_i64(c->d_acc_count.p, 0, (int64_t)c->d_acc_count.n, s), "init");
+    hip_check(launch_fill_i64(c->d_mom.p, 0, (int64_t)c->d_mom.n, s), "init");
+    hip_check(launch_fill_u32((uint32_t *)c->d_spins.p, 0u, (int64_t)(spin_bytes / 4), s), "init");
+    hip_check(launch_apt_init(c->d_inst.p, c->d_desc.p, c->n_blocks, c->d_spins.p, c->d_perm.p,
+                              c->key0, c->key1, TAG_APT_INIT, s),
+              "apt init");
+    // energies of the initial state (no sweep, no counter change)
+    AptArgs a{};
+    a.desc = c->d_desc.p; a.inst = c->d_inst.p; a.rec_col = c->d_rec.p; a.rec_j = c->d_recj.p;
+    a.spins = c->d_spins.p; a.perm = c->d_perm.p; a.lut = c->d_lut.p; a.slot_lut = c->d_slot_lut.p;
+    a.icm_on = c->d_icm_on.p; a.E = c->d_E.p; a.mom = c->d_mom.p; a.icm_info = c->d_icm_info.p;
+    a.ctr = c->d_ctr.p; a.key0 = c->key0; a.key1 = c->key1; a.tag = TAG_APT_SWEEP;
+    a.do_energy = 1; a.mom_from = -1; a.reps = c->reps; a.imax = c->imax; a.ni = c->ni;
+    a.n_blocks = c->n_blocks;
+    hip_check(launch_apt_quad(a, c->quad_lds, s), "initial energies");
+}
+
+void upload_icm_flags(sg_ctx *c, double cutoff)
+{
+    if (c->icm_cutoff_loaded == cutoff) return;
+    std::vector<uint8_t> on((size_t)c->n_inst * c->n_beta);
+    for (size_t i = 0; i < on.size(); ++i) on[i] = c->beta[i] >= cutoff ? 1 : 0;
+    c->d_icm_on.upload(on.data(), on.size(), c->stream, "icm flags");
+    hip_check(hipStreamSynchronize(c->stream), "icm flags");
+    c->icm_cutoff_loaded = cutoff;
+}
+
+AptArgs apt_args(sg_ctx *c, int n_sweeps, int do_icm, int bump)
+{
+    AptArgs a{};
+    a.desc = c->d_desc.p;
+    a.inst = c->d_inst.p;
+    a.rec_col = c->d_rec.p;
+    a.rec_j = c->d_recj.p;
+    a.spins = c->d_spins.p;
+    a.perm = c->d_perm.p;
+    a.lut = c->d_lut.p;
+    a.slot_lut = c->d_slot_lut.p;
+    a.icm_on = c->d_icm_on.p;
+    a.E = c->d_E.p;
+    a.mom = c->d_mom.p;
+    a.icm_info = c->d_icm_info.p;
+    a.ctr = c->d_ctr.p;
+    a.key0 = c->key0;
+    a.key1 = c->key1;
+    a.tag = TAG_APT_SWEEP;
+    a.n_sweeps = n_sweeps;
+    a.do_icm = do_icm;
+    a.do_energy = 1;
+    a.mom_from = -1;
+    a.reps = c->reps;
+    a.imax = c->imax;
+    a.ni = c->ni;
+    a.bump = bump;
+    a.n_blocks = c->n_blocks;
+    return a;
+}
+
+SwapArgs swap_args(sg_ctx *c, int bump_all, int sweeps_per_cycle, int32_t *acc_out, int64_t *trace,
+                   int trace_cap, int record_every)
+{
+    SwapArgs a{};
+    a.inst = c->d_inst.p;
+    a.perm = c->d_perm.p;
+    a.E = c->d_E.p;
+    a.tab = c->d_tab.p;
+    a.tab_off = c->d_tab_off.p;
+    a.tab_len = c->d_tab_len.p;
+    a.best = c->d_best.p;
+    a.trace = trace;
+    a.trace_cap = trace_cap;
+    a.record_every = record_every;
+    a.acc_count = c->d_acc_count.p;
+    a.acc_out = acc_out;
+    a.ctr = c->d_ctr.p;
+    a.key0 = c->key0;
+    a.key1 = c->key1;
+    a.n_beta = c->n_beta;
+    a.reps = c->reps;
+    a.n_inst = c->n_inst;
+    a.bump_all = bump_all;
+    a.sweeps_per_cycle = sweeps_per_cycle;
+    return a;
+}
+
+void require(sg_ctx *c, int mode)
+{
+    if (!c) fail(SG_EINVAL, "context is NULL");
+    if (c->mode != mode) fail(SG_ESTATE, "call does not match the context mode");
+}
+
+bool any_field(const sg_ctx *c)
+{
+    for (auto &L : c->lat)
+        if (L.has_field()) return true;
+    return false;
+}
+
+// --------------------------------------------------------------------- DT-SQA
+void create_sqa(sg_ctx *c, const sg_config *cfg)
+{
+    if (cfg->M < 2 || cfg->M > 64) fail(SG_EINVAL, "M must be in 2..64");
+    if (cfg->M & 1) fail(SG_EUNSUPPORTED, "odd M (Trotter ring with three colours) is not implemented");
+    if (cfg->R < 1 || cfg->R > 65535) fail(SG_EINVAL, "R must be in 1..65535");
+    if (!(cfg->sqa_beta > 0.0) || !std::isfinite(cfg->sqa_beta)) fail(SG_EINVAL, "sqa_beta must be > 0");
+    if ((int64_t)cfg->n_inst * cfg->R > (1 << 28)) fail(SG_ENOMEM, "too many replicas");
+    build_common(c, cfg);
+    init_stream(c, cfg->hip_stream);
+    c->M = cfg->M;
+    c->R = cfg->R;
+    c->H = cfg->M / 2;
+    c->sqa_beta = cfg->sqa_beta;
+    c->smax = 6 + c->hmax;
+    c->nl = (2 * c->smax + 1) * 3;
+    hipStream_t s = c->stream;
+    std::vector<uint4> rec, recj;
+    int64_t words = 0;
+    int npad_max = 0;
+    for (int i = 0; i < c->n_inst; ++i) {
+        const Lat &L = c->lat[i];
+        InstDev I{};
+        I.n = L.n;
+        I.npad = round_up(L.n, 16);
+        I.n_slots = c->M;
+        sqa_records(L, rec, recj, I);
+        I.spin_off = words;
+        words += (int64_t)c->R * I.npad * 2;
+        npad_max = std::max(npad_max, I.npad);
+        c->idev.push_back(I);
+    }
+    c->d_inst.upload(c->idev, s, "instances");
+    c->d_rec.upload(rec, s, "records");
+    c->d_recj.upload(recj, s, "records");
+    c->d_sqa.alloc((size_t)words, "spins");
+    c->d_slice_E.alloc((size_t)c->n_inst * c->R * c->M, "slice energies");
+    c->d_ctr.alloc(8, "counters");
+    hip_check(launch_fill_u32(c->d_ctr.p, 0u, 8, s), "init");
+    c->sqa_lds = sizeof(uint32_t) * (size_t)(2 * (npad_max + 1) + c->nl + 2 * 64) + 16;
+    if (c->sqa_lds > kMaxLds)
+        fail(SG_EUNSUPPORTED, "instance too large for one work-group's LDS (%zu bytes)", c->sqa_lds);
+    SqaArgs a{};
+    a.inst = c->d_inst.p;
+    a.spins = c->d_sqa.p;
+    a.R = c->R;
+    a.M = c->M;
+    a.H = c->H;
+    a.key0 = c->key0;
+    a.key1 = c->key1;
+    hip_check(launch_sqa_init(a, c->n_inst, s), "sqa init");
+}
+
+SqaArgs sqa_args(sg_ctx *c)
+{
+    SqaArgs a{};
+    a.inst = c->d_inst.p;
+    a.rec = c->d_rec.p;
+    a.rec_j = c->d_recj.p;
+    a.spins = c->d_sqa.p;
+    a.lut = c->d_sqa_lut.p;
+    a.slice_E = c->d_slice_E.p;
+    a.R = c->R;
+    a.M = c->M;
+    a.H = c->H;
+    a.smax = c->smax;
+    a.nl = c->nl;
+    a.key0 = c->key0;
+    a.key1 = c->key1;
+    return a;
+}
+
+template <class F>
+sg_status guarded(sg_ctx *c, F &&f)
+{
+    try {
+        f();
+        if (c) c->err.clear();
+        return SG_OK;
+    } catch (const Failure &e) {
+        if (c) c->err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        if (c) c->err = "host allocation failed";
+        return SG_ENOMEM;
+    }
+}
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+sg_status sg_create(const sg_config *cfg, sg_ctx **out)
+{
+    if (!out) return SG_EINVAL;
+    *out = nullptr;
+    sg_ctx *c = nullptr;
+    try {
+        if (!cfg) fail(SG_EINVAL, "config is NULL");
+        c = new sg_ctx();
+        c->mode = cfg->mode;
+        if (cfg->mode == SG_APT) create_apt(c, cfg);
+        else if (cfg->mode == SG_SQA) create_sqa(c, cfg);
+        else fail(SG_EINVAL, "mode must be SG_APT or SG_SQA");
+        hip_check(hipStreamSynchronize(c->stream), "create");
+    } catch (const Failure &e) {
+        g_create_error = e.msg;
+        delete c;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_create_error = "host allocation failed";
+        delete c;
+        return SG_ENOMEM;
+    }
+    g_create_error.clear();
+    *out = c;
+    return SG_OK;
+}
+
+void sg_destroy(sg_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
+
+const char *sg_last_error(const sg_ctx *c)
+{
+    if (!c) return g_create_error.c_str();
+    return c->err.c_str();
+}
+
+sg_status sg_sweep(sg_ctx *c, int32_t n_sweeps)
+{
+    return guarded(c, [&] {
+        require(c, SG_APT);
+        if (n_sweeps < 0) fail(SG_EINVAL, "n_sweeps must be >= 0");
+        if (n_sweeps == 0) return;
+        AptArgs a = apt_args(c, n_sweeps, 0, 1);
+        hip_check(launch_apt_quad(a, c->quad_lds, c->stream), "sweep");
+    });
+}
+
+sg_status sg_icm(sg_ctx *c, double cutoff, int32_t *info_host)
+{
+    return guarded(c, [&] {
+        require(c, SG_APT);
+        if (std::isnan(cutoff)) fail(SG_EINVAL, "cutoff is NaN");
+        if (c->reps >= 2 && any_field(c))
+            fail(SG_EUNSUPPORTED, "ICM with non-zero fields is not supported");
+        upload_icm_flags(c, cutoff);
+        hip_check(launch_fill_u32((uint32_t *)c->d_icm_info.p, 0xFFFFFFFFu, (int64_t)c->d_icm_info.n,
+                                  c->stream),
+                  "icm");
+        AptArgs a = apt_args(c, 0, 1, 2);
+        hip_check(launch_apt_quad(a, c->quad_lds, c->stream), "icm");
+        if (info_host) {
+            c->d_icm_info.download(info_host, c->d_icm_info.n, c->stream, "icm info");
+            hip_check(hipStreamSynchronize(c->stream), "icm");
+            if (c->reps == 1)
+                for (size_t i = 0; i < c->d_icm_info.n; ++i) info_host[i] = -1;
+        }
+    });
+}
+
+sg_status sg_energy(sg_ctx *c, int64_t *E_host)
+{
+    return guarded(c, [&] {
+        if (!c) fail(SG_EINVAL, "context is NULL");
+        if (!E_host) fail(SG_EINVAL, "E_host is NULL");
+        if (c->mode == SG_APT) {
+            const int nb4 = 4 * c->n_quads;
+            std::vector<int32_t> e((size_t)c->n_inst * nb4);
+            c->d_E.download(e.data(), e.size(), c->stream, "energy");
+            hip_check(hipStreamSynchronize(c->stream), "energy");
+            for (int i = 0; i < c->n_inst; ++i)
+                for (int s = 0; s < c->n_slots; ++s)
+                    E_host[(size_t)i * c->n_slots + s] = e[(size_t)i * nb4 + s];
+        } else {
+            SqaArgs a = sqa_args(c);
+            a.n_steps = 0;
+            a.do_energy = 1;
+            a.lut = nullptr;
+            hip_check(launch_sqa(a, c->n_inst, c->sqa_lds, c->stream), "energy");
+            std::vector<int32_t> e((size_t)c->n_inst * c->R * c->M);
+            c->d_slice_E.download(e.data(), e.size(), c->stream, "energy");
+            hip_check(hipStreamSynchronize(c->stream), "energy");
+            for (size_t i = 0; i < e.size(); ++i) E_host[i] = e[i];
+        }
+    });
+}
+
+sg_status sg_swap(sg_ctx *c, int32_t *accepted_host)
+{
+    return guarded(c, [&] {
+        require(c, SG_APT);
+        SwapArgs a = swap_args(c, 0, 0, accepted_host ? c->d_acc_out.p : nullptr, nullptr, 0, 0);
+        hip_check(launch_apt_swap(a, c->stream), "swap");
+        if (accepted_host) {
+            c->d_acc_out.download(accepted_host, (size_t)c->n_inst * (c->n_beta - 1) * c->reps,
+                                  c->stream, "swap");
+            hip_check(hipStreamSynchronize(c->stream), "swap");
+        }
+    });
+}
+
+sg_status sg_run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, double icm_cutoff,
+                     int32_t record_every, int64_t *best_trace)
+{
+    return guarded(c, [&] {
+        require(c, SG_APT);
+        if (n_cycles < 0 || sweeps_per_swap < 1) fail(SG_EINVAL, "bad cycle or sweep count");
+        if (std::isnan(icm_cutoff)) fail(SG_EINVAL, "cutoff is NaN");
+        if (record_every < 0 || (best_trace && record_every == 0))
+            fail(SG_EINVAL, "record_every must be > 0 with a trace");
+        const bool icm = c->reps >= 2 && icm_cutoff != std::numeric_limits<double>::infinity();
+        if (icm && any_field(c)) fail(SG_EUNSUPPORTED, "ICM with non-zero fields is not supported");
+        if (n_cycles == 0) return;
+        upload_icm_flags(c, icm ? icm_cutoff : std::numeric_limits<double>::infinity());
+        const int cap = best_trace ? (int)(n_cycles / record_every) : 0;
+        if (best_trace) {
+            if ((size_t)c->n_inst * cap > c->d_trace.n) c->d_trace.alloc((size_t)c->n_inst * cap, "trace");
+        }
+        int64_t *trace = best_trace ? c->d_trace.p : nullptr;
+        const int rec = best_trace ? record_every : 0;
+        hip_check(launch_fill_u32(c->d_ctr.p + 3, 0u, 1, c->stream), "cycle counter");
+        AptArgs qa = apt_args(c, sweeps_per_swap, icm ? 1 : 0, 0);
+        SwapArgs sa = swap_args(c, 1, sweeps_per_swap, nullptr, trace, cap, rec);
+        // Replay a captured graph of K cycles; the kernels read their step
+        // numbers from device counters, so the same graph is valid every time.
+        const int K = 32;
+        if (!c->gexec || c->g_sweeps != sweeps_per_swap || c->g_icm != (int)icm || c->g_record != rec ||
+            c->g_trace != trace || c->g_trace_cap != cap) {
+            if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+            c->gexec = nullptr;
+            hipGraph_t g = nullptr;
+            hip_check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "capture");
+            hipError_t e = hipSuccess;
+            for (int k = 0; k < K && e == hipSuccess; ++k) {
+                e = launch_apt_quad(qa, c->quad_lds, c->stream);
+                if (e == hipSuccess) e = launch_apt_swap(sa, c->stream);
+            }
+            hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+            hip_check(e, "capture launch");
+            hip_check(e2, "end capture");
+            hipError_t e3 = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            hip_check(e3, "graph instantiate");
+            c->g_sweeps = sweeps_per_swap;
+            c->g_icm = (int)icm;
+            c->g_record = rec;
+            c->g_trace = trace;
+            c->g_trace_cap = cap;
+        }
+        int64_t done = 0;
+        for (; done + K <= n_cycles; done += K) hip_check(hipGraphLaunch(c->gexec, c->stream), "graph launch");
+        for (; done < n_cycles; ++done) {
+            hip_check(launch_apt_quad(qa, c->quad_lds, c->stream), "cycle");
+            hip_check(launch_apt_swap(sa, c->stream), "cycle");
+        }
+        if (best_trace) {
+            std::vector<int64_t> t((size_t)c->n_inst * cap);
+            c->d_trace.download(t.data(), t.size(), c->stream, "trace");
+            hip_check(hipStreamSynchronize(c->stream), "trace");
+            std::memcpy(best_trace, t.data(), t.size() * sizeof(int64_t));
+        }
+    });
+}
+
+sg_status sg_best(sg_ctx *c, int64_t *best_host)
+{
+    return guarded(c, [&] {
+        require(c, SG_APT);
+        if (!best_host) fail(SG_EINVAL, "best_host is NULL");
+        c->d_best.download(best_host, (size_t)c->n_inst, c->stream, "best");
+        hip_check(hipStreamSynchronize(c->stream), "best");
+    });
+}
+
+sg_status sg_swap_counts(sg_ctx *c, int64_t *counts)
+{
+    return guarded(c, [&] {
+        require(c, SG_APT);
+        if (!counts) fail(SG_EINVAL, "counts is NULL");
+        c->d_acc_count.download(counts, (size_t)c->n_inst * (c->n_beta - 1) * c->reps, c->stream,
+                                "swap counts");
+        hip_check(hipStreamSynchronize(c->stream), "swap counts");
+    });
+}
+
+sg_status sg_sqa_anneal(sg_ctx *c, const double *gamma, int32_t n_steps, int64_t *best_E,
+                        int8_t *best_state)
+{
+    return guarded(c, [&] {
+        require(c, SG_SQA);
+        if (n_steps < 0 || (n_steps > 0 && !gamma)) fail(SG_EINVAL, "bad schedule");
+        for (int t = 0; t < n_steps; ++t)
+            if (!(gamma[t] > 0.0) || !std::isfinite(gamma[t])) fail(SG_EINVAL, "gamma must be > 0");
+        // thresholds for every step, FP64 -> uint32 (Supplementary Eq. S.3)
+        const int chunk = 256;
+        int done = 0;
+        std::vector<uint32_t> lut;
+        while (done < n_steps) {
+            const int ns = std::min(chunk, n_steps - done);
+            lut.assign((size_t)ns * c->nl, 0u);
+            for (int t = 0; t < ns; ++t) {
+                const double K = trotter_K(c->sqa_beta, c->M, gamma[done + t]);
+                for (int s = -c->smax; s <= c->smax; ++s)
+                    for (int tt = 0; tt < 3; ++tt)
+                        lut[(size_t)t * c->nl + (s + c->smax) * 3 + tt] =
+                            trotter_threshold(c->sqa_beta, c->M, K, s, 2 * tt - 2);
+            }
+            // the previous chunk's kernel may still read the table: wait before replacing it
+            hip_check(hipStreamSynchronize(c->stream), "anneal");
+            c->d_sqa_lut.upload(lut.data(), lut.size(), c->stream, "sqa thresholds");
+            SqaArgs a = sqa_args(c);
+            a.t0 = (int32_t)c->sqa_steps;
+            a.n_steps = ns;
+            a.lut_step0 = 0;
+            a.do_energy = (done + ns == n_steps) ? 1 : 0;
+            hip_check(launch_sqa(a, c->n_inst, c->sqa_lds, c->stream), "anneal");
+            c->sqa_steps += (uint32_t)ns;
+            done += ns;
+        }
+        if (n_steps == 0) {
+            SqaArgs a = sqa_args(c);
+            a.n_steps = 0;
+            a.do_energy = 1;
+            hip_check(launch_sqa(a, c->n_inst, c->sqa_lds, c->stream), "anneal");
+        }
+        if (best_E || best_state) {
+            const int RM = c->R * c->M;
+            std::vector<int32_t> e((size_t)c->n_inst * RM);
+            c->d_slice_E.download(e.data(), e.size(), c->stream, "anneal");
+            hip_check(hipStreamSynchronize(c->stream), "anneal");
+            for (int i = 0; i < c->n_inst; ++i) {
+                int arg = 0;
+                for (int q = 1; q < RM; ++q)
+                    if (e[(size_t)i * RM + q] < e[(size_t)i * RM + arg]) arg = q;
+                if (best_E) best_E[i] = e[(size_t)i * RM + arg];
+                if (best_state) {
+                    const InstDev &I = c->idev[i];
+                    const int r = arg / c->M, k = arg % c->M;
+                    std::vector<uint32_t> w((size_t)I.npad * 2);
+                    hip_check(hipMemcpyAsync(w.data(),
+                                             c->d_sqa.p + I.spin_off + (int64_t)r * I.npad * 2,
+                                             w.size() * 4, hipMemcpyDeviceToHost, c->stream),
+                              "best state");
+                    hip_check(hipStreamSynchronize(c->stream), "best state");
+                    int8_t *o = best_state + (size_t)i * c->n_max;
+                    std::memset(o, 0, (size_t)c->n_max);
+                    for (int j = 0; j < I.n; ++j)
+                        o[j] = ((w[2 * j + (k & 1)] >> (k >> 1)) & 1u) ? 1 : -1;
+                }
+            }
+        }
+    });
+}
+
+sg_status sg_get_spins(sg_ctx *c, int8_t *out)
+{
+    return guarded(c, [&] {
+        if (!c || !out) fail(SG_EINVAL, "NULL argument");
+        if (c->mode == SG_APT) {
+            const int nb4 = 4 * c->n_quads;
+            std::vector<uint8_t> raw(c->d_spins.n);
+            std::vector<int32_t> perm((size_t)c->n_inst * nb4);
+            c->d_spins.download(raw.data(), raw.size(), c->stream, "spins");
+            c->d_perm.download(perm.data(), perm.size(), c->stream, "spins");
+            hip_check(hipStreamSynchronize(c->stream), "spins");
+            for (int i = 0; i < c->n_inst; ++i) {
+                const InstDev &I = c->idev[i];
+                for (int s = 0; s < c->n_slots; ++s) {
+                    const uint8_t *src = raw.data() + I.spin_off + (int64_t)perm[(size_t)i * nb4 + s] * I.npad;
+                    int8_t *dst = out + ((size_t)i * c->n_slots + s) * c->n_max;
+                    std::memset(dst, 0, (size_t)c->n_max);
+                    for (int j = 0; j < I.n; ++j) dst[j] = src[j] ? 1 : -1;
+                }
+            }
+        } else {
+            std::vector<uint32_t> raw(c->d_sqa.n);
+            c->d_sqa.download(raw.data(), raw.size(), c->stream, "spins");
+            hip_check(hipStreamSynchronize(c->stream), "spins");
+            for (int i = 0; i < c->n_inst; ++i) {
+                const InstDev &I = c->idev[i];
+                for (int r = 0; r < c->R; ++r)
+                    for (int k = 0; k < c->M; ++k) {
+                        const uint32_t *w = raw.data() + I.spin_off + (int64_t)r * I.npad * 2;
+                        int8_t *dst = out + (((size_t)i * c->R + r) * c->M + k) * c->n_max;
+                        std::memset(dst, 0, (size_t)c->n_max);
+                        for (int j = 0; j < I.n; ++j)
+                            dst[j] = ((w[2 * j + (k & 1)] >> (k >> 1)) & 1u) ? 1 : -1;
+                    }
+            }
+        }
+    });
+}
+
+sg_status sg_set_spins(sg_ctx *c, const int8_t *in)
+{
+    return guarded(c, [&] {
+        if (!c || !in) fail(SG_EINVAL, "NULL argument");
+        if (c->mode == SG_APT) {
+            const int nb4 = 4 * c->n_quads;
+            for (int i = 0; i < c->n_inst; ++i)
+                for (int s = 0; s < c->n_slots; ++s)
+                    for (int j = 0; j < c->idev[i].n; ++j) {
+                        const int8_t v = in[((size_t)i * c->n_slots + s) * c->n_max + j];
+                        if (v != 1 && v != -1) fail(SG_EINVAL, "spins must be +1 or -1");
+                    }
+            std::vector<uint8_t> raw(c->d_spins.n, 0);
+            std::vector<int32_t> perm((size_t)c->n_inst * nb4);
+            for (int i = 0; i < c->n_inst; ++i) {
+                const InstDev &I = c->idev[i];
+                for (int s = 0; s < nb4; ++s) {
+                    perm[(size_t)i * nb4 + s] = s;
+                    if (s >= c->n_slots) continue;
+                    uint8_t *dst = raw.data() + I.spin_off + (int64_t)s * I.npad;
+                    const int8_t *src = in + ((size_t)i * c->n_slots + s) * c->n_max;
+                    for (int j = 0; j < I.n; ++j) dst[j] = src[j] > 0 ? 1 : 0;
+                }
+            }
+            c->d_spins.upload(raw.data(), raw.size(), c->stream, "spins");
+            c->d_perm.upload(perm.data(), perm.size(), c->stream, "perm");
+            // energies of the new state
+            AptArgs a = apt_args(c, 0, 0, 0);
+            hip_check(launch_apt_quad(a, c->quad_lds, c->stream), "energy");
+            hip_check(hipStreamSynchronize(c->stream), "spins");
+        } else {
+            std::vector<uint32_t> raw(c->d_sqa.n, 0u);
+            for (int i = 0; i < c->n_inst; ++i) {
+                const InstDev &I = c->idev[i];
+                for (int r = 0; r < c->R; ++r)
+                    for (int k = 0; k < c->M; ++k) {
+                        const int8_t *src = in + (((size_t)i * c->R + r) * c->M + k) * c->n_max;
+                        uint32_t *w = raw.data() + I.spin_off + (int64_t)r * I.npad * 2;
+                        for (int j = 0; j < I.n; ++j) {
+                            if (src[j] != 1 && src[j] != -1) fail(SG_EINVAL, "spins must be +1 or -1");
+                            if (src[j] > 0) w[2 * j + (k & 1)] |= 1u << (k >> 1);
+                        }
+                    }
+            }
+            c->d_sqa.upload(raw.data(), raw.size(), c->stream, "spins");
+            hip_check(hipStreamSynchronize(c->stream), "spins");
+        }
+    });
+}
+
+sg_status sg_get_counters(sg_ctx *c, uint32_t *out3)
+{
+    return guarded(c, [&] {
+        if (!c || !out3) fail(SG_EINVAL, "NULL argument");
+        uint32_t v[8];
+        c->d_ctr.download(v, 8, c->stream, "counters");
+        hip_check(hipStreamSynchronize(c->stream), "counters");
+        if (c->mode == SG_SQA) v[0] = c->sqa_steps;
+        out3[0] = v[0];
+        out3[1] = v[1];
+        out3[2] = v[2];
+    });
+}
+
+// blob: magic, mode, n_inst, sizes, counters[3], best[n_inst], spins (logical, int8)
+static size_t state_size(const sg_ctx *c)
+{
+    const size_t spins = c->mode == SG_APT ? (size_t)c->n_inst * c->n_slots * c->n_max
+                                           : (size_t)c->n_inst * c->R * c->M * c->n_max;
+    return 64 + 8 * (size_t)c->n_inst + spins + (c->mode == SG_APT ? 8 * (size_t)c->n_inst * (c->n_beta - 1) * c->reps : 0);
+}
+
+sg_status sg_get_state(sg_ctx *c, void *blob, size_t *len)
+{
+    return guarded(c, [&] {
+        if (!c || !len) fail(SG_EINVAL, "NULL argument");
+        const size_t need = state_size(c);
+        if (!blob) { *len = need; return; }
+        if (*len < need) fail(SG_EINVAL, "blob too small (%zu < %zu)", *len, need);
+        uint8_t *b = (uint8_t *)blob;
+        std::memset(b, 0, 64);
+        const uint32_t hdr[6] = {0x53474331u, (uint32_t)c->mode, (uint32_t)c->n_inst,
+                                 (uint32_t)c->n_max, (uint32_t)c->n_slots, (uint32_t)(c->R * c->M)};
+        std::memcpy(b, hdr, sizeof hdr);
+        uint32_t ctr[3];
+        if (sg_get_counters(c, ctr) != SG_OK) fail(SG_EHIP, "%s", c->err.c_str());
+        std::memcpy(b + 24, ctr, sizeof ctr);
+        size_t off = 64;
+        if (c->mode == SG_APT) {
+            c->d_best.download((int64_t *)(b + off), (size_t)c->n_inst, c->stream, "state");
+            off += 8 * (size_t)c->n_inst;
+            const size_t na = (size_t)c->n_inst * (c->n_beta - 1) * c->reps;
+            c->d_acc_count.download((int64_t *)(b + off), na, c->stream, "state");
+            off += 8 * na;
+            hip_check(hipStreamSynchronize(c->stream), "state");
+        } else {
+            off += 8 * (size_t)c->n_inst;
+        }
+        if (sg_get_spins(c, (int8_t *)(b + off)) != SG_OK) fail(SG_EHIP, "%s", c->err.c_str());
+        *len = need;
+    });
+}
+
+sg_status sg_set_state(sg_ctx *c, const void *blob, size_t len)
+{
+    return guarded(c, [&] {
+        if (!c || !blob) fail(SG_EINVAL, "NULL argument");
+        if (len != state_size(c)) fail(SG_EINVAL, "blob size does not match the context");
+        const uint8_t *b = (const uint8_t *)blob;
+        uint32_t hdr[6];
+        std::memcpy(hdr, b, sizeof hdr);
+        if (hdr[0] != 0x53474331u || hdr[1] != (uint32_t)c->mode || hdr[2] != (uint32_t)c->n_inst ||
+            hdr[3] != (uint32_t)c->n_max || hdr[4] != (uint32_t)c->n_slots ||
+            hdr[5] != (uint32_t)(c->R * c->M))
+            fail(SG_EINVAL, "blob belongs to a different context shape");
+        uint32_t ctr[3];
+        std::memcpy(ctr, b + 24, sizeof ctr);
+        size_t off = 64;
+        if (c->mode == SG_APT) {
+            c->d_best.upload((const int64_t *)(b + off), (size_t)c->n_inst, c->stream, "state");
+            off += 8 * (size_t)c->n_inst;
+            const size_t na = (size_t)c->n_inst * (c->n_beta - 1) * c->reps;
+            c->d_acc_count.upload((const int64_t *)(b + off), na, c->stream, "state");
+            off += 8 * na;
+        } else {
+            off += 8 * (size_t)c->n_inst;
+        }
+        if (sg_set_spins(c, (const int8_t *)(b + off)) != SG_OK) fail(SG_EINVAL, "%s", c->err.c_str());
+        uint32_t v[8] = {ctr[0], ctr[1], ctr[2], 0u, 0u, 0u, 0u, 0u};
+        c->d_ctr.upload(v, 8, c->stream, "state");
+        if (c->mode == SG_SQA) c->sqa_steps = ctr[0];
+        hip_check(hipStreamSynchronize(c->stream), "state");
+    });
+}
+
+sg_status sg_timer_start(sg_ctx *c)
+{
+    return guarded(c, [&] {
+        if (!c) fail(SG_EINVAL, "context is NULL");
+        if (!c->timer.a) hip_check(hipEventCreate(&c->timer.a), "event");
+        if (!c->timer.b) hip_check(hipEventCreate(&c->timer.b), "event");
+        hip_check(hipEventRecord(c->timer.a, c->stream), "event");
+    });
+}
+
+sg_status sg_timer_stop(sg_ctx *c, float *ms)
+{
+    return guarded(c, [&] {
+        if (!c || !ms) fail(SG_EINVAL, "NULL argument");
+        if (!c->timer.a) fail(SG_ESTATE, "timer not started");
+        hip_check(hipEventRecord(c->timer.b, c->stream), "event");
+        hip_check(hipEventSynchronize(c->timer.b), "event");
+        hip_check(hipEventElapsedTime(ms, c->timer.a, c->timer.b), "event");
+    });
+}
+
+sg_status sg_synchronize(sg_ctx *c)
+{
+    return guarded(c, [&] {
+        if (!c) fail(SG_EINVAL, "context is NULL");
+        hip_check(hipStreamSynchronize(c->stream), "synchronize");
+    });
+}
+
+}  // extern "C"
+
+// ====================================================================== adaptive ladder
+namespace {
+
+double sigma_of_moments(int64_t S1, int64_t S2, int64_t N)
+{
+    const int64_t num = N * S2 - S1 * S1;
+    const double var = (double)num / ((double)N * (double)(N - 1));
+    return std::sqrt(var);
+}
+
+}  // namespace
+
+extern "C" sg_status sg_adaptive_ladder(const sg_lattice *inst, int32_t n_inst,
+                                        const sg_adaptive_params *p, uint64_t seed,
+                                        void *hip_stream, double *beta_out, double *sigma_out,
+                                        int32_t *len_out)
+{
+    sg_ctx *c = nullptr;
+    try {
+        if (!inst || n_inst < 1 || !p || !beta_out || !len_out) fail(SG_EINVAL, "bad arguments");
+        if (p->n_chains < 1 || p->sweeps < 1 || p->tail < 2 || p->tail > p->sweeps || p->max_steps < 1)
+            fail(SG_EINVAL, "bad adaptive parameters");
+        if (!(p->alpha > 0.0) || !std::isfinite(p->beta0) || p->beta0 < 0.0)
+            fail(SG_EINVAL, "bad adaptive parameters");
+        // Chains are the slots of an APT context with one temperature per instance.
+        c = new sg_ctx();
+        c->mode = SG_APT;
+        // slots = chains: n_beta * reps must equal n_chains -> reps = 1, n_beta = chains
+        std::vector<double> ladder((size_t)n_inst * p->n_chains);
+        for (int i = 0; i < n_inst; ++i)
+            for (int k = 0; k < p->n_chains; ++k) ladder[(size_t)i * p->n_chains + k] = p->beta0 + k;
+        sg_config cfg{};
+        cfg.mode = SG_APT;
+        cfg.n_inst = n_inst;
+        cfg.inst = inst;
+        cfg.n_beta = std::max(2, p->n_chains);
+        if (p->n_chains < 2) {
+            ladder.assign((size_t)n_inst * 2, 0.0);
+            for (int i = 0; i < n_inst; ++i) { ladder[2 * i] = p->beta0; ladder[2 * i + 1] = p->beta0 + 1.0; }
+        }
+        cfg.beta = ladder.data();
+        cfg.reps_per_beta = 1;
+        cfg.seed = seed;
+        cfg.hip_stream = hip_stream;
+        create_apt(c, &cfg);
+        hipStream_t s = c->stream;
+        const int nb4 = 4 * c->n_quads;
+        // re-initialise with the adaptive-stage purpose tag
+        hip_check(launch_apt_init(c->d_inst.p, c->d_desc.p, c->n_blocks, c->d_spins.p, c->d_perm.p,
+                                  c->key0, c->key1, TAG_ADAPT_INIT, s),
+                  "adaptive init");
+        // every slot of instance i uses table i (the current beta_t of instance i)
+        std::vector<int32_t> slot_lut((size_t)n_inst * nb4);
+        for (int i = 0; i < n_inst; ++i)
+            for (int k = 0; k < nb4; ++k) slot_lut[(size_t)i * nb4 + k] = i;
+        c->d_slot_lut.upload(slot_lut, s, "adaptive tables");
+        std::vector<double> bt(n_inst, p->beta0);
+        std::vector<int> len(n_inst, 0);
+        std::vector<char> active(n_inst, 1);
+        std::vector<uint32_t> lut((size_t)n_inst * c->ni);
+        std::vector<int64_t> mom((size_t)n_inst * nb4 * 2);
+        for (int step = 0; step < p->max_steps; ++step) {
+            bool any = false;
+            for (int i = 0; i < n_inst; ++i) any |= active[i] != 0;
+            if (!any) break;
+            for (int i = 0; i < n_inst; ++i)
+                for (int I2 = -c->imax; I2 <= c->imax; ++I2)
+                    lut[(size_t)i * c->ni + (I2 + c->imax)] = heat_bath_threshold(bt[i], I2);
+            hip_check(hipStreamSynchronize(s), "adaptive");
+            c->d_lut.upload(lut.data(), lut.size(), s, "adaptive tables");
+            hip_check(launch_fill_i64(c->d_mom.p, 0, (int64_t)c->d_mom.n, s), "adaptive");
+            AptArgs a = apt_args(c, p->sweeps, 0, 1);
+            a.tag = TAG_ADAPT_SWEEP;
+            a.mom_from = p->sweeps - p->tail;
+            a.do_energy = 0;
+            hip_check(launch_apt_quad(a, c->quad_lds, s), "adaptive sweeps");
+            c->d_mom.download(mom.data(), mom.size(), s, "moments");
+            hip_check(hipStreamSynchronize(s), "adaptive");
+            for (int i = 0; i < n_inst; ++i) {
+                if (!active[i]) continue;
+                double sum = 0.0;
+                for (int k = 0; k < p->n_chains; ++k) {
+                    const int64_t *m = &mom[((size_t)i * nb4 + k) * 2];
+                    sum += sigma_of_moments(m[0], m[1], p->tail);
+                }
+                const double sigma = sum / (double)p->n_chains;
+                beta_out[(size_t)i * p->max_steps + step] = bt[i];
+                if (sigma_out) sigma_out[(size_t)i * p->max_steps + step] = sigma;
+                len[i] = step + 1;
+                if (sigma < p->tol) active[i] = 0;
+                else bt[i] = bt[i] + p->alpha / sigma;
+            }
+        }
+        for (int i = 0; i < n_inst; ++i) len_out[i] = len[i];
+    } catch (const Failure &e) {
+        g_create_error = e.msg;
+        delete c;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        delete c;
+        return SG_ENOMEM;
+    }
+    delete c;
+    return SG_OK;
+}

@@ -1,0 +1,154 @@
+// sg_internal.h -- structures shared by the host side (sg_api.cpp) and the
+// device kernels (sg_kernels.hip) of libsg.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sg {
+
+// Random-stream purposes (low 4 bits of Philox counter word 3; word 3 is
+// instance << 4 | purpose).
+enum : uint32_t {
+    TAG_APT_INIT = 1,
+    TAG_APT_SWEEP = 2,
+    TAG_SWAP = 3,
+    TAG_ICM_PAIR = 4,
+    TAG_ICM_PICK = 5,
+    TAG_SQA_INIT = 6,
+    TAG_SQA_SWEEP = 7,
+    TAG_ADAPT_INIT = 8,
+    TAG_ADAPT_SWEEP = 9,
+};
+
+constexpr int kMaxH = 31;      // |h| bound, so that h + 32 fits 6 bits of a site record
+constexpr int kMaxN = 32767;   // sites per instance (16-bit site and neighbour indices)
+constexpr int kQuadThreads = 256;
+constexpr int kSqaThreads = 256;
+constexpr size_t kMaxLds = 160 * 1024;   // LDS per CU on gfx950
+
+// Site record (uint4), one per site:
+//   x: j | d << 16 | jneg << 19 | (h + 32) << 25 | p << 31
+//      d    = number of bonds with J != 0 (0..6)
+//      jneg = bit a set when the bond to neighbour a has J = -1
+//      p    = (DT-SQA phase lists only) parity of the Trotter slices updated
+//   y: nb[0] | nb[1] << 16   (+x, -x)
+//   z: nb[2] | nb[3] << 16   (+y, -y)
+//   w: nb[4] | nb[5] << 16   (+z, -z)
+// An absent bond (open boundary, axis of length one, or J = 0) points at the
+// dummy index n, whose spin word is kept zero.
+
+// Per-instance geometry and buffer offsets on the device.
+struct InstDev {
+    int32_t n;           // sites
+    int32_t npad;        // sites rounded up to a multiple of 16
+    int32_t n_colours;   // colour classes (APT) or phases (DT-SQA)
+    int32_t n_slots;     // APT: n_beta * reps; DT-SQA: M
+    int32_t col_off[3];  // first record of each colour class / phase (relative)
+    int32_t col_cnt[3];  // records in each class / phase
+    int64_t rec_off;     // colour-sorted (or phase) records
+    int64_t recj_off;    // site-ordered records
+    int64_t spin_off;    // APT: byte offset of replica buffer 0; DT-SQA: word offset
+    int32_t slot_off;    // APT: first entry in perm / E / slot_lut / swap arrays
+    int32_t swap_off;    // APT: first pair entry of swap tables
+    int32_t info_off;    // APT: first ICM info record
+    int32_t pad_;
+};
+
+// One work-group task of the APT replica kernel: instance and group of four
+// consecutive logical slots.  inst < 0 = idle filler.
+struct QuadDesc {
+    int32_t inst;
+    int32_t quad;
+};
+
+struct AptArgs {
+    const QuadDesc *desc;
+    const InstDev *inst;
+    const uint4 *rec_col;
+    const uint4 *rec_j;
+    uint8_t *spins;            // physical replica buffers, bytes 0/1 (1 = spin up)
+    const int32_t *perm;       // logical slot -> physical buffer (per instance)
+    const uint32_t *lut;       // heat-bath thresholds, NI per table
+    const int32_t *slot_lut;   // logical slot -> table index
+    const uint8_t *icm_on;     // per (instance, beta index): ICM applies
+    int32_t *E;                // energies per logical slot
+    int64_t *mom;              // per logical slot {sum E, sum E^2} (adaptive stage)
+    int32_t *icm_info;         // per (instance, beta, pair) {m, seed, size, branch}
+    uint32_t *ctr;             // device counters {sweeps, icm calls, swaps, cycles, done}
+    uint32_t key0, key1;
+    uint32_t tag;              // sweep purpose (APT or adaptive)
+    int32_t n_sweeps;
+    int32_t do_icm;
+    int32_t do_energy;
+    int32_t mom_from;          // accumulate moments after sweep index >= mom_from (-1: never)
+    int32_t reps;              // ICM labels per temperature
+    int32_t imax;              // LUT covers fields -imax..imax
+    int32_t ni;                // 2 * imax + 1
+    int32_t bump;              // bit0: advance sweep counter, bit1: advance ICM counter
+    int32_t n_blocks;
+};
+
+struct SwapArgs {
+    const InstDev *inst;
+    const int32_t *n_beta_of;  // unused placeholder for per-instance ladders (all equal)
+    int32_t *perm;
+    int32_t *E;
+    const uint32_t *tab;       // swap thresholds, per pair: T[d] for |dE| = d
+    const int32_t *tab_off;    // per (instance, pair)
+    const int32_t *tab_len;
+    int64_t *best;             // per instance
+    int64_t *trace;            // [inst][trace_cap] or null
+    int32_t trace_cap;
+    int32_t record_every;
+    int64_t *acc_count;        // per (instance, pair, label)
+    int32_t *acc_out;          // per (instance, pair, label) or null
+    uint32_t *ctr;
+    uint32_t key0, key1;
+    int32_t n_beta;
+    int32_t reps;
+    int32_t n_inst;
+    int32_t bump_all;          // 1: end of an APT cycle (advance all counters)
+    int32_t sweeps_per_cycle;
+};
+
+// DT-SQA: spins of replica (inst, r) are n+1 pairs of 32-bit words
+// {even slices, odd slices}; slice k = 2h + p sits at bit h of word p.
+struct SqaArgs {
+    const InstDev *inst;
+    const uint4 *rec;          // phase-sorted records (p in bit 31 of x)
+    const uint4 *rec_j;        // site-ordered records
+    uint32_t *spins;           // [inst][R][npad + 1][2]
+    const uint32_t *lut;       // [step][NL]: index (s + smax) * 3 + (number of up Trotter neighbours)
+    int32_t *slice_E;          // [inst][R][M]
+    int32_t R;
+    int32_t M;
+    int32_t H;                 // M / 2
+    int32_t smax;
+    int32_t nl;
+    int32_t t0;                // global index of the first step
+    int32_t n_steps;
+    int32_t lut_step0;         // row of lut used for the first step
+    int32_t do_energy;
+    uint32_t key0, key1;
+};
+
+// Host-callable launch wrappers (defined in sg_kernels.hip).
+hipError_t launch_apt_init(const InstDev *inst_d, const QuadDesc *desc, int n_blocks,
+                           uint8_t *spins, const int32_t *perm, uint32_t key0, uint32_t key1,
+                           uint32_t tag, hipStream_t s);
+hipError_t launch_apt_quad(const AptArgs &a, size_t lds_bytes, hipStream_t s);
+hipError_t launch_apt_swap(const SwapArgs &a, hipStream_t s);
+hipError_t launch_sqa_init(const SqaArgs &a, int n_inst, hipStream_t s);
+hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, hipStream_t s);
+hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+
+// MLP kernels (sg_mlp.hip).  Parameters: 6625 floats, then mean[4], std[4].
+hipError_t launch_mlp_pass(const float *P, const float *x, const float *y, const int *idx,
+                           int batch, int nblk, float *grad_acc, float *loss_acc, float *out,
+                           float *grad, hipStream_t s);
+hipError_t launch_mlp_adam2(float *P, const float *g, float *m, float *v, float lr, float b1,
+                            float b2, float eps, int step, hipStream_t s);
+
+}  // namespace sg

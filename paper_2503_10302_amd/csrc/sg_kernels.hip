@@ -1,0 +1,691 @@
+// sg_kernels.hip -- gfx950 kernels of libsg.
+//
+// APT replica kernel: one work-group owns four consecutive logical replica
+// slots of one instance.  Their lattices are gathered from the physical
+// replica buffers into LDS, interleaved one byte per slot in a 32-bit word per
+// site, so that one LDS read returns a neighbour's spin in all four slots and
+// the aligned-bond count of Eq. (5) is a byte-wise sum.  One Philox4x32-10
+// block per site and sweep gives the four uniform words of Eq. (6).  Colour
+// classes are separated by work-group barriers (Methods, "Graph Coloring").
+//
+// DT-SQA kernel: one work-group owns one replica of the (d+1)-dimensional
+// lattice of Supplementary Eq. S.3.  Up to 64 Trotter slices are bit-packed
+// per site, even and odd slices in separate words; the six spatial
+// neighbours are summed bit-sliced over all slices of a parity at once.
+#include "sg_internal.h"
+
+namespace sg {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds, two 32x32->64 products.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                          uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        x1 = (uint32_t)p1;
+        x3 = (uint32_t)p0;
+        x0 = n0;
+        x2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(x0, x1, x2, x3);
+}
+
+__device__ __forceinline__ uint32_t bytemask(uint32_t bit) { return bit * 0x01010101u; }
+
+// Per byte (slot): number of present bonds whose J * s_neighbour = +1.
+__device__ __forceinline__ uint32_t aligned_count(const uint32_t *sp, const uint4 r)
+{
+    const uint32_t jn = r.x >> 19;
+    uint32_t k = sp[r.y & 0xFFFFu] ^ bytemask(jn & 1u);
+    k += sp[r.y >> 16] ^ bytemask((jn >> 1) & 1u);
+    k += sp[r.z & 0xFFFFu] ^ bytemask((jn >> 2) & 1u);
+    k += sp[r.z >> 16] ^ bytemask((jn >> 3) & 1u);
+    k += sp[r.w & 0xFFFFu] ^ bytemask((jn >> 4) & 1u);
+    k += sp[r.w >> 16] ^ bytemask((jn >> 5) & 1u);
+    return k;
+}
+
+__device__ __forceinline__ int32_t wave_sum(int32_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int32_t wave_min(int32_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Block-wide sum of four values (blockDim = 256).  red: >= 16 ints of LDS.
+__device__ __forceinline__ void block_sum4(int32_t v[4], int32_t *red)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = wave_sum(v[i]);
+    if (lane == 0)
+        for (int i = 0; i < 4; ++i) red[wv * 4 + i] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = red[i] + red[4 + i] + red[8 + i] + red[12 + i];
+    __syncthreads();
+}
+
+// Exclusive prefix of v over the block in thread order; returns it and the total.
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *red, int32_t *total)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int32_t incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) red[wv] = incl;
+    __syncthreads();
+    int32_t base = 0, tot = 0;
+    for (int w = 0; w < 4; ++w) {
+        if (w < wv) base += red[w];
+        tot += red[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + incl - v;
+}
+
+// Energies (Eq. 8) of the four slots held in sp: E = -1/2 sum_j s_j (I_j + h_j).
+__device__ void quad_energy(const uint32_t *sp, const uint4 *recj, int n, int32_t *red, int32_t e[4])
+{
+    int32_t acc[4] = {0, 0, 0, 0};
+    for (int j = threadIdx.x; j < n; j += kQuadThreads) {
+        const uint4 r = recj[j];
+        const uint32_t k = aligned_count(sp, r);
+        const int32_t d = (int32_t)((r.x >> 16) & 7u);
+        const int32_t hh = (int32_t)((r.x >> 25) & 63u) - 32;
+        const uint32_t w = sp[j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int32_t v = 2 * (int32_t)((k >> (8 * i)) & 0xFFu) - d + 2 * hh;
+            acc[i] += ((w >> (8 * i)) & 1u) ? v : -v;
+        }
+    }
+    block_sum4(acc, red);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) e[i] = -acc[i] / 2;
+}
+
+// Houdayer move on the replica pair held in bytes ba, bb of sp (Algorithm S2,
+// ICMop).  LDS work space: queue[n] (uint16), vis[(n + 31) / 32], red[>= 24].
+__device__ void icm_pair(uint32_t *sp, const uint4 *recj, int n, int ba, int bb, uint32_t w0,
+                         uint32_t w1, uint16_t *queue, uint32_t *vis, int32_t *red, int32_t *info)
+{
+    const int tid = threadIdx.x;
+    const uint32_t mA = 1u << (8 * ba), mB = 1u << (8 * bb);
+    const int chunk = (n + kQuadThreads - 1) / kQuadThreads;
+    const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
+    int32_t cnt = 0;
+    for (int j = lo; j < hi; ++j) {
+        const uint32_t w = sp[j];
+        cnt += ((w & mA) != 0) != ((w & mB) != 0);
+    }
+    const int nvis = (n + 31) >> 5;
+    for (int i = tid; i < nvis; i += kQuadThreads) vis[i] = 0u;
+    int32_t m;
+    const int32_t prefix = block_exclusive_scan(cnt, red, &m);
+    if (m == 0) {
+        if (tid == 0 && info) { info[0] = 0; info[1] = -1; info[2] = 0; info[3] = 0; }
+        __syncthreads();
+        return;
+    }
+    const int32_t k = (int32_t)(((uint64_t)w0 * (uint64_t)(uint32_t)m) >> 32);
+    if (prefix <= k && k < prefix + cnt) {
+        int32_t c = prefix;
+        for (int j = lo; j < hi; ++j) {
+            const uint32_t w = sp[j];
+            if (((w & mA) != 0) != ((w & mB) != 0)) {
+                if (c == k) {
+                    red[16] = j;
+                    queue[0] = (uint16_t)j;
+                    vis[j >> 5] = 1u << (j & 31);
+                    break;
+                }
+                ++c;
+            }
+        }
+    }
+    if (tid == 0) red[17] = 1;   // queue tail
+    __syncthreads();
+    const int32_t seed = red[16];
+    // Level-synchronous breadth-first search over bonds with J != 0 inside q = -1.
+    int32_t head = 0, tail = 1;
+    while (head < tail) {
+        for (int i = head + tid; i < tail; i += kQuadThreads) {
+            const int j = queue[i];
+            const uint4 r = recj[j];
+            const uint32_t nb[6] = {r.y & 0xFFFFu, r.y >> 16, r.z & 0xFFFFu, r.z >> 16,
+                                    r.w & 0xFFFFu, r.w >> 16};
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                const uint32_t v = nb[a];
+                if ((int)v == n) continue;
+                const uint32_t w = sp[v];
+                if (((w & mA) != 0) == ((w & mB) != 0)) continue;
+                const uint32_t bit = 1u << (v & 31u);
+                const uint32_t old = atomicOr(&vis[v >> 5], bit);
+                if (old & bit) continue;
+                const int pos = atomicAdd(&red[17], 1);
+                queue[pos] = (uint16_t)v;
+            }
+        }
+        __syncthreads();
+        head = tail;
+        tail = red[17];
+        __syncthreads();
+    }
+    const int32_t size = tail;
+    int32_t branch;
+    if (2 * size > n) {
+        const uint32_t X = ((w1 >> 31) == 0u) ? mA : mB;
+        branch = ((w1 >> 31) == 0u) ? 1 : 2;
+        for (int j = tid; j < n; j += kQuadThreads) sp[j] ^= X;
+    } else {
+        branch = 0;
+        for (int i = tid; i < size; i += kQuadThreads) sp[queue[i]] ^= (mA | mB);
+    }
+    if (tid == 0 && info) { info[0] = m; info[1] = seed; info[2] = size; info[3] = branch; }
+    __syncthreads();
+}
+
+// Last work-group to finish advances the device counters (every work-group
+// read them at its start).
+__device__ __forceinline__ void finish_and_bump(uint32_t *ctr, int n_blocks, int bump, int n_sweeps)
+{
+    if (!bump) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t prev = atomicAdd(&ctr[4], 1u);
+        if (prev == (uint32_t)(n_blocks - 1)) {
+            if (bump & 1) ctr[0] += (uint32_t)n_sweeps;
+            if (bump & 2) ctr[1] += 1u;
+            ctr[4] = 0u;
+            __threadfence();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Random initial spins (Algorithm S2: random states), slot s = 4q + i uses
+// word i of the block at counter (j, 0, q, inst << 4 | tag).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kQuadThreads) void apt_init_kernel(const InstDev *insts,
+                                                                const QuadDesc *desc,
+                                                                uint8_t *spins, const int32_t *perm,
+                                                                uint32_t key0, uint32_t key1,
+                                                                uint32_t tag)
+{
+    const QuadDesc D = desc[blockIdx.x];
+    if (D.inst < 0) return;
+    const InstDev I = insts[D.inst];
+    const uint32_t c3 = ((uint32_t)D.inst << 4) | tag;
+    uint8_t *base = spins + I.spin_off;
+    const int32_t *pp = perm + I.slot_off + 4 * D.quad;
+    for (int j = threadIdx.x; j < I.npad; j += kQuadThreads) {
+        uint4 w = make_uint4(0u, 0u, 0u, 0u);
+        if (j < I.n) w = philox10((uint32_t)j, 0u, (uint32_t)D.quad, c3, key0, key1);
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            base[(int64_t)pp[i] * I.npad + j] = (j < I.n && ws[i] < 0x80000000u) ? 1 : 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// APT replica kernel: n_sweeps sweeps, optional ICM, optional energies.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
+{
+    extern __shared__ uint32_t lds[];
+    const QuadDesc D = A.desc[blockIdx.x];
+    if (D.inst >= 0) {
+        const InstDev I = A.inst[D.inst];
+        const int tid = threadIdx.x;
+        const int n = I.n, npad = I.npad, ni = A.ni;
+        uint32_t *sp = lds;                              // npad + 4 words
+        uint32_t *lut = sp + npad + 4;                   // 4 * ni
+        int32_t *red = (int32_t *)(lut + 4 * ni);        // 32
+        uint32_t *vis = (uint32_t *)(red + 32);          // (npad + 31) / 32
+        uint16_t *queue = (uint16_t *)(vis + ((npad + 31) >> 5) + 1);   // npad
+        const int q = D.quad;
+        const int32_t *pp = A.perm + I.slot_off + 4 * q;
+        const int64_t b0 = (int64_t)pp[0] * npad, b1 = (int64_t)pp[1] * npad;
+        const int64_t b2 = (int64_t)pp[2] * npad, b3 = (int64_t)pp[3] * npad;
+        const uint8_t *gs = A.spins + I.spin_off;
+        for (int e = tid; e < 4 * ni; e += kQuadThreads) {
+            const int i = e / ni;
+            lut[e] = A.lut[(int64_t)A.slot_lut[I.slot_off + 4 * q + i] * ni + (e - i * ni)];
+        }
+        // gather + transpose: word j holds byte i = spin of slot 4q+i at site j
+        for (int g = tid; g < (npad >> 2); g += kQuadThreads) {
+            const uint32_t v0 = *(const uint32_t *)(gs + b0 + 4 * g);
+            const uint32_t v1 = *(const uint32_t *)(gs + b1 + 4 * g);
+            const uint32_t v2 = *(const uint32_t *)(gs + b2 + 4 * g);
+            const uint32_t v3 = *(const uint32_t *)(gs + b3 + 4 * g);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int sh = 8 * m;
+                sp[4 * g + m] = ((v0 >> sh) & 0xFFu) | (((v1 >> sh) & 0xFFu) << 8) |
+                                (((v2 >> sh) & 0xFFu) << 16) | (((v3 >> sh) & 0xFFu) << 24);
+            }
+        }
+        if (tid < 4) sp[npad + tid] = 0u;
+        __syncthreads();
+
+        const uint32_t t0 = A.ctr[0];
+        const uint32_t c3 = ((uint32_t)D.inst << 4) | A.tag;
+        for (int sw = 0; sw < A.n_sweeps; ++sw) {
+            const uint32_t t = t0 + (uint32_t)sw;
+            for (int c = 0; c < I.n_colours; ++c) {
+                const uint4 *rc = A.rec_col + I.rec_off + A.inst[D.inst].col_off[c];
+                const int cnt = A.inst[D.inst].col_cnt[c];
+                for (int i = tid; i < cnt; i += kQuadThreads) {
+                    const uint4 r = rc[i];
+                    const uint32_t j = r.x & 0xFFFFu;
+                    const uint32_t k = aligned_count(sp, r);
+                    const int32_t base = (int32_t)((r.x >> 25) & 63u) - 32 -
+                                         (int32_t)((r.x >> 16) & 7u) + A.imax;
+                    const uint4 u = philox10(j, t, (uint32_t)q, c3, A.key0, A.key1);
+                    uint32_t nw = (u.x < lut[2 * (int32_t)(k & 0xFFu) + base]) ? 1u : 0u;
+                    nw |= (u.y < lut[ni + 2 * (int32_t)((k >> 8) & 0xFFu) + base]) ? 0x100u : 0u;
+                    nw |= (u.z < lut[2 * ni + 2 * (int32_t)((k >> 16) & 0xFFu) + base]) ? 0x10000u : 0u;
+                    nw |= (u.w < lut[3 * ni + 2 * (int32_t)(k >> 24) + base]) ? 0x1000000u : 0u;
+                    sp[j] = nw;
+                }
+                __syncthreads();
+            }
+            if (A.mom_from >= 0 && sw >= A.mom_from) {
+                int32_t e[4];
+                quad_energy(sp, A.rec_j + I.recj_off, n, red, e);
+                if (tid < 4) {
+                    const int s = 4 * q + tid;
+                    if (s < I.n_slots) {
+                        int64_t *mm = A.mom + 2 * (int64_t)(I.slot_off + s);
+                        mm[0] += e[tid];
+                        mm[1] += (int64_t)e[tid] * e[tid];
+                    }
+                }
+            }
+        }
+
+        if (A.do_icm && A.reps >= 2) {
+            const uint32_t a = A.ctr[1] + 1u;
+            const int n_beta = I.n_slots / A.reps;
+            const int npair = A.reps / 2;
+            const uint4 *recj = A.rec_j + I.recj_off;
+            if (A.reps == 2) {
+                for (int half = 0; half < 2; ++half) {
+                    const int b = 2 * q + half;
+                    if (b >= n_beta || !A.icm_on[D.inst * n_beta + b]) continue;
+                    const uint4 w = philox10((uint32_t)b, a, 0u,
+                                             ((uint32_t)D.inst << 4) | TAG_ICM_PICK, A.key0, A.key1);
+                    icm_pair(sp, recj, n, 2 * half, 2 * half + 1, w.x, w.y, queue, vis, red,
+                             A.icm_info + ((int64_t)I.info_off + b) * 4);
+                }
+            } else if (A.reps == 4) {
+                const int b = q;
+                if (b < n_beta && A.icm_on[D.inst * n_beta + b]) {
+                    const uint32_t wp = philox10((uint32_t)b, a, 0u,
+                                                 ((uint32_t)D.inst << 4) | TAG_ICM_PAIR, A.key0,
+                                                 A.key1).x;
+                    const int pairing = (int)(((uint64_t)wp * 3u) >> 32);
+                    // matchings {01,23}, {02,13}, {03,12}: partner of label 0, then the other two
+                    const int p1 = pairing + 1;
+                    const int o1 = (p1 == 1) ? 2 : 1, o2 = (p1 == 3) ? 2 : 3;
+                    for (int pi = 0; pi < 2; ++pi) {
+                        const uint4 w = philox10((uint32_t)(b * npair + pi), a, 0u,
+                                                 ((uint32_t)D.inst << 4) | TAG_ICM_PICK, A.key0,
+                                                 A.key1);
+                        icm_pair(sp, recj, n, pi ? o1 : 0, pi ? o2 : p1, w.x, w.y, queue, vis, red,
+                                 A.icm_info + ((int64_t)I.info_off + b * npair + pi) * 4);
+                    }
+                }
+            }
+        }
+
+        if (A.do_energy) {
+            int32_t e[4];
+            quad_energy(sp, A.rec_j + I.recj_off, n, red, e);
+            if (tid < 4) {
+                const int s = 4 * q + tid;
+                if (s < I.n_slots) A.E[I.slot_off + s] = e[tid];
+            }
+        }
+
+        if (A.n_sweeps > 0 || A.do_icm) {
+            uint8_t *gw = A.spins + I.spin_off;
+            for (int g = tid; g < (npad >> 2); g += kQuadThreads) {
+                const uint32_t s0 = sp[4 * g], s1 = sp[4 * g + 1], s2 = sp[4 * g + 2],
+                               s3 = sp[4 * g + 3];
+                const uint32_t o[4] = {
+                    (s0 & 0xFFu) | ((s1 & 0xFFu) << 8) | ((s2 & 0xFFu) << 16) | ((s3 & 0xFFu) << 24),
+                    ((s0 >> 8) & 0xFFu) | (((s1 >> 8) & 0xFFu) << 8) | (((s2 >> 8) & 0xFFu) << 16) |
+                        (((s3 >> 8) & 0xFFu) << 24),
+                    ((s0 >> 16) & 0xFFu) | (((s1 >> 16) & 0xFFu) << 8) |
+                        (((s2 >> 16) & 0xFFu) << 16) | (((s3 >> 16) & 0xFFu) << 24),
+                    (s0 >> 24) | ((s1 >> 24) << 8) | ((s2 >> 24) << 16) | ((s3 >> 24) << 24)};
+                *(uint32_t *)(gw + b0 + 4 * g) = o[0];
+                *(uint32_t *)(gw + b1 + 4 * g) = o[1];
+                *(uint32_t *)(gw + b2 + 4 * g) = o[2];
+                *(uint32_t *)(gw + b3 + 4 * g) = o[3];
+            }
+        }
+    }
+    finish_and_bump(A.ctr, A.n_blocks, A.bump, A.n_sweeps);
+}
+
+// ---------------------------------------------------------------------------
+// Replica exchange (Eq. 4), one work-group (64 lanes) per instance.  An
+// accepted exchange swaps the logical->physical mapping of the two slots and
+// their energies; the random word is keyed by the logical pair, so this is
+// the same chain as exchanging the states.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void apt_swap_kernel(SwapArgs A)
+{
+    const int inst = blockIdx.x;
+    const InstDev I = A.inst[inst];
+    const int R = A.reps, nb = A.n_beta;
+    const int npt = (nb - 1) * R;
+    const uint32_t a = A.ctr[2] + 1u;
+    const uint32_t cyc = A.ctr[3] + 1u;
+    int32_t *perm = A.perm + I.slot_off;
+    int32_t *E = A.E + I.slot_off;
+    if (A.acc_out)
+        for (int i = threadIdx.x; i < npt; i += 64) A.acc_out[(int64_t)inst * npt + i] = -1;
+    const int first = (a & 1u) ? 0 : 1;
+    const int npairs = (nb - 1 - first + 1) / 2;
+    for (int idx = threadIdx.x; idx < npairs * R; idx += 64) {
+        const int b = first + 2 * (idx / R), l = idx - (idx / R) * R;
+        const int s0 = b * R + l, s1 = s0 + R;
+        const int32_t e0 = E[s0], e1 = E[s1];
+        const int32_t dE = e1 - e0;
+        int acc;
+        if (dE >= 0) {
+            acc = 1;
+        } else {
+            const int pair = I.swap_off + b;
+            const int32_t d = -dE;
+            if (d < A.tab_len[pair]) {
+                const uint32_t u = philox10((uint32_t)(b * R + l), a, 0u,
+                                            ((uint32_t)inst << 4) | TAG_SWAP, A.key0, A.key1).x;
+                acc = u < A.tab[A.tab_off[pair] + d];
+            } else {
+                acc = 0;
+            }
+        }
+        if (acc) {
+            const int32_t p0 = perm[s0];
+            perm[s0] = perm[s1];
+            perm[s1] = p0;
+            E[s0] = e1;
+            E[s1] = e0;
+        }
+        if (A.acc_out) A.acc_out[(int64_t)inst * npt + s0] = acc;
+        A.acc_count[(int64_t)inst * npt + s0] += acc;
+    }
+    __syncthreads();
+    int32_t m = 0x7FFFFFFF;
+    for (int s = threadIdx.x; s < nb * R; s += 64) m = min(m, E[s]);
+    m = wave_min(m);
+    if (threadIdx.x == 0) {
+        int64_t best = A.best[inst];
+        if ((int64_t)m < best) best = m;
+        A.best[inst] = best;
+        if (A.trace && A.record_every > 0 && (cyc % (uint32_t)A.record_every) == 0u) {
+            const int64_t ti = (int64_t)(cyc / (uint32_t)A.record_every) - 1;
+            if (ti < A.trace_cap) A.trace[(int64_t)inst * A.trace_cap + ti] = best;
+        }
+        __threadfence();
+        const uint32_t prev = atomicAdd(&A.ctr[4], 1u);
+        if (prev == (uint32_t)(A.n_inst - 1)) {
+            if (A.bump_all) {
+                A.ctr[0] += (uint32_t)A.sweeps_per_cycle;
+                A.ctr[1] += 1u;
+                A.ctr[3] += 1u;
+            }
+            A.ctr[2] += 1u;
+            A.ctr[4] = 0u;
+            __threadfence();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// DT-SQA
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kSqaThreads) void sqa_init_kernel(SqaArgs A)
+{
+    const int inst = blockIdx.x / A.R, r = blockIdx.x - inst * A.R;
+    const InstDev I = A.inst[inst];
+    uint32_t *g = A.spins + I.spin_off + (int64_t)r * I.npad * 2;
+    const uint32_t c3 = ((uint32_t)inst << 4) | TAG_SQA_INIT;
+    const int ngrp = (A.H + 3) >> 2;
+    for (int j = threadIdx.x; j < I.npad; j += kSqaThreads) {
+        uint32_t wd[2] = {0u, 0u};
+        if (j < I.n) {
+            for (int p = 0; p < 2; ++p)
+                for (int gq = 0; gq < ngrp; ++gq) {
+                    const uint4 u = philox10((uint32_t)j, 0u,
+                                             ((uint32_t)r << 16) | ((uint32_t)p << 15) | (uint32_t)gq,
+                                             c3, A.key0, A.key1);
+                    const uint32_t us[4] = {u.x, u.y, u.z, u.w};
+                    for (int i = 0; i < 4; ++i) {
+                        const int h = 4 * gq + i;
+                        if (h < A.H && us[i] < 0x80000000u) wd[p] |= 1u << h;
+                    }
+                }
+        }
+        g[2 * j] = wd[0];
+        g[2 * j + 1] = wd[1];
+    }
+}
+
+__device__ __forceinline__ uint32_t rotl_h(uint32_t x, int H, uint32_t mask)
+{
+    return ((x << 1) | (x >> (H - 1))) & mask;
+}
+
+__device__ __forceinline__ uint32_t rotr_h(uint32_t x, int H, uint32_t mask)
+{
+    return ((x >> 1) | (x << (H - 1))) & mask;
+}
+
+__global__ __launch_bounds__(kSqaThreads) void sqa_kernel(SqaArgs A)
+{
+    extern __shared__ uint32_t lds[];
+    const int inst = blockIdx.x / A.R, r = blockIdx.x - inst * A.R;
+    const InstDev I = A.inst[inst];
+    const int tid = threadIdx.x;
+    const int n = I.n, npad = I.npad, H = A.H;
+    const uint32_t mask = (H >= 32) ? 0xFFFFFFFFu : ((1u << H) - 1u);
+    uint32_t *sp = lds;                         // 2 * (npad + 1)
+    uint32_t *lut = sp + 2 * (npad + 1);        // nl
+    int32_t *red = (int32_t *)(lut + A.nl);     // 2 * 64
+    uint32_t *g = A.spins + I.spin_off + (int64_t)r * npad * 2;
+    for (int i = tid; i < 2 * npad; i += kSqaThreads) sp[i] = g[i];
+    if (tid < 2) sp[2 * npad + tid] = 0u;
+    const uint32_t c3 = ((uint32_t)inst << 4) | TAG_SQA_SWEEP;
+    const int ngrp = (H + 3) >> 2;
+    for (int st = 0; st < A.n_steps; ++st) {
+        const uint32_t t = (uint32_t)(A.t0 + st);
+        __syncthreads();
+        for (int i = tid; i < A.nl; i += kSqaThreads)
+            lut[i] = A.lut[(int64_t)(A.lut_step0 + st) * A.nl + i];
+        __syncthreads();
+        for (int c = 0; c < I.n_colours; ++c) {
+            const uint4 *rc = A.rec + I.rec_off + A.inst[inst].col_off[c];
+            const int cnt = A.inst[inst].col_cnt[c];
+            for (int i = tid; i < cnt; i += kSqaThreads) {
+                const uint4 rr = rc[i];
+                const uint32_t j = rr.x & 0xFFFFu;
+                const uint32_t p = rr.x >> 31;
+                const uint32_t jn = rr.x >> 19;
+                // aligned words: bit h = 1 when J * s_neighbour = +1 in slice 2h + p
+                const uint32_t a0 = sp[2 * (rr.y & 0xFFFFu) + p] ^ (0u - (jn & 1u));
+                const uint32_t a1 = sp[2 * (rr.y >> 16) + p] ^ (0u - ((jn >> 1) & 1u));
+                const uint32_t a2 = sp[2 * (rr.z & 0xFFFFu) + p] ^ (0u - ((jn >> 2) & 1u));
+                const uint32_t a3 = sp[2 * (rr.z >> 16) + p] ^ (0u - ((jn >> 3) & 1u));
+                const uint32_t a4 = sp[2 * (rr.w & 0xFFFFu) + p] ^ (0u - ((jn >> 4) & 1u));
+                const uint32_t a5 = sp[2 * (rr.w >> 16) + p] ^ (0u - ((jn >> 5) & 1u));
+                // bit-sliced 6-input count: k = c0 + 2 c1 + 4 c2 per slice
+                const uint32_t s1 = a0 ^ a1 ^ a2, k1 = (a0 & a1) | (a2 & (a0 ^ a1));
+                const uint32_t s2 = a3 ^ a4 ^ a5, k2 = (a3 & a4) | (a5 & (a3 ^ a4));
+                const uint32_t c0 = s1 ^ s2, cy = s1 & s2;
+                const uint32_t c1 = k1 ^ k2 ^ cy, c2 = (k1 & k2) | (cy & (k1 ^ k2));
+                const uint32_t ev = sp[2 * j], od = sp[2 * j + 1];
+                const uint32_t up = p ? ev : rotl_h(od, H, mask);
+                const uint32_t dn = p ? rotr_h(ev, H, mask) : od;
+                const uint32_t t0b = up ^ dn, t1b = up & dn;
+                const int32_t base3 = 3 * ((int32_t)((rr.x >> 25) & 63u) - 32 -
+                                           (int32_t)((rr.x >> 16) & 7u) + A.smax);
+                uint32_t res = 0u;
+                for (int gq = 0; gq < ngrp; ++gq) {
+                    const uint4 u = philox10(j, t, ((uint32_t)r << 16) | (p << 15) | (uint32_t)gq,
+                                             c3, A.key0, A.key1);
+                    const uint32_t us[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                    for (int ii = 0; ii < 4; ++ii) {
+                        const int h = 4 * gq + ii;
+                        if (h < H) {
+                            const int32_t kk = (int32_t)(((c0 >> h) & 1u) | (((c1 >> h) & 1u) << 1) |
+                                                         (((c2 >> h) & 1u) << 2));
+                            const int32_t tt = (int32_t)(((t0b >> h) & 1u) + 2u * ((t1b >> h) & 1u));
+                            if (us[ii] < lut[6 * kk + tt + base3]) res |= 1u << h;
+                        }
+                    }
+                }
+                sp[2 * j + p] = res;
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < 2 * npad; i += kSqaThreads) g[i] = sp[i];
+    if (A.do_energy) {
+        // Energy (Eq. 8, original couplings) of every slice k, threads split over (k, sites).
+        const int M = A.M;
+        for (int k = tid; k < 2 * M; k += kSqaThreads) red[k] = 0;
+        __syncthreads();
+        const uint4 *recj = A.rec_j + I.recj_off;
+        for (int task = tid; task < M * 4; task += kSqaThreads) {
+            const int k = task % M, part = task / M;
+            const int p = k & 1, h = k >> 1;
+            int32_t acc = 0;
+            for (int j = part; j < n; j += 4) {
+                const uint4 rr = recj[j];
+                const uint32_t jn = rr.x >> 19;
+                const uint32_t nbs[6] = {rr.y & 0xFFFFu, rr.y >> 16, rr.z & 0xFFFFu, rr.z >> 16,
+                                         rr.w & 0xFFFFu, rr.w >> 16};
+                int32_t kk = 0;
+#pragma unroll
+                for (int a = 0; a < 6; ++a)
+                    kk += (int32_t)(((sp[2 * nbs[a] + p] >> h) & 1u) ^ ((jn >> a) & 1u));
+                const int32_t d = (int32_t)((rr.x >> 16) & 7u);
+                const int32_t hh = (int32_t)((rr.x >> 25) & 63u) - 32;
+                const int32_t v = 2 * kk - d + 2 * hh;
+                acc += ((sp[2 * j + p] >> h) & 1u) ? v : -v;
+            }
+            atomicAdd(&red[k], acc);
+        }
+        __syncthreads();
+        for (int k = tid; k < M; k += kSqaThreads)
+            A.slice_E[((int64_t)inst * A.R + r) * M + k] = -red[k] / 2;
+    }
+}
+
+__global__ void fill_i64_kernel(int64_t *p, int64_t v, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+hipError_t launch_apt_init(const InstDev *inst_d, const QuadDesc *desc, int n_blocks,
+                           uint8_t *spins, const int32_t *perm, uint32_t key0, uint32_t key1,
+                           uint32_t tag, hipStream_t s)
+{
+    hipLaunchKernelGGL(apt_init_kernel, dim3(n_blocks), dim3(kQuadThreads), 0, s, inst_d, desc,
+                       spins, perm, key0, key1, tag);
+    return hipGetLastError();
+}
+
+static hipError_t allow_lds(const void *fn, size_t bytes)
+{
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_apt_quad(const AptArgs &a, size_t lds_bytes, hipStream_t s)
+{
+    hipError_t e = allow_lds((const void *)apt_quad_kernel, lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(apt_quad_kernel, dim3(a.n_blocks), dim3(kQuadThreads), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_apt_swap(const SwapArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(apt_swap_kernel, dim3(a.n_inst), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sqa_init(const SqaArgs &a, int n_inst, hipStream_t s)
+{
+    hipLaunchKernelGGL(sqa_init_kernel, dim3(n_inst * a.R), dim3(kSqaThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, hipStream_t s)
+{
+    hipError_t e = allow_lds((const void *)sqa_kernel, lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sqa_kernel, dim3(n_inst * a.R), dim3(kSqaThreads), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
+    hipLaunchKernelGGL(fill_i64_kernel, dim3(blocks), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace sg

@@ -1,0 +1,325 @@
+// sg_mlp_api.cpp -- host side of the ladder-predictor network (C ABI in sg.h).
+// The network is a project component that replaces the adaptive stage of
+// Algorithm S2 with a prediction from instance statistics; the adaptive stage
+// remains the fallback and the source of training targets.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "sg.h"
+#include "sg_internal.h"
+
+using namespace sg;
+
+namespace {
+constexpr int NP = SG_MLP_NPARAM;
+constexpr int NPX = NP + 8;   // + feature mean[4], std[4]
+constexpr int NBLK = 64;
+
+struct Err {
+    sg_status code;
+};
+
+void chk(hipError_t e)
+{
+    if (e == hipErrorOutOfMemory) throw Err{SG_ENOMEM};
+    if (e != hipSuccess) throw Err{SG_EHIP};
+}
+
+template <class T>
+T *dalloc(size_t n)
+{
+    T *p = nullptr;
+    chk(hipMalloc((void **)&p, std::max<size_t>(n, 1) * sizeof(T)));
+    return p;
+}
+
+// Same geometry conventions as the spin-glass contexts: j = x + Lx*(y + Ly*z).
+struct Geo {
+    const sg_lattice &L;
+    int n;
+    explicit Geo(const sg_lattice &l) : L(l), n(l.Lx * l.Ly * l.Lz) {}
+    int len(int a) const { return a == 0 ? L.Lx : (a == 1 ? L.Ly : L.Lz); }
+    int coord(int j, int a) const
+    {
+        return a == 0 ? j % L.Lx : (a == 1 ? (j / L.Lx) % L.Ly : j / (L.Lx * L.Ly));
+    }
+    int stride(int a) const { return a == 0 ? 1 : (a == 1 ? L.Lx : L.Lx * L.Ly); }
+    int nbr(int j, int a, int dir) const
+    {
+        const int Ln = len(a);
+        if (Ln < 2) return -1;
+        int c = coord(j, a), c2 = c + dir;
+        if (c2 < 0 || c2 >= Ln) {
+            if (!((L.periodic >> a) & 1u)) return -1;
+            c2 = (c2 + Ln) % Ln;
+        }
+        return j + (c2 - c) * stride(a);
+    }
+    int bond(int j, int a, int dir) const
+    {
+        const int nb = nbr(j, a, dir);
+        if (nb < 0) return 0;
+        return dir > 0 ? L.J[3 * j + a] : L.J[3 * nb + a];
+    }
+};
+
+// Features: cube root of n; mean and variance over sites of |sum of the site's
+// couplings|; fraction of elementary plaquettes (all four bonds present) whose
+// coupling product is negative (frustrated).
+void features_of(const sg_lattice &L, double *f)
+{
+    Geo g(L);
+    double s1 = 0.0, s2 = 0.0;
+    for (int j = 0; j < g.n; ++j) {
+        int c = 0;
+        for (int a = 0; a < 3; ++a) c += g.bond(j, a, +1) + g.bond(j, a, -1);
+        const double v = std::fabs((double)c);
+        s1 += v;
+        s2 += v * v;
+    }
+    const double mean = s1 / (double)g.n;
+    int64_t plaq = 0, frus = 0;
+    for (int j = 0; j < g.n; ++j)
+        for (int a = 0; a < 3; ++a)
+            for (int b = a + 1; b < 3; ++b) {
+                const int ja = g.nbr(j, a, +1), jb = g.nbr(j, b, +1);
+                if (ja < 0 || jb < 0) continue;
+                const int p = g.bond(j, a, +1) * g.bond(ja, b, +1) * g.bond(jb, a, +1) * g.bond(j, b, +1);
+                if (p == 0) continue;
+                ++plaq;
+                frus += p < 0;
+            }
+    f[0] = std::cbrt((double)g.n);
+    f[1] = mean;
+    f[2] = s2 / (double)g.n - mean * mean;
+    f[3] = plaq ? (double)frus / (double)plaq : 0.0;
+}
+
+}  // namespace
+
+struct sg_mlp {
+    hipStream_t stream = nullptr;
+    bool own = false;
+    float *P = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *gacc = nullptr, *loss = nullptr;
+    int step = 0;
+    uint64_t seed = 0;
+    ~sg_mlp()
+    {
+        for (float *p : {P, m, v, grad, gacc, loss})
+            if (p) (void)hipFree(p);
+        if (own && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+extern "C" {
+
+sg_status sg_instance_features(const sg_lattice *inst, int32_t n_inst, double *features)
+{
+    if (!inst || n_inst < 1 || !features) return SG_EINVAL;
+    for (int i = 0; i < n_inst; ++i) {
+        const sg_lattice &L = inst[i];
+        if (L.Lx < 1 || L.Ly < 1 || L.Lz < 1 || !L.J || (int64_t)L.Lx * L.Ly * L.Lz > kMaxN)
+            return SG_EINVAL;
+        features_of(L, features + 4 * (size_t)i);
+    }
+    return SG_OK;
+}
+
+sg_status sg_mlp_create(const float *params, uint64_t seed, void *hip_stream, sg_mlp **out)
+{
+    if (!out) return SG_EINVAL;
+    *out = nullptr;
+    sg_mlp *m = new (std::nothrow) sg_mlp();
+    if (!m) return SG_ENOMEM;
+    try {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) throw Err{SG_EHIP};
+        if (hip_stream) {
+            m->stream = (hipStream_t)hip_stream;
+        } else {
+            chk(hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking));
+            m->own = true;
+        }
+        m->seed = seed;
+        std::vector<float> h(NPX, 0.f);
+        if (params) {
+            std::memcpy(h.data(), params, sizeof(float) * NPX);
+        } else {
+            std::mt19937_64 rng(seed);
+            auto fill = [&](int off, int rows, int fan_in) {
+                std::uniform_real_distribution<float> U(-1.f / std::sqrt((float)fan_in),
+                                                        1.f / std::sqrt((float)fan_in));
+                for (int i = 0; i < rows * fan_in; ++i) h[off + i] = U(rng);
+            };
+            fill(0, 64, 4);
+            fill(64 * 4 + 64, 64, 64);
+            fill(64 * 4 + 64 + 64 * 64 + 64, 33, 64);
+            for (int k = 0; k < 4; ++k) { h[NP + k] = 0.f; h[NP + 4 + k] = 1.f; }
+        }
+        for (int k = 0; k < 4; ++k)
+            if (!(h[NP + 4 + k] > 0.f)) throw Err{SG_EINVAL};
+        m->P = dalloc<float>(NPX);
+        m->m = dalloc<float>(NP);
+        m->v = dalloc<float>(NP);
+        m->grad = dalloc<float>(NP);
+        m->gacc = dalloc<float>((size_t)NBLK * NP);
+        m->loss = dalloc<float>(NBLK);
+        chk(hipMemcpyAsync(m->P, h.data(), sizeof(float) * NPX, hipMemcpyHostToDevice, m->stream));
+        chk(hipMemsetAsync(m->m, 0, sizeof(float) * NP, m->stream));
+        chk(hipMemsetAsync(m->v, 0, sizeof(float) * NP, m->stream));
+        chk(hipStreamSynchronize(m->stream));
+    } catch (const Err &e) {
+        delete m;
+        return e.code;
+    }
+    *out = m;
+    return SG_OK;
+}
+
+void sg_mlp_destroy(sg_mlp *m)
+{
+    if (!m) return;
+    (void)hipStreamSynchronize(m->stream);
+    delete m;
+}
+
+sg_status sg_mlp_set_standardisation(sg_mlp *m, const float *mean4, const float *std4)
+{
+    if (!m || !mean4 || !std4) return SG_EINVAL;
+    for (int k = 0; k < 4; ++k)
+        if (!(std4[k] > 0.f)) return SG_EINVAL;
+    float h[8];
+    std::memcpy(h, mean4, 16);
+    std::memcpy(h + 4, std4, 16);
+    try {
+        chk(hipMemcpyAsync(m->P + NP, h, sizeof h, hipMemcpyHostToDevice, m->stream));
+        chk(hipStreamSynchronize(m->stream));
+    } catch (const Err &e) {
+        return e.code;
+    }
+    return SG_OK;
+}
+
+sg_status sg_mlp_get_params(sg_mlp *m, float *params)
+{
+    if (!m || !params) return SG_EINVAL;
+    try {
+        chk(hipMemcpyAsync(params, m->P, sizeof(float) * NPX, hipMemcpyDeviceToHost, m->stream));
+        chk(hipStreamSynchronize(m->stream));
+    } catch (const Err &e) {
+        return e.code;
+    }
+    return SG_OK;
+}
+
+sg_status sg_mlp_loss_grad(sg_mlp *m, const float *x, const float *y, int32_t batch, float *loss,
+                           float *grad)
+{
+    if (!m || !x || !y || batch < 1 || !loss) return SG_EINVAL;
+    float *dx = nullptr, *dy = nullptr;
+    try {
+        dx = dalloc<float>((size_t)batch * 4);
+        dy = dalloc<float>((size_t)batch * 33);
+        chk(hipMemcpyAsync(dx, x, sizeof(float) * 4 * batch, hipMemcpyHostToDevice, m->stream));
+        chk(hipMemcpyAsync(dy, y, sizeof(float) * 33 * batch, hipMemcpyHostToDevice, m->stream));
+        const int nblk = std::min(NBLK, (int)batch);
+        chk(launch_mlp_pass(m->P, dx, dy, nullptr, batch, nblk, m->gacc, m->loss, nullptr, m->grad,
+                            m->stream));
+        std::vector<float> l(nblk);
+        chk(hipMemcpyAsync(l.data(), m->loss, sizeof(float) * nblk, hipMemcpyDeviceToHost, m->stream));
+        if (grad) chk(hipMemcpyAsync(grad, m->grad, sizeof(float) * NP, hipMemcpyDeviceToHost, m->stream));
+        chk(hipStreamSynchronize(m->stream));
+        double s = 0.0;
+        for (float v : l) s += v;
+        *loss = (float)(s / ((double)batch * 33.0));
+    } catch (const Err &e) {
+        (void)hipFree(dx);
+        (void)hipFree(dy);
+        return e.code;
+    }
+    (void)hipFree(dx);
+    (void)hipFree(dy);
+    return SG_OK;
+}
+
+sg_status sg_mlp_train(sg_mlp *m, const float *x, const float *y, int32_t n, int32_t batch,
+                       int32_t epochs, float lr, float *loss_per_epoch)
+{
+    if (!m || !x || !y || n < 1 || batch < 1 || epochs < 0 || !(lr > 0.f)) return SG_EINVAL;
+    float *dx = nullptr, *dy = nullptr;
+    int *didx = nullptr;
+    try {
+        dx = dalloc<float>((size_t)n * 4);
+        dy = dalloc<float>((size_t)n * 33);
+        didx = dalloc<int>((size_t)n);
+        chk(hipMemcpyAsync(dx, x, sizeof(float) * 4 * (size_t)n, hipMemcpyHostToDevice, m->stream));
+        chk(hipMemcpyAsync(dy, y, sizeof(float) * 33 * (size_t)n, hipMemcpyHostToDevice, m->stream));
+        std::vector<int> order(n);
+        std::iota(order.begin(), order.end(), 0);
+        std::mt19937_64 rng(m->seed ^ 0x9E3779B97F4A7C15ull);
+        std::vector<float> l(NBLK);
+        for (int ep = 0; ep < epochs; ++ep) {
+            std::shuffle(order.begin(), order.end(), rng);
+            chk(hipStreamSynchronize(m->stream));
+            chk(hipMemcpyAsync(didx, order.data(), sizeof(int) * (size_t)n, hipMemcpyHostToDevice,
+                               m->stream));
+            double lsum = 0.0;
+            for (int s0 = 0; s0 < n; s0 += batch) {
+                const int b = std::min(batch, n - s0);
+                const int nblk = std::min(NBLK, b);
+                chk(launch_mlp_pass(m->P, dx, dy, didx + s0, b, nblk, m->gacc, m->loss, nullptr,
+                                    m->grad, m->stream));
+                chk(launch_mlp_adam2(m->P, m->grad, m->m, m->v, lr, 0.9f, 0.999f, 1e-8f, ++m->step,
+                                     m->stream));
+                chk(hipMemcpyAsync(l.data(), m->loss, sizeof(float) * nblk, hipMemcpyDeviceToHost,
+                                   m->stream));
+                chk(hipStreamSynchronize(m->stream));
+                for (int k = 0; k < nblk; ++k) lsum += l[k];
+            }
+            if (loss_per_epoch) loss_per_epoch[ep] = (float)(lsum / ((double)n * 33.0));
+        }
+    } catch (const Err &e) {
+        (void)hipFree(dx); (void)hipFree(dy); (void)hipFree(didx);
+        return e.code;
+    }
+    (void)hipFree(dx); (void)hipFree(dy); (void)hipFree(didx);
+    return SG_OK;
+}
+
+sg_status sg_ladder_predict(sg_mlp *m, const sg_lattice *inst, int32_t n_inst, double *beta_out,
+                            double *cutoff_out)
+{
+    if (!m || !inst || n_inst < 1 || !beta_out) return SG_EINVAL;
+    std::vector<double> f((size_t)n_inst * 4);
+    sg_status st = sg_instance_features(inst, n_inst, f.data());
+    if (st != SG_OK) return st;
+    std::vector<float> xf(f.begin(), f.end()), out((size_t)n_inst * 33);
+    float *dx = nullptr, *dout = nullptr;
+    try {
+        dx = dalloc<float>((size_t)n_inst * 4);
+        dout = dalloc<float>((size_t)n_inst * 33);
+        chk(hipMemcpyAsync(dx, xf.data(), sizeof(float) * xf.size(), hipMemcpyHostToDevice, m->stream));
+        chk(launch_mlp_pass(m->P, dx, nullptr, nullptr, n_inst, std::min(NBLK, (int)n_inst), nullptr,
+                            nullptr, dout, nullptr, m->stream));
+        chk(hipMemcpyAsync(out.data(), dout, sizeof(float) * out.size(), hipMemcpyDeviceToHost, m->stream));
+        chk(hipStreamSynchronize(m->stream));
+    } catch (const Err &e) {
+        (void)hipFree(dx); (void)hipFree(dout);
+        return e.code;
+    }
+    (void)hipFree(dx); (void)hipFree(dout);
+    for (int i = 0; i < n_inst; ++i) {
+        for (int k = 0; k < 32; ++k) beta_out[(size_t)i * 32 + k] = std::exp((double)out[(size_t)i * 33 + k]);
+        if (cutoff_out) cutoff_out[i] = std::exp((double)out[(size_t)i * 33 + 32]);
+    }
+    return SG_OK;
+}
+
+}  // extern "C"

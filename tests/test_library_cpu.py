@@ -1,0 +1,76 @@
+"""Host-side checks of libsg that need no GPU: exports, argument validation, loud failure."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2503_10302_amd import sg
+from paper_2503_10302_amd.inputs import ej_couplings, geometric_ladder
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "sg.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sg_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    import subprocess
+    lib = sg.load()
+    names = _declared()
+    assert len(names) >= 25
+    for nm in names:
+        assert hasattr(lib, nm), nm
+    out = subprocess.run(["nm", "-D", "--defined-only", sg.SO_PATH], capture_output=True, text=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if l.strip()}
+    assert set(names) <= exported
+    assert set(sg.EXPORTS) == set(names)
+
+
+def _expect(code, fn):
+    with pytest.raises(sg.SGError) as e:
+        fn()
+    assert e.value.code == code, str(e.value)
+
+
+def test_invalid_arguments_are_rejected_before_any_device_work():
+    J, _ = ej_couplings(4, 7, seed=1)
+    beta = geometric_ladder(8)
+    _expect(sg.SG_EINVAL, lambda: sg.apt([(J, 7, None)], beta[::-1].copy(), 1, 2))      # descending
+    _expect(sg.SG_EINVAL, lambda: sg.apt([(J, 7, None)], beta, 1, 3))                    # labels
+    _expect(sg.SG_EINVAL, lambda: sg.apt([(J, 7, None)], beta[:1], 1, 2))                # one beta
+    Jbad = J.copy(); Jbad[0, 0, 0, 0] = 2
+    _expect(sg.SG_EINVAL, lambda: sg.apt([(Jbad, 7, None)], beta, 1, 2))                 # |J| > 1
+    h = np.full(64, 40, np.int8)
+    _expect(sg.SG_EINVAL, lambda: sg.apt([(J, 7, h)], beta, 1, 2))                       # |h| > 31
+    Jbig = np.ones((40, 40, 40, 3), np.int8)
+    _expect(sg.SG_EINVAL, lambda: sg.apt([(Jbig, 7, None)], beta, 1, 2))                 # n too large
+    _expect(sg.SG_EINVAL, lambda: sg.sqa([(J, 7, None)], 65, 2, 1.0, 1))                 # M > 64
+    _expect(sg.SG_EUNSUPPORTED, lambda: sg.sqa([(J, 7, None)], 7, 2, 1.0, 1))            # odd M
+    _expect(sg.SG_EINVAL, lambda: sg.sqa([(J, 7, None)], 8, 0, 1.0, 1))                  # R = 0
+    _expect(sg.SG_EINVAL, lambda: sg.sqa([(J, 7, None)], 8, 2, -1.0, 1))                 # beta <= 0
+
+
+def test_no_silent_cpu_fallback():
+    """Valid input on a machine without a GPU fails with SG_EHIP instead of computing elsewhere."""
+    J, _ = ej_couplings(4, 7, seed=1)
+    try:
+        ctx = sg.apt([(J, 7, None)], geometric_ladder(8), 1, 2)
+    except sg.SGError as e:
+        assert e.code == sg.SG_EHIP
+        return
+    ctx.close()
+    pytest.skip("a GPU is present; this check is for hosts without one")
+
+
+def test_binding_module_has_no_oracle_import():
+    import paper_2503_10302_amd
+    pkg = os.path.dirname(paper_2503_10302_amd.__file__)
+    for root, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                txt = open(os.path.join(root, f)).read()
+                assert "import oracle" not in txt and "sg_oracle" not in txt and "sgo_" not in txt, f
