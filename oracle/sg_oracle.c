@@ -245,7 +245,9 @@ void sgo_apt_sweep(const sgo_lattice *lat, uint32_t inst, int32_t n_slots,
  * of the three perfect matchings drawn at random (Methods, "APT details").
  * info[(b * npair + pi) * 4 + {0..3}] = (m, seed site, |C|, branch) with
  * branch 0 = cluster, 1 = whole first replica, 2 = whole second; -1 when the
- * temperature is below the cutoff.  Returns 0, or -5 when h is non-zero. */
+ * temperature is below the cutoff.  Returns 0, or -5 when some pair would be
+ * moved and h is non-zero (the whole-replica branch keeps the energy only for
+ * h = 0); with no temperature at or above the cutoff the call is a no-op. */
 static const int32_t PAIRINGS[3][2][2] = {{{0, 1}, {2, 3}}, {{0, 2}, {1, 3}}, {{0, 3}, {1, 2}}};
 
 int32_t sgo_apt_icm(const sgo_lattice *lat, uint32_t inst, int32_t n_beta, int32_t R_lab,
@@ -254,7 +256,9 @@ int32_t sgo_apt_icm(const sgo_lattice *lat, uint32_t inst, int32_t n_beta, int32
 {
     int32_t n = sgo_n_sites(lat);
     if (R_lab != 2 && R_lab != 4) return 0;
-    if (lat->h)
+    int32_t applies = 0;
+    for (int32_t b = 0; b < n_beta; ++b) applies |= beta[b] >= cutoff;
+    if (lat->h && applies)
         for (int32_t j = 0; j < n; ++j)
             if (lat->h[j] != 0) return -5;
     int32_t npair = R_lab / 2;

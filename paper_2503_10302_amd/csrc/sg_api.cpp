@@ -612,6 +612,15 @@ void require(sg_ctx *c, int mode)
     if (c->mode != mode) fail(SG_ESTATE, "call does not match the context mode");
 }
 
+// ICM would move some pair: two or more labels and a temperature >= cutoff.
+bool icm_applies(const sg_ctx *c, double cutoff)
+{
+    if (c->reps < 2) return false;
+    for (double b : c->beta)
+        if (b >= cutoff) return true;
+    return false;
+}
+
 bool any_field(const sg_ctx *c)
 {
     for (auto &L : c->lat)
@@ -770,7 +779,7 @@ sg_status sg_icm(sg_ctx *c, double cutoff, int32_t *info_host)
     return guarded(c, [&] {
         require(c, SG_APT);
         if (std::isnan(cutoff)) fail(SG_EINVAL, "cutoff is NaN");
-        if (c->reps >= 2 && any_field(c))
+        if (icm_applies(c, cutoff) && any_field(c))
             fail(SG_EUNSUPPORTED, "ICM with non-zero fields is not supported");
         upload_icm_flags(c, cutoff);
         hip_check(launch_fill_u32((uint32_t *)c->d_icm_info.p, 0xFFFFFFFFu, (int64_t)c->d_icm_info.n,
@@ -837,7 +846,7 @@ sg_status sg_run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, doubl
         if (std::isnan(icm_cutoff)) fail(SG_EINVAL, "cutoff is NaN");
         if (record_every < 0 || (best_trace && record_every == 0))
             fail(SG_EINVAL, "record_every must be > 0 with a trace");
-        const bool icm = c->reps >= 2 && icm_cutoff != std::numeric_limits<double>::infinity();
+        const bool icm = icm_applies(c, icm_cutoff);
         if (icm && any_field(c)) fail(SG_EUNSUPPORTED, "ICM with non-zero fields is not supported");
         if (n_cycles == 0) return;
         upload_icm_flags(c, icm ? icm_cutoff : std::numeric_limits<double>::infinity());

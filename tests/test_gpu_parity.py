@@ -131,7 +131,11 @@ def test_apt_with_fields_and_open_axes():
         E = np.zeros(12, np.int64)
         b = np.array([np.iinfo(np.int64).max], np.int64)
         rc, otr, _ = oracle.apt_run(l, i, beta, 2, SEED, 20, 2, float("inf"), 4, ctr, sp, E, b)
+        assert rc == 0
         assert np.array_equal(g[i, :, :l.n], sp) and np.array_equal(trace[i], otr)
+    with pytest.raises(sg.SGError) as e:
+        ctx.run_apt(2, 1, 1.5)
+    assert e.value.code == sg.SG_EUNSUPPORTED
 
 
 def test_checkpoint_resume_is_exact():

@@ -229,6 +229,9 @@ def test_icm_rejects_fields():
     spins = oracle.apt_init(lat, 0, 4, SEED)
     rc, _ = oracle.apt_icm(lat, 0, np.array([1.0, 2.0]), 2, 0.5, SEED, 1, spins)
     assert rc == -5
+    before = spins.copy()
+    rc, info = oracle.apt_icm(lat, 0, np.array([1.0, 2.0]), 2, 5.0, SEED, 1, spins)   # nothing applies
+    assert rc == 0 and np.all(info == -1) and np.array_equal(spins, before)
 
 
 def test_icm_with_gibbs_keeps_product_law():
