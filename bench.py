@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Throughput benchmark on one MI355X.
+
+Headline: spin flips per nanosecond at L = 15 -- DT-SQA over 32 instances of a
+15^3 periodic +-J lattice, M = 64 Trotter slices, R independent replicas,
+beta = M/2, Gamma ramped linearly 3.0 -> 0.01 (one "step" = one annealing step:
+J_perp update + one coloured sweep of every replica, 32 * R * 64 * 3375 spin
+update attempts).  Alongside: batched APT+ICM over 256 mixed-size instances
+(one step = sweep + ICM + energies + swap + running minimum of every instance),
+the plain single-instance APT+ICM cycle, the roofline of the dominant kernel and
+the CPU oracle timed on the host cores.
+
+Prints ONE JSON line.  Inputs are synthetic (seeded +-J instances; the paper's
+instances are not available) and resident on the GPU before timing starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spin flips/ns at L=15; time-to-target residual energy/spin, plain vs batched"
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 full-rate 32-bit lane-operations/s.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic VALU work per spin-flip attempt (full-rate lane-operation equivalents):
+# a quarter of one Philox4x32-10 block (10 rounds x [2 wide 32x32->64 multiplies at
+# MUL_COST slots each + 4 xors]) plus the heat-bath compare.  MUL_COST is the issue
+# cost of v_mad_u64_u32 relative to a full-rate op, measured on the box.
+MUL_COST = 4.0
+ALG_OPS_PER_FLIP = (10 * (2 * MUL_COST + 4)) / 4 + 1
+
+
+def sqa_workload(R, seed0=20000, n_inst=32, L=15, M=64):
+    from paper_2503_10302_amd.inputs import ej_couplings
+    insts = [(ej_couplings(L, 7, seed=seed0 + i)[0], 7, None) for i in range(n_inst)]
+    return insts, M, R, M / 2.0
+
+
+def apt_batched_workload(n_inst=256):
+    from paper_2503_10302_amd.inputs import ej_couplings, geometric_ladder, mixed_sizes
+    sizes = mixed_sizes(n_inst)
+    insts = [(ej_couplings(L, 7, seed=10000 + i)[0], 7, None) for i, L in enumerate(sizes)]
+    return insts, geometric_ladder(32, 0.2, 3.0), sizes
+
+
+def cpu_baseline(insts, M, beta, gam, seconds):
+    """Oracle DT-SQA steps on independent replicas, one per host thread."""
+    import ctypes  # noqa: F401  (ctypes calls release the GIL: threads run in parallel)
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    oracle.build()
+    cores = min(16, os.cpu_count() or 1)
+    lat = [oracle.Lattice(J, p, h) for (J, p, h) in insts]
+    n = lat[0].n
+    # calibrate one step of one replica
+    sp = oracle.sqa_init(lat[0], 0, M, 1, 1234, r0=0)
+    t0 = time.perf_counter()
+    oracle.sqa_step(lat[0], 0, M, 1, beta, gam[0], 1234, 0, sp, r0=0)
+    t1 = time.perf_counter() - t0
+    steps = max(1, int(round(seconds / max(t1, 1e-6))))
+
+    def task(w):
+        i = w % len(lat)
+        s = oracle.sqa_init(lat[i], i, M, 1, 1234, r0=w)
+        for t in range(steps):
+            oracle.sqa_step(lat[i], i, M, 1, beta, gam[t % len(gam)], 1234, t, s, r0=w)
+        return steps * M * n
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        flips = sum(ex.map(task, range(cores)))
+    wall = time.perf_counter() - t0
+    return {"value": flips / (wall * 1e9), "unit": "flips/ns", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} replicas x {steps} DT-SQA steps of the L=15, M=64 workload "
+                      f"({flips:.3g} spin updates, {wall:.1f} s wall)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200, help="timed DT-SQA annealing steps")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--replicas", type=int, default=64, help="R for the L=15 DT-SQA workload")
+    ap.add_argument("--apt-cycles", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["all", "sqa", "apt"], default="all")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs the whole hot path on one GPU; multi-GPU runs are not "
+              "part of it.", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2503_10302_amd import sg
+    from paper_2503_10302_amd.inputs import linear_gamma
+
+    out = {"metric": METRIC, "unit": "flips/ns", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u32", "data": "synthetic (seeded +-J Edwards-Anderson instances)"}
+
+    # ---------------- DT-SQA, L = 15 (headline)
+    insts, M, R, beta = sqa_workload(args.replicas)
+    n = 15 ** 3
+    flips_per_step = len(insts) * R * M * n
+    gam = linear_gamma(max(1000, args.warmup + args.steps))
+    if args.only in ("all", "sqa"):
+        ctx = sg.sqa(insts, M, R, beta, seed=4004)
+        if args.warmup:
+            ctx.sqa_anneal(gam[:args.warmup])
+        ctx.synchronize()
+        ctx.kernel_timing(True)
+        ctx.kernel_time()
+        t0 = time.perf_counter()
+        ctx.timer_start()
+        bE, _ = ctx.sqa_anneal(gam[args.warmup:args.warmup + args.steps])
+        ms = ctx.timer_stop()
+        wall = time.perf_counter() - t0
+        kms, nlaunch = ctx.kernel_time()
+        value = flips_per_step * args.steps / (ms * 1e6)
+        achieved = ALG_OPS_PER_FLIP * flips_per_step * args.steps / (kms * 1e-3) / 1e12
+        out.update({
+            "value": round(value, 3), "ms_per_step": round(ms / args.steps, 5),
+            "config": {"workload": f"dtsqa_L15_M64_R{R}_x32 (32 instances of 15^3 periodic +-J, "
+                                   f"M=64, R={R}, beta=32, Gamma 3.0->0.01 linear)",
+                       "instances": 32, "L": 15, "M": M, "R": R, "beta": beta,
+                       "flips_per_step": flips_per_step},
+            "roofline": {"bound": "alu", "kernel": "sqa_kernel",
+                         "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                         "unit": "Top/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                         "traffic": None, "alg_ops_per_flip": ALG_OPS_PER_FLIP,
+                         "kernel_ms": round(kms, 3), "launches": nlaunch,
+                         "kernel_flips_per_ns": round(flips_per_step * args.steps / (kms * 1e6), 3)},
+            "wall_s_timed": round(wall, 3),
+            "sqa_best_residual_proxy": {"min_E_per_spin": round(float(bE.min()) / n, 5)},
+        })
+        ctx.close()
+
+    # ---------------- batched APT + ICM (config 3) and plain APT (config 1)
+    if args.only in ("all", "apt"):
+        insts3, ladder, sizes = apt_batched_workload()
+        flips_cycle = sum(L ** 3 for L in sizes) * 64
+        c3 = sg.apt(insts3, ladder, seed=777, reps_per_beta=2)
+        c3.run_apt(64, 1, 1.0)
+        c3.synchronize()
+        c3.kernel_timing(True)
+        c3.kernel_time()
+        c3.timer_start()
+        c3.run_apt(args.apt_cycles, 1, 1.0)
+        ms3 = c3.timer_stop()
+        k3, _ = c3.kernel_time()
+        c3.timer_start()
+        c3.sweep(32)
+        ms3s = c3.timer_stop()
+        c3.close()
+        from paper_2503_10302_amd.inputs import ej_couplings, geometric_ladder
+        J8, _ = ej_couplings(8, 7, seed=1)
+        c1 = sg.apt([(J8, 7, None)], geometric_ladder(32, 0.2, 3.0), seed=1001, reps_per_beta=2)
+        c1.run_apt(64, 1, 1.0)
+        c1.synchronize()
+        c1.timer_start()
+        c1.run_apt(args.apt_cycles, 1, 1.0)
+        ms1 = c1.timer_stop()
+        c1.close()
+        apt = {"workload": "256 instances, L round-robin {6,8,10,12,15}, periodic, 32 betas "
+                           "geometric in [0.2, 3.0] x 2 labels, ICM at beta >= 1, 1 sweep per swap",
+               "flips_per_cycle": flips_cycle, "cycles": args.apt_cycles,
+               "ms_per_cycle": round(ms3 / args.apt_cycles, 5),
+               "flips_per_ns": round(flips_cycle * args.apt_cycles / (ms3 * 1e6), 3),
+               "sweep_only_flips_per_ns": round(flips_cycle * 32 / (ms3s * 1e6), 3),
+               "graph_kernel_ms": round(k3, 3)}
+        apt["icm_swap_energy_share"] = round(1.0 - (ms3s / 32) / (ms3 / args.apt_cycles), 4)
+        out["apt_batched"] = apt
+        out["apt_plain"] = {"workload": "one L=8 periodic instance, 32 betas x 2 labels, ICM at beta >= 1",
+                            "ms_per_cycle": round(ms1 / args.apt_cycles, 5),
+                            "flips_per_ns": round(512 * 64 * args.apt_cycles / (ms1 * 1e6), 3)}
+        if args.only == "apt":
+            out.update({"value": apt["flips_per_ns"], "ms_per_step": apt["ms_per_cycle"],
+                        "config": {"workload": "batched APT+ICM, 256 mixed instances (config 3)"}})
+
+    if not args.no_cpu_baseline and args.only in ("all", "sqa"):
+        out["cpu_baseline"] = cpu_baseline(insts, M, beta, gam, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

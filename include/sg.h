@@ -158,6 +158,14 @@ sg_status sg_timer_start(sg_ctx *ctx);
 sg_status sg_timer_stop(sg_ctx *ctx, float *ms);
 sg_status sg_synchronize(sg_ctx *ctx);
 
+/* Kernel timing: while enabled, every main kernel launch (one DT-SQA kernel
+ * per chunk of at most 256 steps, one captured graph of 32 APT cycles) is
+ * bracketed by HIP events on the context's stream.  sg_kernel_time returns
+ * the summed milliseconds and the number of launches since the last call
+ * (or since enabling), and resets the tally. */
+sg_status sg_kernel_timing(sg_ctx *ctx, int32_t enable);
+sg_status sg_kernel_time(sg_ctx *ctx, float *ms, int32_t *launches);
+
 /* ---- adaptive ladder (Algorithm S2 preprocessing; Methods "APT details") ----
  * Chains start random at beta0; each step runs `sweeps` sweeps per chain at
  * beta_t, takes each chain's sample standard deviation of the energy over the

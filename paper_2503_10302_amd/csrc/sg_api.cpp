@@ -275,6 +275,10 @@ struct sg_ctx {
     DevBuf<uint4> d_rec, d_recj;
     DevBuf<uint32_t> d_ctr;      // {sweeps/steps, icm calls, swap attempts, cycles, done}
     Timer timer;
+    // events around every main kernel launch (DT-SQA kernel, APT cycle graph)
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> kev;
+    size_t kev_used = 0;
+    bool ktime = false;
 
     // APT
     int n_beta = 0, reps = 0, n_slots = 0, n_quads = 0, imax = 0, ni = 0;
@@ -305,6 +309,10 @@ struct sg_ctx {
 
     ~sg_ctx()
     {
+        for (auto &e : kev) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (timer.a) (void)hipEventDestroy(timer.a);
         if (timer.b) (void)hipEventDestroy(timer.b);
@@ -700,6 +708,26 @@ SqaArgs sqa_args(sg_ctx *c)
     return a;
 }
 
+// Event pair bracketing one main-kernel launch when kernel timing is on.
+hipEvent_t kernel_event(sg_ctx *c, bool start)
+{
+    if (!c->ktime) return nullptr;
+    if (start) {
+        if (c->kev_used == c->kev.size()) {
+            hipEvent_t a, b;
+            hip_check(hipEventCreate(&a), "event");
+            hip_check(hipEventCreate(&b), "event");
+            c->kev.push_back({a, b});
+        }
+        hipEvent_t e = c->kev[c->kev_used].first;
+        hip_check(hipEventRecord(e, c->stream), "event");
+        return e;
+    }
+    hipEvent_t e = c->kev[c->kev_used++].second;
+    hip_check(hipEventRecord(e, c->stream), "event");
+    return e;
+}
+
 template <class F>
 sg_status guarded(sg_ctx *c, F &&f)
 {
@@ -886,7 +914,11 @@ sg_status sg_run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, doubl
             c->g_trace_cap = cap;
         }
         int64_t done = 0;
-        for (; done + K <= n_cycles; done += K) hip_check(hipGraphLaunch(c->gexec, c->stream), "graph launch");
+        for (; done + K <= n_cycles; done += K) {
+            kernel_event(c, true);
+            hip_check(hipGraphLaunch(c->gexec, c->stream), "graph launch");
+            kernel_event(c, false);
+        }
         for (; done < n_cycles; ++done) {
             hip_check(launch_apt_quad(qa, c->quad_lds, c->stream), "cycle");
             hip_check(launch_apt_swap(sa, c->stream), "cycle");
@@ -951,7 +983,9 @@ sg_status sg_sqa_anneal(sg_ctx *c, const double *gamma, int32_t n_steps, int64_t
             a.n_steps = ns;
             a.lut_step0 = 0;
             a.do_energy = (done + ns == n_steps) ? 1 : 0;
+            kernel_event(c, true);
             hip_check(launch_sqa(a, c->n_inst, c->sqa_lds, c->stream), "anneal");
+            kernel_event(c, false);
             c->sqa_steps += (uint32_t)ns;
             done += ns;
         }
@@ -1182,6 +1216,32 @@ sg_status sg_timer_stop(sg_ctx *c, float *ms)
         hip_check(hipEventRecord(c->timer.b, c->stream), "event");
         hip_check(hipEventSynchronize(c->timer.b), "event");
         hip_check(hipEventElapsedTime(ms, c->timer.a, c->timer.b), "event");
+    });
+}
+
+sg_status sg_kernel_timing(sg_ctx *c, int32_t enable)
+{
+    return guarded(c, [&] {
+        if (!c) fail(SG_EINVAL, "context is NULL");
+        c->ktime = enable != 0;
+        c->kev_used = 0;
+    });
+}
+
+sg_status sg_kernel_time(sg_ctx *c, float *ms, int32_t *launches)
+{
+    return guarded(c, [&] {
+        if (!c || !ms || !launches) fail(SG_EINVAL, "NULL argument");
+        hip_check(hipStreamSynchronize(c->stream), "kernel time");
+        double tot = 0.0;
+        for (size_t i = 0; i < c->kev_used; ++i) {
+            float m = 0.f;
+            hip_check(hipEventElapsedTime(&m, c->kev[i].first, c->kev[i].second), "kernel time");
+            tot += m;
+        }
+        *ms = (float)tot;
+        *launches = (int32_t)c->kev_used;
+        c->kev_used = 0;
     });
 }
 

@@ -50,7 +50,7 @@ EXPORTS = [
     "sg_create", "sg_destroy", "sg_last_error", "sg_sweep", "sg_icm", "sg_energy", "sg_swap",
     "sg_run_apt", "sg_best", "sg_swap_counts", "sg_sqa_anneal", "sg_get_spins", "sg_set_spins",
     "sg_get_counters", "sg_get_state", "sg_set_state", "sg_timer_start", "sg_timer_stop",
-    "sg_synchronize", "sg_adaptive_ladder", "sg_mlp_create", "sg_mlp_destroy",
+    "sg_synchronize", "sg_kernel_timing", "sg_kernel_time", "sg_adaptive_ladder", "sg_mlp_create", "sg_mlp_destroy",
     "sg_instance_features", "sg_mlp_set_standardisation", "sg_mlp_loss_grad", "sg_mlp_train",
     "sg_mlp_get_params", "sg_ladder_predict",
 ]
@@ -87,6 +87,8 @@ def load():
         "sg_timer_start": (i32, [P]),
         "sg_timer_stop": (i32, [P, C.POINTER(C.c_float)]),
         "sg_synchronize": (i32, [P]),
+        "sg_kernel_timing": (i32, [P, i32]),
+        "sg_kernel_time": (i32, [P, C.POINTER(C.c_float), C.POINTER(i32)]),
         "sg_adaptive_ladder": (i32, [C.POINTER(_Lattice), i32, C.POINTER(_Adaptive), u64, P, P, P, P]),
         "sg_mlp_create": (i32, [P, u64, P, C.POINTER(P)]),
         "sg_mlp_destroy": (None, [P]),
@@ -260,6 +262,15 @@ class Context:
 
     def synchronize(self):
         self._check(self.lib.sg_synchronize(self.h))
+
+    def kernel_timing(self, enable=True):
+        self._check(self.lib.sg_kernel_timing(self.h, 1 if enable else 0))
+
+    def kernel_time(self):
+        """(summed ms, launches) of the main kernels since the last query."""
+        ms, n = C.c_float(0), C.c_int32(0)
+        self._check(self.lib.sg_kernel_time(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
 
 def apt(instances, beta, seed, reps_per_beta=2):
