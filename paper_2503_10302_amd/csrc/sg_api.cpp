@@ -290,6 +290,8 @@ struct sg_ctx {
     DevBuf<int64_t> d_best, d_acc_count, d_mom, d_trace;
     DevBuf<int32_t> d_acc_out;
     DevBuf<QuadDesc> d_desc;
+    DevBuf<uint4> d_rowA, d_rowB;
+    DevBuf<uint32_t> d_inst_done;
     int n_blocks = 0;
     size_t quad_lds = 0;
     double icm_cutoff_loaded = std::numeric_limits<double>::quiet_NaN();
@@ -390,6 +392,35 @@ void sqa_records(const Lat &L, std::vector<uint4> &rec, std::vector<uint4> &recj
     for (int j = 0; j < L.n; ++j) recj.push_back(make_record(L, j, 0u));
 }
 
+// Row tables for the cluster search (see sg_internal.h); rows of lx <= 32.
+void apt_rows(const Lat &L, std::vector<uint4> &rowA, std::vector<uint4> &rowB, InstDev &I)
+{
+    I.lx = L.Lx;
+    I.n_rows = L.Ly * L.Lz;
+    if (L.Lx > 32) {
+        I.row_off = -1;
+        return;
+    }
+    I.row_off = (int32_t)rowA.size();
+    for (int r = 0; r < I.n_rows; ++r) {
+        uint32_t m[6] = {0, 0, 0, 0, 0, 0};
+        uint32_t nbrow[4] = {(uint32_t)r, (uint32_t)r, (uint32_t)r, (uint32_t)r};
+        for (int x = 0; x < L.Lx; ++x) {
+            const int j = r * L.Lx + x;
+            for (int a = 0; a < 3; ++a)
+                for (int s = 0; s < 2; ++s) {
+                    const int dir = s ? -1 : +1;
+                    const int v = L.nbr(j, a, dir);
+                    if (v < 0 || L.coupling(j, a, dir) == 0) continue;
+                    m[2 * a + s] |= 1u << x;
+                    if (a > 0) nbrow[2 * (a - 1) + s] = (uint32_t)(v / L.Lx);
+                }
+        }
+        rowA.push_back(make_uint4(m[0], m[1], m[2], m[3]));
+        rowB.push_back(make_uint4(m[4], m[5], nbrow[0] | (nbrow[1] << 16), nbrow[2] | (nbrow[3] << 16)));
+    }
+}
+
 // Work-group tasks, grouped so that all quads of an instance run on one
 // XCD (blocks are dispatched round-robin over the 8 XCDs; each XCD has its own
 // L2 holding that instance's records and tables).  Largest instances first.
@@ -460,7 +491,7 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
     hipStream_t s = c->stream;
     const int nb4 = 4 * c->n_quads;   // physical buffers per instance (slots padded to a quad)
 
-    std::vector<uint4> rec, recj;
+    std::vector<uint4> rec, recj, rowA, rowB;
     std::vector<int32_t> perm, slot_lut, tab_off, tab_len;
     std::vector<uint32_t> lut, tab;
     int64_t spin_bytes = 0;
@@ -473,6 +504,7 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
         I.npad = round_up(L.n, 16);
         I.n_slots = c->n_slots;
         apt_records(L, rec, recj, I);
+        apt_rows(L, rowA, rowB, I);
         I.spin_off = spin_bytes;
         spin_bytes += (int64_t)nb4 * I.npad;
         I.slot_off = i * nb4;
@@ -503,6 +535,8 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
     c->d_inst.upload(c->idev, s, "instances");
     c->d_rec.upload(rec, s, "records");
     c->d_recj.upload(recj, s, "records");
+    c->d_rowA.upload(rowA, s, "row tables");
+    c->d_rowB.upload(rowB, s, "row tables");
     c->d_perm.upload(perm, s, "perm");
     c->d_slot_lut.upload(slot_lut, s, "slot tables");
     c->d_lut.upload(lut, s, "thresholds");
@@ -518,16 +552,21 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
     c->d_icm_info.alloc((size_t)c->n_inst * c->n_beta * std::max(1, c->reps / 2) * 4, "icm info");
     c->d_icm_on.alloc((size_t)c->n_inst * c->n_beta, "icm flags");
     c->d_ctr.alloc(8, "counters");
+    c->d_inst_done.alloc((size_t)c->n_inst, "instance counters");
     std::vector<QuadDesc> desc = make_quad_descs(c->lat, c->n_quads);
     c->n_blocks = (int)desc.size();
     c->d_desc.upload(desc, s, "tasks");
-    int npad_max = 0;
-    for (auto &I : c->idev) npad_max = std::max(npad_max, I.npad);
-    c->quad_lds = sizeof(uint32_t) * (size_t)(npad_max + 4 + 4 * c->ni + 32 + (npad_max + 31) / 32 + 1) +
-                  sizeof(uint16_t) * (size_t)npad_max + 16;
+    c->quad_lds = 0;
+    for (auto &I : c->idev) {
+        const size_t need = sizeof(uint32_t) * (size_t)(I.npad + 4 + 4 * c->ni + 32 + (I.npad + 31) / 32 + 1 +
+                                                        2 * I.n_rows) +
+                            sizeof(uint16_t) * (size_t)I.npad + 16;
+        c->quad_lds = std::max(c->quad_lds, need);
+    }
     if (c->quad_lds > kMaxLds)
         fail(SG_EUNSUPPORTED, "instance too large for one work-group's LDS (%zu bytes)", c->quad_lds);
     hip_check(launch_fill_u32(c->d_ctr.p, 0u, 8, s), "init");
+    hip_check(launch_fill_u32(c->d_inst_done.p, 0u, c->n_inst, s), "init");
     hip_check(launch_fill_i64(c->d_best.p, std::numeric_limits<int64_t>::max(), c->n_inst, s), "init");
     hip_check(launch_fill_i64(c->d_acc_count.p, 0, (int64_t)c->d_acc_count.n, s), "init");
     hip_check(launch_fill_i64(c->d_mom.p, 0, (int64_t)c->d_mom.n, s), "init");
@@ -540,6 +579,7 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
     a.desc = c->d_desc.p; a.inst = c->d_inst.p; a.rec_col = c->d_rec.p; a.rec_j = c->d_recj.p;
     a.spins = c->d_spins.p; a.perm = c->d_perm.p; a.lut = c->d_lut.p; a.slot_lut = c->d_slot_lut.p;
     a.icm_on = c->d_icm_on.p; a.E = c->d_E.p; a.mom = c->d_mom.p; a.icm_info = c->d_icm_info.p;
+    a.rowA = c->d_rowA.p; a.rowB = c->d_rowB.p; a.inst_done = c->d_inst_done.p; a.n_quads = c->n_quads;
     a.ctr = c->d_ctr.p; a.key0 = c->key0; a.key1 = c->key1; a.tag = TAG_APT_SWEEP;
     a.do_energy = 1; a.mom_from = -1; a.reps = c->reps; a.imax = c->imax; a.ni = c->ni;
     a.n_blocks = c->n_blocks;
@@ -571,6 +611,10 @@ AptArgs apt_args(sg_ctx *c, int n_sweeps, int do_icm, int bump)
     a.E = c->d_E.p;
     a.mom = c->d_mom.p;
     a.icm_info = c->d_icm_info.p;
+    a.rowA = c->d_rowA.p;
+    a.rowB = c->d_rowB.p;
+    a.inst_done = c->d_inst_done.p;
+    a.n_quads = c->n_quads;
     a.ctr = c->d_ctr.p;
     a.key0 = c->key0;
     a.key1 = c->key1;
@@ -609,7 +653,7 @@ SwapArgs swap_args(sg_ctx *c, int bump_all, int sweeps_per_cycle, int32_t *acc_o
     a.n_beta = c->n_beta;
     a.reps = c->reps;
     a.n_inst = c->n_inst;
-    a.bump_all = bump_all;
+    a.bump = bump_all ? (1 | 2 | 4 | 8) : 4;
     a.sweeps_per_cycle = sweeps_per_cycle;
     return a;
 }
@@ -675,7 +719,7 @@ void create_sqa(sg_ctx *c, const sg_config *cfg)
     c->d_slice_E.alloc((size_t)c->n_inst * c->R * c->M, "slice energies");
     c->d_ctr.alloc(8, "counters");
     hip_check(launch_fill_u32(c->d_ctr.p, 0u, 8, s), "init");
-    c->sqa_lds = sizeof(uint32_t) * (size_t)(2 * (npad_max + 1) + c->nl + 2 * 64) + 16;
+    c->sqa_lds = sizeof(uint32_t) * (size_t)(2 * (npad_max + 1) + c->nl + 2 * 64 + 5 * 16) + 16;
     if (c->sqa_lds > kMaxLds)
         fail(SG_EUNSUPPORTED, "instance too large for one work-group's LDS (%zu bytes)", c->sqa_lds);
     SqaArgs a{};
@@ -885,8 +929,11 @@ sg_status sg_run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, doubl
         int64_t *trace = best_trace ? c->d_trace.p : nullptr;
         const int rec = best_trace ? record_every : 0;
         hip_check(launch_fill_u32(c->d_ctr.p + 3, 0u, 1, c->stream), "cycle counter");
-        AptArgs qa = apt_args(c, sweeps_per_swap, icm ? 1 : 0, 0);
-        SwapArgs sa = swap_args(c, 1, sweeps_per_swap, nullptr, trace, cap, rec);
+        // one launch per cycle: sweeps, ICM, energies, then the last work-group
+        // of every instance runs its replica exchange (fused swap)
+        AptArgs qa = apt_args(c, sweeps_per_swap, icm ? 1 : 0, 1 | 2 | 4 | 8);
+        qa.fuse_swap = 1;
+        qa.sw = swap_args(c, 1, sweeps_per_swap, nullptr, trace, cap, rec);
         // Replay a captured graph of K cycles; the kernels read their step
         // numbers from device counters, so the same graph is valid every time.
         const int K = 32;
@@ -897,10 +944,7 @@ sg_status sg_run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, doubl
             hipGraph_t g = nullptr;
             hip_check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "capture");
             hipError_t e = hipSuccess;
-            for (int k = 0; k < K && e == hipSuccess; ++k) {
-                e = launch_apt_quad(qa, c->quad_lds, c->stream);
-                if (e == hipSuccess) e = launch_apt_swap(sa, c->stream);
-            }
+            for (int k = 0; k < K && e == hipSuccess; ++k) e = launch_apt_quad(qa, c->quad_lds, c->stream);
             hipError_t e2 = hipStreamEndCapture(c->stream, &g);
             hip_check(e, "capture launch");
             hip_check(e2, "end capture");
@@ -919,10 +963,7 @@ sg_status sg_run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, doubl
             hip_check(hipGraphLaunch(c->gexec, c->stream), "graph launch");
             kernel_event(c, false);
         }
-        for (; done < n_cycles; ++done) {
-            hip_check(launch_apt_quad(qa, c->quad_lds, c->stream), "cycle");
-            hip_check(launch_apt_swap(sa, c->stream), "cycle");
-        }
+        for (; done < n_cycles; ++done) hip_check(launch_apt_quad(qa, c->quad_lds, c->stream), "cycle");
         if (best_trace) {
             std::vector<int64_t> t((size_t)c->n_inst * cap);
             c->d_trace.download(t.data(), t.size(), c->stream, "trace");

@@ -52,8 +52,15 @@ struct InstDev {
     int32_t slot_off;    // APT: first entry in perm / E / slot_lut / swap arrays
     int32_t swap_off;    // APT: first pair entry of swap tables
     int32_t info_off;    // APT: first ICM info record
-    int32_t pad_;
+    int32_t lx;          // row length (x extent)
+    int32_t n_rows;      // Ly * Lz
+    int32_t row_off;     // first entry of the row tables, -1 when lx > 32
 };
+
+// Row tables of an instance for the cluster search (rows of lx <= 32 sites):
+//   rowA[r] = {bond to +x present (bit x), bond to -x, bond to +y, bond to -y}
+//   rowB[r] = {bond to +z, bond to -z, row(+y) | row(-y) << 16, row(+z) | row(-z) << 16}
+// "present" means the neighbour exists and J != 0.
 
 // One work-group task of the APT replica kernel: instance and group of four
 // consecutive logical slots.  inst < 0 = idle filler.
@@ -62,36 +69,9 @@ struct QuadDesc {
     int32_t quad;
 };
 
-struct AptArgs {
-    const QuadDesc *desc;
-    const InstDev *inst;
-    const uint4 *rec_col;
-    const uint4 *rec_j;
-    uint8_t *spins;            // physical replica buffers, bytes 0/1 (1 = spin up)
-    const int32_t *perm;       // logical slot -> physical buffer (per instance)
-    const uint32_t *lut;       // heat-bath thresholds, NI per table
-    const int32_t *slot_lut;   // logical slot -> table index
-    const uint8_t *icm_on;     // per (instance, beta index): ICM applies
-    int32_t *E;                // energies per logical slot
-    int64_t *mom;              // per logical slot {sum E, sum E^2} (adaptive stage)
-    int32_t *icm_info;         // per (instance, beta, pair) {m, seed, size, branch}
-    uint32_t *ctr;             // device counters {sweeps, icm calls, swaps, cycles, done}
-    uint32_t key0, key1;
-    uint32_t tag;              // sweep purpose (APT or adaptive)
-    int32_t n_sweeps;
-    int32_t do_icm;
-    int32_t do_energy;
-    int32_t mom_from;          // accumulate moments after sweep index >= mom_from (-1: never)
-    int32_t reps;              // ICM labels per temperature
-    int32_t imax;              // LUT covers fields -imax..imax
-    int32_t ni;                // 2 * imax + 1
-    int32_t bump;              // bit0: advance sweep counter, bit1: advance ICM counter
-    int32_t n_blocks;
-};
-
+// Replica exchange of one instance (also run at the end of a fused cycle).
 struct SwapArgs {
     const InstDev *inst;
-    const int32_t *n_beta_of;  // unused placeholder for per-instance ladders (all equal)
     int32_t *perm;
     int32_t *E;
     const uint32_t *tab;       // swap thresholds, per pair: T[d] for |dE| = d
@@ -108,8 +88,42 @@ struct SwapArgs {
     int32_t n_beta;
     int32_t reps;
     int32_t n_inst;
-    int32_t bump_all;          // 1: end of an APT cycle (advance all counters)
+    int32_t bump;              // counters advanced by the last work-group (see AptArgs)
     int32_t sweeps_per_cycle;
+};
+
+struct AptArgs {
+    const QuadDesc *desc;
+    const InstDev *inst;
+    const uint4 *rec_col;
+    const uint4 *rec_j;
+    const uint4 *rowA;
+    const uint4 *rowB;
+    uint8_t *spins;            // physical replica buffers, bytes 0/1 (1 = spin up)
+    const int32_t *perm;       // logical slot -> physical buffer (per instance)
+    const uint32_t *lut;       // heat-bath thresholds, NI per table
+    const int32_t *slot_lut;   // logical slot -> table index
+    const uint8_t *icm_on;     // per (instance, beta index): ICM applies
+    int32_t *E;                // energies per logical slot
+    int64_t *mom;              // per logical slot {sum E, sum E^2} (adaptive stage)
+    int32_t *icm_info;         // per (instance, beta, pair) {m, seed, size, branch}
+    uint32_t *ctr;             // device counters {sweeps, icm calls, swaps, cycles, done}
+    uint32_t *inst_done;       // per instance: work-groups finished in this launch
+    uint32_t key0, key1;
+    uint32_t tag;              // sweep purpose (APT or adaptive)
+    int32_t n_sweeps;
+    int32_t do_icm;
+    int32_t do_energy;
+    int32_t mom_from;          // accumulate moments after sweep index >= mom_from (-1: never)
+    int32_t reps;              // ICM labels per temperature
+    int32_t imax;              // LUT covers fields -imax..imax
+    int32_t ni;                // 2 * imax + 1
+    int32_t bump;              // bit0: sweeps += n_sweeps, bit1: icm += 1, bit2: swaps += 1,
+                               // bit3: cycles += 1 (done by the last work-group)
+    int32_t n_blocks;
+    int32_t n_quads;           // quads per instance
+    int32_t fuse_swap;         // last work-group of an instance runs its replica exchange
+    SwapArgs sw;
 };
 
 // DT-SQA: spins of replica (inst, r) are n+1 pairs of 32-bit words

@@ -207,7 +207,8 @@ __device__ void icm_pair(uint32_t *sp, const uint4 *recj, int n, int ba, int bb,
 }
 
 // Last work-group to finish advances the device counters (every work-group
-// read them at its start).
+// read them at its start).  bump: bit0 sweeps += n_sweeps, bit1 ICM calls += 1,
+// bit2 swap attempts += 1, bit3 cycles += 1.
 __device__ __forceinline__ void finish_and_bump(uint32_t *ctr, int n_blocks, int bump, int n_sweeps)
 {
     if (!bump) return;
@@ -218,10 +219,178 @@ __device__ __forceinline__ void finish_and_bump(uint32_t *ctr, int n_blocks, int
         if (prev == (uint32_t)(n_blocks - 1)) {
             if (bump & 1) ctr[0] += (uint32_t)n_sweeps;
             if (bump & 2) ctr[1] += 1u;
+            if (bump & 4) ctr[2] += 1u;
+            if (bump & 8) ctr[3] += 1u;
             ctr[4] = 0u;
             __threadfence();
         }
     }
+}
+
+// Houdayer move on rows of lx <= 32 sites: the overlap set Q and the cluster
+// V are bit rows; one propagation step adds every Q site next to V through a
+// bond with J != 0, until nothing changes.  Same result as a breadth-first
+// search from the seed, with no global memory traffic inside the loop.
+// LDS: Qr[n_rows], Vr[n_rows], red[>= 24].
+__device__ void icm_pair_rows(uint32_t *sp, const uint4 *rowA, const uint4 *rowB, int n, int lx,
+                              int nrows, int ba, int bb, uint32_t w0, uint32_t w1, uint32_t *Qr,
+                              uint32_t *Vr, int32_t *red, int32_t *info)
+{
+    const int tid = threadIdx.x;
+    const uint32_t mA = 1u << (8 * ba), mB = 1u << (8 * bb);
+    const int rpt = (nrows + kQuadThreads - 1) / kQuadThreads;
+    const int r0 = min(nrows, tid * rpt), r1 = min(nrows, r0 + rpt);
+    int32_t cnt = 0;
+    for (int r = r0; r < r1; ++r) {
+        uint32_t q = 0u;
+        const uint32_t *row = sp + r * lx;
+        for (int x = 0; x < lx; ++x) {
+            const uint32_t w = row[x];
+            q |= (uint32_t)(((w & mA) != 0) != ((w & mB) != 0)) << x;
+        }
+        Qr[r] = q;
+        Vr[r] = 0u;
+        cnt += __popc(q);
+    }
+    int32_t m;
+    const int32_t prefix = block_exclusive_scan(cnt, red, &m);
+    if (m == 0) {
+        if (tid == 0 && info) { info[0] = 0; info[1] = -1; info[2] = 0; info[3] = 0; }
+        __syncthreads();
+        return;
+    }
+    const int32_t k = (int32_t)(((uint64_t)w0 * (uint64_t)(uint32_t)m) >> 32);
+    if (prefix <= k && k < prefix + cnt) {
+        int32_t c = prefix;
+        for (int r = r0; r < r1; ++r) {
+            uint32_t q = Qr[r];
+            const int32_t pc = __popc(q);
+            if (k < c + pc) {
+                for (int32_t i = 0; i < k - c; ++i) q &= q - 1u;
+                const int x = __builtin_ctz(q);
+                Vr[r] = 1u << x;
+                red[16] = r * lx + x;
+                break;
+            }
+            c += pc;
+        }
+    }
+    __syncthreads();
+    const int32_t seed = red[16];
+    const uint32_t hi = (uint32_t)(lx - 1);
+    while (true) {
+        int changed = 0;
+        for (int r = r0; r < r1; ++r) {
+            const uint4 a = rowA[r], b = rowB[r];
+            const uint32_t V = Vr[r];
+            const uint32_t right = (V >> 1) | (V << hi);   // bit x <- site x+1 (mod lx)
+            const uint32_t left = (V << 1) | (V >> hi);    // bit x <- site x-1 (mod lx)
+            const uint32_t N = (right & a.x) | (left & a.y) | (Vr[b.z & 0xFFFFu] & a.z) |
+                               (Vr[b.z >> 16] & a.w) | (Vr[b.w & 0xFFFFu] & b.x) |
+                               (Vr[b.w >> 16] & b.y);
+            const uint32_t Vn = V | (N & Qr[r]);
+            if (Vn != V) {
+                Vr[r] = Vn;
+                changed = 1;
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+    int32_t sz = 0;
+    for (int r = r0; r < r1; ++r) sz += __popc(Vr[r]);
+    int32_t tot[4] = {sz, 0, 0, 0};
+    block_sum4(tot, red);
+    const int32_t size = tot[0];
+    int32_t branch;
+    if (2 * size > n) {
+        const uint32_t X = ((w1 >> 31) == 0u) ? mA : mB;
+        branch = ((w1 >> 31) == 0u) ? 1 : 2;
+        for (int j = tid; j < n; j += kQuadThreads) sp[j] ^= X;
+    } else {
+        branch = 0;
+        for (int r = r0; r < r1; ++r) {
+            uint32_t bits = Vr[r];
+            while (bits) {
+                const int x = __builtin_ctz(bits);
+                sp[r * lx + x] ^= (mA | mB);
+                bits &= bits - 1u;
+            }
+        }
+    }
+    if (tid == 0 && info) { info[0] = m; info[1] = seed; info[2] = size; info[3] = branch; }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int32_t load_agent(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Replica exchange (Eq. 4) for one instance, run by one work-group of any
+// size.  An accepted exchange swaps the logical->physical mapping of the two
+// slots and their energies; the random word is keyed by the logical pair, so
+// this is the same chain as exchanging the states.  Energies and the mapping
+// are read with device-scope loads: other work-groups wrote them in this launch.
+__device__ void swap_instance(const SwapArgs &A, int inst, int32_t *red)
+{
+    const InstDev &I = A.inst[inst];
+    const int R = A.reps, nb = A.n_beta;
+    const int npt = (nb - 1) * R;
+    const uint32_t a = A.ctr[2] + 1u;
+    const uint32_t cyc = A.ctr[3] + 1u;
+    int32_t *perm = A.perm + I.slot_off;
+    int32_t *E = A.E + I.slot_off;
+    const int nt = blockDim.x;
+    if (A.acc_out)
+        for (int i = threadIdx.x; i < npt; i += nt) A.acc_out[(int64_t)inst * npt + i] = -1;
+    const int first = (a & 1u) ? 0 : 1;
+    const int npairs = (nb - 1 - first + 1) / 2;
+    for (int idx = threadIdx.x; idx < npairs * R; idx += nt) {
+        const int b = first + 2 * (idx / R), l = idx - (idx / R) * R;
+        const int s0 = b * R + l, s1 = s0 + R;
+        const int32_t e0 = load_agent(E + s0), e1 = load_agent(E + s1);
+        const int32_t dE = e1 - e0;
+        int acc;
+        if (dE >= 0) {
+            acc = 1;
+        } else {
+            const int pair = I.swap_off + b;
+            const int32_t d = -dE;
+            if (d < A.tab_len[pair]) {
+                const uint32_t u = philox10((uint32_t)(b * R + l), a, 0u,
+                                            ((uint32_t)inst << 4) | TAG_SWAP, A.key0, A.key1).x;
+                acc = u < A.tab[A.tab_off[pair] + d];
+            } else {
+                acc = 0;
+            }
+        }
+        if (acc) {
+            const int32_t p0 = load_agent(perm + s0), p1 = load_agent(perm + s1);
+            perm[s0] = p1;
+            perm[s1] = p0;
+            E[s0] = e1;
+            E[s1] = e0;
+        }
+        if (A.acc_out) A.acc_out[(int64_t)inst * npt + s0] = acc;
+        A.acc_count[(int64_t)inst * npt + s0] += acc;
+    }
+    __syncthreads();
+    int32_t m = 0x7FFFFFFF;
+    for (int s = threadIdx.x; s < nb * R; s += nt) m = min(m, load_agent(E + s));
+    m = wave_min(m);
+    if ((threadIdx.x & 63) == 0) red[20 + (threadIdx.x >> 6)] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (nt + 63) / 64; ++w) m = min(m, red[20 + w]);
+        int64_t best = A.best[inst];
+        if ((int64_t)m < best) best = m;
+        A.best[inst] = best;
+        if (A.trace && A.record_every > 0 && (cyc % (uint32_t)A.record_every) == 0u) {
+            const int64_t ti = (int64_t)(cyc / (uint32_t)A.record_every) - 1;
+            if (ti < A.trace_cap) A.trace[(int64_t)inst * A.trace_cap + ti] = best;
+        }
+    }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -264,8 +433,10 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
         uint32_t *sp = lds;                              // npad + 4 words
         uint32_t *lut = sp + npad + 4;                   // 4 * ni
         int32_t *red = (int32_t *)(lut + 4 * ni);        // 32
-        uint32_t *vis = (uint32_t *)(red + 32);          // (npad + 31) / 32
-        uint16_t *queue = (uint16_t *)(vis + ((npad + 31) >> 5) + 1);   // npad
+        uint32_t *vis = (uint32_t *)(red + 32);          // (npad + 31) / 32 + 1
+        uint32_t *Qr = vis + ((npad + 31) >> 5) + 1;     // n_rows
+        uint32_t *Vr = Qr + I.n_rows;                    // n_rows
+        uint16_t *queue = (uint16_t *)(Vr + I.n_rows);   // npad
         const int q = D.quad;
         const int32_t *pp = A.perm + I.slot_off + 4 * q;
         const int64_t b0 = (int64_t)pp[0] * npad, b1 = (int64_t)pp[1] * npad;
@@ -332,34 +503,40 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
             const int n_beta = I.n_slots / A.reps;
             const int npair = A.reps / 2;
             const uint4 *recj = A.rec_j + I.recj_off;
+            int pa[2], pb[2], pbeta[2], pidx[2], np = 0;
+            uint32_t wpick = 0u;
             if (A.reps == 2) {
                 for (int half = 0; half < 2; ++half) {
                     const int b = 2 * q + half;
                     if (b >= n_beta || !A.icm_on[D.inst * n_beta + b]) continue;
-                    const uint4 w = philox10((uint32_t)b, a, 0u,
-                                             ((uint32_t)D.inst << 4) | TAG_ICM_PICK, A.key0, A.key1);
-                    icm_pair(sp, recj, n, 2 * half, 2 * half + 1, w.x, w.y, queue, vis, red,
-                             A.icm_info + ((int64_t)I.info_off + b) * 4);
+                    pa[np] = 2 * half; pb[np] = 2 * half + 1; pbeta[np] = b; pidx[np] = b; ++np;
                 }
             } else if (A.reps == 4) {
                 const int b = q;
                 if (b < n_beta && A.icm_on[D.inst * n_beta + b]) {
-                    const uint32_t wp = philox10((uint32_t)b, a, 0u,
-                                                 ((uint32_t)D.inst << 4) | TAG_ICM_PAIR, A.key0,
-                                                 A.key1).x;
-                    const int pairing = (int)(((uint64_t)wp * 3u) >> 32);
+                    wpick = philox10((uint32_t)b, a, 0u, ((uint32_t)D.inst << 4) | TAG_ICM_PAIR,
+                                     A.key0, A.key1).x;
+                    const int pairing = (int)(((uint64_t)wpick * 3u) >> 32);
                     // matchings {01,23}, {02,13}, {03,12}: partner of label 0, then the other two
                     const int p1 = pairing + 1;
-                    const int o1 = (p1 == 1) ? 2 : 1, o2 = (p1 == 3) ? 2 : 3;
-                    for (int pi = 0; pi < 2; ++pi) {
-                        const uint4 w = philox10((uint32_t)(b * npair + pi), a, 0u,
-                                                 ((uint32_t)D.inst << 4) | TAG_ICM_PICK, A.key0,
-                                                 A.key1);
-                        icm_pair(sp, recj, n, pi ? o1 : 0, pi ? o2 : p1, w.x, w.y, queue, vis, red,
-                                 A.icm_info + ((int64_t)I.info_off + b * npair + pi) * 4);
-                    }
+                    pa[0] = 0; pb[0] = p1;
+                    pa[1] = (p1 == 1) ? 2 : 1; pb[1] = (p1 == 3) ? 2 : 3;
+                    pbeta[0] = pbeta[1] = b;
+                    pidx[0] = b * npair; pidx[1] = b * npair + 1;
+                    np = 2;
                 }
             }
+            for (int k2 = 0; k2 < np; ++k2) {
+                const uint4 w = philox10((uint32_t)pidx[k2], a, 0u,
+                                         ((uint32_t)D.inst << 4) | TAG_ICM_PICK, A.key0, A.key1);
+                int32_t *info = A.icm_info + ((int64_t)I.info_off + pidx[k2]) * 4;
+                if (I.row_off >= 0)
+                    icm_pair_rows(sp, A.rowA + I.row_off, A.rowB + I.row_off, n, I.lx, I.n_rows,
+                                  pa[k2], pb[k2], w.x, w.y, Qr, Vr, red, info);
+                else
+                    icm_pair(sp, recj, n, pa[k2], pb[k2], w.x, w.y, queue, vis, red, info);
+            }
+            (void)pbeta;
         }
 
         if (A.do_energy) {
@@ -390,83 +567,32 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
             }
         }
     }
+    if (A.fuse_swap && D.inst >= 0) {
+        // the last of the instance's work-groups exchanges its replicas
+        __shared__ int last;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            last = atomicAdd(&A.inst_done[D.inst], 1u) == (uint32_t)(A.n_quads - 1);
+            if (last) {
+                A.inst_done[D.inst] = 0u;
+                __threadfence();
+            }
+        }
+        __syncthreads();
+        if (last) swap_instance(A.sw, D.inst, (int32_t *)(lds + 0));
+    }
     finish_and_bump(A.ctr, A.n_blocks, A.bump, A.n_sweeps);
 }
 
 // ---------------------------------------------------------------------------
-// Replica exchange (Eq. 4), one work-group (64 lanes) per instance.  An
-// accepted exchange swaps the logical->physical mapping of the two slots and
-// their energies; the random word is keyed by the logical pair, so this is
-// the same chain as exchanging the states.
+// Replica exchange (Eq. 4) as its own launch, one 64-lane work-group per instance.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void apt_swap_kernel(SwapArgs A)
 {
-    const int inst = blockIdx.x;
-    const InstDev I = A.inst[inst];
-    const int R = A.reps, nb = A.n_beta;
-    const int npt = (nb - 1) * R;
-    const uint32_t a = A.ctr[2] + 1u;
-    const uint32_t cyc = A.ctr[3] + 1u;
-    int32_t *perm = A.perm + I.slot_off;
-    int32_t *E = A.E + I.slot_off;
-    if (A.acc_out)
-        for (int i = threadIdx.x; i < npt; i += 64) A.acc_out[(int64_t)inst * npt + i] = -1;
-    const int first = (a & 1u) ? 0 : 1;
-    const int npairs = (nb - 1 - first + 1) / 2;
-    for (int idx = threadIdx.x; idx < npairs * R; idx += 64) {
-        const int b = first + 2 * (idx / R), l = idx - (idx / R) * R;
-        const int s0 = b * R + l, s1 = s0 + R;
-        const int32_t e0 = E[s0], e1 = E[s1];
-        const int32_t dE = e1 - e0;
-        int acc;
-        if (dE >= 0) {
-            acc = 1;
-        } else {
-            const int pair = I.swap_off + b;
-            const int32_t d = -dE;
-            if (d < A.tab_len[pair]) {
-                const uint32_t u = philox10((uint32_t)(b * R + l), a, 0u,
-                                            ((uint32_t)inst << 4) | TAG_SWAP, A.key0, A.key1).x;
-                acc = u < A.tab[A.tab_off[pair] + d];
-            } else {
-                acc = 0;
-            }
-        }
-        if (acc) {
-            const int32_t p0 = perm[s0];
-            perm[s0] = perm[s1];
-            perm[s1] = p0;
-            E[s0] = e1;
-            E[s1] = e0;
-        }
-        if (A.acc_out) A.acc_out[(int64_t)inst * npt + s0] = acc;
-        A.acc_count[(int64_t)inst * npt + s0] += acc;
-    }
-    __syncthreads();
-    int32_t m = 0x7FFFFFFF;
-    for (int s = threadIdx.x; s < nb * R; s += 64) m = min(m, E[s]);
-    m = wave_min(m);
-    if (threadIdx.x == 0) {
-        int64_t best = A.best[inst];
-        if ((int64_t)m < best) best = m;
-        A.best[inst] = best;
-        if (A.trace && A.record_every > 0 && (cyc % (uint32_t)A.record_every) == 0u) {
-            const int64_t ti = (int64_t)(cyc / (uint32_t)A.record_every) - 1;
-            if (ti < A.trace_cap) A.trace[(int64_t)inst * A.trace_cap + ti] = best;
-        }
-        __threadfence();
-        const uint32_t prev = atomicAdd(&A.ctr[4], 1u);
-        if (prev == (uint32_t)(A.n_inst - 1)) {
-            if (A.bump_all) {
-                A.ctr[0] += (uint32_t)A.sweeps_per_cycle;
-                A.ctr[1] += 1u;
-                A.ctr[3] += 1u;
-            }
-            A.ctr[2] += 1u;
-            A.ctr[4] = 0u;
-            __threadfence();
-        }
-    }
+    __shared__ int32_t red[32];
+    swap_instance(A, blockIdx.x, red);
+    finish_and_bump(A.ctr, A.n_inst, A.bump, A.sweeps_per_cycle);
 }
 
 // ---------------------------------------------------------------------------
@@ -520,9 +646,19 @@ __global__ __launch_bounds__(kSqaThreads) void sqa_kernel(SqaArgs A)
     uint32_t *sp = lds;                         // 2 * (npad + 1)
     uint32_t *lut = sp + 2 * (npad + 1);        // nl
     int32_t *red = (int32_t *)(lut + A.nl);     // 2 * 64
+    // Spread tables: for a 4-bit slice group of one bit plane, the plane's
+    // contribution to the four threshold indices, one byte per slice.  Index
+    // weights: 6, 12, 24 for the aligned-neighbour count bits, 1, 2 for the
+    // number of up Trotter neighbours (table index = 6 k + t + 3 (h - d + smax)).
+    uint32_t *spread = (uint32_t *)(red + 128); // 5 * 16
     uint32_t *g = A.spins + I.spin_off + (int64_t)r * npad * 2;
     for (int i = tid; i < 2 * npad; i += kSqaThreads) sp[i] = g[i];
     if (tid < 2) sp[2 * npad + tid] = 0u;
+    if (tid < 80) {
+        const uint32_t w[5] = {6u, 12u, 24u, 1u, 2u};
+        const uint32_t nib = (uint32_t)(tid & 15), pl = (uint32_t)(tid >> 4);
+        spread[tid] = w[pl] * ((nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21));
+    }
     const uint32_t c3 = ((uint32_t)inst << 4) | TAG_SQA_SWEEP;
     const int ngrp = (H + 3) >> 2;
     for (int st = 0; st < A.n_steps; ++st) {
@@ -549,31 +685,34 @@ __global__ __launch_bounds__(kSqaThreads) void sqa_kernel(SqaArgs A)
                 // bit-sliced 6-input count: k = c0 + 2 c1 + 4 c2 per slice
                 const uint32_t s1 = a0 ^ a1 ^ a2, k1 = (a0 & a1) | (a2 & (a0 ^ a1));
                 const uint32_t s2 = a3 ^ a4 ^ a5, k2 = (a3 & a4) | (a5 & (a3 ^ a4));
-                const uint32_t c0 = s1 ^ s2, cy = s1 & s2;
-                const uint32_t c1 = k1 ^ k2 ^ cy, c2 = (k1 & k2) | (cy & (k1 ^ k2));
+                const uint32_t cy = s1 & s2;
+                const uint32_t c0 = (s1 ^ s2) & mask;
+                const uint32_t c1 = (k1 ^ k2 ^ cy) & mask;
+                const uint32_t c2 = ((k1 & k2) | (cy & (k1 ^ k2))) & mask;
                 const uint32_t ev = sp[2 * j], od = sp[2 * j + 1];
                 const uint32_t up = p ? ev : rotl_h(od, H, mask);
                 const uint32_t dn = p ? rotr_h(ev, H, mask) : od;
                 const uint32_t t0b = up ^ dn, t1b = up & dn;
-                const int32_t base3 = 3 * ((int32_t)((rr.x >> 25) & 63u) - 32 -
-                                           (int32_t)((rr.x >> 16) & 7u) + A.smax);
+                const uint32_t base4 = (uint32_t)(3 * ((int32_t)((rr.x >> 25) & 63u) - 32 -
+                                                      (int32_t)((rr.x >> 16) & 7u) + A.smax)) *
+                                       0x01010101u;
                 uint32_t res = 0u;
                 for (int gq = 0; gq < ngrp; ++gq) {
+                    const int sh = 4 * gq;
+                    // four threshold indices, one byte each (all < 256)
+                    const uint32_t idx4 = spread[(c0 >> sh) & 15u] + spread[16 + ((c1 >> sh) & 15u)] +
+                                          spread[32 + ((c2 >> sh) & 15u)] +
+                                          spread[48 + ((t0b >> sh) & 15u)] +
+                                          spread[64 + ((t1b >> sh) & 15u)] + base4;
                     const uint4 u = philox10(j, t, ((uint32_t)r << 16) | (p << 15) | (uint32_t)gq,
                                              c3, A.key0, A.key1);
-                    const uint32_t us[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-                    for (int ii = 0; ii < 4; ++ii) {
-                        const int h = 4 * gq + ii;
-                        if (h < H) {
-                            const int32_t kk = (int32_t)(((c0 >> h) & 1u) | (((c1 >> h) & 1u) << 1) |
-                                                         (((c2 >> h) & 1u) << 2));
-                            const int32_t tt = (int32_t)(((t0b >> h) & 1u) + 2u * ((t1b >> h) & 1u));
-                            if (us[ii] < lut[6 * kk + tt + base3]) res |= 1u << h;
-                        }
-                    }
+                    uint32_t b4 = (u.x < lut[idx4 & 0xFFu]) ? 1u : 0u;
+                    b4 |= (u.y < lut[(idx4 >> 8) & 0xFFu]) ? 2u : 0u;
+                    b4 |= (u.z < lut[(idx4 >> 16) & 0xFFu]) ? 4u : 0u;
+                    b4 |= (u.w < lut[idx4 >> 24]) ? 8u : 0u;
+                    res |= b4 << sh;
                 }
-                sp[2 * j + p] = res;
+                sp[2 * j + p] = res & mask;
             }
             __syncthreads();
         }

@@ -138,6 +138,23 @@ def test_apt_with_fields_and_open_axes():
     assert e.value.code == sg.SG_EUNSUPPORTED
 
 
+def test_apt_long_rows_use_queue_search():
+    """x extent above 32 sites: the cluster search falls back to the breadth-first queue."""
+    insts = [_inst((40, 3, 3), 7, 41), _inst((37, 2, 4), 5, 42), _inst((6, 6, 6), 7, 43)]
+    beta = geometric_ladder(6, 0.4, 3.0)
+    ctx = sg.apt(insts, beta, SEED, reps_per_beta=4)
+    trace = ctx.run_apt(40, 1, 0.5, record_every=10)
+    g = ctx.spins()
+    for i, inst in enumerate(insts):
+        l = _olat(inst)
+        sp = oracle.apt_init(l, i, 24, SEED)
+        ctr = np.zeros(3, np.uint32)
+        E = np.zeros(24, np.int64)
+        b = np.array([np.iinfo(np.int64).max], np.int64)
+        rc, otr, _ = oracle.apt_run(l, i, beta, 4, SEED, 40, 1, 0.5, 10, ctr, sp, E, b)
+        assert rc == 0 and np.array_equal(g[i, :, :l.n], sp) and np.array_equal(trace[i], otr)
+
+
 def test_checkpoint_resume_is_exact():
     insts = [_inst(*m) for m in MIXED[:4]]
     beta = geometric_ladder(8, 0.2, 3.0)
