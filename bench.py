@@ -27,14 +27,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "spin flips/ns at L=15; time-to-target residual energy/spin, plain vs batched"
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 full-rate 32-bit lane-operations/s.
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# Algorithmic VALU work per spin-flip attempt (full-rate lane-operation equivalents):
-# a quarter of one Philox4x32-10 block (10 rounds x [2 wide 32x32->64 multiplies at
-# MUL_COST slots each + 4 xors]) plus the heat-bath compare.  MUL_COST is the issue
-# cost of v_mad_u64_u32 relative to a full-rate op, measured on the box.
-MUL_COST = 4.0
-ALG_OPS_PER_FLIP = (10 * (2 * MUL_COST + 4)) / 4 + 1
+# MI355X VALU: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6e12 lane-operations/s for
+# full-rate 32-bit operations (the published 157.3 TFLOP/s FP32 vector rate is this
+# figure times two flops per FMA).  Three-operand (VOP3) integer operations such as the
+# 32x32->64 multiply-add issue at half that rate (two slots).
+VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
+# Algorithmic VALU work per spin-update attempt, in full-rate slots: a quarter of one
+# Philox4x32-10 block (10 rounds x [2 multiply-adds x 2 slots + 4 xors x 1 slot]) plus
+# the threshold compare.  Index arithmetic, LDS traffic and the neighbour sums are
+# implementation overhead and are not counted.
+ALG_OPS_PER_FLIP = (10 * (2 * 2 + 4)) / 4 + 1
 
 
 def sqa_workload(R, seed0=20000, n_inst=32, L=15, M=64):

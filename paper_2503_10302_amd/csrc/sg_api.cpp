@@ -291,7 +291,6 @@ struct sg_ctx {
     DevBuf<int32_t> d_acc_out;
     DevBuf<QuadDesc> d_desc;
     DevBuf<uint4> d_rowA, d_rowB;
-    DevBuf<uint32_t> d_inst_done;
     int n_blocks = 0;
     size_t quad_lds = 0;
     double icm_cutoff_loaded = std::numeric_limits<double>::quiet_NaN();
@@ -552,7 +551,6 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
     c->d_icm_info.alloc((size_t)c->n_inst * c->n_beta * std::max(1, c->reps / 2) * 4, "icm info");
     c->d_icm_on.alloc((size_t)c->n_inst * c->n_beta, "icm flags");
     c->d_ctr.alloc(8, "counters");
-    c->d_inst_done.alloc((size_t)c->n_inst, "instance counters");
     std::vector<QuadDesc> desc = make_quad_descs(c->lat, c->n_quads);
     c->n_blocks = (int)desc.size();
     c->d_desc.upload(desc, s, "tasks");
@@ -566,7 +564,6 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
     if (c->quad_lds > kMaxLds)
         fail(SG_EUNSUPPORTED, "instance too large for one work-group's LDS (%zu bytes)", c->quad_lds);
     hip_check(launch_fill_u32(c->d_ctr.p, 0u, 8, s), "init");
-    hip_check(launch_fill_u32(c->d_inst_done.p, 0u, c->n_inst, s), "init");
     hip_check(launch_fill_i64(c->d_best.p, std::numeric_limits<int64_t>::max(), c->n_inst, s), "init");
     hip_check(launch_fill_i64(c->d_acc_count.p, 0, (int64_t)c->d_acc_count.n, s), "init");
     hip_check(launch_fill_i64(c->d_mom.p, 0, (int64_t)c->d_mom.n, s), "init");
@@ -579,7 +576,7 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
     a.desc = c->d_desc.p; a.inst = c->d_inst.p; a.rec_col = c->d_rec.p; a.rec_j = c->d_recj.p;
     a.spins = c->d_spins.p; a.perm = c->d_perm.p; a.lut = c->d_lut.p; a.slot_lut = c->d_slot_lut.p;
     a.icm_on = c->d_icm_on.p; a.E = c->d_E.p; a.mom = c->d_mom.p; a.icm_info = c->d_icm_info.p;
-    a.rowA = c->d_rowA.p; a.rowB = c->d_rowB.p; a.inst_done = c->d_inst_done.p; a.n_quads = c->n_quads;
+    a.rowA = c->d_rowA.p; a.rowB = c->d_rowB.p;
     a.ctr = c->d_ctr.p; a.key0 = c->key0; a.key1 = c->key1; a.tag = TAG_APT_SWEEP;
     a.do_energy = 1; a.mom_from = -1; a.reps = c->reps; a.imax = c->imax; a.ni = c->ni;
     a.n_blocks = c->n_blocks;
@@ -596,7 +593,7 @@ void upload_icm_flags(sg_ctx *c, double cutoff)
     c->icm_cutoff_loaded = cutoff;
 }
 
-AptArgs apt_args(sg_ctx *c, int n_sweeps, int do_icm, int bump)
+AptArgs apt_args(sg_ctx *c, int n_sweeps, int do_icm)
 {
     AptArgs a{};
     a.desc = c->d_desc.p;
@@ -613,8 +610,6 @@ AptArgs apt_args(sg_ctx *c, int n_sweeps, int do_icm, int bump)
     a.icm_info = c->d_icm_info.p;
     a.rowA = c->d_rowA.p;
     a.rowB = c->d_rowB.p;
-    a.inst_done = c->d_inst_done.p;
-    a.n_quads = c->n_quads;
     a.ctr = c->d_ctr.p;
     a.key0 = c->key0;
     a.key1 = c->key1;
@@ -626,13 +621,12 @@ AptArgs apt_args(sg_ctx *c, int n_sweeps, int do_icm, int bump)
     a.reps = c->reps;
     a.imax = c->imax;
     a.ni = c->ni;
-    a.bump = bump;
+    a.cyc_k = 0;
     a.n_blocks = c->n_blocks;
     return a;
 }
 
-SwapArgs swap_args(sg_ctx *c, int bump_all, int sweeps_per_cycle, int32_t *acc_out, int64_t *trace,
-                   int trace_cap, int record_every)
+SwapArgs swap_args(sg_ctx *c, int32_t *acc_out, int64_t *trace, int trace_cap, int record_every)
 {
     SwapArgs a{};
     a.inst = c->d_inst.p;
@@ -653,8 +647,7 @@ SwapArgs swap_args(sg_ctx *c, int bump_all, int sweeps_per_cycle, int32_t *acc_o
     a.n_beta = c->n_beta;
     a.reps = c->reps;
     a.n_inst = c->n_inst;
-    a.bump = bump_all ? (1 | 2 | 4 | 8) : 4;
-    a.sweeps_per_cycle = sweeps_per_cycle;
+    a.cyc_k = 0;
     return a;
 }
 
@@ -841,8 +834,9 @@ sg_status sg_sweep(sg_ctx *c, int32_t n_sweeps)
         require(c, SG_APT);
         if (n_sweeps < 0) fail(SG_EINVAL, "n_sweeps must be >= 0");
         if (n_sweeps == 0) return;
-        AptArgs a = apt_args(c, n_sweeps, 0, 1);
+        AptArgs a = apt_args(c, n_sweeps, 0);
         hip_check(launch_apt_quad(a, c->quad_lds, c->stream), "sweep");
+        hip_check(launch_advance(c->d_ctr.p, (uint32_t)n_sweeps, 0u, 0u, 0u, c->stream), "sweep");
     });
 }
 
@@ -857,8 +851,9 @@ sg_status sg_icm(sg_ctx *c, double cutoff, int32_t *info_host)
         hip_check(launch_fill_u32((uint32_t *)c->d_icm_info.p, 0xFFFFFFFFu, (int64_t)c->d_icm_info.n,
                                   c->stream),
                   "icm");
-        AptArgs a = apt_args(c, 0, 1, 2);
+        AptArgs a = apt_args(c, 0, 1);
         hip_check(launch_apt_quad(a, c->quad_lds, c->stream), "icm");
+        hip_check(launch_advance(c->d_ctr.p, 0u, 1u, 0u, 0u, c->stream), "icm");
         if (info_host) {
             c->d_icm_info.download(info_host, c->d_icm_info.n, c->stream, "icm info");
             hip_check(hipStreamSynchronize(c->stream), "icm");
@@ -899,8 +894,9 @@ sg_status sg_swap(sg_ctx *c, int32_t *accepted_host)
 {
     return guarded(c, [&] {
         require(c, SG_APT);
-        SwapArgs a = swap_args(c, 0, 0, accepted_host ? c->d_acc_out.p : nullptr, nullptr, 0, 0);
+        SwapArgs a = swap_args(c, accepted_host ? c->d_acc_out.p : nullptr, nullptr, 0, 0);
         hip_check(launch_apt_swap(a, c->stream), "swap");
+        hip_check(launch_advance(c->d_ctr.p, 0u, 0u, 1u, 0u, c->stream), "swap");
         if (accepted_host) {
             c->d_acc_out.download(accepted_host, (size_t)c->n_inst * (c->n_beta - 1) * c->reps,
                                   c->stream, "swap");
@@ -929,13 +925,13 @@ sg_status sg_run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, doubl
         int64_t *trace = best_trace ? c->d_trace.p : nullptr;
         const int rec = best_trace ? record_every : 0;
         hip_check(launch_fill_u32(c->d_ctr.p + 3, 0u, 1, c->stream), "cycle counter");
-        // one launch per cycle: sweeps, ICM, energies, then the last work-group
-        // of every instance runs its replica exchange (fused swap)
-        AptArgs qa = apt_args(c, sweeps_per_swap, icm ? 1 : 0, 1 | 2 | 4 | 8);
-        qa.fuse_swap = 1;
-        qa.sw = swap_args(c, 1, sweeps_per_swap, nullptr, trace, cap, rec);
-        // Replay a captured graph of K cycles; the kernels read their step
-        // numbers from device counters, so the same graph is valid every time.
+        AptArgs qa = apt_args(c, sweeps_per_swap, icm ? 1 : 0);
+        SwapArgs sa = swap_args(c, nullptr, trace, cap, rec);
+        const uint32_t S = (uint32_t)sweeps_per_swap;
+        // Replay a captured graph of K cycles.  Inside the graph cycle k reads
+        // its step numbers as (counters + k * per-cycle increments); one
+        // one-thread kernel at the end advances the counters by K cycles, so
+        // the same graph is valid on every replay.
         const int K = 32;
         if (!c->gexec || c->g_sweeps != sweeps_per_swap || c->g_icm != (int)icm || c->g_record != rec ||
             c->g_trace != trace || c->g_trace_cap != cap) {
@@ -944,7 +940,13 @@ sg_status sg_run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, doubl
             hipGraph_t g = nullptr;
             hip_check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "capture");
             hipError_t e = hipSuccess;
-            for (int k = 0; k < K && e == hipSuccess; ++k) e = launch_apt_quad(qa, c->quad_lds, c->stream);
+            for (int k = 0; k < K && e == hipSuccess; ++k) {
+                qa.cyc_k = k;
+                sa.cyc_k = k;
+                e = launch_apt_quad(qa, c->quad_lds, c->stream);
+                if (e == hipSuccess) e = launch_apt_swap(sa, c->stream);
+            }
+            if (e == hipSuccess) e = launch_advance(c->d_ctr.p, K * S, K, K, K, c->stream);
             hipError_t e2 = hipStreamEndCapture(c->stream, &g);
             hip_check(e, "capture launch");
             hip_check(e2, "end capture");
@@ -963,7 +965,13 @@ sg_status sg_run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, doubl
             hip_check(hipGraphLaunch(c->gexec, c->stream), "graph launch");
             kernel_event(c, false);
         }
-        for (; done < n_cycles; ++done) hip_check(launch_apt_quad(qa, c->quad_lds, c->stream), "cycle");
+        qa.cyc_k = 0;
+        sa.cyc_k = 0;
+        for (; done < n_cycles; ++done) {
+            hip_check(launch_apt_quad(qa, c->quad_lds, c->stream), "cycle");
+            hip_check(launch_apt_swap(sa, c->stream), "cycle");
+            hip_check(launch_advance(c->d_ctr.p, S, 1u, 1u, 1u, c->stream), "cycle");
+        }
         if (best_trace) {
             std::vector<int64_t> t((size_t)c->n_inst * cap);
             c->d_trace.download(t.data(), t.size(), c->stream, "trace");
@@ -1131,7 +1139,7 @@ sg_status sg_set_spins(sg_ctx *c, const int8_t *in)
             c->d_spins.upload(raw.data(), raw.size(), c->stream, "spins");
             c->d_perm.upload(perm.data(), perm.size(), c->stream, "perm");
             // energies of the new state
-            AptArgs a = apt_args(c, 0, 0, 0);
+            AptArgs a = apt_args(c, 0, 0);
             hip_check(launch_apt_quad(a, c->quad_lds, c->stream), "energy");
             hip_check(hipStreamSynchronize(c->stream), "spins");
         } else {
@@ -1367,11 +1375,12 @@ extern "C" sg_status sg_adaptive_ladder(const sg_lattice *inst, int32_t n_inst,
             hip_check(hipStreamSynchronize(s), "adaptive");
             c->d_lut.upload(lut.data(), lut.size(), s, "adaptive tables");
             hip_check(launch_fill_i64(c->d_mom.p, 0, (int64_t)c->d_mom.n, s), "adaptive");
-            AptArgs a = apt_args(c, p->sweeps, 0, 1);
+            AptArgs a = apt_args(c, p->sweeps, 0);
             a.tag = TAG_ADAPT_SWEEP;
             a.mom_from = p->sweeps - p->tail;
             a.do_energy = 0;
             hip_check(launch_apt_quad(a, c->quad_lds, s), "adaptive sweeps");
+            hip_check(launch_advance(c->d_ctr.p, (uint32_t)p->sweeps, 0u, 0u, 0u, s), "adaptive");
             c->d_mom.download(mom.data(), mom.size(), s, "moments");
             hip_check(hipStreamSynchronize(s), "adaptive");
             for (int i = 0; i < n_inst; ++i) {

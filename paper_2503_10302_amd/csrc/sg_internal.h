@@ -88,8 +88,7 @@ struct SwapArgs {
     int32_t n_beta;
     int32_t reps;
     int32_t n_inst;
-    int32_t bump;              // counters advanced by the last work-group (see AptArgs)
-    int32_t sweeps_per_cycle;
+    int32_t cyc_k;             // cycle offset of this launch inside a captured graph
 };
 
 struct AptArgs {
@@ -107,8 +106,7 @@ struct AptArgs {
     int32_t *E;                // energies per logical slot
     int64_t *mom;              // per logical slot {sum E, sum E^2} (adaptive stage)
     int32_t *icm_info;         // per (instance, beta, pair) {m, seed, size, branch}
-    uint32_t *ctr;             // device counters {sweeps, icm calls, swaps, cycles, done}
-    uint32_t *inst_done;       // per instance: work-groups finished in this launch
+    uint32_t *ctr;             // device counters {sweeps, icm calls, swaps, cycles}
     uint32_t key0, key1;
     uint32_t tag;              // sweep purpose (APT or adaptive)
     int32_t n_sweeps;
@@ -118,12 +116,10 @@ struct AptArgs {
     int32_t reps;              // ICM labels per temperature
     int32_t imax;              // LUT covers fields -imax..imax
     int32_t ni;                // 2 * imax + 1
-    int32_t bump;              // bit0: sweeps += n_sweeps, bit1: icm += 1, bit2: swaps += 1,
-                               // bit3: cycles += 1 (done by the last work-group)
     int32_t n_blocks;
-    int32_t n_quads;           // quads per instance
-    int32_t fuse_swap;         // last work-group of an instance runs its replica exchange
-    SwapArgs sw;
+    int32_t cyc_k;             // cycle offset of this launch inside a captured graph: the
+                               // kernel uses sweep counter ctr[0] + cyc_k * n_sweeps and ICM
+                               // call ctr[1] + cyc_k + 1; counters advance only between graphs
 };
 
 // DT-SQA: spins of replica (inst, r) are n+1 pairs of 32-bit words
@@ -157,6 +153,9 @@ hipError_t launch_sqa_init(const SqaArgs &a, int n_inst, hipStream_t s);
 hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+// ctr[i] += d[i] for the four counters (one thread; ordered by the stream).
+hipError_t launch_advance(uint32_t *ctr, uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3,
+                          hipStream_t s);
 
 // MLP kernels (sg_mlp.hip).  Parameters: 6625 floats, then mean[4], std[4].
 hipError_t launch_mlp_pass(const float *P, const float *x, const float *y, const int *idx,

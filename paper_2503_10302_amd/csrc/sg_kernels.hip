@@ -206,27 +206,6 @@ __device__ void icm_pair(uint32_t *sp, const uint4 *recj, int n, int ba, int bb,
     __syncthreads();
 }
 
-// Last work-group to finish advances the device counters (every work-group
-// read them at its start).  bump: bit0 sweeps += n_sweeps, bit1 ICM calls += 1,
-// bit2 swap attempts += 1, bit3 cycles += 1.
-__device__ __forceinline__ void finish_and_bump(uint32_t *ctr, int n_blocks, int bump, int n_sweeps)
-{
-    if (!bump) return;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t prev = atomicAdd(&ctr[4], 1u);
-        if (prev == (uint32_t)(n_blocks - 1)) {
-            if (bump & 1) ctr[0] += (uint32_t)n_sweeps;
-            if (bump & 2) ctr[1] += 1u;
-            if (bump & 4) ctr[2] += 1u;
-            if (bump & 8) ctr[3] += 1u;
-            ctr[4] = 0u;
-            __threadfence();
-        }
-    }
-}
-
 // Houdayer move on rows of lx <= 32 sites: the overlap set Q and the cluster
 // V are bit rows; one propagation step adds every Q site next to V through a
 // bond with J != 0, until nothing changes.  Same result as a breadth-first
@@ -321,23 +300,17 @@ __device__ void icm_pair_rows(uint32_t *sp, const uint4 *rowA, const uint4 *rowB
     __syncthreads();
 }
 
-__device__ __forceinline__ int32_t load_agent(const int32_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Replica exchange (Eq. 4) for one instance, run by one work-group of any
-// size.  An accepted exchange swaps the logical->physical mapping of the two
-// slots and their energies; the random word is keyed by the logical pair, so
-// this is the same chain as exchanging the states.  Energies and the mapping
-// are read with device-scope loads: other work-groups wrote them in this launch.
+// Replica exchange (Eq. 4) for one instance, run by one work-group.  An
+// accepted exchange swaps the logical->physical mapping of the two slots and
+// their energies; the random word is keyed by the logical pair, so this is the
+// same chain as exchanging the states.
 __device__ void swap_instance(const SwapArgs &A, int inst, int32_t *red)
 {
     const InstDev &I = A.inst[inst];
     const int R = A.reps, nb = A.n_beta;
     const int npt = (nb - 1) * R;
-    const uint32_t a = A.ctr[2] + 1u;
-    const uint32_t cyc = A.ctr[3] + 1u;
+    const uint32_t a = A.ctr[2] + (uint32_t)A.cyc_k + 1u;
+    const uint32_t cyc = A.ctr[3] + (uint32_t)A.cyc_k + 1u;
     int32_t *perm = A.perm + I.slot_off;
     int32_t *E = A.E + I.slot_off;
     const int nt = blockDim.x;
@@ -348,7 +321,7 @@ __device__ void swap_instance(const SwapArgs &A, int inst, int32_t *red)
     for (int idx = threadIdx.x; idx < npairs * R; idx += nt) {
         const int b = first + 2 * (idx / R), l = idx - (idx / R) * R;
         const int s0 = b * R + l, s1 = s0 + R;
-        const int32_t e0 = load_agent(E + s0), e1 = load_agent(E + s1);
+        const int32_t e0 = E[s0], e1 = E[s1];
         const int32_t dE = e1 - e0;
         int acc;
         if (dE >= 0) {
@@ -365,7 +338,7 @@ __device__ void swap_instance(const SwapArgs &A, int inst, int32_t *red)
             }
         }
         if (acc) {
-            const int32_t p0 = load_agent(perm + s0), p1 = load_agent(perm + s1);
+            const int32_t p0 = perm[s0], p1 = perm[s1];
             perm[s0] = p1;
             perm[s1] = p0;
             E[s0] = e1;
@@ -376,7 +349,7 @@ __device__ void swap_instance(const SwapArgs &A, int inst, int32_t *red)
     }
     __syncthreads();
     int32_t m = 0x7FFFFFFF;
-    for (int s = threadIdx.x; s < nb * R; s += nt) m = min(m, load_agent(E + s));
+    for (int s = threadIdx.x; s < nb * R; s += nt) m = min(m, E[s]);
     m = wave_min(m);
     if ((threadIdx.x & 63) == 0) red[20 + (threadIdx.x >> 6)] = m;
     __syncthreads();
@@ -462,7 +435,7 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
         if (tid < 4) sp[npad + tid] = 0u;
         __syncthreads();
 
-        const uint32_t t0 = A.ctr[0];
+        const uint32_t t0 = A.ctr[0] + (uint32_t)(A.cyc_k * A.n_sweeps);
         const uint32_t c3 = ((uint32_t)D.inst << 4) | A.tag;
         for (int sw = 0; sw < A.n_sweeps; ++sw) {
             const uint32_t t = t0 + (uint32_t)sw;
@@ -499,7 +472,7 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
         }
 
         if (A.do_icm && A.reps >= 2) {
-            const uint32_t a = A.ctr[1] + 1u;
+            const uint32_t a = A.ctr[1] + (uint32_t)A.cyc_k + 1u;
             const int n_beta = I.n_slots / A.reps;
             const int npair = A.reps / 2;
             const uint4 *recj = A.rec_j + I.recj_off;
@@ -567,22 +540,6 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
             }
         }
     }
-    if (A.fuse_swap && D.inst >= 0) {
-        // the last of the instance's work-groups exchanges its replicas
-        __shared__ int last;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            __threadfence();
-            last = atomicAdd(&A.inst_done[D.inst], 1u) == (uint32_t)(A.n_quads - 1);
-            if (last) {
-                A.inst_done[D.inst] = 0u;
-                __threadfence();
-            }
-        }
-        __syncthreads();
-        if (last) swap_instance(A.sw, D.inst, (int32_t *)(lds + 0));
-    }
-    finish_and_bump(A.ctr, A.n_blocks, A.bump, A.n_sweeps);
 }
 
 // ---------------------------------------------------------------------------
@@ -592,7 +549,6 @@ __global__ __launch_bounds__(64) void apt_swap_kernel(SwapArgs A)
 {
     __shared__ int32_t red[32];
     swap_instance(A, blockIdx.x, red);
-    finish_and_bump(A.ctr, A.n_inst, A.bump, A.sweeps_per_cycle);
 }
 
 // ---------------------------------------------------------------------------
@@ -751,6 +707,16 @@ __global__ __launch_bounds__(kSqaThreads) void sqa_kernel(SqaArgs A)
     }
 }
 
+__global__ void advance_kernel(uint32_t *ctr, uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctr[0] += d0;
+        ctr[1] += d1;
+        ctr[2] += d2;
+        ctr[3] += d3;
+    }
+}
+
 __global__ void fill_i64_kernel(int64_t *p, int64_t v, int64_t n)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -808,6 +774,13 @@ hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, hipStream_
     hipError_t e = allow_lds((const void *)sqa_kernel, lds_bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sqa_kernel, dim3(n_inst * a.R), dim3(kSqaThreads), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(uint32_t *ctr, uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, ctr, d0, d1, d2, d3);
     return hipGetLastError();
 }
 
