@@ -396,7 +396,7 @@ void apt_rows(const Lat &L, std::vector<uint4> &rowA, std::vector<uint4> &rowB, 
 {
     I.lx = L.Lx;
     I.n_rows = L.Ly * L.Lz;
-    if (L.Lx > 32) {
+    if (L.Lx > 32 || I.n_rows > kQuadThreads * 4) {   // rows of one word, <= 4 rows per thread
         I.row_off = -1;
         return;
     }
@@ -430,9 +430,10 @@ std::vector<QuadDesc> make_quad_descs(const std::vector<Lat> &lat, int n_quads)
     for (int i = 0; i < ni; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lat[a].n > lat[b].n; });
     std::vector<QuadDesc> out;
+    // within an instance the last quads hold the largest betas, where ICM runs: start them first
     if (ni < 8) {
         for (int i : order)
-            for (int q = 0; q < n_quads; ++q) out.push_back({i, q});
+            for (int q = n_quads - 1; q >= 0; --q) out.push_back({i, q});
         return out;
     }
     const int X = 8;
@@ -441,7 +442,7 @@ std::vector<QuadDesc> make_quad_descs(const std::vector<Lat> &lat, int n_quads)
     for (int i : order) {
         const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         load[x] += (int64_t)lat[i].n;
-        for (int q = 0; q < n_quads; ++q) qs[x].push_back({i, q});
+        for (int q = n_quads - 1; q >= 0; --q) qs[x].push_back({i, q});
     }
     size_t len = 0;
     for (auto &v : qs) len = std::max(len, v.size());
@@ -557,7 +558,7 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
     c->quad_lds = 0;
     for (auto &I : c->idev) {
         const size_t need = sizeof(uint32_t) * (size_t)(I.npad + 4 + 4 * c->ni + 32 + (I.npad + 31) / 32 + 1 +
-                                                        2 * I.n_rows) +
+                                                        4 * I.n_rows) +
                             sizeof(uint16_t) * (size_t)I.npad + 16;
         c->quad_lds = std::max(c->quad_lds, need);
     }
@@ -712,7 +713,8 @@ void create_sqa(sg_ctx *c, const sg_config *cfg)
     c->d_slice_E.alloc((size_t)c->n_inst * c->R * c->M, "slice energies");
     c->d_ctr.alloc(8, "counters");
     hip_check(launch_fill_u32(c->d_ctr.p, 0u, 8, s), "init");
-    c->sqa_lds = sizeof(uint32_t) * (size_t)(2 * (npad_max + 1) + c->nl + 2 * 64 + 5 * 16) + 16;
+    if (c->nl > 256) fail(SG_EUNSUPPORTED, "field range too large for the threshold table");
+    c->sqa_lds = sizeof(uint32_t) * (size_t)(464 + 2 * (npad_max + 1)) + 16;
     if (c->sqa_lds > kMaxLds)
         fail(SG_EUNSUPPORTED, "instance too large for one work-group's LDS (%zu bytes)", c->sqa_lds);
     SqaArgs a{};

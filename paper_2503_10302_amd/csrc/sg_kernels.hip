@@ -206,98 +206,132 @@ __device__ void icm_pair(uint32_t *sp, const uint4 *recj, int n, int ba, int bb,
     __syncthreads();
 }
 
-// Houdayer move on rows of lx <= 32 sites: the overlap set Q and the cluster
-// V are bit rows; one propagation step adds every Q site next to V through a
-// bond with J != 0, until nothing changes.  Same result as a breadth-first
-// search from the seed, with no global memory traffic inside the loop.
-// LDS: Qr[n_rows], Vr[n_rows], red[>= 24].
-__device__ void icm_pair_rows(uint32_t *sp, const uint4 *rowA, const uint4 *rowB, int n, int lx,
-                              int nrows, int ba, int bb, uint32_t w0, uint32_t w1, uint32_t *Qr,
-                              uint32_t *Vr, int32_t *red, int32_t *info)
+// Houdayer moves on up to two replica pairs at once, on rows of lx <= 32
+// sites (Algorithm S2, ICMop).  The overlap set Q and the cluster V of each
+// pair are bit rows; one propagation step adds every Q site next to V through
+// a bond with J != 0, until no row of either pair changes.  This reaches the
+// same connected component as a breadth-first search from the seed.  Each
+// thread owns at most kRowsPerThread consecutive rows, whose bond masks stay in
+// registers.  LDS: Qr[2][n_rows], Vr[2][n_rows], red[>= 24].
+constexpr int kRowsPerThread = 4;
+
+__device__ void icm_pairs_rows(uint32_t *sp, const uint4 *rowA, const uint4 *rowB, int n, int lx,
+                               int nrows, int np, const int *ba, const int *bb, const uint32_t *w0,
+                               const uint32_t *w1, uint32_t *Qr, uint32_t *Vr, int32_t *red,
+                               int32_t *const *info)
 {
     const int tid = threadIdx.x;
-    const uint32_t mA = 1u << (8 * ba), mB = 1u << (8 * bb);
     const int rpt = (nrows + kQuadThreads - 1) / kQuadThreads;
     const int r0 = min(nrows, tid * rpt), r1 = min(nrows, r0 + rpt);
-    int32_t cnt = 0;
-    for (int r = r0; r < r1; ++r) {
-        uint32_t q = 0u;
+    const int nr = r1 - r0;
+    uint32_t mA[2], mB[2];
+    int32_t cnt[2] = {0, 0};
+    for (int p = 0; p < np; ++p) {
+        mA[p] = 1u << (8 * ba[p]);
+        mB[p] = 1u << (8 * bb[p]);
+    }
+    uint4 ra[kRowsPerThread], rb[kRowsPerThread];
+#pragma unroll
+    for (int i = 0; i < kRowsPerThread; ++i)
+        if (i < nr) {
+            ra[i] = rowA[r0 + i];
+            rb[i] = rowB[r0 + i];
+        }
+#pragma unroll
+    for (int i = 0; i < kRowsPerThread; ++i) {
+        if (i >= nr) continue;
+        const int r = r0 + i;
+        uint32_t q[2] = {0u, 0u};
         const uint32_t *row = sp + r * lx;
         for (int x = 0; x < lx; ++x) {
             const uint32_t w = row[x];
-            q |= (uint32_t)(((w & mA) != 0) != ((w & mB) != 0)) << x;
+            for (int p = 0; p < np; ++p)
+                q[p] |= (uint32_t)(((w & mA[p]) != 0) != ((w & mB[p]) != 0)) << x;
         }
-        Qr[r] = q;
-        Vr[r] = 0u;
-        cnt += __popc(q);
+        for (int p = 0; p < np; ++p) {
+            Qr[p * nrows + r] = q[p];
+            Vr[p * nrows + r] = 0u;
+            cnt[p] += __popc(q[p]);
+        }
     }
-    int32_t m;
-    const int32_t prefix = block_exclusive_scan(cnt, red, &m);
-    if (m == 0) {
-        if (tid == 0 && info) { info[0] = 0; info[1] = -1; info[2] = 0; info[3] = 0; }
-        __syncthreads();
-        return;
-    }
-    const int32_t k = (int32_t)(((uint64_t)w0 * (uint64_t)(uint32_t)m) >> 32);
-    if (prefix <= k && k < prefix + cnt) {
-        int32_t c = prefix;
-        for (int r = r0; r < r1; ++r) {
-            uint32_t q = Qr[r];
-            const int32_t pc = __popc(q);
-            if (k < c + pc) {
-                for (int32_t i = 0; i < k - c; ++i) q &= q - 1u;
-                const int x = __builtin_ctz(q);
-                Vr[r] = 1u << x;
-                red[16] = r * lx + x;
-                break;
+    int32_t m[2] = {0, 0}, seed[2] = {-1, -1};
+    for (int p = 0; p < np; ++p) {
+        const int32_t prefix = block_exclusive_scan(cnt[p], red, &m[p]);
+        if (m[p] == 0) continue;
+        const int32_t k = (int32_t)(((uint64_t)w0[p] * (uint64_t)(uint32_t)m[p]) >> 32);
+        if (prefix <= k && k < prefix + cnt[p]) {
+            int32_t c = prefix;
+            for (int r = r0; r < r1; ++r) {
+                uint32_t qq = Qr[p * nrows + r];
+                const int32_t pc = __popc(qq);
+                if (k < c + pc) {
+                    for (int32_t i = 0; i < k - c; ++i) qq &= qq - 1u;
+                    const int x = __builtin_ctz(qq);
+                    Vr[p * nrows + r] = 1u << x;
+                    red[16 + p] = r * lx + x;
+                    break;
+                }
+                c += pc;
             }
-            c += pc;
         }
     }
     __syncthreads();
-    const int32_t seed = red[16];
+    for (int p = 0; p < np; ++p)
+        if (m[p] > 0) seed[p] = red[16 + p];
     const uint32_t hi = (uint32_t)(lx - 1);
     while (true) {
         int changed = 0;
-        for (int r = r0; r < r1; ++r) {
-            const uint4 a = rowA[r], b = rowB[r];
-            const uint32_t V = Vr[r];
-            const uint32_t right = (V >> 1) | (V << hi);   // bit x <- site x+1 (mod lx)
-            const uint32_t left = (V << 1) | (V >> hi);    // bit x <- site x-1 (mod lx)
-            const uint32_t N = (right & a.x) | (left & a.y) | (Vr[b.z & 0xFFFFu] & a.z) |
-                               (Vr[b.z >> 16] & a.w) | (Vr[b.w & 0xFFFFu] & b.x) |
-                               (Vr[b.w >> 16] & b.y);
-            const uint32_t Vn = V | (N & Qr[r]);
-            if (Vn != V) {
-                Vr[r] = Vn;
-                changed = 1;
+#pragma unroll
+        for (int i = 0; i < kRowsPerThread; ++i) {
+            if (i >= nr) continue;
+            const int r = r0 + i;
+            for (int p = 0; p < np; ++p) {
+                if (m[p] == 0) continue;
+                const uint32_t *Vp = Vr + p * nrows;
+                const uint32_t V = Vp[r];
+                const uint32_t right = (V >> 1) | (V << hi);   // bit x <- site x+1 (mod lx)
+                const uint32_t left = (V << 1) | (V >> hi);    // bit x <- site x-1 (mod lx)
+                const uint32_t N = (right & ra[i].x) | (left & ra[i].y) |
+                                   (Vp[rb[i].z & 0xFFFFu] & ra[i].z) | (Vp[rb[i].z >> 16] & ra[i].w) |
+                                   (Vp[rb[i].w & 0xFFFFu] & rb[i].x) | (Vp[rb[i].w >> 16] & rb[i].y);
+                const uint32_t Vn = V | (N & Qr[p * nrows + r]);
+                if (Vn != V) {
+                    Vr[p * nrows + r] = Vn;
+                    changed = 1;
+                }
             }
         }
         if (!__syncthreads_or(changed)) break;
     }
-    int32_t sz = 0;
-    for (int r = r0; r < r1; ++r) sz += __popc(Vr[r]);
-    int32_t tot[4] = {sz, 0, 0, 0};
+    int32_t tot[4] = {0, 0, 0, 0};
+    for (int p = 0; p < np; ++p)
+        for (int r = r0; r < r1; ++r) tot[p] += __popc(Vr[p * nrows + r]);
     block_sum4(tot, red);
-    const int32_t size = tot[0];
-    int32_t branch;
-    if (2 * size > n) {
-        const uint32_t X = ((w1 >> 31) == 0u) ? mA : mB;
-        branch = ((w1 >> 31) == 0u) ? 1 : 2;
-        for (int j = tid; j < n; j += kQuadThreads) sp[j] ^= X;
-    } else {
-        branch = 0;
-        for (int r = r0; r < r1; ++r) {
-            uint32_t bits = Vr[r];
-            while (bits) {
-                const int x = __builtin_ctz(bits);
-                sp[r * lx + x] ^= (mA | mB);
-                bits &= bits - 1u;
+    for (int p = 0; p < np; ++p) {
+        int32_t branch = 0;
+        if (m[p] > 0) {
+            if (2 * tot[p] > n) {
+                const uint32_t X = ((w1[p] >> 31) == 0u) ? mA[p] : mB[p];
+                branch = ((w1[p] >> 31) == 0u) ? 1 : 2;
+                for (int j = tid; j < n; j += kQuadThreads) sp[j] ^= X;
+            } else {
+                for (int r = r0; r < r1; ++r) {
+                    uint32_t bits = Vr[p * nrows + r];
+                    while (bits) {
+                        const int x = __builtin_ctz(bits);
+                        sp[r * lx + x] ^= (mA[p] | mB[p]);
+                        bits &= bits - 1u;
+                    }
+                }
             }
         }
+        if (tid == 0 && info[p]) {
+            int32_t *o = info[p];
+            if (m[p] == 0) { o[0] = 0; o[1] = -1; o[2] = 0; o[3] = 0; }
+            else { o[0] = m[p]; o[1] = seed[p]; o[2] = tot[p]; o[3] = branch; }
+        }
+        __syncthreads();
     }
-    if (tid == 0 && info) { info[0] = m; info[1] = seed; info[2] = size; info[3] = branch; }
-    __syncthreads();
 }
 
 // Replica exchange (Eq. 4) for one instance, run by one work-group.  An
@@ -407,9 +441,9 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
         uint32_t *lut = sp + npad + 4;                   // 4 * ni
         int32_t *red = (int32_t *)(lut + 4 * ni);        // 32
         uint32_t *vis = (uint32_t *)(red + 32);          // (npad + 31) / 32 + 1
-        uint32_t *Qr = vis + ((npad + 31) >> 5) + 1;     // n_rows
-        uint32_t *Vr = Qr + I.n_rows;                    // n_rows
-        uint16_t *queue = (uint16_t *)(Vr + I.n_rows);   // npad
+        uint32_t *Qr = vis + ((npad + 31) >> 5) + 1;     // 2 * n_rows
+        uint32_t *Vr = Qr + 2 * I.n_rows;                // 2 * n_rows
+        uint16_t *queue = (uint16_t *)(Vr + 2 * I.n_rows);   // npad
         const int q = D.quad;
         const int32_t *pp = A.perm + I.slot_off + 4 * q;
         const int64_t b0 = (int64_t)pp[0] * npad, b1 = (int64_t)pp[1] * npad;
@@ -499,15 +533,25 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
                     np = 2;
                 }
             }
-            for (int k2 = 0; k2 < np; ++k2) {
-                const uint4 w = philox10((uint32_t)pidx[k2], a, 0u,
-                                         ((uint32_t)D.inst << 4) | TAG_ICM_PICK, A.key0, A.key1);
-                int32_t *info = A.icm_info + ((int64_t)I.info_off + pidx[k2]) * 4;
-                if (I.row_off >= 0)
-                    icm_pair_rows(sp, A.rowA + I.row_off, A.rowB + I.row_off, n, I.lx, I.n_rows,
-                                  pa[k2], pb[k2], w.x, w.y, Qr, Vr, red, info);
-                else
-                    icm_pair(sp, recj, n, pa[k2], pb[k2], w.x, w.y, queue, vis, red, info);
+            if (np > 0 && I.row_off >= 0) {
+                uint32_t w0[2], w1[2];
+                int32_t *info[2];
+                for (int k2 = 0; k2 < np; ++k2) {
+                    const uint4 w = philox10((uint32_t)pidx[k2], a, 0u,
+                                             ((uint32_t)D.inst << 4) | TAG_ICM_PICK, A.key0, A.key1);
+                    w0[k2] = w.x;
+                    w1[k2] = w.y;
+                    info[k2] = A.icm_info + ((int64_t)I.info_off + pidx[k2]) * 4;
+                }
+                icm_pairs_rows(sp, A.rowA + I.row_off, A.rowB + I.row_off, n, I.lx, I.n_rows, np, pa,
+                               pb, w0, w1, Qr, Vr, red, info);
+            } else {
+                for (int k2 = 0; k2 < np; ++k2) {
+                    const uint4 w = philox10((uint32_t)pidx[k2], a, 0u,
+                                             ((uint32_t)D.inst << 4) | TAG_ICM_PICK, A.key0, A.key1);
+                    icm_pair(sp, recj, n, pa[k2], pb[k2], w.x, w.y, queue, vis, red,
+                             A.icm_info + ((int64_t)I.info_off + pidx[k2]) * 4);
+                }
             }
             (void)pbeta;
         }
@@ -599,14 +643,16 @@ __global__ __launch_bounds__(kSqaThreads) void sqa_kernel(SqaArgs A)
     const int tid = threadIdx.x;
     const int n = I.n, npad = I.npad, H = A.H;
     const uint32_t mask = (H >= 32) ? 0xFFFFFFFFu : ((1u << H) - 1u);
-    uint32_t *sp = lds;                         // 2 * (npad + 1)
-    uint32_t *lut = sp + 2 * (npad + 1);        // nl
-    int32_t *red = (int32_t *)(lut + A.nl);     // 2 * 64
+    // Fixed-offset tables first (constant LDS addresses): thresholds (<= 256
+    // entries), spread tables, reduction scratch; then the replica.
+    uint32_t *lut = lds;                        // 256
     // Spread tables: for a 4-bit slice group of one bit plane, the plane's
     // contribution to the four threshold indices, one byte per slice.  Index
     // weights: 6, 12, 24 for the aligned-neighbour count bits, 1, 2 for the
     // number of up Trotter neighbours (table index = 6 k + t + 3 (h - d + smax)).
-    uint32_t *spread = (uint32_t *)(red + 128); // 5 * 16
+    uint32_t *spread = lds + 256;               // 5 * 16
+    int32_t *red = (int32_t *)(lds + 336);      // 2 * 64
+    uint32_t *sp = lds + 464;                   // 2 * (npad + 1)
     uint32_t *g = A.spins + I.spin_off + (int64_t)r * npad * 2;
     for (int i = tid; i < 2 * npad; i += kSqaThreads) sp[i] = g[i];
     if (tid < 2) sp[2 * npad + tid] = 0u;
@@ -662,10 +708,11 @@ __global__ __launch_bounds__(kSqaThreads) void sqa_kernel(SqaArgs A)
                                           spread[64 + ((t1b >> sh) & 15u)] + base4;
                     const uint4 u = philox10(j, t, ((uint32_t)r << 16) | (p << 15) | (uint32_t)gq,
                                              c3, A.key0, A.key1);
-                    uint32_t b4 = (u.x < lut[idx4 & 0xFFu]) ? 1u : 0u;
-                    b4 |= (u.y < lut[(idx4 >> 8) & 0xFFu]) ? 2u : 0u;
-                    b4 |= (u.z < lut[(idx4 >> 16) & 0xFFu]) ? 4u : 0u;
-                    b4 |= (u.w < lut[idx4 >> 24]) ? 8u : 0u;
+                    const uint8_t *lb = (const uint8_t *)lut;   // byte addressing: idx * 4
+                    uint32_t b4 = (u.x < *(const uint32_t *)(lb + ((idx4 << 2) & 0x3FCu))) ? 1u : 0u;
+                    b4 |= (u.y < *(const uint32_t *)(lb + ((idx4 >> 6) & 0x3FCu))) ? 2u : 0u;
+                    b4 |= (u.z < *(const uint32_t *)(lb + ((idx4 >> 14) & 0x3FCu))) ? 4u : 0u;
+                    b4 |= (u.w < *(const uint32_t *)(lb + ((idx4 >> 22) & 0x3FCu))) ? 8u : 0u;
                     res |= b4 << sh;
                 }
                 sp[2 * j + p] = res & mask;
