@@ -107,8 +107,10 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *red,
 __device__ void quad_energy(const uint32_t *sp, const uint4 *recj, int n, int32_t *red, int32_t e[4])
 {
     int32_t acc[4] = {0, 0, 0, 0};
+    uint4 rnext = ((int)threadIdx.x < n) ? recj[threadIdx.x] : make_uint4(0u, 0u, 0u, 0u);
     for (int j = threadIdx.x; j < n; j += kQuadThreads) {
-        const uint4 r = recj[j];
+        const uint4 r = rnext;
+        if (j + kQuadThreads < n) rnext = recj[j + kQuadThreads];   // prefetch
         const uint32_t k = aligned_count(sp, r);
         const int32_t d = (int32_t)((r.x >> 16) & 7u);
         const int32_t hh = (int32_t)((r.x >> 25) & 63u) - 32;
@@ -211,55 +213,59 @@ __device__ void icm_pair(uint32_t *sp, const uint4 *recj, int n, int ba, int bb,
 // pair are bit rows; one propagation step adds every Q site next to V through
 // a bond with J != 0, until no row of either pair changes.  This reaches the
 // same connected component as a breadth-first search from the seed.  Each
-// thread owns at most kRowsPerThread consecutive rows, whose bond masks stay in
+// thread owns consecutive rows; the bond masks of its first row stay in
 // registers.  LDS: Qr[2][n_rows], Vr[2][n_rows], red[>= 24].
-constexpr int kRowsPerThread = 4;
+// Pair p uses bytes (pa >> 8p) & 3 and (pb >> 8p) & 3 of the site words.
+
+__device__ __forceinline__ uint32_t row_step(const uint32_t *Vp, int r, uint32_t hi, const uint4 a,
+                                             const uint4 b, uint32_t Q)
+{
+    const uint32_t V = Vp[r];
+    const uint32_t right = (V >> 1) | (V << hi);   // bit x <- site x+1 (mod lx)
+    const uint32_t left = (V << 1) | (V >> hi);    // bit x <- site x-1 (mod lx)
+    const uint32_t N = (right & a.x) | (left & a.y) | (Vp[b.z & 0xFFFFu] & a.z) |
+                       (Vp[b.z >> 16] & a.w) | (Vp[b.w & 0xFFFFu] & b.x) | (Vp[b.w >> 16] & b.y);
+    return V | (N & Q);
+}
 
 __device__ void icm_pairs_rows(uint32_t *sp, const uint4 *rowA, const uint4 *rowB, int n, int lx,
-                               int nrows, int np, const int *ba, const int *bb, const uint32_t *w0,
-                               const uint32_t *w1, uint32_t *Qr, uint32_t *Vr, int32_t *red,
-                               int32_t *const *info)
+                               int nrows, int np, uint32_t pa, uint32_t pb, uint4 w01,
+                               uint32_t *Qr, uint32_t *Vr, int32_t *red, int32_t *info0,
+                               int32_t *info1)
 {
     const int tid = threadIdx.x;
     const int rpt = (nrows + kQuadThreads - 1) / kQuadThreads;
     const int r0 = min(nrows, tid * rpt), r1 = min(nrows, r0 + rpt);
-    const int nr = r1 - r0;
-    uint32_t mA[2], mB[2];
-    int32_t cnt[2] = {0, 0};
-    for (int p = 0; p < np; ++p) {
-        mA[p] = 1u << (8 * ba[p]);
-        mB[p] = 1u << (8 * bb[p]);
-    }
-    uint4 ra[kRowsPerThread], rb[kRowsPerThread];
-#pragma unroll
-    for (int i = 0; i < kRowsPerThread; ++i)
-        if (i < nr) {
-            ra[i] = rowA[r0 + i];
-            rb[i] = rowB[r0 + i];
-        }
-#pragma unroll
-    for (int i = 0; i < kRowsPerThread; ++i) {
-        if (i >= nr) continue;
-        const int r = r0 + i;
-        uint32_t q[2] = {0u, 0u};
+    const uint32_t mA0 = 1u << (8 * (pa & 3u)), mB0 = 1u << (8 * (pb & 3u));
+    const uint32_t mA1 = 1u << (8 * ((pa >> 8) & 3u)), mB1 = 1u << (8 * ((pb >> 8) & 3u));
+    int32_t c0 = 0, c1 = 0;
+    for (int r = r0; r < r1; ++r) {
+        uint32_t q0 = 0u, q1 = 0u;
         const uint32_t *row = sp + r * lx;
         for (int x = 0; x < lx; ++x) {
             const uint32_t w = row[x];
-            for (int p = 0; p < np; ++p)
-                q[p] |= (uint32_t)(((w & mA[p]) != 0) != ((w & mB[p]) != 0)) << x;
+            q0 |= (uint32_t)(((w & mA0) != 0) != ((w & mB0) != 0)) << x;
+            q1 |= (uint32_t)(((w & mA1) != 0) != ((w & mB1) != 0)) << x;
         }
-        for (int p = 0; p < np; ++p) {
-            Qr[p * nrows + r] = q[p];
-            Vr[p * nrows + r] = 0u;
-            cnt[p] += __popc(q[p]);
+        Qr[r] = q0;
+        Vr[r] = 0u;
+        c0 += __popc(q0);
+        if (np > 1) {
+            Qr[nrows + r] = q1;
+            Vr[nrows + r] = 0u;
+            c1 += __popc(q1);
         }
     }
-    int32_t m[2] = {0, 0}, seed[2] = {-1, -1};
+    int32_t m0, m1 = 0;
     for (int p = 0; p < np; ++p) {
-        const int32_t prefix = block_exclusive_scan(cnt[p], red, &m[p]);
-        if (m[p] == 0) continue;
-        const int32_t k = (int32_t)(((uint64_t)w0[p] * (uint64_t)(uint32_t)m[p]) >> 32);
-        if (prefix <= k && k < prefix + cnt[p]) {
+        const int32_t cnt = p ? c1 : c0;
+        int32_t m;
+        const int32_t prefix = block_exclusive_scan(cnt, red, &m);
+        if (p) m1 = m; else m0 = m;
+        if (m == 0) continue;
+        const uint32_t w = p ? w01.z : w01.x;
+        const int32_t k = (int32_t)(((uint64_t)w * (uint64_t)(uint32_t)m) >> 32);
+        if (prefix <= k && k < prefix + cnt) {
             int32_t c = prefix;
             for (int r = r0; r < r1; ++r) {
                 uint32_t qq = Qr[p * nrows + r];
@@ -276,59 +282,62 @@ __device__ void icm_pairs_rows(uint32_t *sp, const uint4 *rowA, const uint4 *row
         }
     }
     __syncthreads();
-    for (int p = 0; p < np; ++p)
-        if (m[p] > 0) seed[p] = red[16 + p];
+    const int32_t seed0 = m0 > 0 ? red[16] : -1;
+    const int32_t seed1 = (np > 1 && m1 > 0) ? red[17] : -1;
     const uint32_t hi = (uint32_t)(lx - 1);
+    const bool act0 = m0 > 0, act1 = np > 1 && m1 > 0;
+    uint4 a0 = make_uint4(0u, 0u, 0u, 0u), b0 = a0;
+    if (r0 < r1) {
+        a0 = rowA[r0];
+        b0 = rowB[r0];
+    }
     while (true) {
         int changed = 0;
-#pragma unroll
-        for (int i = 0; i < kRowsPerThread; ++i) {
-            if (i >= nr) continue;
-            const int r = r0 + i;
-            for (int p = 0; p < np; ++p) {
-                if (m[p] == 0) continue;
-                const uint32_t *Vp = Vr + p * nrows;
-                const uint32_t V = Vp[r];
-                const uint32_t right = (V >> 1) | (V << hi);   // bit x <- site x+1 (mod lx)
-                const uint32_t left = (V << 1) | (V >> hi);    // bit x <- site x-1 (mod lx)
-                const uint32_t N = (right & ra[i].x) | (left & ra[i].y) |
-                                   (Vp[rb[i].z & 0xFFFFu] & ra[i].z) | (Vp[rb[i].z >> 16] & ra[i].w) |
-                                   (Vp[rb[i].w & 0xFFFFu] & rb[i].x) | (Vp[rb[i].w >> 16] & rb[i].y);
-                const uint32_t Vn = V | (N & Qr[p * nrows + r]);
-                if (Vn != V) {
-                    Vr[p * nrows + r] = Vn;
-                    changed = 1;
-                }
+        for (int r = r0; r < r1; ++r) {
+            const uint4 a = (r == r0) ? a0 : rowA[r];
+            const uint4 b = (r == r0) ? b0 : rowB[r];
+            if (act0) {
+                const uint32_t Vn = row_step(Vr, r, hi, a, b, Qr[r]);
+                if (Vn != Vr[r]) { Vr[r] = Vn; changed = 1; }
+            }
+            if (act1) {
+                const uint32_t Vn = row_step(Vr + nrows, r, hi, a, b, Qr[nrows + r]);
+                if (Vn != Vr[nrows + r]) { Vr[nrows + r] = Vn; changed = 1; }
             }
         }
         if (!__syncthreads_or(changed)) break;
     }
     int32_t tot[4] = {0, 0, 0, 0};
-    for (int p = 0; p < np; ++p)
-        for (int r = r0; r < r1; ++r) tot[p] += __popc(Vr[p * nrows + r]);
+    for (int r = r0; r < r1; ++r) {
+        tot[0] += __popc(Vr[r]);
+        if (np > 1) tot[1] += __popc(Vr[nrows + r]);
+    }
     block_sum4(tot, red);
     for (int p = 0; p < np; ++p) {
+        const int32_t m = p ? m1 : m0, size = tot[p];
+        const uint32_t mA = p ? mA1 : mA0, mB = p ? mB1 : mB0;
+        const uint32_t w1 = p ? w01.w : w01.y;
         int32_t branch = 0;
-        if (m[p] > 0) {
-            if (2 * tot[p] > n) {
-                const uint32_t X = ((w1[p] >> 31) == 0u) ? mA[p] : mB[p];
-                branch = ((w1[p] >> 31) == 0u) ? 1 : 2;
+        if (m > 0) {
+            if (2 * size > n) {
+                const uint32_t X = ((w1 >> 31) == 0u) ? mA : mB;
+                branch = ((w1 >> 31) == 0u) ? 1 : 2;
                 for (int j = tid; j < n; j += kQuadThreads) sp[j] ^= X;
             } else {
                 for (int r = r0; r < r1; ++r) {
                     uint32_t bits = Vr[p * nrows + r];
                     while (bits) {
                         const int x = __builtin_ctz(bits);
-                        sp[r * lx + x] ^= (mA[p] | mB[p]);
+                        sp[r * lx + x] ^= (mA | mB);
                         bits &= bits - 1u;
                     }
                 }
             }
         }
-        if (tid == 0 && info[p]) {
-            int32_t *o = info[p];
-            if (m[p] == 0) { o[0] = 0; o[1] = -1; o[2] = 0; o[3] = 0; }
-            else { o[0] = m[p]; o[1] = seed[p]; o[2] = tot[p]; o[3] = branch; }
+        int32_t *o = p ? info1 : info0;
+        if (tid == 0 && o) {
+            if (m == 0) { o[0] = 0; o[1] = -1; o[2] = 0; o[3] = 0; }
+            else { o[0] = m; o[1] = p ? seed1 : seed0; o[2] = size; o[3] = branch; }
         }
         __syncthreads();
     }
@@ -476,8 +485,10 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
             for (int c = 0; c < I.n_colours; ++c) {
                 const uint4 *rc = A.rec_col + I.rec_off + A.inst[D.inst].col_off[c];
                 const int cnt = A.inst[D.inst].col_cnt[c];
+                uint4 rnext = (tid < cnt) ? rc[tid] : make_uint4(0u, 0u, 0u, 0u);
                 for (int i = tid; i < cnt; i += kQuadThreads) {
-                    const uint4 r = rc[i];
+                    const uint4 r = rnext;
+                    if (i + kQuadThreads < cnt) rnext = rc[i + kQuadThreads];   // prefetch
                     const uint32_t j = r.x & 0xFFFFu;
                     const uint32_t k = aligned_count(sp, r);
                     const int32_t base = (int32_t)((r.x >> 25) & 63u) - 32 -
@@ -510,50 +521,52 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
             const int n_beta = I.n_slots / A.reps;
             const int npair = A.reps / 2;
             const uint4 *recj = A.rec_j + I.recj_off;
-            int pa[2], pb[2], pbeta[2], pidx[2], np = 0;
-            uint32_t wpick = 0u;
+            // up to two pairs in this tile: bytes (pa, pb) and their record / random-word indices
+            uint32_t pa = 0u, pb = 0u;
+            int np = 0, pidx0 = 0, pidx1 = 0;
             if (A.reps == 2) {
                 for (int half = 0; half < 2; ++half) {
                     const int b = 2 * q + half;
                     if (b >= n_beta || !A.icm_on[D.inst * n_beta + b]) continue;
-                    pa[np] = 2 * half; pb[np] = 2 * half + 1; pbeta[np] = b; pidx[np] = b; ++np;
+                    pa |= (uint32_t)(2 * half) << (8 * np);
+                    pb |= (uint32_t)(2 * half + 1) << (8 * np);
+                    if (np) pidx1 = b; else pidx0 = b;
+                    ++np;
                 }
             } else if (A.reps == 4) {
                 const int b = q;
                 if (b < n_beta && A.icm_on[D.inst * n_beta + b]) {
-                    wpick = philox10((uint32_t)b, a, 0u, ((uint32_t)D.inst << 4) | TAG_ICM_PAIR,
-                                     A.key0, A.key1).x;
-                    const int pairing = (int)(((uint64_t)wpick * 3u) >> 32);
+                    const uint32_t wp = philox10((uint32_t)b, a, 0u,
+                                                 ((uint32_t)D.inst << 4) | TAG_ICM_PAIR, A.key0,
+                                                 A.key1).x;
+                    const uint32_t pairing = (uint32_t)(((uint64_t)wp * 3u) >> 32);
                     // matchings {01,23}, {02,13}, {03,12}: partner of label 0, then the other two
-                    const int p1 = pairing + 1;
-                    pa[0] = 0; pb[0] = p1;
-                    pa[1] = (p1 == 1) ? 2 : 1; pb[1] = (p1 == 3) ? 2 : 3;
-                    pbeta[0] = pbeta[1] = b;
-                    pidx[0] = b * npair; pidx[1] = b * npair + 1;
+                    const uint32_t p1 = pairing + 1u;
+                    pa = 0u | ((p1 == 1u ? 2u : 1u) << 8);
+                    pb = p1 | ((p1 == 3u ? 2u : 3u) << 8);
+                    pidx0 = b * npair;
+                    pidx1 = b * npair + 1;
                     np = 2;
                 }
             }
-            if (np > 0 && I.row_off >= 0) {
-                uint32_t w0[2], w1[2];
-                int32_t *info[2];
-                for (int k2 = 0; k2 < np; ++k2) {
-                    const uint4 w = philox10((uint32_t)pidx[k2], a, 0u,
-                                             ((uint32_t)D.inst << 4) | TAG_ICM_PICK, A.key0, A.key1);
-                    w0[k2] = w.x;
-                    w1[k2] = w.y;
-                    info[k2] = A.icm_info + ((int64_t)I.info_off + pidx[k2]) * 4;
-                }
-                icm_pairs_rows(sp, A.rowA + I.row_off, A.rowB + I.row_off, n, I.lx, I.n_rows, np, pa,
-                               pb, w0, w1, Qr, Vr, red, info);
-            } else {
-                for (int k2 = 0; k2 < np; ++k2) {
-                    const uint4 w = philox10((uint32_t)pidx[k2], a, 0u,
-                                             ((uint32_t)D.inst << 4) | TAG_ICM_PICK, A.key0, A.key1);
-                    icm_pair(sp, recj, n, pa[k2], pb[k2], w.x, w.y, queue, vis, red,
-                             A.icm_info + ((int64_t)I.info_off + pidx[k2]) * 4);
+            if (np > 0) {
+                const uint32_t c3p = ((uint32_t)D.inst << 4) | TAG_ICM_PICK;
+                const uint4 u0 = philox10((uint32_t)pidx0, a, 0u, c3p, A.key0, A.key1);
+                const uint4 u1 = philox10((uint32_t)pidx1, a, 0u, c3p, A.key0, A.key1);
+                int32_t *info0 = A.icm_info + ((int64_t)I.info_off + pidx0) * 4;
+                int32_t *info1 = A.icm_info + ((int64_t)I.info_off + pidx1) * 4;
+                if (I.row_off >= 0) {
+                    icm_pairs_rows(sp, A.rowA + I.row_off, A.rowB + I.row_off, n, I.lx, I.n_rows, np,
+                                   pa, pb, make_uint4(u0.x, u0.y, u1.x, u1.y), Qr, Vr, red, info0,
+                                   info1);
+                } else {
+                    icm_pair(sp, recj, n, (int)(pa & 3u), (int)(pb & 3u), u0.x, u0.y, queue, vis,
+                             red, info0);
+                    if (np > 1)
+                        icm_pair(sp, recj, n, (int)((pa >> 8) & 3u), (int)((pb >> 8) & 3u), u1.x,
+                                 u1.y, queue, vis, red, info1);
                 }
             }
-            (void)pbeta;
         }
 
         if (A.do_energy) {
