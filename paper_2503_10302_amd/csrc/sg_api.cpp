@@ -290,7 +290,7 @@ struct sg_ctx {
     DevBuf<int64_t> d_best, d_acc_count, d_mom, d_trace;
     DevBuf<int32_t> d_acc_out;
     DevBuf<QuadDesc> d_desc;
-    DevBuf<uint4> d_rowA, d_rowB;
+    DevBuf<uint4> d_rowA, d_rowB, d_rowC;
     int n_blocks = 0;
     size_t quad_lds = 0;
     double icm_cutoff_loaded = std::numeric_limits<double>::quiet_NaN();
@@ -392,7 +392,8 @@ void sqa_records(const Lat &L, std::vector<uint4> &rec, std::vector<uint4> &recj
 }
 
 // Row tables for the cluster search (see sg_internal.h); rows of lx <= 32.
-void apt_rows(const Lat &L, std::vector<uint4> &rowA, std::vector<uint4> &rowB, InstDev &I)
+void apt_rows(const Lat &L, std::vector<uint4> &rowA, std::vector<uint4> &rowB,
+              std::vector<uint4> &rowC, InstDev &I)
 {
     I.lx = L.Lx;
     I.n_rows = L.Ly * L.Lz;
@@ -415,8 +416,13 @@ void apt_rows(const Lat &L, std::vector<uint4> &rowA, std::vector<uint4> &rowB, 
                     if (a > 0) nbrow[2 * (a - 1) + s] = (uint32_t)(v / L.Lx);
                 }
         }
+        uint32_t neg[3] = {0, 0, 0};
+        for (int x = 0; x < L.Lx; ++x)
+            for (int a = 0; a < 3; ++a)
+                if (L.coupling(r * L.Lx + x, a, +1) < 0) neg[a] |= 1u << x;
         rowA.push_back(make_uint4(m[0], m[1], m[2], m[3]));
         rowB.push_back(make_uint4(m[4], m[5], nbrow[0] | (nbrow[1] << 16), nbrow[2] | (nbrow[3] << 16)));
+        rowC.push_back(make_uint4(neg[0], neg[1], neg[2], 0u));
     }
 }
 
@@ -491,7 +497,7 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
     hipStream_t s = c->stream;
     const int nb4 = 4 * c->n_quads;   // physical buffers per instance (slots padded to a quad)
 
-    std::vector<uint4> rec, recj, rowA, rowB;
+    std::vector<uint4> rec, recj, rowA, rowB, rowC;
     std::vector<int32_t> perm, slot_lut, tab_off, tab_len;
     std::vector<uint32_t> lut, tab;
     int64_t spin_bytes = 0;
@@ -504,7 +510,7 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
         I.npad = round_up(L.n, 16);
         I.n_slots = c->n_slots;
         apt_records(L, rec, recj, I);
-        apt_rows(L, rowA, rowB, I);
+        apt_rows(L, rowA, rowB, rowC, I);
         I.spin_off = spin_bytes;
         spin_bytes += (int64_t)nb4 * I.npad;
         I.slot_off = i * nb4;
@@ -537,6 +543,7 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
     c->d_recj.upload(recj, s, "records");
     c->d_rowA.upload(rowA, s, "row tables");
     c->d_rowB.upload(rowB, s, "row tables");
+    c->d_rowC.upload(rowC, s, "row tables");
     c->d_perm.upload(perm, s, "perm");
     c->d_slot_lut.upload(slot_lut, s, "slot tables");
     c->d_lut.upload(lut, s, "thresholds");
@@ -558,7 +565,7 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
     c->quad_lds = 0;
     for (auto &I : c->idev) {
         const size_t need = sizeof(uint32_t) * (size_t)(I.npad + 4 + 4 * c->ni + 32 + (I.npad + 31) / 32 + 1 +
-                                                        4 * I.n_rows) +
+                                                        6 * I.n_rows) +
                             sizeof(uint16_t) * (size_t)I.npad + 16;
         c->quad_lds = std::max(c->quad_lds, need);
     }
@@ -577,9 +584,9 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
     a.desc = c->d_desc.p; a.inst = c->d_inst.p; a.rec_col = c->d_rec.p; a.rec_j = c->d_recj.p;
     a.spins = c->d_spins.p; a.perm = c->d_perm.p; a.lut = c->d_lut.p; a.slot_lut = c->d_slot_lut.p;
     a.icm_on = c->d_icm_on.p; a.E = c->d_E.p; a.mom = c->d_mom.p; a.icm_info = c->d_icm_info.p;
-    a.rowA = c->d_rowA.p; a.rowB = c->d_rowB.p;
+    a.rowA = c->d_rowA.p; a.rowB = c->d_rowB.p; a.rowC = c->d_rowC.p;
     a.ctr = c->d_ctr.p; a.key0 = c->key0; a.key1 = c->key1; a.tag = TAG_APT_SWEEP;
-    a.do_energy = 1; a.mom_from = -1; a.reps = c->reps; a.imax = c->imax; a.ni = c->ni;
+    a.do_energy = 2; a.mom_from = -1; a.reps = c->reps; a.imax = c->imax; a.ni = c->ni;
     a.n_blocks = c->n_blocks;
     hip_check(launch_apt_quad(a, c->quad_lds, s), "initial energies");
 }
@@ -611,6 +618,7 @@ AptArgs apt_args(sg_ctx *c, int n_sweeps, int do_icm)
     a.icm_info = c->d_icm_info.p;
     a.rowA = c->d_rowA.p;
     a.rowB = c->d_rowB.p;
+    a.rowC = c->d_rowC.p;
     a.ctr = c->d_ctr.p;
     a.key0 = c->key0;
     a.key1 = c->key1;
@@ -1142,6 +1150,7 @@ sg_status sg_set_spins(sg_ctx *c, const int8_t *in)
             c->d_perm.upload(perm.data(), perm.size(), c->stream, "perm");
             // energies of the new state
             AptArgs a = apt_args(c, 0, 0);
+            a.do_energy = 2;
             hip_check(launch_apt_quad(a, c->quad_lds, c->stream), "energy");
             hip_check(hipStreamSynchronize(c->stream), "spins");
         } else {
@@ -1357,6 +1366,11 @@ extern "C" sg_status sg_adaptive_ladder(const sg_lattice *inst, int32_t n_inst,
         hip_check(launch_apt_init(c->d_inst.p, c->d_desc.p, c->n_blocks, c->d_spins.p, c->d_perm.p,
                                   c->key0, c->key1, TAG_ADAPT_INIT, s),
                   "adaptive init");
+        {   // energies of the re-initialised chains
+            AptArgs a = apt_args(c, 0, 0);
+            a.do_energy = 2;
+            hip_check(launch_apt_quad(a, c->quad_lds, s), "adaptive energies");
+        }
         // every slot of instance i uses table i (the current beta_t of instance i)
         std::vector<int32_t> slot_lut((size_t)n_inst * nb4);
         for (int i = 0; i < n_inst; ++i)
@@ -1380,7 +1394,7 @@ extern "C" sg_status sg_adaptive_ladder(const sg_lattice *inst, int32_t n_inst,
             AptArgs a = apt_args(c, p->sweeps, 0);
             a.tag = TAG_ADAPT_SWEEP;
             a.mom_from = p->sweeps - p->tail;
-            a.do_energy = 0;
+            a.do_energy = 1;
             hip_check(launch_apt_quad(a, c->quad_lds, s), "adaptive sweeps");
             hip_check(launch_advance(c->d_ctr.p, (uint32_t)p->sweeps, 0u, 0u, 0u, s), "adaptive");
             c->d_mom.download(mom.data(), mom.size(), s, "moments");

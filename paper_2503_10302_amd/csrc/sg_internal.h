@@ -60,6 +60,7 @@ struct InstDev {
 // Row tables of an instance for the cluster search (rows of lx <= 32 sites):
 //   rowA[r] = {bond to +x present (bit x), bond to -x, bond to +y, bond to -y}
 //   rowB[r] = {bond to +z, bond to -z, row(+y) | row(-y) << 16, row(+z) | row(-z) << 16}
+//   rowC[r] = {J = -1 on the bond to +x, to +y, to +z, 0}
 // "present" means the neighbour exists and J != 0.
 
 // One work-group task of the APT replica kernel: instance and group of four
@@ -98,6 +99,7 @@ struct AptArgs {
     const uint4 *rec_j;
     const uint4 *rowA;
     const uint4 *rowB;
+    const uint4 *rowC;
     uint8_t *spins;            // physical replica buffers, bytes 0/1 (1 = spin up)
     const int32_t *perm;       // logical slot -> physical buffer (per instance)
     const uint32_t *lut;       // heat-bath thresholds, NI per table
@@ -111,7 +113,7 @@ struct AptArgs {
     uint32_t tag;              // sweep purpose (APT or adaptive)
     int32_t n_sweeps;
     int32_t do_icm;
-    int32_t do_energy;
+    int32_t do_energy;         // 0: leave E, 1: E += change in this launch, 2: recompute E
     int32_t mom_from;          // accumulate moments after sweep index >= mom_from (-1: never)
     int32_t reps;              // ICM labels per temperature
     int32_t imax;              // LUT covers fields -imax..imax

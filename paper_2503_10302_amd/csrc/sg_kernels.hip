@@ -228,11 +228,12 @@ __device__ __forceinline__ uint32_t row_step(const uint32_t *Vp, int r, uint32_t
     return V | (N & Q);
 }
 
-__device__ void icm_pairs_rows(uint32_t *sp, const uint4 *rowA, const uint4 *rowB, int n, int lx,
-                               int nrows, int np, uint32_t pa, uint32_t pb, uint4 w01,
-                               uint32_t *Qr, uint32_t *Vr, int32_t *red, int32_t *info0,
-                               int32_t *info1)
+__device__ void icm_pairs_rows(uint32_t *sp, const uint4 *rowA, const uint4 *rowB,
+                               const uint4 *rowC, int n, int lx, int nrows, int np, uint32_t pa,
+                               uint32_t pb, uint4 w01, uint32_t *Qr, uint32_t *Vr, int32_t *red,
+                               int32_t *info0, int32_t *info1, int32_t *dE01)
 {
+    uint32_t *Sr = Vr + 2 * nrows;   // spins of each pair's first replica (bit = up)
     const int tid = threadIdx.x;
     const int rpt = (nrows + kQuadThreads - 1) / kQuadThreads;
     const int r0 = min(nrows, tid * rpt), r1 = min(nrows, r0 + rpt);
@@ -242,17 +243,22 @@ __device__ void icm_pairs_rows(uint32_t *sp, const uint4 *rowA, const uint4 *row
     for (int r = r0; r < r1; ++r) {
         uint32_t q0 = 0u, q1 = 0u;
         const uint32_t *row = sp + r * lx;
+        uint32_t s0 = 0u, s1 = 0u;
         for (int x = 0; x < lx; ++x) {
             const uint32_t w = row[x];
             q0 |= (uint32_t)(((w & mA0) != 0) != ((w & mB0) != 0)) << x;
             q1 |= (uint32_t)(((w & mA1) != 0) != ((w & mB1) != 0)) << x;
+            s0 |= (uint32_t)((w & mA0) != 0) << x;
+            s1 |= (uint32_t)((w & mA1) != 0) << x;
         }
         Qr[r] = q0;
         Vr[r] = 0u;
+        Sr[r] = s0;
         c0 += __popc(q0);
         if (np > 1) {
             Qr[nrows + r] = q1;
             Vr[nrows + r] = 0u;
+            Sr[nrows + r] = s1;
             c1 += __popc(q1);
         }
     }
@@ -307,12 +313,27 @@ __device__ void icm_pairs_rows(uint32_t *sp, const uint4 *rowA, const uint4 *row
         }
         if (!__syncthreads_or(changed)) break;
     }
+    // cluster sizes and, for each pair, the sum of J s_i s_j of the first replica over
+    // bonds that cross the cluster boundary (counted once, along +x, +y, +z)
     int32_t tot[4] = {0, 0, 0, 0};
     for (int r = r0; r < r1; ++r) {
-        tot[0] += __popc(Vr[r]);
-        if (np > 1) tot[1] += __popc(Vr[nrows + r]);
+        const uint4 a = rowA[r], b = rowB[r], cc = rowC[r];
+        for (int p = 0; p < np; ++p) {
+            const uint32_t *Vp = Vr + p * nrows, *Sp = Sr + p * nrows;
+            const uint32_t V = Vp[r], S = Sp[r];
+            tot[p] += __popc(V);
+            const uint32_t Vx = (V >> 1) | (V << hi), Sx = (S >> 1) | (S << hi);
+            const uint32_t X0 = (V ^ Vx) & a.x, N0 = S ^ Sx ^ cc.x;
+            const uint32_t X1 = (V ^ Vp[b.z & 0xFFFFu]) & a.z, N1 = S ^ Sp[b.z & 0xFFFFu] ^ cc.y;
+            const uint32_t X2 = (V ^ Vp[b.w & 0xFFFFu]) & b.x, N2 = S ^ Sp[b.w & 0xFFFFu] ^ cc.z;
+            tot[2 + p] += __popc(X0 & ~N0) - __popc(X0 & N0) + __popc(X1 & ~N1) - __popc(X1 & N1) +
+                          __popc(X2 & ~N2) - __popc(X2 & N2);
+        }
     }
     block_sum4(tot, red);
+    // cluster flip of the first replica: crossing bonds change sign -> dE = 2 * sum
+    dE01[0] = (m0 > 0 && 2 * tot[0] <= n) ? 2 * tot[2] : 0;
+    dE01[1] = (np > 1 && m1 > 0 && 2 * tot[1] <= n) ? 2 * tot[3] : 0;
     for (int p = 0; p < np; ++p) {
         const int32_t m = p ? m1 : m0, size = tot[p];
         const uint32_t mA = p ? mA1 : mA0, mB = p ? mB1 : mB0;
@@ -451,8 +472,8 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
         int32_t *red = (int32_t *)(lut + 4 * ni);        // 32
         uint32_t *vis = (uint32_t *)(red + 32);          // (npad + 31) / 32 + 1
         uint32_t *Qr = vis + ((npad + 31) >> 5) + 1;     // 2 * n_rows
-        uint32_t *Vr = Qr + 2 * I.n_rows;                // 2 * n_rows
-        uint16_t *queue = (uint16_t *)(Vr + 2 * I.n_rows);   // npad
+        uint32_t *Vr = Qr + 2 * I.n_rows;                // 2 * n_rows, then S rows 2 * n_rows
+        uint16_t *queue = (uint16_t *)(Vr + 4 * I.n_rows);   // npad
         const int q = D.quad;
         const int32_t *pp = A.perm + I.slot_off + 4 * q;
         const int64_t b0 = (int64_t)pp[0] * npad, b1 = (int64_t)pp[1] * npad;
@@ -480,6 +501,9 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
 
         const uint32_t t0 = A.ctr[0] + (uint32_t)(A.cyc_k * A.n_sweeps);
         const uint32_t c3 = ((uint32_t)D.inst << 4) | A.tag;
+        // this thread's share of each slot's energy change in this launch
+        int32_t dE[4] = {0, 0, 0, 0};
+        bool full_energy = A.do_energy == 2;
         for (int sw = 0; sw < A.n_sweeps; ++sw) {
             const uint32_t t = t0 + (uint32_t)sw;
             for (int c = 0; c < I.n_colours; ++c) {
@@ -494,23 +518,32 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
                     const int32_t base = (int32_t)((r.x >> 25) & 63u) - 32 -
                                          (int32_t)((r.x >> 16) & 7u) + A.imax;
                     const uint4 u = philox10(j, t, (uint32_t)q, c3, A.key0, A.key1);
-                    uint32_t nw = (u.x < lut[2 * (int32_t)(k & 0xFFu) + base]) ? 1u : 0u;
-                    nw |= (u.y < lut[ni + 2 * (int32_t)((k >> 8) & 0xFFu) + base]) ? 0x100u : 0u;
-                    nw |= (u.z < lut[2 * ni + 2 * (int32_t)((k >> 16) & 0xFFu) + base]) ? 0x10000u : 0u;
-                    nw |= (u.w < lut[3 * ni + 2 * (int32_t)(k >> 24) + base]) ? 0x1000000u : 0u;
+                    const uint32_t old = sp[j];
+                    const uint32_t us[4] = {u.x, u.y, u.z, u.w};
+                    uint32_t nw = 0u;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int32_t idx = 2 * (int32_t)((k >> (8 * b)) & 0xFFu) + base;
+                        const uint32_t up = us[b] < lut[b * ni + idx] ? 1u : 0u;
+                        nw |= up << (8 * b);
+                        // Eq. (8): flipping s_j changes E by -(s_new - s_old) * I_j, I_j = idx - imax
+                        const int32_t I2 = 2 * (idx - A.imax);
+                        if (up != ((old >> (8 * b)) & 1u)) dE[b] += up ? -I2 : I2;
+                    }
                     sp[j] = nw;
                 }
                 __syncthreads();
             }
             if (A.mom_from >= 0 && sw >= A.mom_from) {
-                int32_t e[4];
-                quad_energy(sp, A.rec_j + I.recj_off, n, red, e);
+                int32_t e[4] = {dE[0], dE[1], dE[2], dE[3]};
+                block_sum4(e, red);
                 if (tid < 4) {
                     const int s = 4 * q + tid;
                     if (s < I.n_slots) {
+                        const int64_t ec = (int64_t)A.E[I.slot_off + s] + e[tid];
                         int64_t *mm = A.mom + 2 * (int64_t)(I.slot_off + s);
-                        mm[0] += e[tid];
-                        mm[1] += (int64_t)e[tid] * e[tid];
+                        mm[0] += ec;
+                        mm[1] += ec * ec;
                     }
                 }
             }
@@ -556,10 +589,21 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
                 int32_t *info0 = A.icm_info + ((int64_t)I.info_off + pidx0) * 4;
                 int32_t *info1 = A.icm_info + ((int64_t)I.info_off + pidx1) * 4;
                 if (I.row_off >= 0) {
-                    icm_pairs_rows(sp, A.rowA + I.row_off, A.rowB + I.row_off, n, I.lx, I.n_rows, np,
-                                   pa, pb, make_uint4(u0.x, u0.y, u1.x, u1.y), Qr, Vr, red, info0,
-                                   info1);
+                    int32_t d01[2];
+                    icm_pairs_rows(sp, A.rowA + I.row_off, A.rowB + I.row_off, A.rowC + I.row_off, n,
+                                   I.lx, I.n_rows, np, pa, pb, make_uint4(u0.x, u0.y, u1.x, u1.y),
+                                   Qr, Vr, red, info0, info1, d01);
+                    if (tid == 0) {
+                        // isoenergetic move: the partner's energy changes by the opposite amount
+                        dE[pa & 3u] += d01[0];
+                        dE[pb & 3u] -= d01[0];
+                        if (np > 1) {
+                            dE[(pa >> 8) & 3u] += d01[1];
+                            dE[(pb >> 8) & 3u] -= d01[1];
+                        }
+                    }
                 } else {
+                    full_energy = true;
                     icm_pair(sp, recj, n, (int)(pa & 3u), (int)(pb & 3u), u0.x, u0.y, queue, vis,
                              red, info0);
                     if (np > 1)
@@ -569,12 +613,18 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
             }
         }
 
-        if (A.do_energy) {
+        if (A.do_energy && full_energy) {
             int32_t e[4];
             quad_energy(sp, A.rec_j + I.recj_off, n, red, e);
             if (tid < 4) {
                 const int s = 4 * q + tid;
                 if (s < I.n_slots) A.E[I.slot_off + s] = e[tid];
+            }
+        } else if (A.do_energy) {
+            block_sum4(dE, red);
+            if (tid < 4) {
+                const int s = 4 * q + tid;
+                if (s < I.n_slots) A.E[I.slot_off + s] += dE[tid];
             }
         }
 
