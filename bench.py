@@ -171,6 +171,10 @@ def main():
     ap.add_argument("--only", choices=["all", "sqa", "apt"], default="all")
     ap.add_argument("--ttt", action="store_true", help="time-to-target run (plain vs batched APT+ICM)")
     ap.add_argument("--ttt-cycles", type=int, default=20000)
+    ap.add_argument("--learned", action="store_true",
+                    help="time-to-target of plain, batched-adaptive and batched-learned APT+ICM "
+                         "on 256 held-out L=15 instances (shipped network)")
+    ap.add_argument("--plain-sample", type=int, default=16)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -184,6 +188,13 @@ def main():
     if args.ttt:
         print(json.dumps(time_to_target(e0_cycles=args.ttt_cycles, max_cycles=args.ttt_cycles)),
               flush=True)
+        return
+    if args.learned:
+        from paper_2503_10302_amd import ladder
+        res = ladder.evaluate(ladder.default_params(), n=256, cycles=args.ttt_cycles,
+                              e0_cycles=args.ttt_cycles, plain_sample=args.plain_sample)
+        res["metric"] = "time to residual energy per spin <= 0.007, 256 held-out L=15 instances"
+        print(json.dumps(res), flush=True)
         return
 
     out = {"metric": METRIC, "unit": "flips/ns", "n_gpus": 1, "steps": args.steps,

@@ -1,0 +1,54 @@
+"""The learned ladder on the GPU: what the trained network gains over the adaptive stage,
+and the fallback when a predicted ladder fails the acceptance band."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2503_10302_amd import ladder
+
+pytestmark = pytest.mark.gpu
+
+
+def test_trained_network_replaces_the_adaptive_stage():
+    """16 held-out L = 15 instances (seeds outside the training range): the shipped
+    network's ladders pass the band check without fallback, lie within 5 % (rms in log
+    beta) of the adaptive stage's own ladders, and cost a small fraction of its time,
+    pilot run included."""
+    inst = ladder._instances(range(16), (15,), 90000)
+    t0 = time.perf_counter()
+    lad_l, fell_back, acc = ladder.learned_ladders(inst, 7)
+    t_learned = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res = ladder.adaptive_ladders(inst, 8, **ladder.ADAPTIVE)
+    t_adaptive = time.perf_counter() - t0
+    lad_a = np.stack([ladder.resample(r[0]) for r in res])
+    print(f"learned {t_learned:.3f} s, adaptive {t_adaptive:.3f} s", flush=True)
+    assert not fell_back.any()
+    assert np.all(np.diff(lad_l, axis=1) > 0)
+    rms = float(np.sqrt(np.mean((np.log(lad_l) - np.log(lad_a)) ** 2)))
+    assert rms < 0.05, rms
+    # acceptance over the checked pairs near the adaptive target erfc(alpha / 2) = 0.377
+    mid = acc[:, :31 - ladder.TAIL_EXEMPT]
+    assert abs(float(mid.mean()) - 0.377) < 0.04
+    assert t_learned * 5 < t_adaptive
+
+
+def test_band_violation_falls_back_to_the_adaptive_stage():
+    """A network whose ladder barely spans any temperature (acceptance near 1) fails the
+    band on every instance, and every ladder then comes from the adaptive stage."""
+    p = ladder.default_params().copy()
+    nout = ladder.N_RUNGS + 1
+    p[ladder.OFF_W3:ladder.OFF_B3] = 0.0           # outputs = output biases
+    inc = 1e-3
+    p[ladder.OFF_B3 + 1:ladder.OFF_B3 + ladder.N_RUNGS] = inc + np.log(-np.expm1(-inc))
+    assert ladder.OFF_B3 + nout == p.size - 8
+    inst = ladder._instances(range(4), (6,), 91000)
+    lad, fell_back, acc = ladder.learned_ladders(inst, 9, params=p, pilot=200)
+    assert fell_back.all()
+    assert (acc[:, 0] > ladder.BAND[1]).all()
+    # the fallback is the adaptive stage itself: the same call gives the same ladders
+    ref = ladder.adaptive_ladders(inst, 10, **ladder.ADAPTIVE)
+    for i in range(4):
+        np.testing.assert_array_equal(lad[i], ladder.resample(ref[i][0]))
+        assert lad[i, 0] == 0.5 and np.all(np.diff(lad[i]) > 0)

@@ -1,0 +1,73 @@
+"""Host-side pieces of the learned-ladder module (no GPU): ladder resampling, the cutoff
+label, network targets, the per-pair acceptance bookkeeping and the band check."""
+import math
+
+import numpy as np
+
+import oracle
+from paper_2503_10302_amd import ladder
+
+
+def test_resample_keeps_endpoints_order_and_identity():
+    rng = np.random.default_rng(3)
+    b = np.cumsum(rng.uniform(0.01, 0.3, 20)) + 0.5
+    r = ladder.resample(b)
+    assert r.size == ladder.N_RUNGS
+    assert r[0] == b[0] and r[-1] == b[-1]
+    assert np.all(np.diff(r) > 0)
+    b32 = np.cumsum(rng.uniform(0.01, 0.3, 32)) + 0.5
+    np.testing.assert_array_equal(ladder.resample(b32), b32)
+    # a linear ladder stays linear
+    np.testing.assert_allclose(ladder.resample(np.linspace(0.5, 3.0, 7)), np.linspace(0.5, 3.0, 32))
+
+
+def test_cutoff_label_is_first_rung_at_or_above_one():
+    assert ladder.cutoff_label([0.5, 0.9, 1.0, 1.2]) == 1.0
+    assert ladder.cutoff_label([0.5, 0.9, 1.1, 1.2]) == 1.1
+    assert ladder.cutoff_label([0.5, 0.7, 0.9]) == 0.9
+
+
+def test_targets_are_log_ladder_and_log_cutoff():
+    b = np.array([0.5, 0.6, 0.8, 1.05, 1.5, 2.5])
+    t = ladder.targets(b)
+    assert t.shape == (ladder.N_RUNGS + 1,)
+    np.testing.assert_allclose(np.exp(t[:ladder.N_RUNGS]), ladder.resample(b), rtol=1e-14)
+    assert math.isclose(math.exp(t[-1]), ladder.cutoff_label(ladder.resample(b)), rel_tol=1e-14)
+
+
+def test_attempt_counts_follow_the_swap_schedule():
+    """acceptance() divides by the number of attempts each pair had; count the attempts the
+    oracle's swap step actually makes (a flag other than -1) and check that counting every
+    attempt as accepted gives exactly 1 for every pair."""
+    n_beta, R, n = 6, 2, 8
+    beta = np.linspace(0.5, 1.5, n_beta)
+    spins = np.ones((n_beta * R, n), np.int8)
+    E = np.zeros(n_beta * R, np.int64)
+    for cycles in (1, 2, 7, 10):
+        attempted = np.zeros((n_beta - 1) * R, np.int64)
+        for a in range(1, cycles + 1):
+            flags = oracle.apt_swap(0, beta, R, 99, a, spins, E)
+            attempted += flags != -1
+        acc = ladder.acceptance(attempted[None, :], cycles, n_beta, R)
+        if cycles == 1:     # only the even pairs have been tried
+            np.testing.assert_array_equal(acc[0, 0::2], 1.0)
+            assert np.isnan(acc[0, 1::2]).all()
+            assert not ladder.in_band(acc, skip_last=0)[0]
+        else:
+            np.testing.assert_array_equal(acc, np.ones((1, n_beta - 1)))
+
+
+def test_band_and_tail_exemption():
+    lo, hi = ladder.BAND
+    assert math.isclose(lo, 0.5 * math.erfc(1.25 / 2)) and math.isclose(hi, 1.5 * math.erfc(1.25 / 2))
+    good = np.full((1, 31), 0.38)
+    cold = good.copy()
+    cold[0, -2:] = [0.1, 0.02]
+    warm = good.copy()
+    warm[0, 3] = 0.1
+    high = good.copy()
+    high[0, 0] = 0.9
+    acc = np.concatenate([good, cold, warm, high])
+    np.testing.assert_array_equal(ladder.in_band(acc, skip_last=0), [True, False, False, False])
+    np.testing.assert_array_equal(ladder.in_band(acc, skip_last=2), [True, True, False, False])
+    assert ladder.TAIL_EXEMPT == 2
