@@ -232,6 +232,9 @@ def main():
                          "unit": "Top/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                          "traffic": None, "alg_ops_per_flip": ALG_OPS_PER_FLIP,
                          "kernel_ms": round(kms, 3), "launches": nlaunch,
+                         "launch_config": {"threads": ctx.launch_config()[0],
+                                           "tasks_per_record": ctx.launch_config()[1],
+                                           "chosen_by": "autotuner"},
                          "kernel_flips_per_ns": round(flips_per_step * args.steps / (kms * 1e6), 3)},
             "wall_s_timed": round(wall, 3),
             "sqa_best_residual_proxy": {"min_E_per_spin": round(float(bE.min()) / n, 5)},

@@ -25,6 +25,7 @@ constexpr int kMaxH = 31;      // |h| bound, so that h + 32 fits 6 bits of a sit
 constexpr int kMaxN = 32767;   // sites per instance (16-bit site and neighbour indices)
 constexpr int kQuadThreads = 256;
 constexpr int kSqaThreads = 512;
+constexpr int kSqaTabWords = 464;        // static LDS of the DT-SQA kernel (tables)
 constexpr size_t kMaxLds = 160 * 1024;   // LDS per CU on gfx950
 
 // Site record (uint4), one per site:
@@ -152,7 +153,11 @@ hipError_t launch_apt_init(const InstDev *inst_d, const QuadDesc *desc, int n_bl
 hipError_t launch_apt_quad(const AptArgs &a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_apt_swap(const SwapArgs &a, hipStream_t s);
 hipError_t launch_sqa_init(const SqaArgs &a, int n_inst, hipStream_t s);
-hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, hipStream_t s);
+// DT-SQA kernel in one of its launch configurations: work-group size 256, 512 or
+// 1024 threads, SPLIT 1 or 2 tasks per (site, parity) record (2 needs M/2 in 29..32).
+bool sqa_config_valid(int threads, int split, int H);
+hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, int threads, int split,
+                      hipStream_t s);
 hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 // ctr[i] += d[i] for the four counters (one thread; ordered by the stream).

@@ -698,44 +698,143 @@ __device__ __forceinline__ uint32_t rotr_h(uint32_t x, int H, uint32_t mask)
     return ((x >> 1) | (x << (H - 1))) & mask;
 }
 
-__global__ __launch_bounds__(kSqaThreads) void sqa_kernel(SqaArgs A)
+// Byte offset of the 4-bit slice group g of a bit plane into a 16-entry
+// 32-bit table: ((x >> 4g) & 15) * 4.
+template <int NG>
+__device__ __forceinline__ uint32_t nib_off(uint32_t x, int g)
 {
+    if (NG > 0) return g == 0 ? ((x << 2) & 0x3Cu) : ((x >> (4 * g - 2)) & 0x3Cu);
+    return ((x >> (4 * g)) & 15u) << 2;
+}
+
+__device__ __forceinline__ uint32_t lds_word(const uint32_t *base, uint32_t byte_off)
+{
+    return *(const uint32_t *)((const uint8_t *)base + byte_off);
+}
+
+// acc = 2 acc + (u < T): the borrow of u - T shifted into acc (two VOP2 operations).
+__device__ __forceinline__ uint32_t shift_in_lt(uint32_t acc, uint32_t u, uint32_t T)
+{
+    uint32_t d;
+    asm("v_sub_co_u32_e32 %1, vcc, %2, %3\n\t"
+        "v_addc_co_u32_e32 %0, vcc, %0, %0, vcc"
+        : "+v"(acc), "=&v"(d)
+        : "v"(u), "v"(T)
+        : "vcc");
+    return acc;
+}
+
+// New states of the H slices of one parity at one site (Supplementary Eq. S.3 with
+// the heat-bath rule of Eq. 6).  Slice h = 4 g + i takes word i of the Philox block
+// of group g; its threshold index is a byte of idx4, assembled from the bit planes
+// of the aligned-neighbour count (c0, c1, c2) and of the number of up Trotter
+// neighbours (t0, t1) through the spread tables.  Groups run from the highest to the
+// lowest so that the borrow chain leaves slice h at bit h.  SCALED: table indices are
+// stored pre-multiplied by 4 (byte offsets), possible when the table has <= 64 rows.
+// NG > 0: groups [g_lo, g_lo + NG) unrolled (the planes are pre-shifted by 4 g_lo
+// bits, so group g reads bits 4 (g - g_lo)); NG == 0: groups [0, ngrp), not unrolled.
+template <int NG, bool SCALED>
+__device__ __forceinline__ uint32_t sqa_slices(const uint32_t *lut, const uint32_t *spread,
+                                               uint32_t c0, uint32_t c1, uint32_t c2,
+                                               uint32_t t0b, uint32_t t1b, uint32_t base4,
+                                               uint32_t j, uint32_t t, uint32_t x2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1, int ngrp, uint32_t g_lo)
+{
+    uint32_t res = 0u;
+    const int ng = NG > 0 ? NG : ngrp;
+#pragma unroll
+    for (int g = ng - 1; g >= 0; --g) {
+        const uint32_t idx4 = lds_word(spread, nib_off<NG>(c0, g)) +
+                              lds_word(spread + 16, nib_off<NG>(c1, g)) +
+                              lds_word(spread + 32, nib_off<NG>(c2, g)) +
+                              lds_word(spread + 48, nib_off<NG>(t0b, g)) +
+                              lds_word(spread + 64, nib_off<NG>(t1b, g)) + base4;
+        const uint4 u = philox10(j, t, x2 | (g_lo + (uint32_t)g), c3, k0, k1);
+        uint32_t o0, o1, o2, o3;
+        if (SCALED) {
+            o0 = idx4 & 0xFFu;
+            o1 = (idx4 >> 8) & 0xFFu;
+            o2 = (idx4 >> 16) & 0xFFu;
+            o3 = idx4 >> 24;
+        } else {
+            o0 = (idx4 << 2) & 0x3FCu;
+            o1 = (idx4 >> 6) & 0x3FCu;
+            o2 = (idx4 >> 14) & 0x3FCu;
+            o3 = (idx4 >> 22) & 0x3FCu;
+        }
+        res = shift_in_lt(res, u.w, lds_word(lut, o3));
+        res = shift_in_lt(res, u.z, lds_word(lut, o2));
+        res = shift_in_lt(res, u.y, lds_word(lut, o1));
+        res = shift_in_lt(res, u.x, lds_word(lut, o0));
+    }
+    return res;
+}
+
+// THREADS: work-group size.  SPLIT: tasks per (site, parity) record; with SPLIT = 2
+// (only for 8 slice groups) a task updates 16 slices and stores a 16-bit half word.
+// Waves are limited to 64 VGPRs (8 waves per SIMD).
+template <int THREADS, int NG, bool SCALED, int SPLIT>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void sqa_kernel(SqaArgs A)
+{
+    static_assert(SPLIT == 1 || (SPLIT == 2 && NG == 8), "split needs 8 slice groups");
+    // Tables at fixed (static) LDS addresses, so that table offsets need no base
+    // register: thresholds (<= 256 entries), spread tables, reduction scratch.  The
+    // replica lives in dynamic LDS.
+    __shared__ uint32_t tabs[kSqaTabWords];
     extern __shared__ uint32_t lds[];
     const int inst = blockIdx.x / A.R, r = blockIdx.x - inst * A.R;
     const InstDev I = A.inst[inst];
     const int tid = threadIdx.x;
     const int n = I.n, npad = I.npad, H = A.H;
     const uint32_t mask = (H >= 32) ? 0xFFFFFFFFu : ((1u << H) - 1u);
-    // Fixed-offset tables first (constant LDS addresses): thresholds (<= 256
-    // entries), spread tables, reduction scratch; then the replica.
-    uint32_t *lut = lds;                        // 256
+    uint32_t *lut = tabs;                       // 2 * 128 (double-buffered rows)
     // Spread tables: for a 4-bit slice group of one bit plane, the plane's
     // contribution to the four threshold indices, one byte per slice.  Index
     // weights: 6, 12, 24 for the aligned-neighbour count bits, 1, 2 for the
-    // number of up Trotter neighbours (table index = 6 k + t + 3 (h - d + smax)).
-    uint32_t *spread = lds + 256;               // 5 * 16
-    int32_t *red = (int32_t *)(lds + 336);      // 2 * 64
-    uint32_t *sp = lds + 464;                   // 2 * (npad + 1)
+    // number of up Trotter neighbours (table index = 6 k + t + 3 (h - d + smax)),
+    // times 4 when SCALED.
+    uint32_t *spread = tabs + 256;              // 5 * 16
+    int32_t *red = (int32_t *)(tabs + 336);     // 2 * 64
+    uint32_t *sp = lds;                         // 2 * (npad + 1)
     uint32_t *g = A.spins + I.spin_off + (int64_t)r * npad * 2;
-    for (int i = tid; i < 2 * npad; i += kSqaThreads) sp[i] = g[i];
+    for (int i = tid; i < 2 * npad; i += THREADS) sp[i] = g[i];
     if (tid < 2) sp[2 * npad + tid] = 0u;
     if (tid < 80) {
         const uint32_t w[5] = {6u, 12u, 24u, 1u, 2u};
         const uint32_t nib = (uint32_t)(tid & 15), pl = (uint32_t)(tid >> 4);
-        spread[tid] = w[pl] * ((nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21));
+        spread[tid] = (SCALED ? 4u : 1u) * w[pl] *
+                      ((nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21));
     }
     const uint32_t c3 = ((uint32_t)inst << 4) | TAG_SQA_SWEEP;
     const int ngrp = (H + 3) >> 2;
+    // Threshold rows: a table of <= 128 entries is double-buffered, the next step's
+    // row written during the current step's first phase (no extra barrier); a larger
+    // table is reloaded between steps.
+    // An energy-only launch (n_steps == 0) has no threshold table (A.lut may be null).
+    const bool dbuf = A.nl <= 128;
+    if (dbuf && A.n_steps > 0)
+        for (int i = tid; i < A.nl; i += THREADS) lut[i] = A.lut[(int64_t)A.lut_step0 * A.nl + i];
+    __syncthreads();
     for (int st = 0; st < A.n_steps; ++st) {
         const uint32_t t = (uint32_t)(A.t0 + st);
-        __syncthreads();
-        for (int i = tid; i < A.nl; i += kSqaThreads)
-            lut[i] = A.lut[(int64_t)(A.lut_step0 + st) * A.nl + i];
-        __syncthreads();
+        const uint32_t *lrow = lut + (dbuf ? 128 * (st & 1) : 0);
+        if (!dbuf) {
+            for (int i = tid; i < A.nl; i += THREADS)
+                lut[i] = A.lut[(int64_t)(A.lut_step0 + st) * A.nl + i];
+            __syncthreads();
+        }
+        // every phase ends with a barrier, so the previous step's readers of this
+        // step's double buffer (and of a reloaded table) are done
         for (int c = 0; c < I.n_colours; ++c) {
+            if (dbuf && c == 0 && st + 1 < A.n_steps)
+                for (int i = tid; i < A.nl; i += THREADS)
+                    lut[128 * ((st + 1) & 1) + i] = A.lut[(int64_t)(A.lut_step0 + st + 1) * A.nl + i];
             const uint4 *rc = A.rec + I.rec_off + A.inst[inst].col_off[c];
             const int cnt = A.inst[inst].col_cnt[c];
-            for (int i = tid; i < cnt; i += kSqaThreads) {
+            for (int it = tid; it < SPLIT * cnt; it += THREADS) {
+                const int i = SPLIT == 1 ? it : (it >> 1);
+                const uint32_t half = SPLIT == 1 ? 0u : (uint32_t)(it & 1);
                 const uint4 rr = rc[i];
                 const uint32_t j = rr.x & 0xFFFFu;
                 const uint32_t p = rr.x >> 31;
@@ -758,44 +857,41 @@ __global__ __launch_bounds__(kSqaThreads) void sqa_kernel(SqaArgs A)
                 const uint32_t up = p ? ev : rotl_h(od, H, mask);
                 const uint32_t dn = p ? rotr_h(ev, H, mask) : od;
                 const uint32_t t0b = up ^ dn, t1b = up & dn;
-                const uint32_t base4 = (uint32_t)(3 * ((int32_t)((rr.x >> 25) & 63u) - 32 -
-                                                      (int32_t)((rr.x >> 16) & 7u) + A.smax)) *
+                const uint32_t base4 = (SCALED ? 4u : 1u) *
+                                       (uint32_t)(3 * ((int32_t)((rr.x >> 25) & 63u) - 32 -
+                                                       (int32_t)((rr.x >> 16) & 7u) + A.smax)) *
                                        0x01010101u;
-                uint32_t res = 0u;
-                for (int gq = 0; gq < ngrp; ++gq) {
-                    const int sh = 4 * gq;
-                    // four threshold indices, one byte each (all < 256)
-                    const uint32_t idx4 = spread[(c0 >> sh) & 15u] + spread[16 + ((c1 >> sh) & 15u)] +
-                                          spread[32 + ((c2 >> sh) & 15u)] +
-                                          spread[48 + ((t0b >> sh) & 15u)] +
-                                          spread[64 + ((t1b >> sh) & 15u)] + base4;
-                    const uint4 u = philox10(j, t, ((uint32_t)r << 16) | (p << 15) | (uint32_t)gq,
-                                             c3, A.key0, A.key1);
-                    const uint8_t *lb = (const uint8_t *)lut;   // byte addressing: idx * 4
-                    uint32_t b4 = (u.x < *(const uint32_t *)(lb + ((idx4 << 2) & 0x3FCu))) ? 1u : 0u;
-                    b4 |= (u.y < *(const uint32_t *)(lb + ((idx4 >> 6) & 0x3FCu))) ? 2u : 0u;
-                    b4 |= (u.z < *(const uint32_t *)(lb + ((idx4 >> 14) & 0x3FCu))) ? 4u : 0u;
-                    b4 |= (u.w < *(const uint32_t *)(lb + ((idx4 >> 22) & 0x3FCu))) ? 8u : 0u;
-                    res |= b4 << sh;
+                const uint32_t x2 = ((uint32_t)r << 16) | (p << 15);
+                if (SPLIT == 1) {
+                    const uint32_t res = sqa_slices<NG, SCALED>(lrow, spread, c0, c1, c2, t0b, t1b,
+                                                                base4, j, t, x2, c3, A.key0,
+                                                                A.key1, ngrp, 0u);
+                    sp[2 * j + p] = res & mask;
+                } else {
+                    const uint32_t sh = 16u * half;
+                    const uint32_t res = sqa_slices<4, SCALED>(
+                        lrow, spread, c0 >> sh, c1 >> sh, c2 >> sh, t0b >> sh, t1b >> sh, base4, j,
+                        t, x2, c3, A.key0, A.key1, 4, 4u * half);
+                    ((uint16_t *)(sp + 2 * j + p))[half] = (uint16_t)(res & (mask >> sh));
                 }
-                sp[2 * j + p] = res & mask;
             }
             __syncthreads();
         }
     }
     __syncthreads();
-    for (int i = tid; i < 2 * npad; i += kSqaThreads) g[i] = sp[i];
+    for (int i = tid; i < 2 * npad; i += THREADS) g[i] = sp[i];
     if (A.do_energy) {
         // Energy (Eq. 8, original couplings) of every slice k, threads split over (k, sites).
         const int M = A.M;
-        for (int k = tid; k < 2 * M; k += kSqaThreads) red[k] = 0;
+        for (int k = tid; k < 2 * M; k += THREADS) red[k] = 0;
         __syncthreads();
         const uint4 *recj = A.rec_j + I.recj_off;
-        for (int task = tid; task < M * 4; task += kSqaThreads) {
+        const int parts = THREADS / M > 1 ? THREADS / M : 1;
+        for (int task = tid; task < M * parts; task += THREADS) {
             const int k = task % M, part = task / M;
             const int p = k & 1, h = k >> 1;
             int32_t acc = 0;
-            for (int j = part; j < n; j += 4) {
+            for (int j = part; j < n; j += parts) {
                 const uint4 rr = recj[j];
                 const uint32_t jn = rr.x >> 19;
                 const uint32_t nbs[6] = {rr.y & 0xFFFFu, rr.y >> 16, rr.z & 0xFFFFu, rr.z >> 16,
@@ -812,7 +908,7 @@ __global__ __launch_bounds__(kSqaThreads) void sqa_kernel(SqaArgs A)
             atomicAdd(&red[k], acc);
         }
         __syncthreads();
-        for (int k = tid; k < M; k += kSqaThreads)
+        for (int k = tid; k < M; k += THREADS)
             A.slice_E[((int64_t)inst * A.R + r) * M + k] = -red[k] / 2;
     }
 }
@@ -879,12 +975,48 @@ hipError_t launch_sqa_init(const SqaArgs &a, int n_inst, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, hipStream_t s)
+template <int THREADS, int NG, bool SCALED, int SPLIT>
+hipError_t launch_sqa_t(const SqaArgs &a, int n_inst, size_t lds_bytes, hipStream_t s)
 {
-    hipError_t e = allow_lds((const void *)sqa_kernel, lds_bytes);
+    const void *k = (const void *)sqa_kernel<THREADS, NG, SCALED, SPLIT>;
+    hipError_t e = allow_lds(k, lds_bytes + sizeof(uint32_t) * kSqaTabWords);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sqa_kernel, dim3(n_inst * a.R), dim3(kSqaThreads), lds_bytes, s, a);
+    hipLaunchKernelGGL((sqa_kernel<THREADS, NG, SCALED, SPLIT>), dim3(n_inst * a.R), dim3(THREADS),
+                       lds_bytes, s, a);
     return hipGetLastError();
+}
+
+template <int THREADS, bool SCALED>
+hipError_t launch_sqa_s(const SqaArgs &a, int n_inst, size_t lds_bytes, int split, hipStream_t s)
+{
+    if (((a.H + 3) >> 2) != 8) return launch_sqa_t<THREADS, 0, SCALED, 1>(a, n_inst, lds_bytes, s);
+    return split == 2 ? launch_sqa_t<THREADS, 8, SCALED, 2>(a, n_inst, lds_bytes, s)
+                      : launch_sqa_t<THREADS, 8, SCALED, 1>(a, n_inst, lds_bytes, s);
+}
+
+template <int THREADS>
+hipError_t launch_sqa_n(const SqaArgs &a, int n_inst, size_t lds_bytes, int split, hipStream_t s)
+{
+    return a.nl <= 64 ? launch_sqa_s<THREADS, true>(a, n_inst, lds_bytes, split, s)
+                      : launch_sqa_s<THREADS, false>(a, n_inst, lds_bytes, split, s);
+}
+
+bool sqa_config_valid(int threads, int split, int H)
+{
+    if (threads != 256 && threads != 512 && threads != 1024) return false;
+    if (split == 2) return ((H + 3) >> 2) == 8;
+    return split == 1;
+}
+
+hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, int threads, int split,
+                      hipStream_t s)
+{
+    if (!sqa_config_valid(threads, split, a.H)) return hipErrorInvalidValue;
+    switch (threads) {
+    case 256: return launch_sqa_n<256>(a, n_inst, lds_bytes, split, s);
+    case 1024: return launch_sqa_n<1024>(a, n_inst, lds_bytes, split, s);
+    default: return launch_sqa_n<512>(a, n_inst, lds_bytes, split, s);
+    }
 }
 
 hipError_t launch_advance(uint32_t *ctr, uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3,

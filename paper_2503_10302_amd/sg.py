@@ -48,7 +48,8 @@ class _Adaptive(C.Structure):
 
 EXPORTS = [
     "sg_create", "sg_destroy", "sg_last_error", "sg_sweep", "sg_icm", "sg_energy", "sg_swap",
-    "sg_run_apt", "sg_best", "sg_swap_counts", "sg_sqa_anneal", "sg_get_spins", "sg_set_spins",
+    "sg_run_apt", "sg_best", "sg_swap_counts", "sg_sqa_anneal", "sg_get_launch_config",
+    "sg_set_launch_config", "sg_get_spins", "sg_set_spins",
     "sg_get_counters", "sg_get_state", "sg_set_state", "sg_timer_start", "sg_timer_stop",
     "sg_synchronize", "sg_kernel_timing", "sg_kernel_time", "sg_adaptive_ladder", "sg_mlp_create", "sg_mlp_destroy",
     "sg_instance_features", "sg_mlp_set_standardisation", "sg_mlp_loss_grad", "sg_mlp_train",
@@ -79,6 +80,8 @@ def load():
         "sg_best": (i32, [P, P]),
         "sg_swap_counts": (i32, [P, P]),
         "sg_sqa_anneal": (i32, [P, P, i32, P, P]),
+        "sg_get_launch_config": (i32, [P, P]),
+        "sg_set_launch_config": (i32, [P, P]),
         "sg_get_spins": (i32, [P, P]),
         "sg_set_spins": (i32, [P, P]),
         "sg_get_counters": (i32, [P, P]),
@@ -222,6 +225,16 @@ class Context:
         bs = np.zeros((self.n_inst, self.n_max), np.int8)
         self._check(self.lib.sg_sqa_anneal(self.h, _p(g), g.size, _p(bE), _p(bs)))
         return bE, bs
+
+    def launch_config(self):
+        """DT-SQA (work-group size, tasks per record); (0, 0) until the autotuner ran."""
+        c = np.zeros(2, np.int32)
+        self._check(self.lib.sg_get_launch_config(self.h, _p(c)))
+        return int(c[0]), int(c[1])
+
+    def set_launch_config(self, threads, split):
+        c = np.array([threads, split], np.int32)
+        self._check(self.lib.sg_set_launch_config(self.h, _p(c)))
 
     # -- state
     def spins(self):

@@ -200,6 +200,65 @@ def test_sqa_matches_oracle(M):
     assert ctx.counters()[0] == 12
 
 
+def test_sqa_energy_without_schedule():
+    """Slice energies right after creation and after a zero-step anneal: the kernel runs
+    its energy pass with no threshold table."""
+    insts = [_inst((5, 5, 5), 7, 51), _inst((4, 4, 4), 7, 52, hmax=3)]
+    M, R = 8, 2
+    ctx = sg.sqa(insts, M, R, 2.0, SEED)
+    E0 = ctx.energy()
+    bE, _ = ctx.sqa_anneal(np.zeros(0))
+    g = ctx.spins()
+    for i, inst in enumerate(insts):
+        l = _olat(inst)
+        sp = oracle.sqa_init(l, i, M, R, SEED)
+        assert np.array_equal(g[i, :, :, :l.n], sp)
+        ref = np.array([[oracle.energy(l, sp[r, k]) for k in range(M)] for r in range(R)])
+        assert np.array_equal(E0[i], ref)
+        assert bE[i] == ref.min()
+
+
+SQA_CONFIGS = [(256, 1), (512, 1), (1024, 1), (256, 2), (512, 2), (1024, 2)]
+
+
+@pytest.mark.parametrize("hmax,M", [(0, 64), (6, 64), (20, 64), (0, 6), (20, 6), (0, 60)])
+def test_sqa_every_launch_config_matches_oracle(hmax, M):
+    """Every DT-SQA launch configuration (work-group size, tasks per record) against the
+    oracle, with threshold tables small enough to be pre-scaled (hmax 0), larger (6) and
+    too large for double buffering (20); an odd number of steps; the autotuner's pick."""
+    insts = [_inst((5, 5, 5), 7, 41, hmax=hmax), _inst((4, 4, 6), 5, 42, hmax=hmax),
+             _inst((3, 2, 5), 0, 43, hmax=hmax, p_absent=0.2 if hmax == 0 else 0.0)]
+    R, beta = 2, 2.0
+    gam = linear_gamma(9, 3.0, 0.01)
+    lats = [_olat(x) for x in insts]
+    ref = []
+    for i, l in enumerate(lats):
+        sp = oracle.sqa_init(l, i, M, R, SEED)
+        obE, _, osE = oracle.sqa_anneal(l, i, M, R, beta, gam, SEED, 0, sp)
+        ref.append((sp, osE, obE))
+    for cfg in SQA_CONFIGS + [None]:
+        ctx = sg.sqa(insts, M, R, beta, SEED)
+        if cfg is not None:
+            if cfg[1] == 2 and not 29 <= M // 2 <= 32:
+                with pytest.raises(sg.SGError) as e:
+                    ctx.set_launch_config(*cfg)
+                assert e.value.code == sg.SG_EINVAL
+                ctx.close()
+                continue
+            ctx.set_launch_config(*cfg)
+        assert ctx.launch_config() == (cfg or (0, 0))
+        bE, _ = ctx.sqa_anneal(gam)
+        if cfg is None:
+            assert ctx.launch_config() in SQA_CONFIGS
+        g = ctx.spins()
+        sE = ctx.energy()
+        for i, l in enumerate(lats):
+            sp, osE, obE = ref[i]
+            assert np.array_equal(g[i, :, :, :l.n], sp), f"config {cfg} instance {i}"
+            assert np.array_equal(sE[i], osE) and bE[i] == obE, f"config {cfg} instance {i}"
+        ctx.close()
+
+
 def test_adaptive_ladder_matches_oracle():
     insts = [_inst((4, 4, 4), 7, 31), _inst((5, 5, 5), 7, 32), _inst((3, 4, 5), 7, 33)]
     kw = dict(beta0=0.5, alpha=1.25, tol=2.5, n_chains=10, sweeps=60, tail=25, max_steps=8)
