@@ -139,15 +139,14 @@ sg_status sg_swap_counts(sg_ctx *ctx, int64_t *counts_host);
 sg_status sg_sqa_anneal(sg_ctx *ctx, const double *gamma, int32_t n_steps, int64_t *best_E,
                         int8_t *best_state);
 
-/* DT-SQA launch configuration (implementation choice; results do not depend on it).
- * cfg[0] = work-group size (256, 512 or 1024), cfg[1] = tasks per (site, parity)
- * record (1, or 2 when M/2 is 29..32).  The first sg_sqa_anneal of a context whose
- * configuration is unset times every valid configuration for a few steps on a
- * scratch copy of the replicas and keeps the fastest (cached per workload shape
- * for the process).  get: {0, 0} while unset.  set: {0, 0} re-enables the
- * autotuner; an invalid pair gives SG_EINVAL. */
-sg_status sg_get_launch_config(sg_ctx *ctx, int32_t *cfg2);
-sg_status sg_set_launch_config(sg_ctx *ctx, const int32_t *cfg2);
+/* DT-SQA work-group size (an implementation choice; results do not depend on it):
+ * a multiple of 64 in 128..1024.  The first sg_sqa_anneal of a context whose size
+ * is unset (0) times 256, 512, 768 and 1024 for a few steps on a scratch copy of the
+ * replicas and keeps the fastest (cached per workload shape for the process).
+ * get: 0 while unset.  set: 0 re-enables the autotuner; any other value outside the
+ * allowed set gives SG_EINVAL. */
+sg_status sg_get_launch_config(sg_ctx *ctx, int32_t *threads);
+sg_status sg_set_launch_config(sg_ctx *ctx, int32_t threads);
 
 /* Spins in logical order, +1/-1.  APT [n_inst][n_beta*reps][n_max];
  * DT-SQA [n_inst][R][M][n_max]; n_max = largest n, unused tail zero. */

@@ -309,7 +309,7 @@ struct sg_ctx {
     DevBuf<int32_t> d_slice_E;
     size_t sqa_lds = 0;
     uint32_t sqa_steps = 0;
-    int sqa_threads = 0, sqa_split = 0;   // 0: chosen by the autotuner on the next anneal
+    int sqa_threads = 0;   // work-group size; 0: chosen by the autotuner on the next anneal
 
     ~sg_ctx()
     {
@@ -759,13 +759,16 @@ SqaArgs sqa_args(sg_ctx *c)
 }
 
 // ---- DT-SQA launch-configuration autotuner
-// Candidates: work-group size x tasks per record.  Each is timed over up to 32
-// steps on a scratch copy of the replicas (the context's state, counters and
-// results are untouched: every configuration computes the same bits), twice, and
-// the fastest minimum wins.  The
-// choice is cached per workload shape for the life of the process.
+// Candidates: work-groups of 4, 8, 12 and 16 waves (a whole number of waves per
+// SIMD; other sizes leave the four SIMDs of a CU unevenly loaded and measured 10-25 %
+// slower).  Each is timed over up to 32 steps on a scratch copy of the replicas (the
+// context's state, counters and results are untouched: every size computes the same
+// bits), twice, and the fastest minimum wins.  The size sets the number of record
+// passes per colour phase (its ragged last pass) and, with the LDS per replica, the
+// work-groups and waves resident per CU.  The choice is cached per workload shape for
+// the life of the process.
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> g_tune_cache;
+std::map<std::string, int> g_tune_cache;
 
 std::string sqa_tune_key(const sg_ctx *c)
 {
@@ -784,32 +787,30 @@ void sqa_autotune(sg_ctx *c, const SqaArgs &base, int ns)
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
-            c->sqa_threads = it->second.first;
-            c->sqa_split = it->second.second;
+            c->sqa_threads = it->second;
             return;
         }
     }
-    const int cand[6][2] = {{512, 1}, {512, 2}, {256, 1}, {256, 2}, {1024, 1}, {1024, 2}};
+    constexpr int kCand = 4;   // 256, 512, 768, 1024 threads
     DevBuf<uint32_t> scratch;
     scratch.alloc(c->d_sqa.n, "autotune scratch");
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "autotune");
     hip_check(hipEventCreate(&e1), "autotune");
-    float best_ms[6];
-    for (int q = 0; q < 6; ++q) best_ms[q] = std::numeric_limits<float>::infinity();
+    float best_ms[kCand];
+    for (int q = 0; q < kCand; ++q) best_ms[q] = std::numeric_limits<float>::infinity();
     SqaArgs a = base;
     a.spins = scratch.p;
     a.n_steps = std::min(ns, 32);
     a.do_energy = 0;
     hipError_t err = hipSuccess;
     for (int rep = 0; rep < 2 && err == hipSuccess; ++rep)
-        for (int q = 0; q < 6 && err == hipSuccess; ++q) {
-            if (!sqa_config_valid(cand[q][0], cand[q][1], c->H)) continue;
+        for (int q = 0; q < kCand && err == hipSuccess; ++q) {
+            const int threads = 256 * (q + 1);
             err = hipMemcpyAsync(scratch.p, c->d_sqa.p, c->d_sqa.n * sizeof(uint32_t),
                                  hipMemcpyDeviceToDevice, c->stream);
             if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
-            if (err == hipSuccess)
-                err = launch_sqa(a, c->n_inst, c->sqa_lds, cand[q][0], cand[q][1], c->stream);
+            if (err == hipSuccess) err = launch_sqa(a, c->n_inst, c->sqa_lds, threads, c->stream);
             if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
             if (err == hipSuccess) err = hipEventSynchronize(e1);
             float ms = 0.f;
@@ -820,16 +821,14 @@ void sqa_autotune(sg_ctx *c, const SqaArgs &base, int ns)
     (void)hipEventDestroy(e1);
     hip_check(err, "autotune");
     int pick = 0;
-    for (int q = 1; q < 6; ++q)
+    for (int q = 1; q < kCand; ++q)
         if (best_ms[q] < best_ms[pick]) pick = q;
-    c->sqa_threads = cand[pick][0];
-    c->sqa_split = cand[pick][1];
+    c->sqa_threads = 256 * (pick + 1);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = {c->sqa_threads, c->sqa_split};
+    g_tune_cache[key] = c->sqa_threads;
 }
 
 int sqa_threads_or_default(const sg_ctx *c) { return c->sqa_threads ? c->sqa_threads : 512; }
-int sqa_split_or_default(const sg_ctx *c) { return c->sqa_split ? c->sqa_split : 1; }
 
 // Event pair bracketing one main-kernel launch when kernel timing is on.
 hipEvent_t kernel_event(sg_ctx *c, bool start)
@@ -967,8 +966,7 @@ sg_status sg_energy(sg_ctx *c, int64_t *E_host)
             a.n_steps = 0;
             a.do_energy = 1;
             a.lut = nullptr;
-            hip_check(launch_sqa(a, c->n_inst, c->sqa_lds, sqa_threads_or_default(c),
-                                 sqa_split_or_default(c), c->stream),
+            hip_check(launch_sqa(a, c->n_inst, c->sqa_lds, sqa_threads_or_default(c), c->stream),
                       "energy");
             std::vector<int32_t> e((size_t)c->n_inst * c->R * c->M);
             c->d_slice_E.download(e.data(), e.size(), c->stream, "energy");
@@ -1090,28 +1088,22 @@ sg_status sg_swap_counts(sg_ctx *c, int64_t *counts)
     });
 }
 
-sg_status sg_get_launch_config(sg_ctx *c, int32_t *cfg2)
+sg_status sg_get_launch_config(sg_ctx *c, int32_t *threads)
 {
     return guarded(c, [&] {
         require(c, SG_SQA);
-        if (!cfg2) fail(SG_EINVAL, "cfg is NULL");
-        cfg2[0] = c->sqa_threads;
-        cfg2[1] = c->sqa_split;
+        if (!threads) fail(SG_EINVAL, "threads is NULL");
+        *threads = c->sqa_threads;
     });
 }
 
-sg_status sg_set_launch_config(sg_ctx *c, const int32_t *cfg2)
+sg_status sg_set_launch_config(sg_ctx *c, int32_t threads)
 {
     return guarded(c, [&] {
         require(c, SG_SQA);
-        if (!cfg2) fail(SG_EINVAL, "cfg is NULL");
-        if (cfg2[0] == 0 && cfg2[1] == 0) {
-            c->sqa_threads = c->sqa_split = 0;
-            return;
-        }
-        if (!sqa_config_valid(cfg2[0], cfg2[1], c->H)) fail(SG_EINVAL, "invalid launch configuration");
-        c->sqa_threads = cfg2[0];
-        c->sqa_split = cfg2[1];
+        if (threads != 0 && !sqa_config_valid(threads))
+            fail(SG_EINVAL, "work-group size must be a multiple of 64 in 128..1024");
+        c->sqa_threads = threads;
     });
 }
 
@@ -1147,8 +1139,7 @@ sg_status sg_sqa_anneal(sg_ctx *c, const double *gamma, int32_t n_steps, int64_t
             a.do_energy = (done + ns == n_steps) ? 1 : 0;
             if (c->sqa_threads == 0) sqa_autotune(c, a, ns);
             kernel_event(c, true);
-            hip_check(launch_sqa(a, c->n_inst, c->sqa_lds, c->sqa_threads, c->sqa_split,
-                                 c->stream),
+            hip_check(launch_sqa(a, c->n_inst, c->sqa_lds, c->sqa_threads, c->stream),
                       "anneal");
             kernel_event(c, false);
             c->sqa_steps += (uint32_t)ns;
@@ -1158,8 +1149,7 @@ sg_status sg_sqa_anneal(sg_ctx *c, const double *gamma, int32_t n_steps, int64_t
             SqaArgs a = sqa_args(c);
             a.n_steps = 0;
             a.do_energy = 1;
-            hip_check(launch_sqa(a, c->n_inst, c->sqa_lds, sqa_threads_or_default(c),
-                                 sqa_split_or_default(c), c->stream),
+            hip_check(launch_sqa(a, c->n_inst, c->sqa_lds, sqa_threads_or_default(c), c->stream),
                       "anneal");
         }
         if (best_E || best_state) {

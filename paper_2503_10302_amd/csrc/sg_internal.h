@@ -153,11 +153,9 @@ hipError_t launch_apt_init(const InstDev *inst_d, const QuadDesc *desc, int n_bl
 hipError_t launch_apt_quad(const AptArgs &a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_apt_swap(const SwapArgs &a, hipStream_t s);
 hipError_t launch_sqa_init(const SqaArgs &a, int n_inst, hipStream_t s);
-// DT-SQA kernel in one of its launch configurations: work-group size 256, 512 or
-// 1024 threads, SPLIT 1 or 2 tasks per (site, parity) record (2 needs M/2 in 29..32).
-bool sqa_config_valid(int threads, int split, int H);
-hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, int threads, int split,
-                      hipStream_t s);
+// DT-SQA kernel with a work-group of `threads` (a multiple of 64 in 128..1024).
+bool sqa_config_valid(int threads);
+hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, int threads, hipStream_t s);
 hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 // ctr[i] += d[i] for the four counters (one thread; ordered by the stream).

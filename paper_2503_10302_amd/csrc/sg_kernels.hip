@@ -770,14 +770,13 @@ __device__ __forceinline__ uint32_t sqa_slices(const uint32_t *lut, const uint32
     return res;
 }
 
-// THREADS: work-group size.  SPLIT: tasks per (site, parity) record; with SPLIT = 2
-// (only for 8 slice groups) a task updates 16 slices and stores a 16-bit half word.
-// Waves are limited to 64 VGPRs (8 waves per SIMD).
-template <int THREADS, int NG, bool SCALED, int SPLIT>
-__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(8, 8)))
+// The work-group size is a launch-time choice (a multiple of 64, at most 1024);
+// waves are limited to 64 VGPRs (8 waves per SIMD).
+template <int NG, bool SCALED>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)))
 void sqa_kernel(SqaArgs A)
 {
-    static_assert(SPLIT == 1 || (SPLIT == 2 && NG == 8), "split needs 8 slice groups");
+    const int THREADS = blockDim.x;
     // Tables at fixed (static) LDS addresses, so that table offsets need no base
     // register: thresholds (<= 256 entries), spread tables, reduction scratch.  The
     // replica lives in dynamic LDS.
@@ -832,9 +831,7 @@ void sqa_kernel(SqaArgs A)
                     lut[128 * ((st + 1) & 1) + i] = A.lut[(int64_t)(A.lut_step0 + st + 1) * A.nl + i];
             const uint4 *rc = A.rec + I.rec_off + A.inst[inst].col_off[c];
             const int cnt = A.inst[inst].col_cnt[c];
-            for (int it = tid; it < SPLIT * cnt; it += THREADS) {
-                const int i = SPLIT == 1 ? it : (it >> 1);
-                const uint32_t half = SPLIT == 1 ? 0u : (uint32_t)(it & 1);
+            for (int i = tid; i < cnt; i += THREADS) {
                 const uint4 rr = rc[i];
                 const uint32_t j = rr.x & 0xFFFFu;
                 const uint32_t p = rr.x >> 31;
@@ -862,18 +859,10 @@ void sqa_kernel(SqaArgs A)
                                                        (int32_t)((rr.x >> 16) & 7u) + A.smax)) *
                                        0x01010101u;
                 const uint32_t x2 = ((uint32_t)r << 16) | (p << 15);
-                if (SPLIT == 1) {
-                    const uint32_t res = sqa_slices<NG, SCALED>(lrow, spread, c0, c1, c2, t0b, t1b,
-                                                                base4, j, t, x2, c3, A.key0,
-                                                                A.key1, ngrp, 0u);
-                    sp[2 * j + p] = res & mask;
-                } else {
-                    const uint32_t sh = 16u * half;
-                    const uint32_t res = sqa_slices<4, SCALED>(
-                        lrow, spread, c0 >> sh, c1 >> sh, c2 >> sh, t0b >> sh, t1b >> sh, base4, j,
-                        t, x2, c3, A.key0, A.key1, 4, 4u * half);
-                    ((uint16_t *)(sp + 2 * j + p))[half] = (uint16_t)(res & (mask >> sh));
-                }
+                const uint32_t res = sqa_slices<NG, SCALED>(lrow, spread, c0, c1, c2, t0b, t1b,
+                                                            base4, j, t, x2, c3, A.key0, A.key1,
+                                                            ngrp, 0u);
+                sp[2 * j + p] = res & mask;
             }
             __syncthreads();
         }
@@ -975,48 +964,27 @@ hipError_t launch_sqa_init(const SqaArgs &a, int n_inst, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int THREADS, int NG, bool SCALED, int SPLIT>
-hipError_t launch_sqa_t(const SqaArgs &a, int n_inst, size_t lds_bytes, hipStream_t s)
+template <int NG, bool SCALED>
+hipError_t launch_sqa_t(const SqaArgs &a, int n_inst, size_t lds_bytes, int threads, hipStream_t s)
 {
-    const void *k = (const void *)sqa_kernel<THREADS, NG, SCALED, SPLIT>;
+    const void *k = (const void *)sqa_kernel<NG, SCALED>;
     hipError_t e = allow_lds(k, lds_bytes + sizeof(uint32_t) * kSqaTabWords);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((sqa_kernel<THREADS, NG, SCALED, SPLIT>), dim3(n_inst * a.R), dim3(THREADS),
-                       lds_bytes, s, a);
+    hipLaunchKernelGGL((sqa_kernel<NG, SCALED>), dim3(n_inst * a.R), dim3(threads), lds_bytes, s, a);
     return hipGetLastError();
 }
 
-template <int THREADS, bool SCALED>
-hipError_t launch_sqa_s(const SqaArgs &a, int n_inst, size_t lds_bytes, int split, hipStream_t s)
-{
-    if (((a.H + 3) >> 2) != 8) return launch_sqa_t<THREADS, 0, SCALED, 1>(a, n_inst, lds_bytes, s);
-    return split == 2 ? launch_sqa_t<THREADS, 8, SCALED, 2>(a, n_inst, lds_bytes, s)
-                      : launch_sqa_t<THREADS, 8, SCALED, 1>(a, n_inst, lds_bytes, s);
-}
+bool sqa_config_valid(int threads) { return threads >= 128 && threads <= 1024 && threads % 64 == 0; }
 
-template <int THREADS>
-hipError_t launch_sqa_n(const SqaArgs &a, int n_inst, size_t lds_bytes, int split, hipStream_t s)
+hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, int threads, hipStream_t s)
 {
-    return a.nl <= 64 ? launch_sqa_s<THREADS, true>(a, n_inst, lds_bytes, split, s)
-                      : launch_sqa_s<THREADS, false>(a, n_inst, lds_bytes, split, s);
-}
-
-bool sqa_config_valid(int threads, int split, int H)
-{
-    if (threads != 256 && threads != 512 && threads != 1024) return false;
-    if (split == 2) return ((H + 3) >> 2) == 8;
-    return split == 1;
-}
-
-hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, int threads, int split,
-                      hipStream_t s)
-{
-    if (!sqa_config_valid(threads, split, a.H)) return hipErrorInvalidValue;
-    switch (threads) {
-    case 256: return launch_sqa_n<256>(a, n_inst, lds_bytes, split, s);
-    case 1024: return launch_sqa_n<1024>(a, n_inst, lds_bytes, split, s);
-    default: return launch_sqa_n<512>(a, n_inst, lds_bytes, split, s);
-    }
+    if (!sqa_config_valid(threads)) return hipErrorInvalidValue;
+    const bool scaled = a.nl <= 64;
+    if (((a.H + 3) >> 2) == 8)
+        return scaled ? launch_sqa_t<8, true>(a, n_inst, lds_bytes, threads, s)
+                      : launch_sqa_t<8, false>(a, n_inst, lds_bytes, threads, s);
+    return scaled ? launch_sqa_t<0, true>(a, n_inst, lds_bytes, threads, s)
+                  : launch_sqa_t<0, false>(a, n_inst, lds_bytes, threads, s);
 }
 
 hipError_t launch_advance(uint32_t *ctr, uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3,

@@ -81,7 +81,7 @@ def load():
         "sg_swap_counts": (i32, [P, P]),
         "sg_sqa_anneal": (i32, [P, P, i32, P, P]),
         "sg_get_launch_config": (i32, [P, P]),
-        "sg_set_launch_config": (i32, [P, P]),
+        "sg_set_launch_config": (i32, [P, i32]),
         "sg_get_spins": (i32, [P, P]),
         "sg_set_spins": (i32, [P, P]),
         "sg_get_counters": (i32, [P, P]),
@@ -227,14 +227,13 @@ class Context:
         return bE, bs
 
     def launch_config(self):
-        """DT-SQA (work-group size, tasks per record); (0, 0) until the autotuner ran."""
-        c = np.zeros(2, np.int32)
-        self._check(self.lib.sg_get_launch_config(self.h, _p(c)))
-        return int(c[0]), int(c[1])
+        """DT-SQA work-group size; 0 until the autotuner has run."""
+        t = C.c_int32(0)
+        self._check(self.lib.sg_get_launch_config(self.h, C.byref(t)))
+        return t.value
 
-    def set_launch_config(self, threads, split):
-        c = np.array([threads, split], np.int32)
-        self._check(self.lib.sg_set_launch_config(self.h, _p(c)))
+    def set_launch_config(self, threads):
+        self._check(self.lib.sg_set_launch_config(self.h, int(threads)))
 
     # -- state
     def spins(self):

@@ -218,14 +218,14 @@ def test_sqa_energy_without_schedule():
         assert bE[i] == ref.min()
 
 
-SQA_CONFIGS = [(256, 1), (512, 1), (1024, 1), (256, 2), (512, 2), (1024, 2)]
+SQA_THREADS = [192, 256, 320, 448, 512, 576, 768, 1024]
 
 
 @pytest.mark.parametrize("hmax,M", [(0, 64), (6, 64), (20, 64), (0, 6), (20, 6), (0, 60)])
 def test_sqa_every_launch_config_matches_oracle(hmax, M):
-    """Every DT-SQA launch configuration (work-group size, tasks per record) against the
-    oracle, with threshold tables small enough to be pre-scaled (hmax 0), larger (6) and
-    too large for double buffering (20); an odd number of steps; the autotuner's pick."""
+    """DT-SQA at several work-group sizes against the oracle, with threshold tables small
+    enough to be pre-scaled (hmax 0), larger (6) and too large for double buffering (20);
+    an odd number of steps; and the autotuner's pick."""
     insts = [_inst((5, 5, 5), 7, 41, hmax=hmax), _inst((4, 4, 6), 5, 42, hmax=hmax),
              _inst((3, 2, 5), 0, 43, hmax=hmax, p_absent=0.2 if hmax == 0 else 0.0)]
     R, beta = 2, 2.0
@@ -236,27 +236,25 @@ def test_sqa_every_launch_config_matches_oracle(hmax, M):
         sp = oracle.sqa_init(l, i, M, R, SEED)
         obE, _, osE = oracle.sqa_anneal(l, i, M, R, beta, gam, SEED, 0, sp)
         ref.append((sp, osE, obE))
-    for cfg in SQA_CONFIGS + [None]:
+    for threads in SQA_THREADS + [0]:
         ctx = sg.sqa(insts, M, R, beta, SEED)
-        if cfg is not None:
-            if cfg[1] == 2 and not 29 <= M // 2 <= 32:
-                with pytest.raises(sg.SGError) as e:
-                    ctx.set_launch_config(*cfg)
-                assert e.value.code == sg.SG_EINVAL
-                ctx.close()
-                continue
-            ctx.set_launch_config(*cfg)
-        assert ctx.launch_config() == (cfg or (0, 0))
+        ctx.set_launch_config(threads)
+        assert ctx.launch_config() == threads
         bE, _ = ctx.sqa_anneal(gam)
-        if cfg is None:
-            assert ctx.launch_config() in SQA_CONFIGS
+        if threads == 0:
+            assert ctx.launch_config() in (256, 512, 768, 1024)
         g = ctx.spins()
         sE = ctx.energy()
         for i, l in enumerate(lats):
             sp, osE, obE = ref[i]
-            assert np.array_equal(g[i, :, :, :l.n], sp), f"config {cfg} instance {i}"
-            assert np.array_equal(sE[i], osE) and bE[i] == obE, f"config {cfg} instance {i}"
+            assert np.array_equal(g[i, :, :, :l.n], sp), f"threads {threads} instance {i}"
+            assert np.array_equal(sE[i], osE) and bE[i] == obE, f"threads {threads} instance {i}"
         ctx.close()
+    ctx = sg.sqa(insts, M, R, beta, SEED)
+    for bad in (100, 64, 1088, -64):
+        with pytest.raises(sg.SGError) as e:
+            ctx.set_launch_config(bad)
+        assert e.value.code == sg.SG_EINVAL
 
 
 def test_adaptive_ladder_matches_oracle():
