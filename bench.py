@@ -38,6 +38,22 @@ VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 # the threshold compare.  Index arithmetic, LDS traffic and the neighbour sums are
 # implementation overhead and are not counted.
 ALG_OPS_PER_FLIP = (10 * (2 * 2 + 4)) / 4 + 1
+# HBM traffic of one DT-SQA launch (R = 1024, 200 steps) from two rocprofv3 counter
+# runs, FETCH_SIZE then WRITE_SIZE (KiB per dispatch), each scaled by what the same
+# counter reads for a plain 256 MiB copy (fetch x 2.0, write x 1.0).  Reported only
+# while the kernel source is the one measured.
+SQA_TRAFFIC = {"kernel_src_sha256_16": "e1730dc460646f9f", "R": 1024, "steps": 200,
+               "fetch_kib": 452648.3, "write_kib": 872448.0, "fetch_scale": 2.0, "write_scale": 1.0}
+
+
+def sqa_traffic(R, steps):
+    import hashlib
+    src = os.path.join(ROOT, "paper_2503_10302_amd", "csrc", "sg_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    t = SQA_TRAFFIC
+    if sha != t["kernel_src_sha256_16"] or R != t["R"] or steps != t["steps"]:
+        return None
+    return round((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024)
 
 
 def sqa_workload(R, seed0=20000, n_inst=32, L=15, M=64):
@@ -88,7 +104,7 @@ def cpu_baseline(insts, M, beta, gam, seconds):
 
 def time_to_target(rho0=0.007, e0_cycles=20000, max_cycles=20000, chunk=250, seeds=(101, 202),
                    ttt_seed=303, n_inst=256):
-    """Time to residual energy per spin rho <= rho0 (Eq. 2) on the config-3 batch.
+    """Time to residual energy per spin rho <= rho0 (Eq. 2) on the batch of 256 mixed instances.
 
     E0 per instance is the lowest energy seen in two long batched APT+ICM runs and in every
     run below (the paper's instances and ground energies are not available).  Batched: all
@@ -140,7 +156,7 @@ def time_to_target(rho0=0.007, e0_cycles=20000, max_cycles=20000, chunk=250, see
     cyc_all = int(first.max()) if reached_b == n_inst else None
     ms_per_cycle = ms_b / max_cycles
     out = {
-        "metric": "time to residual energy per spin <= 0.007, 256 mixed instances (config 3)",
+        "metric": "time to residual energy per spin <= 0.007, 256 mixed instances (L = 6..15)",
         "rho0": rho0, "e0": f"min over 2 x {e0_cycles}-cycle batched runs and all runs below",
         "batched": {"ms_per_cycle": round(ms_per_cycle, 5), "reached": reached_b,
                     "cycles_all_reached": cyc_all,
@@ -231,7 +247,10 @@ def main():
             "roofline": {"bound": "alu", "kernel": "sqa_kernel",
                          "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                          "unit": "Top/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                         "traffic": None, "alg_ops_per_flip": ALG_OPS_PER_FLIP,
+                         "traffic": sqa_traffic(R, args.steps),
+                         "traffic_unit": "bytes per launch (HBM, counters)",
+                         "alg_bytes_per_launch": 2 * len(insts) * R * ((n + 15) // 16 * 16) * 8,
+                         "alg_ops_per_flip": ALG_OPS_PER_FLIP,
                          "kernel_ms": round(kms, 3), "launches": nlaunch,
                          "launch_config": {"threads": ctx.launch_config(),
                                            "chosen_by": "autotuner"},
@@ -241,7 +260,7 @@ def main():
         })
         ctx.close()
 
-    # ---------------- batched APT + ICM (config 3) and plain APT (config 1)
+    # ---------------- batched APT + ICM (256 mixed instances) and plain APT (one L = 8 instance)
     if args.only in ("all", "apt"):
         insts3, ladder, sizes = apt_batched_workload()
         flips_cycle = sum(L ** 3 for L in sizes) * 64
@@ -281,7 +300,7 @@ def main():
                             "flips_per_ns": round(512 * 64 * args.apt_cycles / (ms1 * 1e6), 3)}
         if args.only == "apt":
             out.update({"value": apt["flips_per_ns"], "ms_per_step": apt["ms_per_cycle"],
-                        "config": {"workload": "batched APT+ICM, 256 mixed instances (config 3)"}})
+                        "config": {"workload": "batched APT+ICM, 256 mixed instances (L = 6..15)"}})
 
     if not args.no_cpu_baseline and args.only in ("all", "sqa"):
         out["cpu_baseline"] = cpu_baseline(insts, M, beta, gam, args.cpu_seconds)

@@ -761,7 +761,7 @@ SqaArgs sqa_args(sg_ctx *c)
 // ---- DT-SQA launch-configuration autotuner
 // Candidates: work-groups of 4, 8, 12 and 16 waves (a whole number of waves per
 // SIMD; other sizes leave the four SIMDs of a CU unevenly loaded and measured 10-25 %
-// slower).  Each is timed over up to 32 steps on a scratch copy of the replicas (the
+// slower).  Each is timed over 2..32 steps on a scratch copy of the replicas (the
 // context's state, counters and results are untouched: every size computes the same
 // bits), twice, and the fastest minimum wins.  The size sets the number of record
 // passes per colour phase (its ragged last pass) and, with the LDS per replica, the
@@ -801,7 +801,11 @@ void sqa_autotune(sg_ctx *c, const SqaArgs &base, int ns)
     for (int q = 0; q < kCand; ++q) best_ms[q] = std::numeric_limits<float>::infinity();
     SqaArgs a = base;
     a.spins = scratch.p;
-    a.n_steps = std::min(ns, 32);
+    // about 1.5e10 spin updates per timed launch (a few ms), 2..32 steps
+    double per_step = 0.0;
+    for (const InstDev &I : c->idev) per_step += (double)I.n * c->M * c->R;
+    const int want = (int)std::min(32.0, std::max(2.0, 1.5e10 / std::max(per_step, 1.0)));
+    a.n_steps = std::min(ns, want);
     a.do_energy = 0;
     hipError_t err = hipSuccess;
     for (int rep = 0; rep < 2 && err == hipSuccess; ++rep)

@@ -217,7 +217,7 @@ def default_params():
 
 
 def learned_ladders(instances, seed, params=None, pilot=1000, cutoff=None):
-    """Config-5 flow: predicted ladders, a pilot APT+ICM run, the band check, and the
+    """The learned-ladder flow: predicted ladders, a pilot APT+ICM run, the band check, and the
     adaptive stage for every instance whose ladder fails it.
 
     Returns (ladders [n][32], fell_back [n] bool, pilot acceptance [n][31])."""

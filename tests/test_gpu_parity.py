@@ -294,7 +294,7 @@ def test_mlp_gradient_matches_fp64_oracle():
 
 
 # --------------------------------------------------------------- full-size configurations
-def test_config1_plain_apt_full_size_prefix():
+def test_plain_apt_L8_full_size_prefix():
     """L = 8 periodic, 32 betas geometric in [0.2, 3.0], 2 replicas per beta, ICM at beta >= 1."""
     J, _ = ej_couplings(8, 7, seed=1)
     beta = geometric_ladder(32, 0.2, 3.0)
@@ -310,7 +310,7 @@ def test_config1_plain_apt_full_size_prefix():
     assert np.array_equal(ctx.swap_counts()[0], oacc)
 
 
-def test_config3_batched_apt_sampled_instances():
+def test_batched_apt_256_mixed_sampled_instances():
     """256 instances, L round-robin over {6, 8, 10, 12, 15}, periodic, 32 betas x 2 replicas."""
     sizes = mixed_sizes(256)
     insts = [(ej_couplings(L, 7, seed=10000 + i)[0], 7, None) for i, L in enumerate(sizes)]
@@ -334,7 +334,7 @@ def test_config3_batched_apt_sampled_instances():
         assert E[i].tolist() == [oracle.energy(l, s[:l.n]) for s in g[i]]
 
 
-def test_config2_sqa_sampled_replicas():
+def test_sqa_L10_M32_R64_sampled_replicas():
     """L = 10 periodic, M = 32, R = 64, beta = 4, Gamma 3.0 -> 0.01 over 2000 steps (prefix)."""
     J, _ = ej_couplings(10, 7, seed=1)
     gam = linear_gamma(2000)
@@ -348,7 +348,7 @@ def test_config2_sqa_sampled_replicas():
         assert np.array_equal(g[0, r, :, :], sp[0]), f"replica {r}"
 
 
-def test_config4_sqa_l15_sampled_replicas():
+def test_sqa_L15_M64_R64_sampled_replicas():
     """32 instances of L = 15 periodic (three colours), M = 64, R = 64, beta = 32."""
     insts = [(ej_couplings(15, 7, seed=20000 + i)[0], 7, None) for i in range(32)]
     gam = linear_gamma(1000)
