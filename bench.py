@@ -102,77 +102,95 @@ def cpu_baseline(insts, M, beta, gam, seconds):
                       f"({flips:.3g} spin updates, {wall:.1f} s wall)"}
 
 
-def time_to_target(rho0=0.007, e0_cycles=20000, max_cycles=20000, chunk=250, seeds=(101, 202),
-                   ttt_seed=303, n_inst=256):
+def time_to_target(rho0=0.007, e0_cycles=30000, max_cycles=100000, chunk=250, bchunk=5000,
+                   seeds=(101, 202, 303), ttt_seed=404, n_inst=256):
     """Time to residual energy per spin rho <= rho0 (Eq. 2) on the batch of 256 mixed instances.
 
-    E0 per instance is the lowest energy seen in two long batched APT+ICM runs and in every
-    run below (the paper's instances and ground energies are not available).  Batched: all
-    instances in one context, time until every instance has reached the target.  Plain: each
-    instance alone in its own context, run in chunks until it reaches the target; total time
-    is the sum over instances.
+    E0 per instance is the lowest energy seen in three long batched APT+ICM runs with other seeds
+    (the paper's instances and ground energies are not available); the target E0 + rho0 n stays
+    fixed.  Batched: all instances in one context, run in chunks with a per-cycle trace until every
+    instance has reached its target.  Plain: each instance alone in its own context, run in chunks
+    until it reaches its target; the total is the sum over instances.  Runs that go below E0 are
+    counted in "e0_beaten" (a diagnostic of E0, not used to move the target).
     """
     from paper_2503_10302_amd import sg
     insts, ladder, sizes = apt_batched_workload(n_inst)
-    n = np.array([L ** 3 for L in sizes])
+    sizes = np.array(sizes)
+    n = sizes ** 3
     E0 = np.full(n_inst, np.iinfo(np.int64).max)
     for sd in seeds:
         c = sg.apt(insts, ladder, seed=sd, reps_per_beta=2)
         c.run_apt(e0_cycles, 1, 1.0)
         E0 = np.minimum(E0, c.best())
         c.close()
-    # batched run with a per-cycle trace
+    target = E0 + rho0 * n
+    # batched: chunks with a per-cycle trace until all instances are at the target
     c = sg.apt(insts, ladder, seed=ttt_seed, reps_per_beta=2)
-    c.synchronize()
-    c.timer_start()
-    tr = c.run_apt(max_cycles, 1, 1.0, record_every=1)
-    ms_b = c.timer_stop()
+    first = np.full(n_inst, -1)
+    done, ms_b = 0, 0.0
+    best = None
+    while done < max_cycles and (first < 0).any():
+        c.synchronize()
+        c.timer_start()
+        tr = c.run_apt(bchunk, 1, 1.0, record_every=1)
+        ms_b += c.timer_stop()
+        hit = tr <= target[:, None]
+        new = (first < 0) & hit.any(axis=1)
+        first[new] = done + hit[new].argmax(axis=1) + 1
+        done += bchunk
+        best = tr[:, -1]
     c.close()
-    E0 = np.minimum(E0, tr[:, -1])
-    # plain runs, one instance per context, chunked until the target is reached
-    plain_ms = 0.0
+    ms_per_cycle = ms_b / done
+    # plain: one instance per context
+    plain_ms = np.zeros(n_inst)
     plain_cycles = np.full(n_inst, -1)
+    plain_best = np.zeros(n_inst, np.int64)
     for i in range(n_inst):
         ci = sg.apt([insts[i]], ladder, seed=ttt_seed + 1 + i, reps_per_beta=2)
-        target = E0[i] + rho0 * n[i]
-        done = 0
+        k = 0
         ci.synchronize()
         ci.timer_start()
-        while done < max_cycles:
+        while k < max_cycles:
             ci.run_apt(chunk, 1, 1.0)
-            done += chunk
-            b = int(ci.best()[0])
-            if b <= target:
-                plain_cycles[i] = done
+            k += chunk
+            if int(ci.best()[0]) <= target[i]:
+                plain_cycles[i] = k
                 break
-        plain_ms += ci.timer_stop()
-        E0[i] = min(E0[i], int(ci.best()[0]))
+        plain_ms[i] = ci.timer_stop()
+        plain_best[i] = int(ci.best()[0])
         ci.close()
-    target = E0 + rho0 * n
-    hit = tr <= target[:, None]
-    first = np.where(hit.any(axis=1), hit.argmax(axis=1) + 1, -1)
     reached_b = int((first > 0).sum())
     reached_p = int((plain_cycles > 0).sum())
     cyc_all = int(first.max()) if reached_b == n_inst else None
-    ms_per_cycle = ms_b / max_cycles
+    t_b = np.sort(np.where(first > 0, first, np.inf)) * ms_per_cycle / 1e3
+
+    def q(a, f):
+        k = int(np.ceil(f * n_inst)) - 1
+        return None if not np.isfinite(a[k]) else round(float(a[k]), 4)
+
+    # plain, run one after another: time until a fraction f is done, fastest instances first
+    t_p = np.cumsum(np.sort(np.where(plain_cycles > 0, plain_ms, np.inf))) / 1e3
     out = {
         "metric": "time to residual energy per spin <= 0.007, 256 mixed instances (L = 6..15)",
-        "rho0": rho0, "e0": f"min over 2 x {e0_cycles}-cycle batched runs and all runs below",
+        "rho0": rho0, "e0": f"min over {len(seeds)} x {e0_cycles}-cycle batched runs (other seeds)",
+        "e0_beaten": int(((best < E0) | (plain_best < E0)).sum()),
         "batched": {"ms_per_cycle": round(ms_per_cycle, 5), "reached": reached_b,
                     "cycles_all_reached": cyc_all,
                     "wall_s_all_reached": None if cyc_all is None else round(cyc_all * ms_per_cycle / 1e3, 4),
+                    "wall_s_50_90_99pct": [q(t_b, 0.5), q(t_b, 0.9), q(t_b, 0.99)],
                     "cycles_median": float(np.median(first[first > 0])) if reached_b else None},
-        "plain": {"reached": reached_p, "wall_s_total": round(plain_ms / 1e3, 3),
+        "plain": {"reached": reached_p, "wall_s_total": round(float(plain_ms.sum()) / 1e3, 3),
+                  "wall_s_50_90_99pct": [q(t_p, 0.5), q(t_p, 0.9), q(t_p, 0.99)],
                   "cycles_median": float(np.median(plain_cycles[plain_cycles > 0])) if reached_p else None,
                   "chunk_cycles": chunk},
-        "by_size": {int(L): {"batched_cycles_median": float(np.median(first[(np.array(sizes) == L) & (first > 0)]))
-                             if ((np.array(sizes) == L) & (first > 0)).any() else None,
-                             "plain_cycles_median": float(np.median(plain_cycles[(np.array(sizes) == L) & (plain_cycles > 0)]))
-                             if ((np.array(sizes) == L) & (plain_cycles > 0)).any() else None}
-                    for L in sorted(set(sizes))},
+        "by_size": {int(L): {"batched_cycles_median": float(np.median(first[(sizes == L) & (first > 0)]))
+                             if ((sizes == L) & (first > 0)).any() else None,
+                             "plain_cycles_median": float(np.median(plain_cycles[(sizes == L) & (plain_cycles > 0)]))
+                             if ((sizes == L) & (plain_cycles > 0)).any() else None}
+                    for L in sorted(set(sizes.tolist()))},
     }
     if cyc_all is not None and reached_p == n_inst:
-        out["speedup_batched_over_plain"] = round(plain_ms / (cyc_all * ms_per_cycle), 2)
+        out["speedup_batched_over_plain"] = round(float(plain_ms.sum()) / (cyc_all * ms_per_cycle), 2)
     return out
 
 
@@ -187,7 +205,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["all", "sqa", "apt"], default="all")
     ap.add_argument("--ttt", action="store_true", help="time-to-target run (plain vs batched APT+ICM)")
-    ap.add_argument("--ttt-cycles", type=int, default=20000)
+    ap.add_argument("--ttt-cycles", type=int, default=30000,
+                    help="length of each reference run that fixes E0 (--ttt), of each run (--learned)")
     ap.add_argument("--learned", action="store_true",
                     help="time-to-target of plain, batched-adaptive and batched-learned APT+ICM "
                          "on 256 held-out L=15 instances (shipped network)")
@@ -203,8 +222,7 @@ def main():
     from paper_2503_10302_amd.inputs import linear_gamma
 
     if args.ttt:
-        print(json.dumps(time_to_target(e0_cycles=args.ttt_cycles, max_cycles=args.ttt_cycles)),
-              flush=True)
+        print(json.dumps(time_to_target(e0_cycles=args.ttt_cycles)), flush=True)
         return
     if args.learned:
         from paper_2503_10302_amd import ladder
