@@ -17,7 +17,10 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
+# SG_ORACLE_SO names a separately built copy of the oracle (the planted-mistake tests
+# load mutated builds this way); it is loaded as is, never rebuilt.
+_VARIANT = os.environ.get("SG_ORACLE_SO")
+_SO = _VARIANT or os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "sg_oracle.c")
 
 TAG_APT_INIT, TAG_APT_SWEEP, TAG_SWAP, TAG_ICM_PAIR, TAG_ICM_PICK = 1, 2, 3, 4, 5
@@ -27,6 +30,8 @@ MLP_NPARAM = 64 * 4 + 64 + 64 * 64 + 64 + 33 * 64 + 33
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
+    if _VARIANT:
+        return _SO
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp"
         subprocess.check_call(
