@@ -399,10 +399,17 @@ void apt_rows(const Lat &L, std::vector<uint4> &rowA, std::vector<uint4> &rowB,
               std::vector<uint4> &rowC, InstDev &I)
 {
     I.lx = L.Lx;
+    I.ly = L.Ly;
+    I.lz = L.Lz;
     I.n_rows = L.Ly * L.Lz;
+    I.planes = 0;
     if (L.Lx > 32 || I.n_rows > kQuadThreads * 4) {   // rows of one word, <= 4 rows per thread
         I.row_off = -1;
         return;
+    }
+    if (L.Ly <= 64) {
+        const int ppw = 64 / L.Ly;
+        I.planes = (L.Lz + ppw - 1) / ppw <= kQuadThreads / 64 ? 1 : 0;
     }
     I.row_off = (int32_t)rowA.size();
     for (int r = 0; r < I.n_rows; ++r) {

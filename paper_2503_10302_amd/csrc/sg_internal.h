@@ -56,6 +56,9 @@ struct InstDev {
     int32_t lx;          // row length (x extent)
     int32_t n_rows;      // Ly * Lz
     int32_t row_off;     // first entry of the row tables, -1 when lx > 32
+    int32_t ly, lz;      // y and z extents (rows are r = y + ly z)
+    int32_t planes;      // 1: every y-z plane's rows fit one per lane in one wave and all
+                         //    planes in the work-group's waves (wave-local cluster search)
 };
 
 // Row tables of an instance for the cluster search (rows of lx <= 32 sites):

@@ -364,6 +364,183 @@ __device__ void icm_pairs_rows(uint32_t *sp, const uint4 *rowA, const uint4 *row
     }
 }
 
+// The same moves as icm_pairs_rows, for lattices whose x-rows fit one per lane with whole
+// y-z planes in each wave (wave w holds planes [w ppw, (w + 1) ppw), ppw = 64 / ly).  The
+// breadth-first search becomes a flood fill: inside a wave, rows grow along x in registers
+// and along y and z by lane shuffles until nothing changes; then waves exchange the rows of
+// their boundary planes through LDS at a work-group barrier, until no wave gains a site.
+// The fill reaches the same connected component, so the cluster (and every result) is the
+// same as the search's.
+__device__ __forceinline__ uint32_t xfill(uint32_t V, uint32_t Q, uint32_t mr, uint32_t ml,
+                                          uint32_t hi)
+{
+    while (true) {
+        const uint32_t right = (V >> 1) | (V << hi), left = (V << 1) | (V >> hi);
+        const uint32_t Vn = V | (((right & mr) | (left & ml)) & Q);
+        if (Vn == V) return V;
+        V = Vn;
+    }
+}
+
+__device__ void icm_pairs_planes(uint32_t *sp, const uint4 *rowA, const uint4 *rowB,
+                                 const uint4 *rowC, int n, int lx, int ly, int lz, int np,
+                                 uint32_t pa, uint32_t pb, uint4 w01, uint32_t *Qr, uint32_t *Vr,
+                                 int32_t *red, int32_t *info0, int32_t *info1, int32_t *dE01)
+{
+    const int nrows = ly * lz;
+    uint32_t *Sr = Vr + 2 * nrows;   // spins of each pair's first replica (bit = up)
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int ppw = 64 / ly;
+    const int pl = lane / ly;
+    const int z = wv * ppw + pl, y = lane - pl * ly;
+    const bool own = pl < ppw && z < lz;
+    const int r = own ? z * ly + y : 0;
+    const uint32_t mA0 = 1u << (8 * (pa & 3u)), mB0 = 1u << (8 * (pb & 3u));
+    const uint32_t mA1 = 1u << (8 * ((pa >> 8) & 3u)), mB1 = 1u << (8 * ((pb >> 8) & 3u));
+    uint32_t q0 = 0u, q1 = 0u, s0 = 0u, s1 = 0u;
+    if (own) {
+        const uint32_t *row = sp + r * lx;
+        for (int x = 0; x < lx; ++x) {
+            const uint32_t w = row[x];
+            q0 |= (uint32_t)(((w & mA0) != 0) != ((w & mB0) != 0)) << x;
+            q1 |= (uint32_t)(((w & mA1) != 0) != ((w & mB1) != 0)) << x;
+            s0 |= (uint32_t)((w & mA0) != 0) << x;
+            s1 |= (uint32_t)((w & mA1) != 0) << x;
+        }
+        Sr[r] = s0;
+        if (np > 1) Sr[nrows + r] = s1;
+        else q1 = 0u;
+    }
+    // seeds: the k-th site with q = -1 in ascending site order; threads hold rows in
+    // ascending row order (lanes past the last plane of a wave hold none)
+    uint32_t V0 = 0u, V1 = 0u;
+    int32_t m0 = 0, m1 = 0;
+    for (int p = 0; p < np; ++p) {
+        const uint32_t qq0 = p ? q1 : q0;
+        const int32_t cnt = __popc(qq0);
+        int32_t m;
+        const int32_t prefix = block_exclusive_scan(cnt, red, &m);
+        if (p) m1 = m; else m0 = m;
+        if (m == 0) continue;
+        const uint32_t w = p ? w01.z : w01.x;
+        const int32_t k = (int32_t)(((uint64_t)w * (uint64_t)(uint32_t)m) >> 32);
+        if (own && prefix <= k && k < prefix + cnt) {
+            uint32_t qq = qq0;
+            for (int32_t i = 0; i < k - prefix; ++i) qq &= qq - 1u;
+            const int x = __builtin_ctz(qq);
+            if (p) V1 = 1u << x; else V0 = 1u << x;
+            red[16 + p] = r * lx + x;
+        }
+    }
+    __syncthreads();
+    const int32_t seed0 = m0 > 0 ? red[16] : -1;
+    const int32_t seed1 = (np > 1 && m1 > 0) ? red[17] : -1;
+    const uint32_t hi = (uint32_t)(lx - 1);
+    uint4 a = make_uint4(0u, 0u, 0u, 0u), b = a;
+    if (own) {
+        a = rowA[r];
+        b = rowB[r];
+    }
+    // source lanes of the +y, -y, +z, -z neighbour rows inside this wave, -1 outside
+    const int nbr[4] = {(int)(b.z & 0xFFFFu), (int)(b.z >> 16), (int)(b.w & 0xFFFFu),
+                        (int)(b.w >> 16)};
+    int src[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const int zr = nbr[d] / ly, yr = nbr[d] - (nbr[d] / ly) * ly;
+        src[d] = (own && zr / ppw == wv) ? (zr - wv * ppw) * ly + yr : -1;
+    }
+    const uint32_t mk[4] = {a.z, a.w, b.x, b.y};
+    const uint32_t Q0 = (m0 > 0) ? q0 : 0u, Q1 = (m1 > 0) ? q1 : 0u;
+    uint32_t X0[2] = {0u, 0u}, X1[2] = {0u, 0u};   // +z / -z rows from other waves
+    while (true) {
+        // closure inside the wave
+        while (true) {
+            V0 = xfill(V0, Q0, a.x, a.y, hi);
+            V1 = xfill(V1, Q1, a.x, a.y, hi);
+            uint32_t N0 = 0u, N1 = 0u;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int sl = src[d] >= 0 ? src[d] : lane;
+                const uint32_t u0 = __shfl(V0, sl, 64), u1 = __shfl(V1, sl, 64);
+                const uint32_t e0 = src[d] >= 0 ? u0 : (d == 2 ? X0[0] : (d == 3 ? X0[1] : 0u));
+                const uint32_t e1 = src[d] >= 0 ? u1 : (d == 2 ? X1[0] : (d == 3 ? X1[1] : 0u));
+                N0 |= e0 & mk[d];
+                N1 |= e1 & mk[d];
+            }
+            const uint32_t n0 = V0 | (N0 & Q0), n1 = V1 | (N1 & Q1);
+            const int grew = (n0 != V0) || (n1 != V1);
+            V0 = n0;
+            V1 = n1;
+            if (!__any(grew)) break;
+        }
+        // exchange boundary planes between waves
+        if (own) {
+            Vr[r] = V0;
+            Vr[nrows + r] = V1;
+        }
+        __syncthreads();
+        int changed = 0;
+        if (own) {
+#pragma unroll
+            for (int d = 2; d < 4; ++d) {
+                if (src[d] >= 0) continue;
+                X0[d - 2] = Vr[nbr[d]];
+                X1[d - 2] = Vr[nrows + nbr[d]];
+                if ((X0[d - 2] & mk[d] & Q0 & ~V0) | (X1[d - 2] & mk[d] & Q1 & ~V1)) changed = 1;
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+    // cluster sizes and, for each pair, the sum of J s_i s_j of the first replica over
+    // bonds that cross the cluster boundary (counted once, along +x, +y, +z)
+    int32_t tot[4] = {0, 0, 0, 0};
+    if (own) {
+        const uint4 cc = rowC[r];
+        for (int p = 0; p < np; ++p) {
+            const uint32_t *Vp = Vr + p * nrows, *Sp = Sr + p * nrows;
+            const uint32_t V = p ? V1 : V0, S = p ? s1 : s0;
+            tot[p] += __popc(V);
+            const uint32_t Vx = (V >> 1) | (V << hi), Sx = (S >> 1) | (S << hi);
+            const uint32_t X0b = (V ^ Vx) & a.x, N0b = S ^ Sx ^ cc.x;
+            const uint32_t X1b = (V ^ Vp[b.z & 0xFFFFu]) & a.z, N1b = S ^ Sp[b.z & 0xFFFFu] ^ cc.y;
+            const uint32_t X2b = (V ^ Vp[b.w & 0xFFFFu]) & b.x, N2b = S ^ Sp[b.w & 0xFFFFu] ^ cc.z;
+            tot[2 + p] += __popc(X0b & ~N0b) - __popc(X0b & N0b) + __popc(X1b & ~N1b) -
+                          __popc(X1b & N1b) + __popc(X2b & ~N2b) - __popc(X2b & N2b);
+        }
+    }
+    block_sum4(tot, red);
+    // cluster flip of the first replica: crossing bonds change sign -> dE = 2 * sum
+    dE01[0] = (m0 > 0 && 2 * tot[0] <= n) ? 2 * tot[2] : 0;
+    dE01[1] = (np > 1 && m1 > 0 && 2 * tot[1] <= n) ? 2 * tot[3] : 0;
+    for (int p = 0; p < np; ++p) {
+        const int32_t m = p ? m1 : m0, size = tot[p];
+        const uint32_t mA = p ? mA1 : mA0, mB = p ? mB1 : mB0;
+        const uint32_t w1 = p ? w01.w : w01.y;
+        int32_t branch = 0;
+        if (m > 0) {
+            if (2 * size > n) {
+                const uint32_t X = ((w1 >> 31) == 0u) ? mA : mB;
+                branch = ((w1 >> 31) == 0u) ? 1 : 2;
+                for (int j = tid; j < n; j += kQuadThreads) sp[j] ^= X;
+            } else if (own) {
+                uint32_t bits = p ? V1 : V0;
+                while (bits) {
+                    const int x = __builtin_ctz(bits);
+                    sp[r * lx + x] ^= (mA | mB);
+                    bits &= bits - 1u;
+                }
+            }
+        }
+        int32_t *o = p ? info1 : info0;
+        if (tid == 0 && o) {
+            if (m == 0) { o[0] = 0; o[1] = -1; o[2] = 0; o[3] = 0; }
+            else { o[0] = m; o[1] = p ? seed1 : seed0; o[2] = size; o[3] = branch; }
+        }
+        __syncthreads();
+    }
+}
+
 // Replica exchange (Eq. 4) for one instance, run by one work-group.  An
 // accepted exchange swaps the logical->physical mapping of the two slots and
 // their energies; the random word is keyed by the logical pair, so this is the
@@ -590,9 +767,16 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
                 int32_t *info1 = A.icm_info + ((int64_t)I.info_off + pidx1) * 4;
                 if (I.row_off >= 0) {
                     int32_t d01[2];
-                    icm_pairs_rows(sp, A.rowA + I.row_off, A.rowB + I.row_off, A.rowC + I.row_off, n,
-                                   I.lx, I.n_rows, np, pa, pb, make_uint4(u0.x, u0.y, u1.x, u1.y),
-                                   Qr, Vr, red, info0, info1, d01);
+                    if (I.planes)
+                        icm_pairs_planes(sp, A.rowA + I.row_off, A.rowB + I.row_off,
+                                         A.rowC + I.row_off, n, I.lx, I.ly, I.lz, np, pa, pb,
+                                         make_uint4(u0.x, u0.y, u1.x, u1.y), Qr, Vr, red, info0,
+                                         info1, d01);
+                    else
+                        icm_pairs_rows(sp, A.rowA + I.row_off, A.rowB + I.row_off,
+                                       A.rowC + I.row_off, n, I.lx, I.n_rows, np, pa, pb,
+                                       make_uint4(u0.x, u0.y, u1.x, u1.y), Qr, Vr, red, info0,
+                                       info1, d01);
                     if (tid == 0) {
                         // isoenergetic move: the partner's energy changes by the opposite amount
                         dE[pa & 3u] += d01[0];

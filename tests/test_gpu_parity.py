@@ -155,6 +155,28 @@ def test_apt_long_rows_use_queue_search():
         assert rc == 0 and np.array_equal(g[i, :, :l.n], sp) and np.array_equal(trace[i], otr)
 
 
+@pytest.mark.parametrize("reps", [2, 4])
+def test_apt_cluster_search_layouts(reps):
+    """Row-bitset cluster search in both layouts: whole y-z planes per wave (wave-local fill:
+    a wave filled exactly by 64-row planes, four waves of planes, open axes) and one row per
+    thread in thread order (more than 64 rows per plane, or more planes than four waves hold)."""
+    insts = [_inst((2, 64, 4), 7, 61), _inst((5, 16, 16), 5, 62), _inst((5, 7, 9), 1, 63),
+             _inst((4, 20, 20), 7, 64), _inst((3, 70, 2), 7, 65), _inst((7, 13, 20), 3, 66)]
+    beta = geometric_ladder(6, 0.4, 3.0)
+    ctx = sg.apt(insts, beta, SEED, reps_per_beta=reps)
+    trace = ctx.run_apt(30, 1, 0.5, record_every=5)
+    g = ctx.spins()
+    for i, inst in enumerate(insts):
+        l = _olat(inst)
+        sp = oracle.apt_init(l, i, 6 * reps, SEED)
+        ctr = np.zeros(3, np.uint32)
+        E = np.zeros(6 * reps, np.int64)
+        b = np.array([np.iinfo(np.int64).max], np.int64)
+        rc, otr, _ = oracle.apt_run(l, i, beta, reps, SEED, 30, 1, 0.5, 5, ctr, sp, E, b)
+        assert rc == 0 and np.array_equal(g[i, :, :l.n], sp), f"instance {i}"
+        assert np.array_equal(trace[i], otr), f"instance {i}"
+
+
 def test_checkpoint_resume_is_exact():
     insts = [_inst(*m) for m in MIXED[:4]]
     beta = geometric_ladder(8, 0.2, 3.0)
