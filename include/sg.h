@@ -151,6 +151,12 @@ sg_status sg_set_launch_config(sg_ctx *ctx, int32_t threads);
 /* Spins in logical order, +1/-1.  APT [n_inst][n_beta*reps][n_max];
  * DT-SQA [n_inst][R][M][n_max]; n_max = largest n, unused tail zero. */
 sg_status sg_get_spins(sg_ctx *ctx, int8_t *spins_host);
+/* A part of one instance's state, for sampling large contexts: APT logical slots
+ * [first, first + count) as [count][n], DT-SQA replicas [first, first + count) as
+ * [count][M][n] (n = that instance's site count), +1/-1.  SG_EINVAL when the
+ * instance or the range is outside the context. */
+sg_status sg_get_spins_range(sg_ctx *ctx, int32_t inst, int32_t first, int32_t count,
+                             int8_t *spins_host);
 sg_status sg_set_spins(sg_ctx *ctx, const int8_t *spins_host);
 
 /* Counters {sweeps or SQA steps done, ICM calls, swap attempts}. */

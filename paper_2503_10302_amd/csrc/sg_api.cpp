@@ -1231,6 +1231,47 @@ sg_status sg_get_spins(sg_ctx *c, int8_t *out)
     });
 }
 
+sg_status sg_get_spins_range(sg_ctx *c, int32_t inst, int32_t first, int32_t count, int8_t *out)
+{
+    return guarded(c, [&] {
+        if (!c || !out) fail(SG_EINVAL, "NULL argument");
+        if (inst < 0 || inst >= c->n_inst) fail(SG_EINVAL, "instance out of range");
+        const int total = c->mode == SG_APT ? c->n_slots : c->R;
+        if (first < 0 || count < 0 || (int64_t)first + count > total)
+            fail(SG_EINVAL, "range outside the instance's %s", c->mode == SG_APT ? "slots" : "replicas");
+        const InstDev &I = c->idev[inst];
+        if (count == 0) return;
+        if (c->mode == SG_APT) {
+            const int nb4 = 4 * c->n_quads;
+            std::vector<int32_t> perm((size_t)nb4);
+            hip_check(hipMemcpyAsync(perm.data(), c->d_perm.p + (size_t)inst * nb4, perm.size() * 4,
+                                     hipMemcpyDeviceToHost, c->stream),
+                      "spins");
+            hip_check(hipStreamSynchronize(c->stream), "spins");
+            std::vector<uint8_t> buf((size_t)I.npad);
+            for (int s = 0; s < count; ++s) {
+                hip_check(hipMemcpyAsync(buf.data(),
+                                         c->d_spins.p + I.spin_off + (int64_t)perm[first + s] * I.npad,
+                                         buf.size(), hipMemcpyDeviceToHost, c->stream),
+                          "spins");
+                hip_check(hipStreamSynchronize(c->stream), "spins");
+                for (int j = 0; j < I.n; ++j) out[(size_t)s * I.n + j] = buf[j] ? 1 : -1;
+            }
+        } else {
+            std::vector<uint32_t> w((size_t)count * I.npad * 2);
+            hip_check(hipMemcpyAsync(w.data(), c->d_sqa.p + I.spin_off + (int64_t)first * I.npad * 2,
+                                     w.size() * 4, hipMemcpyDeviceToHost, c->stream),
+                      "spins");
+            hip_check(hipStreamSynchronize(c->stream), "spins");
+            for (int r = 0; r < count; ++r)
+                for (int k = 0; k < c->M; ++k)
+                    for (int j = 0; j < I.n; ++j)
+                        out[((size_t)r * c->M + k) * I.n + j] =
+                            ((w[(size_t)r * I.npad * 2 + 2 * j + (k & 1)] >> (k >> 1)) & 1u) ? 1 : -1;
+        }
+    });
+}
+
 sg_status sg_set_spins(sg_ctx *c, const int8_t *in)
 {
     return guarded(c, [&] {

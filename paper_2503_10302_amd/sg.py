@@ -49,7 +49,7 @@ class _Adaptive(C.Structure):
 EXPORTS = [
     "sg_create", "sg_destroy", "sg_last_error", "sg_sweep", "sg_icm", "sg_energy", "sg_swap",
     "sg_run_apt", "sg_best", "sg_swap_counts", "sg_sqa_anneal", "sg_get_launch_config",
-    "sg_set_launch_config", "sg_get_spins", "sg_set_spins",
+    "sg_set_launch_config", "sg_get_spins", "sg_get_spins_range", "sg_set_spins",
     "sg_get_counters", "sg_get_state", "sg_set_state", "sg_timer_start", "sg_timer_stop",
     "sg_synchronize", "sg_kernel_timing", "sg_kernel_time", "sg_adaptive_ladder", "sg_mlp_create", "sg_mlp_destroy",
     "sg_instance_features", "sg_mlp_set_standardisation", "sg_mlp_loss_grad", "sg_mlp_train",
@@ -83,6 +83,7 @@ def load():
         "sg_get_launch_config": (i32, [P, P]),
         "sg_set_launch_config": (i32, [P, i32]),
         "sg_get_spins": (i32, [P, P]),
+        "sg_get_spins_range": (i32, [P, i32, i32, i32, P]),
         "sg_set_spins": (i32, [P, P]),
         "sg_get_counters": (i32, [P, P]),
         "sg_get_state": (i32, [P, P, C.POINTER(C.c_size_t)]),
@@ -242,6 +243,14 @@ class Context:
         else:
             s = np.zeros((self.n_inst, self.R, self.M, self.n_max), np.int8)
         self._check(self.lib.sg_get_spins(self.h, _p(s)))
+        return s
+
+    def spins_range(self, inst, first, count):
+        """APT slots / DT-SQA replicas [first, first + count) of one instance."""
+        n = int(self.ns[inst])
+        shape = (count, n) if self.mode == SG_APT else (count, self.M, n)
+        s = np.zeros(shape, np.int8)
+        self._check(self.lib.sg_get_spins_range(self.h, int(inst), int(first), int(count), _p(s)))
         return s
 
     def set_spins(self, s):

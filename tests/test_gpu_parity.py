@@ -354,6 +354,9 @@ def test_batched_apt_256_mixed_sampled_instances():
     for i in range(0, 256, 37):
         l = oracle.Lattice(insts[i][0], 7)
         assert E[i].tolist() == [oracle.energy(l, s[:l.n]) for s in g[i]]
+    # the range reader returns the same logical slots
+    for i, first, count in ((4, 0, 64), (131, 17, 5), (255, 63, 1)):
+        assert np.array_equal(ctx.spins_range(i, first, count), g[i, first:first + count, :insts[i][0][..., 0].size])
 
 
 def test_sqa_L10_M32_R64_sampled_replicas():
@@ -368,6 +371,27 @@ def test_sqa_L10_M32_R64_sampled_replicas():
         sp = oracle.sqa_init(l, 0, 32, 1, 2002, r0=r)
         oracle.sqa_anneal(l, 0, 32, 1, 4.0, gam[:6], 2002, 0, sp, r0=r)
         assert np.array_equal(g[0, r, :, :], sp[0]), f"replica {r}"
+
+
+def test_sqa_L15_M64_R1024_sampled_replicas_benchmark_configuration():
+    """The timed workload itself: 32 instances of L = 15, M = 64, R = 1024, beta = 32, in the
+    launch configuration the autotuner picks; sampled replicas against the oracle."""
+    insts = [(ej_couplings(15, 7, seed=20000 + i)[0], 7, None) for i in range(32)]
+    gam = linear_gamma(1000)
+    ctx = sg.sqa(insts, 64, 1024, 32.0, 4004)
+    bE, _ = ctx.sqa_anneal(gam[:4])
+    assert ctx.launch_config() in (256, 512, 768, 1024)
+    sE = ctx.energy()
+    for i, r in ((0, 0), (17, 511), (31, 1023)):
+        l = oracle.Lattice(insts[i][0], 7)
+        sp = oracle.sqa_init(l, i, 64, 1, 4004, r0=r)
+        _, _, osE = oracle.sqa_anneal(l, i, 64, 1, 32.0, gam[:4], 4004, 0, sp, r0=r)
+        assert np.array_equal(ctx.spins_range(i, r, 1)[0], sp[0]), f"instance {i} replica {r}"
+        assert np.array_equal(sE[i, r], osE[0])
+    assert np.array_equal(bE, sE.reshape(32, -1).min(axis=1))
+    with pytest.raises(sg.SGError) as e:
+        ctx.spins_range(0, 1020, 5)
+    assert e.value.code == sg.SG_EINVAL
 
 
 def test_sqa_L15_M64_R64_sampled_replicas():
