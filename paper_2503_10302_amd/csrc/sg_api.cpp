@@ -345,6 +345,20 @@ void init_stream(sg_ctx *c, void *s)
     }
 }
 
+// LDS of one APT work-group (see apt_quad_kernel): tile, four threshold tables,
+// reduction scratch, cluster-search row bitmaps, and for the queue search (rows longer
+// than 32 sites) the visited bits and the queue.
+size_t apt_lds_bytes(int npad, int n_rows, int ni, bool queue)
+{
+    size_t words = (size_t)(npad + 4 + 4 * ni + 32 + 6 * n_rows);
+    size_t bytes = 16;
+    if (queue) {
+        words += (size_t)((npad + 31) / 32 + 1);
+        bytes += sizeof(uint16_t) * (size_t)npad;
+    }
+    return sizeof(uint32_t) * words + bytes;
+}
+
 // Colour classes of the spatial lattice (Methods, "Graph Coloring").
 void apt_records(const Lat &L, std::vector<uint4> &rec, std::vector<uint4> &recj, InstDev &I)
 {
@@ -574,9 +588,7 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
     c->d_desc.upload(desc, s, "tasks");
     c->quad_lds = 0;
     for (auto &I : c->idev) {
-        const size_t need = sizeof(uint32_t) * (size_t)(I.npad + 4 + 4 * c->ni + 32 + (I.npad + 31) / 32 + 1 +
-                                                        6 * I.n_rows) +
-                            sizeof(uint16_t) * (size_t)I.npad + 16;
+        const size_t need = apt_lds_bytes(I.npad, I.n_rows, c->ni, I.row_off < 0);
         c->quad_lds = std::max(c->quad_lds, need);
     }
     if (c->quad_lds > kMaxLds)

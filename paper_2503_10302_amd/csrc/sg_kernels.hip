@@ -38,6 +38,23 @@ __device__ __forceinline__ uint4 philox10(uint32_t x0, uint32_t x1, uint32_t x2,
     return make_uint4(x0, x1, x2, x3);
 }
 
+__device__ __forceinline__ uint32_t lds_word(const uint32_t *base, uint32_t byte_off)
+{
+    return *(const uint32_t *)((const uint8_t *)base + byte_off);
+}
+
+// acc = 2 acc + (u < T): the borrow of u - T shifted into acc (two VOP2 operations).
+__device__ __forceinline__ uint32_t shift_in_lt(uint32_t acc, uint32_t u, uint32_t T)
+{
+    uint32_t d;
+    asm("v_sub_co_u32_e32 %1, vcc, %2, %3\n\t"
+        "v_addc_co_u32_e32 %0, vcc, %0, %0, vcc"
+        : "+v"(acc), "=&v"(d)
+        : "v"(u), "v"(T)
+        : "vcc");
+    return acc;
+}
+
 __device__ __forceinline__ uint32_t bytemask(uint32_t bit) { return bit * 0x01010101u; }
 
 // Per byte (slot): number of present bonds whose J * s_neighbour = +1.
@@ -647,10 +664,11 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
         uint32_t *sp = lds;                              // npad + 4 words
         uint32_t *lut = sp + npad + 4;                   // 4 * ni
         int32_t *red = (int32_t *)(lut + 4 * ni);        // 32
-        uint32_t *vis = (uint32_t *)(red + 32);          // (npad + 31) / 32 + 1
-        uint32_t *Qr = vis + ((npad + 31) >> 5) + 1;     // 2 * n_rows
+        uint32_t *Qr = (uint32_t *)(red + 32);           // 2 * n_rows
         uint32_t *Vr = Qr + 2 * I.n_rows;                // 2 * n_rows, then S rows 2 * n_rows
-        uint16_t *queue = (uint16_t *)(Vr + 4 * I.n_rows);   // npad
+        // queue search only (rows longer than 32 sites): allocated when some instance needs it
+        uint32_t *vis = Vr + 4 * I.n_rows;               // (npad + 31) / 32 + 1
+        uint16_t *queue = (uint16_t *)(vis + ((npad + 31) >> 5) + 1);   // npad
         const int q = D.quad;
         const int32_t *pp = A.perm + I.slot_off + 4 * q;
         const int64_t b0 = (int64_t)pp[0] * npad, b1 = (int64_t)pp[1] * npad;
@@ -681,6 +699,10 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
         // this thread's share of each slot's energy change in this launch
         int32_t dE[4] = {0, 0, 0, 0};
         bool full_energy = A.do_energy == 2;
+        // threshold offsets: table of slot b at b * ni; with ni <= 16 the four byte offsets
+        // of one site fit one word (index bytes + table starts, times 4)
+        const bool scaled = ni <= 16;
+        const uint32_t soff4 = (uint32_t)ni * 0x03020100u;
         for (int sw = 0; sw < A.n_sweeps; ++sw) {
             const uint32_t t = t0 + (uint32_t)sw;
             for (int c = 0; c < I.n_colours; ++c) {
@@ -691,21 +713,40 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
                     const uint4 r = rnext;
                     if (i + kQuadThreads < cnt) rnext = rc[i + kQuadThreads];   // prefetch
                     const uint32_t j = r.x & 0xFFFFu;
-                    const uint32_t k = aligned_count(sp, r);
-                    const int32_t base = (int32_t)((r.x >> 25) & 63u) - 32 -
-                                         (int32_t)((r.x >> 16) & 7u) + A.imax;
+                    const uint32_t k4 = aligned_count(sp, r);
+                    // table index per slot byte: 2 k + h - d + imax (>= 0, <= 2 imax)
+                    const uint32_t base = ((r.x >> 25) & 63u) + (uint32_t)(A.imax - 32) -
+                                          ((r.x >> 16) & 7u);
+                    const uint32_t idx4 = (k4 << 1) + __builtin_amdgcn_perm(0u, base, 0u);   // base in every byte
                     const uint4 u = philox10(j, t, (uint32_t)q, c3, A.key0, A.key1);
                     const uint32_t old = sp[j];
-                    const uint32_t us[4] = {u.x, u.y, u.z, u.w};
-                    uint32_t nw = 0u;
+                    uint32_t o0, o1, o2, o3;
+                    if (scaled) {
+                        const uint32_t off4 = (idx4 + soff4) << 2;
+                        o0 = off4 & 0xFFu;
+                        o1 = (off4 >> 8) & 0xFFu;
+                        o2 = (off4 >> 16) & 0xFFu;
+                        o3 = off4 >> 24;
+                    } else {
+                        o0 = (idx4 & 0xFFu) << 2;
+                        o1 = (((idx4 >> 8) & 0xFFu) + (uint32_t)ni) << 2;
+                        o2 = (((idx4 >> 16) & 0xFFu) + 2u * (uint32_t)ni) << 2;
+                        o3 = ((idx4 >> 24) + 3u * (uint32_t)ni) << 2;
+                    }
+                    uint32_t acc = 0u;   // bit b: new state of slot b (Eq. 6)
+                    acc = shift_in_lt(acc, u.w, lds_word(lut, o3));
+                    acc = shift_in_lt(acc, u.z, lds_word(lut, o2));
+                    acc = shift_in_lt(acc, u.y, lds_word(lut, o1));
+                    acc = shift_in_lt(acc, u.x, lds_word(lut, o0));
+                    const uint32_t nw = __umul24(acc, 0x00204081u) & 0x01010101u;   // bit b -> byte b
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
-                        const int32_t idx = 2 * (int32_t)((k >> (8 * b)) & 0xFFu) + base;
-                        const uint32_t up = us[b] < lut[b * ni + idx] ? 1u : 0u;
-                        nw |= up << (8 * b);
-                        // Eq. (8): flipping s_j changes E by -(s_new - s_old) * I_j, I_j = idx - imax
-                        const int32_t I2 = 2 * (idx - A.imax);
-                        if (up != ((old >> (8 * b)) & 1u)) dE[b] += up ? -I2 : I2;
+                        // Eq. (8): the update changes E by -(s_new - s_old) I_j = 2 (o - n) I_j,
+                        // with o, n the old and new states (0/1) and I_j = index - imax
+                        const int32_t ob = (int32_t)((old >> (8 * b)) & 1u);
+                        const int32_t nb = (int32_t)((acc >> b) & 1u);
+                        const int32_t Ij = (int32_t)((idx4 >> (8 * b)) & 0xFFu) - A.imax;
+                        dE[b] += __mul24(ob - nb, 2 * Ij);
                     }
                     sp[j] = nw;
                 }
@@ -889,23 +930,6 @@ __device__ __forceinline__ uint32_t nib_off(uint32_t x, int g)
 {
     if (NG > 0) return g == 0 ? ((x << 2) & 0x3Cu) : ((x >> (4 * g - 2)) & 0x3Cu);
     return ((x >> (4 * g)) & 15u) << 2;
-}
-
-__device__ __forceinline__ uint32_t lds_word(const uint32_t *base, uint32_t byte_off)
-{
-    return *(const uint32_t *)((const uint8_t *)base + byte_off);
-}
-
-// acc = 2 acc + (u < T): the borrow of u - T shifted into acc (two VOP2 operations).
-__device__ __forceinline__ uint32_t shift_in_lt(uint32_t acc, uint32_t u, uint32_t T)
-{
-    uint32_t d;
-    asm("v_sub_co_u32_e32 %1, vcc, %2, %3\n\t"
-        "v_addc_co_u32_e32 %0, vcc, %0, %0, vcc"
-        : "+v"(acc), "=&v"(d)
-        : "v"(u), "v"(T)
-        : "vcc");
-    return acc;
 }
 
 // New states of the H slices of one parity at one site (Supplementary Eq. S.3 with
