@@ -177,6 +177,32 @@ def test_apt_cluster_search_layouts(reps):
         assert np.array_equal(trace[i], otr), f"instance {i}"
 
 
+def test_paper_geometry_15x15x12_open_in_x_and_y():
+    """The paper's logical-instance geometry (15 x 15 x 12, open in x and y, periodic in z):
+    batched APT + ICM with 4 labels per temperature and DT-SQA at M = 64, sampled against
+    the oracle."""
+    insts = [(ej_couplings((15, 15, 12), 4, seed=70000 + i)[0], 4, None) for i in range(8)]
+    beta = geometric_ladder(32, 0.2, 3.0)
+    ctx = sg.apt(insts, beta, 99, 4)
+    tr = ctx.run_apt(3, 1, 1.0, record_every=1)
+    for i in (0, 7):
+        l = oracle.Lattice(insts[i][0], 4)
+        sp = oracle.apt_init(l, i, 128, 99)
+        ctr = np.zeros(3, np.uint32)
+        E = np.zeros(128, np.int64)
+        b = np.array([np.iinfo(np.int64).max], np.int64)
+        rc, otr, _ = oracle.apt_run(l, i, beta, 4, 99, 3, 1, 1.0, 1, ctr, sp, E, b)
+        assert rc == 0 and np.array_equal(ctx.spins_range(i, 0, 128), sp), f"APT instance {i}"
+        assert np.array_equal(tr[i], otr)
+    q = sg.sqa(insts, 64, 16, 32.0, 98)
+    q.sqa_anneal(linear_gamma(1000)[:3])
+    for i, r in ((0, 0), (5, 15)):
+        l = oracle.Lattice(insts[i][0], 4)
+        sp = oracle.sqa_init(l, i, 64, 1, 98, r0=r)
+        oracle.sqa_anneal(l, i, 64, 1, 32.0, linear_gamma(1000)[:3], 98, 0, sp, r0=r)
+        assert np.array_equal(q.spins_range(i, r, 1)[0], sp[0]), f"DT-SQA instance {i} replica {r}"
+
+
 def test_checkpoint_resume_is_exact():
     insts = [_inst(*m) for m in MIXED[:4]]
     beta = geometric_ladder(8, 0.2, 3.0)
