@@ -287,6 +287,7 @@ struct sg_ctx {
     std::vector<double> beta;    // [n_inst][n_beta]
     DevBuf<uint8_t> d_spins;
     DevBuf<int32_t> d_perm, d_E, d_slot_lut, d_tab_off, d_tab_len, d_icm_info;
+    DevBuf<int32_t> d_perm2, d_E2;   // second mapping / energy buffers of the cycle graph
     DevBuf<uint32_t> d_lut, d_tab;
     DevBuf<uint8_t> d_icm_on;
     DevBuf<int64_t> d_best, d_acc_count, d_mom, d_trace;
@@ -576,6 +577,8 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
     c->d_tab_len.upload(tab_len, s, "swap lengths");
     c->d_spins.alloc((size_t)spin_bytes, "spins");
     c->d_E.alloc((size_t)c->n_inst * nb4, "energies");
+    c->d_perm2.alloc((size_t)c->n_inst * nb4, "perm");
+    c->d_E2.alloc((size_t)c->n_inst * nb4, "energies");
     c->d_mom.alloc((size_t)c->n_inst * nb4 * 2, "moments");
     c->d_best.alloc((size_t)c->n_inst, "best");
     c->d_acc_count.alloc((size_t)c->n_inst * (c->n_beta - 1) * c->reps, "swap counts");
@@ -654,6 +657,7 @@ AptArgs apt_args(sg_ctx *c, int n_sweeps, int do_icm)
     a.ni = c->ni;
     a.cyc_k = 0;
     a.n_blocks = c->n_blocks;
+    a.fused_swap = 0;
     return a;
 }
 
@@ -661,6 +665,8 @@ SwapArgs swap_args(sg_ctx *c, int32_t *acc_out, int64_t *trace, int trace_cap, i
 {
     SwapArgs a{};
     a.inst = c->d_inst.p;
+    a.perm_in = c->d_perm.p;
+    a.E_in = c->d_E.p;
     a.perm = c->d_perm.p;
     a.E = c->d_E.p;
     a.tab = c->d_tab.p;
@@ -1040,7 +1046,10 @@ sg_status sg_run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, doubl
         // Replay a captured graph of K cycles.  Inside the graph cycle k reads
         // its step numbers as (counters + k * per-cycle increments); one
         // one-thread kernel at the end advances the counters by K cycles, so
-        // the same graph is valid on every replay.
+        // the same graph is valid on every replay.  The exchange of cycle k - 1
+        // runs at the start of cycle k's replica kernel, which reads the mapping
+        // and energies from one buffer pair and writes them to the other; a last
+        // exchange launch after cycle K - 1 brings them back to the first pair.
         const int K = 32;
         if (!c->gexec || c->g_sweeps != sweeps_per_swap || c->g_icm != (int)icm || c->g_record != rec ||
             c->g_trace != trace || c->g_trace_cap != cap) {
@@ -1049,12 +1058,29 @@ sg_status sg_run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, doubl
             hipGraph_t g = nullptr;
             hip_check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "capture");
             hipError_t e = hipSuccess;
+            int32_t *pa = c->d_perm.p, *pb = c->d_perm2.p, *ea = c->d_E.p, *eb = c->d_E2.p;
             for (int k = 0; k < K && e == hipSuccess; ++k) {
-                qa.cyc_k = k;
-                sa.cyc_k = k;
-                e = launch_apt_quad(qa, c->quad_lds, c->stream);
-                if (e == hipSuccess) e = launch_apt_swap(sa, c->stream);
+                AptArgs fa = qa;
+                fa.cyc_k = k;
+                if (k > 0) {
+                    const bool odd = (k & 1) != 0;
+                    fa.fused_swap = 1;
+                    fa.sw = sa;
+                    fa.sw.cyc_k = k - 1;
+                    fa.sw.perm_in = odd ? pa : pb;
+                    fa.sw.E_in = odd ? ea : eb;
+                    fa.sw.perm = odd ? pb : pa;
+                    fa.sw.E = fa.E = odd ? eb : ea;
+                    fa.perm = fa.sw.perm;
+                }
+                e = launch_apt_quad(fa, c->quad_lds, c->stream);
             }
+            static_assert(K % 2 == 0, "the last replica kernel must write the second buffers");
+            SwapArgs last = sa;
+            last.cyc_k = K - 1;
+            last.perm_in = pb;
+            last.E_in = eb;
+            if (e == hipSuccess) e = launch_apt_swap(last, c->stream);
             if (e == hipSuccess) e = launch_advance(c->d_ctr.p, K * S, K, K, K, c->stream);
             hipError_t e2 = hipStreamEndCapture(c->stream, &g);
             hip_check(e, "capture launch");

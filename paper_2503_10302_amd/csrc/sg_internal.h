@@ -77,7 +77,9 @@ struct QuadDesc {
 // Replica exchange of one instance (also run at the end of a fused cycle).
 struct SwapArgs {
     const InstDev *inst;
-    int32_t *perm;
+    const int32_t *perm_in;    // state before the exchange (may equal perm / E)
+    const int32_t *E_in;
+    int32_t *perm;             // state after it
     int32_t *E;
     const uint32_t *tab;       // swap thresholds, per pair: T[d] for |dE| = d
     const int32_t *tab_off;    // per (instance, pair)
@@ -126,6 +128,10 @@ struct AptArgs {
     int32_t cyc_k;             // cycle offset of this launch inside a captured graph: the
                                // kernel uses sweep counter ctr[0] + cyc_k * n_sweeps and ICM
                                // call ctr[1] + cyc_k + 1; counters advance only between graphs
+    int32_t fused_swap;        // 1: first perform the replica exchange described by sw (the
+                               //    previous cycle's attempt) for this work-group's slots,
+                               //    reading sw.perm_in / sw.E_in and writing sw.perm and E
+    SwapArgs sw;
 };
 
 // DT-SQA: spins of replica (inst, r) are n+1 pairs of 32-bit words

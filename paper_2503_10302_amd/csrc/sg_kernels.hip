@@ -558,20 +558,58 @@ __device__ void icm_pairs_planes(uint32_t *sp, const uint4 *rowA, const uint4 *r
     }
 }
 
-// Replica exchange (Eq. 4) for one instance, run by one work-group.  An
-// accepted exchange swaps the logical->physical mapping of the two slots and
-// their energies; the random word is keyed by the logical pair, so this is the
-// same chain as exchanging the states.
+// Replica exchange (Eq. 4): the decision for temperature pair (b, b + 1), label l, at
+// attempt a.  A non-negative Delta-beta * Delta-E is always accepted; otherwise the
+// precomputed threshold for |Delta E| is compared with the pair's random word.
+__device__ __forceinline__ int swap_decision(const SwapArgs &A, int inst, const InstDev &I, int b,
+                                             int l, int32_t e0, int32_t e1, uint32_t a)
+{
+    const int32_t dE = e1 - e0;
+    if (dE >= 0) return 1;
+    const int pair = I.swap_off + b;
+    const int32_t d = -dE;
+    if (d >= A.tab_len[pair]) return 0;
+    const uint32_t u = philox10((uint32_t)(b * A.reps + l), a, 0u, ((uint32_t)inst << 4) | TAG_SWAP,
+                                A.key0, A.key1).x;
+    return u < A.tab[A.tab_off[pair] + d] ? 1 : 0;
+}
+
+// Running minimum of the instance's energies after an attempt and its trace entry.
+__device__ __forceinline__ void record_best(const SwapArgs &A, int inst, int32_t m)
+{
+    const uint32_t cyc = A.ctr[3] + (uint32_t)A.cyc_k + 1u;
+    int64_t best = A.best[inst];
+    if ((int64_t)m < best) best = m;
+    A.best[inst] = best;
+    if (A.trace && A.record_every > 0 && (cyc % (uint32_t)A.record_every) == 0u) {
+        const int64_t ti = (int64_t)(cyc / (uint32_t)A.record_every) - 1;
+        if (ti < A.trace_cap) A.trace[(int64_t)inst * A.trace_cap + ti] = best;
+    }
+}
+
+// Replica exchange for one instance, run by one work-group.  An accepted exchange
+// swaps the logical->physical mapping of the two slots and their energies; the random
+// word is keyed by the logical pair, so this is the same chain as exchanging the
+// states.  Reads perm_in / E_in and writes perm / E (in place when they are the same).
 __device__ void swap_instance(const SwapArgs &A, int inst, int32_t *red)
 {
     const InstDev &I = A.inst[inst];
     const int R = A.reps, nb = A.n_beta;
     const int npt = (nb - 1) * R;
     const uint32_t a = A.ctr[2] + (uint32_t)A.cyc_k + 1u;
-    const uint32_t cyc = A.ctr[3] + (uint32_t)A.cyc_k + 1u;
+    const int32_t *pin = A.perm_in + I.slot_off, *ein = A.E_in + I.slot_off;
     int32_t *perm = A.perm + I.slot_off;
     int32_t *E = A.E + I.slot_off;
     const int nt = blockDim.x;
+    if (pin != perm) {
+        // separate buffers: carry every slot (padding included) over first
+        const int nb4 = (I.n_slots + 3) & ~3;
+        for (int i = threadIdx.x; i < nb4; i += nt) {
+            perm[i] = pin[i];
+            E[i] = ein[i];
+        }
+        __syncthreads();
+    }
     if (A.acc_out)
         for (int i = threadIdx.x; i < npt; i += nt) A.acc_out[(int64_t)inst * npt + i] = -1;
     const int first = (a & 1u) ? 0 : 1;
@@ -579,24 +617,10 @@ __device__ void swap_instance(const SwapArgs &A, int inst, int32_t *red)
     for (int idx = threadIdx.x; idx < npairs * R; idx += nt) {
         const int b = first + 2 * (idx / R), l = idx - (idx / R) * R;
         const int s0 = b * R + l, s1 = s0 + R;
-        const int32_t e0 = E[s0], e1 = E[s1];
-        const int32_t dE = e1 - e0;
-        int acc;
-        if (dE >= 0) {
-            acc = 1;
-        } else {
-            const int pair = I.swap_off + b;
-            const int32_t d = -dE;
-            if (d < A.tab_len[pair]) {
-                const uint32_t u = philox10((uint32_t)(b * R + l), a, 0u,
-                                            ((uint32_t)inst << 4) | TAG_SWAP, A.key0, A.key1).x;
-                acc = u < A.tab[A.tab_off[pair] + d];
-            } else {
-                acc = 0;
-            }
-        }
+        const int32_t e0 = ein[s0], e1 = ein[s1];
+        const int32_t p0 = pin[s0], p1 = pin[s1];
+        const int acc = swap_decision(A, inst, I, b, l, e0, e1, a);
         if (acc) {
-            const int32_t p0 = perm[s0], p1 = perm[s1];
             perm[s0] = p1;
             perm[s1] = p0;
             E[s0] = e1;
@@ -613,13 +637,51 @@ __device__ void swap_instance(const SwapArgs &A, int inst, int32_t *red)
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < (nt + 63) / 64; ++w) m = min(m, red[20 + w]);
-        int64_t best = A.best[inst];
-        if ((int64_t)m < best) best = m;
-        A.best[inst] = best;
-        if (A.trace && A.record_every > 0 && (cyc % (uint32_t)A.record_every) == 0u) {
-            const int64_t ti = (int64_t)(cyc / (uint32_t)A.record_every) - 1;
-            if (ti < A.trace_cap) A.trace[(int64_t)inst * A.trace_cap + ti] = best;
+        record_best(A, inst, m);
+    }
+    __syncthreads();
+}
+
+// The exchange of the previous cycle done at the start of an APT work-group instead of
+// in a launch of its own: the same decisions as swap_instance for the work-group's four
+// logical slots (the work-group of a pair's lower slot counts it), and on quad 0 the
+// running minimum.  The new mapping and energies of the four slots go to lperm / lE
+// (LDS) and the mapping to A.perm.
+__device__ void fused_swap_quad(const SwapArgs &A, int inst, int q, int32_t *lperm, int32_t *lE)
+{
+    const InstDev &I = A.inst[inst];
+    const int tid = threadIdx.x;
+    const uint32_t a = A.ctr[2] + (uint32_t)A.cyc_k + 1u;
+    const int32_t *pin = A.perm_in + I.slot_off, *ein = A.E_in + I.slot_off;
+    if (tid < 4) {
+        const int s = 4 * q + tid;
+        int32_t pv = pin[s], ev = ein[s];
+        if (s < I.n_slots) {
+            const int R = A.reps, nb = A.n_beta;
+            const int b = s / R, l = s - b * R;
+            const int first = (a & 1u) ? 0 : 1;
+            int lo = -1;
+            if (b >= first && ((b - first) & 1) == 0 && b + 1 < nb) lo = b;
+            else if (b - 1 >= first && ((b - 1 - first) & 1) == 0) lo = b - 1;
+            if (lo >= 0) {
+                const int s0 = lo * R + l, s1 = s0 + R;
+                const int acc = swap_decision(A, inst, I, lo, l, ein[s0], ein[s1], a);
+                if (acc) {
+                    const int pt = (s == s0) ? s1 : s0;
+                    pv = pin[pt];
+                    ev = ein[pt];
+                }
+                if (s == s0) A.acc_count[(int64_t)inst * (nb - 1) * R + s0] += acc;
+            }
         }
+        A.perm[I.slot_off + s] = pv;
+        lperm[tid] = pv;
+        lE[tid] = ev;
+    }
+    if (q == 0 && tid == 0) {
+        int32_t m = 0x7FFFFFFF;
+        for (int s = 0; s < I.n_slots; ++s) m = min(m, ein[s]);
+        record_best(A, inst, m);
     }
     __syncthreads();
 }
@@ -670,9 +732,17 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
         uint32_t *vis = Vr + 4 * I.n_rows;               // (npad + 31) / 32 + 1
         uint16_t *queue = (uint16_t *)(vis + ((npad + 31) >> 5) + 1);   // npad
         const int q = D.quad;
-        const int32_t *pp = A.perm + I.slot_off + 4 * q;
-        const int64_t b0 = (int64_t)pp[0] * npad, b1 = (int64_t)pp[1] * npad;
-        const int64_t b2 = (int64_t)pp[2] * npad, b3 = (int64_t)pp[3] * npad;
+        int32_t e_in = 0;   // fused exchange: this slot's energy after it (threads 0..3)
+        int32_t pq[4];
+        if (A.fused_swap) {
+            fused_swap_quad(A.sw, D.inst, q, red + 24, red + 28);
+            for (int i = 0; i < 4; ++i) pq[i] = red[24 + i];
+            if (tid < 4) e_in = red[28 + tid];
+        } else {
+            for (int i = 0; i < 4; ++i) pq[i] = A.perm[I.slot_off + 4 * q + i];
+        }
+        const int64_t b0 = (int64_t)pq[0] * npad, b1 = (int64_t)pq[1] * npad;
+        const int64_t b2 = (int64_t)pq[2] * npad, b3 = (int64_t)pq[3] * npad;
         const uint8_t *gs = A.spins + I.spin_off;
         for (int e = tid; e < 4 * ni; e += kQuadThreads) {
             const int i = e / ni;
@@ -758,7 +828,8 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
                 if (tid < 4) {
                     const int s = 4 * q + tid;
                     if (s < I.n_slots) {
-                        const int64_t ec = (int64_t)A.E[I.slot_off + s] + e[tid];
+                        const int32_t e0 = A.fused_swap ? e_in : A.E[I.slot_off + s];
+                        const int64_t ec = (int64_t)e0 + e[tid];
                         int64_t *mm = A.mom + 2 * (int64_t)(I.slot_off + s);
                         mm[0] += ec;
                         mm[1] += ec * ec;
@@ -849,8 +920,13 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
             block_sum4(dE, red);
             if (tid < 4) {
                 const int s = 4 * q + tid;
-                if (s < I.n_slots) A.E[I.slot_off + s] += dE[tid];
+                if (s < I.n_slots) {
+                    if (A.fused_swap) A.E[I.slot_off + s] = e_in + dE[tid];
+                    else A.E[I.slot_off + s] += dE[tid];
+                }
             }
+        } else if (A.fused_swap && tid < 4 && 4 * q + tid < I.n_slots) {
+            A.E[I.slot_off + 4 * q + tid] = e_in;
         }
 
         if (A.n_sweeps > 0 || A.do_icm) {

@@ -95,7 +95,7 @@ def test_apt_cycles_match_oracle(reps, S, cutoff):
     insts = [_inst(*m) for m in MIXED[:6]]
     beta = geometric_ladder(10, 0.2, 3.0)
     ctx = sg.apt(insts, beta, SEED + reps, reps_per_beta=reps)
-    n_cyc = 45                                   # graph replays of 32 cycles plus a ragged tail
+    n_cyc = 77                                   # two replays of the 32-cycle graph plus a ragged tail
     trace = ctx.run_apt(n_cyc, S, cutoff, record_every=5)
     g = ctx.spins()
     best = ctx.best()
