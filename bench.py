@@ -33,11 +33,20 @@ METRIC = "spin flips/ns at L=15; time-to-target residual energy/spin, plain vs b
 # figure times two flops per FMA).  Three-operand (VOP3) integer operations such as the
 # 32x32->64 multiply-add issue at half that rate (two slots).
 VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
-# Algorithmic VALU work per spin-update attempt, in full-rate slots: a quarter of one
-# Philox4x32-10 block (10 rounds x [2 multiply-adds x 2 slots + 4 xors x 1 slot]) plus
-# the threshold compare.  Index arithmetic, LDS traffic and the neighbour sums are
-# implementation overhead and are not counted.
-ALG_OPS_PER_FLIP = (10 * (2 * 2 + 4)) / 4 + 1
+# Algorithmic VALU work per DT-SQA spin-update attempt, in full-rate slots.  One
+# Philox4x32-10 block (10 rounds, each two 32x32->64 multiply-adds at 2 slots and four
+# xors at 1 slot) serves four Trotter slices.  Its counter (2 site + parity, step,
+# replica << 16 | group, instance) differs between lanes in word 0 only, so the products
+# of the uniform half in rounds 1 and 2 are scalar-unit work, and round 1's vector
+# product with its xor and round 2's vector product are the same for every slice group
+# of a site.  Per group: 2 (round 2) + 7 (round 3) + 8 x 7 (rounds 4-10) = 65 slots; per
+# site and parity 3 + 2 more, shared by its groups; plus the threshold compare.  Index
+# arithmetic, LDS traffic and the neighbour sums are implementation overhead and are
+# not counted.
+def alg_ops_per_flip(groups):
+    return 65 / 4 + 5 / (4 * groups) + 1
+
+
 # HBM traffic of one DT-SQA launch (R = 1024, 200 steps) from two rocprofv3 counter
 # runs, FETCH_SIZE then WRITE_SIZE (KiB per dispatch), each scaled by what the same
 # counter reads for a plain 256 MiB copy (fetch x 2.0, write x 1.0).  Reported only
@@ -263,7 +272,8 @@ def main():
         wall = time.perf_counter() - t0
         kms, nlaunch = ctx.kernel_time()
         value = flips_per_step * args.steps / (ms * 1e6)
-        achieved = ALG_OPS_PER_FLIP * flips_per_step * args.steps / (kms * 1e-3) / 1e12
+        ops_flip = alg_ops_per_flip((M // 2 + 3) // 4)
+        achieved = ops_flip * flips_per_step * args.steps / (kms * 1e-3) / 1e12
         out.update({
             "value": round(value, 3), "ms_per_step": round(ms / args.steps, 5),
             "config": {"workload": f"dtsqa_L15_M64_R{R}_x32 (32 instances of 15^3 periodic +-J, "
@@ -276,7 +286,7 @@ def main():
                          "traffic": sqa_traffic(R, args.steps),
                          "traffic_unit": "bytes per launch (HBM, counters)",
                          "alg_bytes_per_launch": 2 * len(insts) * R * ((n + 15) // 16 * 16) * 8,
-                         "alg_ops_per_flip": ALG_OPS_PER_FLIP,
+                         "alg_ops_per_flip": round(ops_flip, 3),
                          "kernel_ms": round(kms, 3), "launches": nlaunch,
                          "launch_config": {"threads": ctx.launch_config(),
                                            "chosen_by": "autotuner"},

@@ -401,13 +401,15 @@ int32_t sgo_apt_run(const sgo_lattice *lat, uint32_t inst, int32_t n_beta, int32
 
 /* ------------------------------------------------------------------------- */
 /* DT-SQA (Algorithm S1).  Spins [r][k][n]: replica r0 + r, Trotter slice k.  */
-/* Slice k = 2 hh + p draws word (hh & 3) of the block with counter word 2   */
-/* equal to (r << 16) | (p << 15) | (hh >> 2).                               */
+/* Slice k = 2 hh + p at site j draws word (hh & 3) of the block with        */
+/* counter words 0 and 2 equal to 2 j + p and (r << 16) | (hh >> 2).         */
 /* ------------------------------------------------------------------------- */
+static uint32_t sqa_c0(int32_t j, int32_t k) { return ((uint32_t)j << 1) | ((uint32_t)k & 1u); }
+
 static uint32_t sqa_c2(int32_t r, int32_t k)
 {
-    uint32_t p = (uint32_t)k & 1u, hh = (uint32_t)k >> 1;
-    return ((uint32_t)r << 16) | (p << 15) | (hh >> 2);
+    uint32_t hh = (uint32_t)k >> 1;
+    return ((uint32_t)r << 16) | (hh >> 2);
 }
 
 void sgo_sqa_init(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t r0, int32_t R,
@@ -417,7 +419,7 @@ void sgo_sqa_init(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t r0, 
     for (int32_t r = 0; r < R; ++r)
         for (int32_t k = 0; k < M; ++k)
             for (int32_t j = 0; j < n; ++j) {
-                uint32_t w = sgo_word(seed, (uint32_t)j, 0u, sqa_c2(r0 + r, k), inst,
+                uint32_t w = sgo_word(seed, sqa_c0(j, k), 0u, sqa_c2(r0 + r, k), inst,
                                       SGO_TAG_SQA_INIT, (k >> 1) & 3);
                 spins[((int64_t)r * M + k) * n + j] = (w < 0x80000000u) ? 1 : -1;
             }
@@ -440,7 +442,7 @@ void sgo_sqa_step(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t r0, 
                     int8_t dn = spins[((int64_t)r * M + (k + 1) % M) * n + j];
                     int32_t s = sgo_local_field(lat, slice, j);
                     uint32_t T = sgo_sqa_threshold(beta, M, gamma, s, up + dn);
-                    uint32_t u = sgo_word(seed, (uint32_t)j, t, sqa_c2(r0 + r, k), inst,
+                    uint32_t u = sgo_word(seed, sqa_c0(j, k), t, sqa_c2(r0 + r, k), inst,
                                           SGO_TAG_SQA_SWEEP, (k >> 1) & 3);
                     slice[j] = (u < T) ? 1 : -1;
                 }

@@ -974,9 +974,8 @@ __global__ __launch_bounds__(kSqaThreads) void sqa_init_kernel(SqaArgs A)
         if (j < I.n) {
             for (int p = 0; p < 2; ++p)
                 for (int gq = 0; gq < ngrp; ++gq) {
-                    const uint4 u = philox10((uint32_t)j, 0u,
-                                             ((uint32_t)r << 16) | ((uint32_t)p << 15) | (uint32_t)gq,
-                                             c3, A.key0, A.key1);
+                    const uint4 u = philox10(((uint32_t)j << 1) | (uint32_t)p, 0u,
+                                             ((uint32_t)r << 16) | (uint32_t)gq, c3, A.key0, A.key1);
                     const uint32_t us[4] = {u.x, u.y, u.z, u.w};
                     for (int i = 0; i < 4; ++i) {
                         const int h = 4 * gq + i;
@@ -1001,39 +1000,54 @@ __device__ __forceinline__ uint32_t rotr_h(uint32_t x, int H, uint32_t mask)
 
 // Byte offset of the 4-bit slice group g of a bit plane into a 16-entry
 // 32-bit table: ((x >> 4g) & 15) * 4.
-template <int NG>
 __device__ __forceinline__ uint32_t nib_off(uint32_t x, int g)
 {
-    if (NG > 0) return g == 0 ? ((x << 2) & 0x3Cu) : ((x >> (4 * g - 2)) & 0x3Cu);
-    return ((x >> (4 * g)) & 15u) << 2;
+    return g == 0 ? ((x << 2) & 0x3Cu) : ((x >> (4 * g - 2)) & 0x3Cu);
+}
+
+// Two bit planes a, b interleaved by 4-bit slice group: byte m of the even word holds
+// group 2m of a (low nibble) and of b (high nibble), byte m of the odd word group 2m + 1.
+__device__ __forceinline__ void pair_planes(uint32_t a, uint32_t b, uint32_t &ev, uint32_t &od)
+{
+    ev = (a & 0x0F0F0F0Fu) | ((b << 4) & 0xF0F0F0F0u);
+    od = ((a >> 4) & 0x0F0F0F0Fu) | (b & 0xF0F0F0F0u);
+}
+
+// Byte offset of group g of a pair of planes into a 256-entry 32-bit table.
+__device__ __forceinline__ uint32_t pair_off(uint32_t ev, uint32_t od, int g)
+{
+    return (((g & 1) ? od : ev) >> (8 * (g >> 1)) & 0xFFu) << 2;
 }
 
 // New states of the H slices of one parity at one site (Supplementary Eq. S.3 with
 // the heat-bath rule of Eq. 6).  Slice h = 4 g + i takes word i of the Philox block
-// of group g; its threshold index is a byte of idx4, assembled from the bit planes
-// of the aligned-neighbour count (c0, c1, c2) and of the number of up Trotter
-// neighbours (t0, t1) through the spread tables.  Groups run from the highest to the
-// lowest so that the borrow chain leaves slice h at bit h.  SCALED: table indices are
-// stored pre-multiplied by 4 (byte offsets), possible when the table has <= 64 rows.
-// NG > 0: groups [g_lo, g_lo + NG) unrolled (the planes are pre-shifted by 4 g_lo
-// bits, so group g reads bits 4 (g - g_lo)); NG == 0: groups [0, ngrp), not unrolled.
+// of group g; its threshold index is a byte of idx4, the sum of the contributions of
+// the bit planes of the aligned-neighbour count (c0, c1, c2) and of the number of up
+// Trotter neighbours (t0, t1), read from two pair tables (planes c0, c1 and c2, t0,
+// indexed by a byte of pair_planes) and one 16-entry table (t1).  Groups run from the
+// highest to the lowest so that the borrow chain leaves slice h at bit h.  The block
+// counter is (2 j + p, step, r << 16 | g, instance): only its first word differs
+// between the lanes, so the products of the other half in the first two rounds are
+// work-group uniform (scalar unit) and the first-round product of 2 j + p is shared by
+// all groups.  SCALED: table indices are stored pre-multiplied by 4 (byte offsets),
+// possible when the table has <= 64 rows.  NG > 0: NG groups, unrolled; NG == 0: ngrp
+// groups, not unrolled.
 template <int NG, bool SCALED>
-__device__ __forceinline__ uint32_t sqa_slices(const uint32_t *lut, const uint32_t *spread,
-                                               uint32_t c0, uint32_t c1, uint32_t c2,
-                                               uint32_t t0b, uint32_t t1b, uint32_t base4,
-                                               uint32_t j, uint32_t t, uint32_t x2, uint32_t c3,
-                                               uint32_t k0, uint32_t k1, int ngrp, uint32_t g_lo)
+__device__ __forceinline__ uint32_t sqa_slices(const uint32_t *lut, const uint32_t *tab01,
+                                               const uint32_t *tab2t, const uint32_t *tab1,
+                                               uint32_t e01, uint32_t o01, uint32_t e2t,
+                                               uint32_t o2t, uint32_t t1b, uint32_t base4,
+                                               uint32_t jp, uint32_t t, uint32_t x2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1, int ngrp)
 {
     uint32_t res = 0u;
     const int ng = NG > 0 ? NG : ngrp;
 #pragma unroll
     for (int g = ng - 1; g >= 0; --g) {
-        const uint32_t idx4 = lds_word(spread, nib_off<NG>(c0, g)) +
-                              lds_word(spread + 16, nib_off<NG>(c1, g)) +
-                              lds_word(spread + 32, nib_off<NG>(c2, g)) +
-                              lds_word(spread + 48, nib_off<NG>(t0b, g)) +
-                              lds_word(spread + 64, nib_off<NG>(t1b, g)) + base4;
-        const uint4 u = philox10(j, t, x2 | (g_lo + (uint32_t)g), c3, k0, k1);
+        const uint32_t idx4 = lds_word(tab01, pair_off(e01, o01, g)) +
+                              lds_word(tab2t, pair_off(e2t, o2t, g)) +
+                              lds_word(tab1, nib_off(t1b, g)) + base4;
+        const uint4 u = philox10(jp, t, x2 | (uint32_t)g, c3, k0, k1);
         uint32_t o0, o1, o2, o3;
         if (SCALED) {
             o0 = idx4 & 0xFFu;
@@ -1072,22 +1086,29 @@ void sqa_kernel(SqaArgs A)
     const int n = I.n, npad = I.npad, H = A.H;
     const uint32_t mask = (H >= 32) ? 0xFFFFFFFFu : ((1u << H) - 1u);
     uint32_t *lut = tabs;                       // 2 * 128 (double-buffered rows)
-    // Spread tables: for a 4-bit slice group of one bit plane, the plane's
-    // contribution to the four threshold indices, one byte per slice.  Index
-    // weights: 6, 12, 24 for the aligned-neighbour count bits, 1, 2 for the
-    // number of up Trotter neighbours (table index = 6 k + t + 3 (h - d + smax)),
-    // times 4 when SCALED.
-    uint32_t *spread = tabs + 256;              // 5 * 16
-    int32_t *red = (int32_t *)(tabs + 336);     // 2 * 64
+    // Spread tables: for 4-bit slice groups of bit planes, the planes' contribution
+    // to the four threshold indices, one byte per slice.  Index weights: 6, 12, 24
+    // for the aligned-neighbour count bits, 1, 2 for the number of up Trotter
+    // neighbours (table index = 6 k + t + 3 (h - d + smax)), times 4 when SCALED.
+    // Planes c0 and c1 share one 256-entry table, c2 and t0 another.
+    uint32_t *tab01 = tabs + 256;               // 256
+    uint32_t *tab2t = tabs + 512;               // 256
+    uint32_t *tab1 = tabs + 768;                // 16
+    int32_t *red = (int32_t *)(tabs + 784);     // 2 * 64
     uint32_t *sp = lds;                         // 2 * (npad + 1)
     uint32_t *g = A.spins + I.spin_off + (int64_t)r * npad * 2;
     for (int i = tid; i < 2 * npad; i += THREADS) sp[i] = g[i];
     if (tid < 2) sp[2 * npad + tid] = 0u;
-    if (tid < 80) {
-        const uint32_t w[5] = {6u, 12u, 24u, 1u, 2u};
-        const uint32_t nib = (uint32_t)(tid & 15), pl = (uint32_t)(tid >> 4);
-        spread[tid] = (SCALED ? 4u : 1u) * w[pl] *
-                      ((nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21));
+    for (int e = tid; e < 528; e += THREADS) {
+        // bit i of a nibble -> byte i
+        auto spread = [](uint32_t nib) {
+            return (nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21);
+        };
+        const uint32_t lo = (uint32_t)e & 15u, hi = ((uint32_t)e >> 4) & 15u;
+        const uint32_t v = e < 256   ? 6u * spread(lo) + 12u * spread(hi)
+                           : e < 512 ? 24u * spread(lo) + spread(hi)
+                                     : 2u * spread(lo);
+        tabs[256 + e] = (SCALED ? 4u : 1u) * v;
     }
     const uint32_t c3 = ((uint32_t)inst << 4) | TAG_SQA_SWEEP;
     const int ngrp = (H + 3) >> 2;
@@ -1142,10 +1163,13 @@ void sqa_kernel(SqaArgs A)
                                        (uint32_t)(3 * ((int32_t)((rr.x >> 25) & 63u) - 32 -
                                                        (int32_t)((rr.x >> 16) & 7u) + A.smax)) *
                                        0x01010101u;
-                const uint32_t x2 = ((uint32_t)r << 16) | (p << 15);
-                const uint32_t res = sqa_slices<NG, SCALED>(lrow, spread, c0, c1, c2, t0b, t1b,
-                                                            base4, j, t, x2, c3, A.key0, A.key1,
-                                                            ngrp, 0u);
+                uint32_t e01, o01, e2t, o2t;
+                pair_planes(c0, c1, e01, o01);
+                pair_planes(c2, t0b, e2t, o2t);
+                const uint32_t res = sqa_slices<NG, SCALED>(lrow, tab01, tab2t, tab1, e01, o01, e2t,
+                                                            o2t, t1b, base4, (j << 1) | p, t,
+                                                            (uint32_t)r << 16, c3, A.key0,
+                                                            A.key1, ngrp);
                 sp[2 * j + p] = res & mask;
             }
             __syncthreads();
