@@ -1042,12 +1042,15 @@ __device__ __forceinline__ uint32_t sqa_slices(const uint32_t *lut, const uint32
 {
     uint32_t res = 0u;
     const int ng = NG > 0 ? NG : ngrp;
+    // Software pipeline: the spread-table reads of group g - 1 and the threshold reads
+    // of group g are issued before group g's Philox block, whose arithmetic covers
+    // their LDS latency.
+    uint32_t s0 = lds_word(tab01, pair_off(e01, o01, ng - 1));
+    uint32_t s1 = lds_word(tab2t, pair_off(e2t, o2t, ng - 1));
+    uint32_t s2 = lds_word(tab1, nib_off(t1b, ng - 1));
 #pragma unroll
     for (int g = ng - 1; g >= 0; --g) {
-        const uint32_t idx4 = lds_word(tab01, pair_off(e01, o01, g)) +
-                              lds_word(tab2t, pair_off(e2t, o2t, g)) +
-                              lds_word(tab1, nib_off(t1b, g)) + base4;
-        const uint4 u = philox10(jp, t, x2 | (uint32_t)g, c3, k0, k1);
+        const uint32_t idx4 = s0 + s1 + s2 + base4;
         uint32_t o0, o1, o2, o3;
         if (SCALED) {
             o0 = idx4 & 0xFFu;
@@ -1060,10 +1063,19 @@ __device__ __forceinline__ uint32_t sqa_slices(const uint32_t *lut, const uint32
             o2 = (idx4 >> 14) & 0x3FCu;
             o3 = (idx4 >> 22) & 0x3FCu;
         }
-        res = shift_in_lt(res, u.w, lds_word(lut, o3));
-        res = shift_in_lt(res, u.z, lds_word(lut, o2));
-        res = shift_in_lt(res, u.y, lds_word(lut, o1));
-        res = shift_in_lt(res, u.x, lds_word(lut, o0));
+        const uint32_t T3 = lds_word(lut, o3), T2 = lds_word(lut, o2);
+        const uint32_t T1 = lds_word(lut, o1), T0 = lds_word(lut, o0);
+        if (g > 0) {
+            s0 = lds_word(tab01, pair_off(e01, o01, g - 1));
+            s1 = lds_word(tab2t, pair_off(e2t, o2t, g - 1));
+            s2 = lds_word(tab1, nib_off(t1b, g - 1));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const uint4 u = philox10(jp, t, x2 | (uint32_t)g, c3, k0, k1);
+        res = shift_in_lt(res, u.w, T3);
+        res = shift_in_lt(res, u.z, T2);
+        res = shift_in_lt(res, u.y, T1);
+        res = shift_in_lt(res, u.x, T0);
     }
     return res;
 }
