@@ -788,7 +788,6 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
                     const uint32_t base = ((r.x >> 25) & 63u) + (uint32_t)(A.imax - 32) -
                                           ((r.x >> 16) & 7u);
                     const uint32_t idx4 = (k4 << 1) + __builtin_amdgcn_perm(0u, base, 0u);   // base in every byte
-                    const uint4 u = philox10(j, t, (uint32_t)q, c3, A.key0, A.key1);
                     const uint32_t old = sp[j];
                     uint32_t o0, o1, o2, o3;
                     if (scaled) {
@@ -803,11 +802,17 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
                         o2 = (((idx4 >> 16) & 0xFFu) + 2u * (uint32_t)ni) << 2;
                         o3 = ((idx4 >> 24) + 3u * (uint32_t)ni) << 2;
                     }
+                    // thresholds read before the Philox block, whose arithmetic covers
+                    // their LDS latency
+                    const uint32_t T3 = lds_word(lut, o3), T2 = lds_word(lut, o2);
+                    const uint32_t T1 = lds_word(lut, o1), T0 = lds_word(lut, o0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const uint4 u = philox10(j, t, (uint32_t)q, c3, A.key0, A.key1);
                     uint32_t acc = 0u;   // bit b: new state of slot b (Eq. 6)
-                    acc = shift_in_lt(acc, u.w, lds_word(lut, o3));
-                    acc = shift_in_lt(acc, u.z, lds_word(lut, o2));
-                    acc = shift_in_lt(acc, u.y, lds_word(lut, o1));
-                    acc = shift_in_lt(acc, u.x, lds_word(lut, o0));
+                    acc = shift_in_lt(acc, u.w, T3);
+                    acc = shift_in_lt(acc, u.z, T2);
+                    acc = shift_in_lt(acc, u.y, T1);
+                    acc = shift_in_lt(acc, u.x, T0);
                     const uint32_t nw = __umul24(acc, 0x00204081u) & 0x01010101u;   // bit b -> byte b
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
