@@ -38,6 +38,26 @@ __device__ __forceinline__ uint4 philox10(uint32_t x0, uint32_t x1, uint32_t x2,
     return make_uint4(x0, x1, x2, x3);
 }
 
+// Rounds [r0, r1) of Philox4x32-10 on the state x with the key k of round r0 (the key
+// is advanced): philox10 split in two so that other work can sit between the halves.
+template <int R0, int R1>
+__device__ __forceinline__ void philox_rounds(uint32_t x[4], uint32_t k[2])
+{
+#pragma unroll
+    for (int r = R0; r < R1; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * x[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ x[1] ^ k[0];
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ x[3] ^ k[1];
+        x[1] = (uint32_t)p1;
+        x[3] = (uint32_t)p0;
+        x[0] = n0;
+        x[2] = n2;
+        k[0] += 0x9E3779B9u;
+        k[1] += 0xBB67AE85u;
+    }
+}
+
 __device__ __forceinline__ uint32_t lds_word(const uint32_t *base, uint32_t byte_off)
 {
     return *(const uint32_t *)((const uint8_t *)base + byte_off);
@@ -783,12 +803,27 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
                     const uint4 r = rnext;
                     if (i + kQuadThreads < cnt) rnext = rc[i + kQuadThreads];   // prefetch
                     const uint32_t j = r.x & 0xFFFFu;
-                    const uint32_t k4 = aligned_count(sp, r);
+                    // The first half of the site's Philox block covers the latency of the
+                    // neighbour reads, the second half that of the threshold reads.
+                    const uint32_t jn = r.x >> 19;
+                    const uint32_t nb0 = sp[r.y & 0xFFFFu], nb1 = sp[r.y >> 16];
+                    const uint32_t nb2 = sp[r.z & 0xFFFFu], nb3 = sp[r.z >> 16];
+                    const uint32_t nb4 = sp[r.w & 0xFFFFu], nb5 = sp[r.w >> 16];
+                    const uint32_t old = sp[j];
+                    __builtin_amdgcn_sched_barrier(0);
+                    uint32_t x[4] = {j, t, (uint32_t)q, c3}, key[2] = {A.key0, A.key1};
+                    philox_rounds<0, 5>(x, key);
+                    __builtin_amdgcn_sched_barrier(0);
+                    // per byte (slot): number of present bonds whose J * s_neighbour = +1
+                    const uint32_t k4 = (nb0 ^ bytemask(jn & 1u)) + (nb1 ^ bytemask((jn >> 1) & 1u)) +
+                                        (nb2 ^ bytemask((jn >> 2) & 1u)) +
+                                        (nb3 ^ bytemask((jn >> 3) & 1u)) +
+                                        (nb4 ^ bytemask((jn >> 4) & 1u)) +
+                                        (nb5 ^ bytemask((jn >> 5) & 1u));
                     // table index per slot byte: 2 k + h - d + imax (>= 0, <= 2 imax)
                     const uint32_t base = ((r.x >> 25) & 63u) + (uint32_t)(A.imax - 32) -
                                           ((r.x >> 16) & 7u);
                     const uint32_t idx4 = (k4 << 1) + __builtin_amdgcn_perm(0u, base, 0u);   // base in every byte
-                    const uint32_t old = sp[j];
                     uint32_t o0, o1, o2, o3;
                     if (scaled) {
                         const uint32_t off4 = (idx4 + soff4) << 2;
@@ -802,12 +837,11 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
                         o2 = (((idx4 >> 16) & 0xFFu) + 2u * (uint32_t)ni) << 2;
                         o3 = ((idx4 >> 24) + 3u * (uint32_t)ni) << 2;
                     }
-                    // thresholds read before the Philox block, whose arithmetic covers
-                    // their LDS latency
                     const uint32_t T3 = lds_word(lut, o3), T2 = lds_word(lut, o2);
                     const uint32_t T1 = lds_word(lut, o1), T0 = lds_word(lut, o0);
                     __builtin_amdgcn_sched_barrier(0);
-                    const uint4 u = philox10(j, t, (uint32_t)q, c3, A.key0, A.key1);
+                    philox_rounds<5, 10>(x, key);
+                    const uint4 u = make_uint4(x[0], x[1], x[2], x[3]);
                     uint32_t acc = 0u;   // bit b: new state of slot b (Eq. 6)
                     acc = shift_in_lt(acc, u.w, T3);
                     acc = shift_in_lt(acc, u.z, T2);
