@@ -667,41 +667,55 @@ __device__ void swap_instance(const SwapArgs &A, int inst, int32_t *red)
 // logical slots (the work-group of a pair's lower slot counts it), and on quad 0 the
 // running minimum.  The new mapping and energies of the four slots go to lperm / lE
 // (LDS) and the mapping to A.perm.
-__device__ void fused_swap_quad(const SwapArgs &A, int inst, int q, int32_t *lperm, int32_t *lE)
+__device__ void fused_swap_quad(const SwapArgs &A, const InstDev &I, int inst, int q,
+                                int32_t *lperm, int32_t *lE)
 {
-    const InstDev &I = A.inst[inst];
     const int tid = threadIdx.x;
     const uint32_t a = A.ctr[2] + (uint32_t)A.cyc_k + 1u;
     const int32_t *pin = A.perm_in + I.slot_off, *ein = A.E_in + I.slot_off;
     if (tid < 4) {
+        // every load of the decision is issued before any of it is used: the slot's and
+        // its partner's mapping and energy, the pair's table bounds, and the random word
         const int s = 4 * q + tid;
-        int32_t pv = pin[s], ev = ein[s];
+        const int R = A.reps, nb = A.n_beta;
+        const int b = s / R, l = s - b * R;
+        const int first = (a & 1u) ? 0 : 1;
+        int lo = -1;
         if (s < I.n_slots) {
-            const int R = A.reps, nb = A.n_beta;
-            const int b = s / R, l = s - b * R;
-            const int first = (a & 1u) ? 0 : 1;
-            int lo = -1;
             if (b >= first && ((b - first) & 1) == 0 && b + 1 < nb) lo = b;
             else if (b - 1 >= first && ((b - 1 - first) & 1) == 0) lo = b - 1;
-            if (lo >= 0) {
-                const int s0 = lo * R + l, s1 = s0 + R;
-                const int acc = swap_decision(A, inst, I, lo, l, ein[s0], ein[s1], a);
-                if (acc) {
-                    const int pt = (s == s0) ? s1 : s0;
-                    pv = pin[pt];
-                    ev = ein[pt];
-                }
-                if (s == s0) A.acc_count[(int64_t)inst * (nb - 1) * R + s0] += acc;
+        }
+        const int s0 = lo >= 0 ? lo * R + l : s;
+        const int pt = lo < 0 ? s : (s == s0 ? s0 + R : s0);
+        int32_t pv = pin[s], ev = ein[s];
+        const int32_t pp = pin[pt], ep = ein[pt];
+        int32_t len = 0, off = 0;
+        if (lo >= 0) {
+            len = A.tab_len[I.swap_off + lo];
+            off = A.tab_off[I.swap_off + lo];
+        }
+        const uint32_t u = philox10((uint32_t)s0, a, 0u, ((uint32_t)inst << 4) | TAG_SWAP, A.key0,
+                                    A.key1).x;
+        if (lo >= 0) {
+            // Delta E of the pair (b, b + 1) = E(b + 1) - E(b)
+            const int32_t dE = (s == s0) ? ep - ev : ev - ep;
+            const int acc = dE >= 0 ? 1 : (-dE < len && u < A.tab[off - dE]) ? 1 : 0;
+            if (acc) {
+                pv = pp;
+                ev = ep;
             }
+            if (s == s0) A.acc_count[(int64_t)inst * (nb - 1) * R + s0] += acc;
         }
         A.perm[I.slot_off + s] = pv;
         lperm[tid] = pv;
         lE[tid] = ev;
     }
-    if (q == 0 && tid == 0) {
+    if (q == 0 && tid < 64) {
+        // running minimum of the energies after the exchange (the same set as before it)
         int32_t m = 0x7FFFFFFF;
-        for (int s = 0; s < I.n_slots; ++s) m = min(m, ein[s]);
-        record_best(A, inst, m);
+        for (int i = tid; i < I.n_slots; i += 64) m = min(m, ein[i]);
+        m = wave_min(m);
+        if (tid == 0) record_best(A, inst, m);
     }
     __syncthreads();
 }
@@ -752,10 +766,14 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
         uint32_t *vis = Vr + 4 * I.n_rows;               // (npad + 31) / 32 + 1
         uint16_t *queue = (uint16_t *)(vis + ((npad + 31) >> 5) + 1);   // npad
         const int q = D.quad;
+        for (int e = tid; e < 4 * ni; e += kQuadThreads) {
+            const int i = e / ni;
+            lut[e] = A.lut[(int64_t)A.slot_lut[I.slot_off + 4 * q + i] * ni + (e - i * ni)];
+        }
         int32_t e_in = 0;   // fused exchange: this slot's energy after it (threads 0..3)
         int32_t pq[4];
         if (A.fused_swap) {
-            fused_swap_quad(A.sw, D.inst, q, red + 24, red + 28);
+            fused_swap_quad(A.sw, I, D.inst, q, red + 24, red + 28);
             for (int i = 0; i < 4; ++i) pq[i] = red[24 + i];
             if (tid < 4) e_in = red[28 + tid];
         } else {
@@ -764,10 +782,6 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
         const int64_t b0 = (int64_t)pq[0] * npad, b1 = (int64_t)pq[1] * npad;
         const int64_t b2 = (int64_t)pq[2] * npad, b3 = (int64_t)pq[3] * npad;
         const uint8_t *gs = A.spins + I.spin_off;
-        for (int e = tid; e < 4 * ni; e += kQuadThreads) {
-            const int i = e / ni;
-            lut[e] = A.lut[(int64_t)A.slot_lut[I.slot_off + 4 * q + i] * ni + (e - i * ni)];
-        }
         // gather + transpose: word j holds byte i = spin of slot 4q+i at site j
         for (int g = tid; g < (npad >> 2); g += kQuadThreads) {
             const uint32_t v0 = *(const uint32_t *)(gs + b0 + 4 * g);
