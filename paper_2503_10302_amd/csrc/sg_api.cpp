@@ -388,6 +388,7 @@ void apt_records(const Lat &L, std::vector<uint4> &rec, std::vector<uint4> &recj
 // the slices of parity p = (c - label sum) mod C when p is 0 or 1.
 void sqa_records(const Lat &L, std::vector<uint4> &rec, std::vector<uint4> &recj, InstDev &I)
 {
+    if (2 * L.n + 1 > 0xFFFF) fail(SG_EUNSUPPORTED, "DT-SQA lattice of %d sites is too large", L.n);
     const bool three = L.any_odd_ring();
     const int C = three ? 3 : 2;
     I.n_colours = C;
@@ -401,7 +402,15 @@ void sqa_records(const Lat &L, std::vector<uint4> &rec, std::vector<uint4> &recj
         for (int j = 0; j < L.n; ++j) {
             const int p = ((c - L.label_sum(j, three)) % C + C) % C;
             if (p > 1) continue;
-            rec.push_back(make_record(L, j, (uint32_t)p));
+            uint4 rr = make_record(L, j, (uint32_t)p);
+            // neighbour fields -> word offsets 2 nb + p into the replica's spin words
+            auto wo = [p](uint32_t f) {
+                return (2u * (f & 0xFFFFu) + (uint32_t)p) | ((2u * (f >> 16) + (uint32_t)p) << 16);
+            };
+            rr.y = wo(rr.y);
+            rr.z = wo(rr.z);
+            rr.w = wo(rr.w);
+            rec.push_back(rr);
             ++I.col_cnt[c];
         }
         off += I.col_cnt[c];

@@ -37,7 +37,9 @@ constexpr size_t kMaxLds = 160 * 1024;   // LDS per CU on gfx950
 //   z: nb[2] | nb[3] << 16   (+y, -y)
 //   w: nb[4] | nb[5] << 16   (+z, -z)
 // An absent bond (open boundary, axis of length one, or J = 0) points at the
-// dummy index n, whose spin word is kept zero.
+// dummy index n, whose spin word is kept zero.  The DT-SQA phase lists hold, in
+// place of each nb, the word offset 2 nb + p of the neighbour's spin word of
+// parity p.
 
 // Per-instance geometry and buffer offsets on the device.
 struct InstDev {

@@ -1074,10 +1074,11 @@ __device__ __forceinline__ uint32_t pair_off(uint32_t ev, uint32_t od, int g)
 
 // New states of the H slices of one parity at one site (Supplementary Eq. S.3 with
 // the heat-bath rule of Eq. 6).  Slice h = 4 g + i takes word i of the Philox block
-// of group g; its threshold index is a byte of idx4, the sum of the contributions of
-// the bit planes of the aligned-neighbour count (c0, c1, c2) and of the number of up
-// Trotter neighbours (t0, t1), read from two pair tables (planes c0, c1 and c2, t0,
-// indexed by a byte of pair_planes) and one 16-entry table (t1).  Groups run from the
+// of group g; its threshold index is a byte of idx4 (relative to lut, the row already
+// moved by the site's field and degree), the sum of the contributions of the bit
+// planes of the aligned-neighbour count (c0, c1, c2) and of the number of up Trotter
+// neighbours (t0, t1), read from two pair tables (planes c0, c1 and c2, t0, indexed by
+// a byte of pair_planes) and one 16-entry table (t1).  Groups run from the
 // highest to the lowest so that the borrow chain leaves slice h at bit h.  The block
 // counter is (2 j + p, step, r << 16 | g, instance): only its first word differs
 // between the lanes, so the products of the other half in the first two rounds are
@@ -1089,8 +1090,8 @@ template <int NG, bool SCALED>
 __device__ __forceinline__ uint32_t sqa_slices(const uint32_t *lut, const uint32_t *tab01,
                                                const uint32_t *tab2t, const uint32_t *tab1,
                                                uint32_t e01, uint32_t o01, uint32_t e2t,
-                                               uint32_t o2t, uint32_t t1b, uint32_t base4,
-                                               uint32_t jp, uint32_t t, uint32_t x2, uint32_t c3,
+                                               uint32_t o2t, uint32_t t1b, uint32_t jp,
+                                               uint32_t t, uint32_t x2, uint32_t c3,
                                                uint32_t k0, uint32_t k1, int ngrp)
 {
     uint32_t res = 0u;
@@ -1103,7 +1104,7 @@ __device__ __forceinline__ uint32_t sqa_slices(const uint32_t *lut, const uint32
     uint32_t s2 = lds_word(tab1, nib_off(t1b, ng - 1));
 #pragma unroll
     for (int g = ng - 1; g >= 0; --g) {
-        const uint32_t idx4 = s0 + s1 + s2 + base4;
+        const uint32_t idx4 = s0 + s1 + s2;
         uint32_t o0, o1, o2, o3;
         if (SCALED) {
             o0 = idx4 & 0xFFu;
@@ -1207,12 +1208,13 @@ void sqa_kernel(SqaArgs A)
                 const uint32_t p = rr.x >> 31;
                 const uint32_t jn = rr.x >> 19;
                 // aligned words: bit h = 1 when J * s_neighbour = +1 in slice 2h + p
-                const uint32_t a0 = sp[2 * (rr.y & 0xFFFFu) + p] ^ (0u - (jn & 1u));
-                const uint32_t a1 = sp[2 * (rr.y >> 16) + p] ^ (0u - ((jn >> 1) & 1u));
-                const uint32_t a2 = sp[2 * (rr.z & 0xFFFFu) + p] ^ (0u - ((jn >> 2) & 1u));
-                const uint32_t a3 = sp[2 * (rr.z >> 16) + p] ^ (0u - ((jn >> 3) & 1u));
-                const uint32_t a4 = sp[2 * (rr.w & 0xFFFFu) + p] ^ (0u - ((jn >> 4) & 1u));
-                const uint32_t a5 = sp[2 * (rr.w >> 16) + p] ^ (0u - ((jn >> 5) & 1u));
+                // (the record holds the neighbours' word offsets 2 nb + p)
+                const uint32_t a0 = sp[rr.y & 0xFFFFu] ^ (0u - (jn & 1u));
+                const uint32_t a1 = sp[rr.y >> 16] ^ (0u - ((jn >> 1) & 1u));
+                const uint32_t a2 = sp[rr.z & 0xFFFFu] ^ (0u - ((jn >> 2) & 1u));
+                const uint32_t a3 = sp[rr.z >> 16] ^ (0u - ((jn >> 3) & 1u));
+                const uint32_t a4 = sp[rr.w & 0xFFFFu] ^ (0u - ((jn >> 4) & 1u));
+                const uint32_t a5 = sp[rr.w >> 16] ^ (0u - ((jn >> 5) & 1u));
                 // bit-sliced 6-input count: k = c0 + 2 c1 + 4 c2 per slice
                 const uint32_t s1 = a0 ^ a1 ^ a2, k1 = (a0 & a1) | (a2 & (a0 ^ a1));
                 const uint32_t s2 = a3 ^ a4 ^ a5, k2 = (a3 & a4) | (a5 & (a3 ^ a4));
@@ -1224,15 +1226,14 @@ void sqa_kernel(SqaArgs A)
                 const uint32_t up = p ? ev : rotl_h(od, H, mask);
                 const uint32_t dn = p ? rotr_h(ev, H, mask) : od;
                 const uint32_t t0b = up ^ dn, t1b = up & dn;
-                const uint32_t base4 = (SCALED ? 4u : 1u) *
-                                       (uint32_t)(3 * ((int32_t)((rr.x >> 25) & 63u) - 32 -
-                                                       (int32_t)((rr.x >> 16) & 7u) + A.smax)) *
-                                       0x01010101u;
+                // the site's part of the threshold index, 3 (h - d + smax), moves the row
+                const uint32_t *lsite = lrow + 3 * ((int32_t)((rr.x >> 25) & 63u) - 32 -
+                                                    (int32_t)((rr.x >> 16) & 7u) + A.smax);
                 uint32_t e01, o01, e2t, o2t;
                 pair_planes(c0, c1, e01, o01);
                 pair_planes(c2, t0b, e2t, o2t);
-                const uint32_t res = sqa_slices<NG, SCALED>(lrow, tab01, tab2t, tab1, e01, o01, e2t,
-                                                            o2t, t1b, base4, (j << 1) | p, t,
+                const uint32_t res = sqa_slices<NG, SCALED>(lsite, tab01, tab2t, tab1, e01, o01, e2t,
+                                                            o2t, t1b, (j << 1) | p, t,
                                                             (uint32_t)r << 16, c3, A.key0,
                                                             A.key1, ngrp);
                 sp[2 * j + p] = res & mask;
