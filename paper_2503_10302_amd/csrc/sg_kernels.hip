@@ -419,6 +419,113 @@ __device__ __forceinline__ uint32_t xfill(uint32_t V, uint32_t Q, uint32_t mr, u
     }
 }
 
+// xfill on two rows of at most 16 sites packed in one word (bits 0..15 and 16..31):
+// shifts are masked so that nothing crosses between the halves.
+__device__ __forceinline__ uint32_t xfill2(uint32_t V, uint32_t Q, uint32_t mr, uint32_t ml,
+                                           uint32_t hi)
+{
+    while (true) {
+        const uint32_t right = ((V >> 1) & 0x7FFF7FFFu) | ((V & 0x00010001u) << hi);
+        const uint32_t left = ((V << 1) & 0xFFFEFFFEu) | ((V >> hi) & 0x00010001u);
+        const uint32_t Vn = V | (((right & mr) | (left & ml)) & Q);
+        if (Vn == V) return V;
+        V = Vn;
+    }
+}
+
+// The flood fill of icm_pairs_planes for both pairs (V0, V1: this lane's row of each
+// pair's cluster, seeds on entry).  PACK (rows of at most 16 sites): both pairs in one
+// word, so one fill along x, four lane shuffles and one exchanged word per row serve
+// both.  On return Vr holds the final rows: packed (Vr[row]) or Vr[p * nrows + row].
+template <bool PACK>
+__device__ __forceinline__ void plane_fill(uint32_t &V0, uint32_t &V1, uint32_t Q0, uint32_t Q1,
+                                           const uint4 a, const uint32_t mk[4], const int src[4],
+                                           const int nbr[4], bool own, int r, int nrows,
+                                           int lane, uint32_t hi, uint32_t *Vr)
+{
+    if (PACK) {
+        uint32_t W = V0 | (V1 << 16);
+        const uint32_t Qw = Q0 | (Q1 << 16), mr = a.x | (a.x << 16), ml = a.y | (a.y << 16);
+        uint32_t mkw[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) mkw[d] = mk[d] | (mk[d] << 16);
+        uint32_t X[2] = {0u, 0u};   // +z / -z rows from other waves
+        while (true) {
+            while (true) {   // closure inside the wave
+                W = xfill2(W, Qw, mr, ml, hi);
+                uint32_t N = 0u;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const int sl = src[d] >= 0 ? src[d] : lane;
+                    const uint32_t u = __shfl(W, sl, 64);
+                    const uint32_t e = src[d] >= 0 ? u : (d == 2 ? X[0] : (d == 3 ? X[1] : 0u));
+                    N |= e & mkw[d];
+                }
+                const uint32_t n = W | (N & Qw);
+                const int grew = n != W;
+                W = n;
+                if (!__any(grew)) break;
+            }
+            // exchange boundary planes between waves
+            if (own) Vr[r] = W;
+            __syncthreads();
+            int changed = 0;
+            if (own) {
+#pragma unroll
+                for (int d = 2; d < 4; ++d) {
+                    if (src[d] >= 0) continue;
+                    X[d - 2] = Vr[nbr[d]];
+                    if (X[d - 2] & mkw[d] & Qw & ~W) changed = 1;
+                }
+            }
+            if (!__syncthreads_or(changed)) break;
+        }
+        V0 = W & 0xFFFFu;
+        V1 = W >> 16;
+    } else {
+        uint32_t X0[2] = {0u, 0u}, X1[2] = {0u, 0u};   // +z / -z rows from other waves
+        while (true) {
+            // closure inside the wave
+            while (true) {
+                V0 = xfill(V0, Q0, a.x, a.y, hi);
+                V1 = xfill(V1, Q1, a.x, a.y, hi);
+                uint32_t N0 = 0u, N1 = 0u;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const int sl = src[d] >= 0 ? src[d] : lane;
+                    const uint32_t u0 = __shfl(V0, sl, 64), u1 = __shfl(V1, sl, 64);
+                    const uint32_t e0 = src[d] >= 0 ? u0 : (d == 2 ? X0[0] : (d == 3 ? X0[1] : 0u));
+                    const uint32_t e1 = src[d] >= 0 ? u1 : (d == 2 ? X1[0] : (d == 3 ? X1[1] : 0u));
+                    N0 |= e0 & mk[d];
+                    N1 |= e1 & mk[d];
+                }
+                const uint32_t n0 = V0 | (N0 & Q0), n1 = V1 | (N1 & Q1);
+                const int grew = (n0 != V0) || (n1 != V1);
+                V0 = n0;
+                V1 = n1;
+                if (!__any(grew)) break;
+            }
+            // exchange boundary planes between waves
+            if (own) {
+                Vr[r] = V0;
+                Vr[nrows + r] = V1;
+            }
+            __syncthreads();
+            int changed = 0;
+            if (own) {
+#pragma unroll
+                for (int d = 2; d < 4; ++d) {
+                    if (src[d] >= 0) continue;
+                    X0[d - 2] = Vr[nbr[d]];
+                    X1[d - 2] = Vr[nrows + nbr[d]];
+                    if ((X0[d - 2] & mk[d] & Q0 & ~V0) | (X1[d - 2] & mk[d] & Q1 & ~V1)) changed = 1;
+                }
+            }
+            if (!__syncthreads_or(changed)) break;
+        }
+    }
+}
+
 __device__ void icm_pairs_planes(uint32_t *sp, const uint4 *rowA, const uint4 *rowB,
                                  const uint4 *rowC, int n, int lx, int ly, int lz, int np,
                                  uint32_t pa, uint32_t pb, uint4 w01, uint32_t *Qr, uint32_t *Vr,
@@ -489,59 +596,28 @@ __device__ void icm_pairs_planes(uint32_t *sp, const uint4 *rowA, const uint4 *r
     }
     const uint32_t mk[4] = {a.z, a.w, b.x, b.y};
     const uint32_t Q0 = (m0 > 0) ? q0 : 0u, Q1 = (m1 > 0) ? q1 : 0u;
-    uint32_t X0[2] = {0u, 0u}, X1[2] = {0u, 0u};   // +z / -z rows from other waves
-    while (true) {
-        // closure inside the wave
-        while (true) {
-            V0 = xfill(V0, Q0, a.x, a.y, hi);
-            V1 = xfill(V1, Q1, a.x, a.y, hi);
-            uint32_t N0 = 0u, N1 = 0u;
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                const int sl = src[d] >= 0 ? src[d] : lane;
-                const uint32_t u0 = __shfl(V0, sl, 64), u1 = __shfl(V1, sl, 64);
-                const uint32_t e0 = src[d] >= 0 ? u0 : (d == 2 ? X0[0] : (d == 3 ? X0[1] : 0u));
-                const uint32_t e1 = src[d] >= 0 ? u1 : (d == 2 ? X1[0] : (d == 3 ? X1[1] : 0u));
-                N0 |= e0 & mk[d];
-                N1 |= e1 & mk[d];
-            }
-            const uint32_t n0 = V0 | (N0 & Q0), n1 = V1 | (N1 & Q1);
-            const int grew = (n0 != V0) || (n1 != V1);
-            V0 = n0;
-            V1 = n1;
-            if (!__any(grew)) break;
-        }
-        // exchange boundary planes between waves
-        if (own) {
-            Vr[r] = V0;
-            Vr[nrows + r] = V1;
-        }
-        __syncthreads();
-        int changed = 0;
-        if (own) {
-#pragma unroll
-            for (int d = 2; d < 4; ++d) {
-                if (src[d] >= 0) continue;
-                X0[d - 2] = Vr[nbr[d]];
-                X1[d - 2] = Vr[nrows + nbr[d]];
-                if ((X0[d - 2] & mk[d] & Q0 & ~V0) | (X1[d - 2] & mk[d] & Q1 & ~V1)) changed = 1;
-            }
-        }
-        if (!__syncthreads_or(changed)) break;
-    }
+    const bool pack = lx <= 16;
+    if (pack)
+        plane_fill<true>(V0, V1, Q0, Q1, a, mk, src, nbr, own, r, nrows, lane, hi, Vr);
+    else
+        plane_fill<false>(V0, V1, Q0, Q1, a, mk, src, nbr, own, r, nrows, lane, hi, Vr);
     // cluster sizes and, for each pair, the sum of J s_i s_j of the first replica over
     // bonds that cross the cluster boundary (counted once, along +x, +y, +z)
     int32_t tot[4] = {0, 0, 0, 0};
     if (own) {
         const uint4 cc = rowC[r];
         for (int p = 0; p < np; ++p) {
-            const uint32_t *Vp = Vr + p * nrows, *Sp = Sr + p * nrows;
+            const uint32_t *Sp = Sr + p * nrows;
+            // final cluster row idx of pair p (packed rows: half p of Vr[idx])
+            auto vrow = [&](uint32_t idx) {
+                return pack ? (Vr[idx] >> (16 * p)) & 0xFFFFu : Vr[p * nrows + idx];
+            };
             const uint32_t V = p ? V1 : V0, S = p ? s1 : s0;
             tot[p] += __popc(V);
             const uint32_t Vx = (V >> 1) | (V << hi), Sx = (S >> 1) | (S << hi);
             const uint32_t X0b = (V ^ Vx) & a.x, N0b = S ^ Sx ^ cc.x;
-            const uint32_t X1b = (V ^ Vp[b.z & 0xFFFFu]) & a.z, N1b = S ^ Sp[b.z & 0xFFFFu] ^ cc.y;
-            const uint32_t X2b = (V ^ Vp[b.w & 0xFFFFu]) & b.x, N2b = S ^ Sp[b.w & 0xFFFFu] ^ cc.z;
+            const uint32_t X1b = (V ^ vrow(b.z & 0xFFFFu)) & a.z, N1b = S ^ Sp[b.z & 0xFFFFu] ^ cc.y;
+            const uint32_t X2b = (V ^ vrow(b.w & 0xFFFFu)) & b.x, N2b = S ^ Sp[b.w & 0xFFFFu] ^ cc.z;
             tot[2 + p] += __popc(X0b & ~N0b) - __popc(X0b & N0b) + __popc(X1b & ~N1b) -
                           __popc(X1b & N1b) + __popc(X2b & ~N2b) - __popc(X2b & N2b);
         }

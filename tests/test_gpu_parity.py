@@ -158,10 +158,14 @@ def test_apt_long_rows_use_queue_search():
 @pytest.mark.parametrize("reps", [2, 4])
 def test_apt_cluster_search_layouts(reps):
     """Row-bitset cluster search in both layouts: whole y-z planes per wave (wave-local fill:
-    a wave filled exactly by 64-row planes, four waves of planes, open axes) and one row per
-    thread in thread order (more than 64 rows per plane, or more planes than four waves hold)."""
+    a wave filled exactly by 64-row planes, four waves of planes, open axes; rows of at most
+    16 sites with both pairs packed in one word, 16 exactly, and 17 to 32 sites one word per
+    pair) and one row per thread in thread order (more than 64 rows per plane, or more planes
+    than four waves hold)."""
     insts = [_inst((2, 64, 4), 7, 61), _inst((5, 16, 16), 5, 62), _inst((5, 7, 9), 1, 63),
-             _inst((4, 20, 20), 7, 64), _inst((3, 70, 2), 7, 65), _inst((7, 13, 20), 3, 66)]
+             _inst((4, 20, 20), 7, 64), _inst((3, 70, 2), 7, 65), _inst((7, 13, 20), 3, 66),
+             _inst((16, 4, 4), 7, 67), _inst((20, 6, 6), 7, 68), _inst((32, 8, 8), 7, 69),
+             _inst((17, 5, 12), 5, 70), _inst((20, 16, 16), 6, 71)]
     beta = geometric_ladder(6, 0.4, 3.0)
     ctx = sg.apt(insts, beta, SEED, reps_per_beta=reps)
     trace = ctx.run_apt(30, 1, 0.5, record_every=5)
