@@ -544,6 +544,7 @@ __device__ void icm_pairs_planes(uint32_t *sp, const uint4 *rowA, const uint4 *r
     uint32_t q0 = 0u, q1 = 0u, s0 = 0u, s1 = 0u;
     if (own) {
         const uint32_t *row = sp + r * lx;
+#pragma unroll 4
         for (int x = 0; x < lx; ++x) {
             const uint32_t w = row[x];
             q0 |= (uint32_t)(((w & mA0) != 0) != ((w & mB0) != 0)) << x;
@@ -557,14 +558,16 @@ __device__ void icm_pairs_planes(uint32_t *sp, const uint4 *rowA, const uint4 *r
     }
     // seeds: the k-th site with q = -1 in ascending site order; threads hold rows in
     // ascending row order (lanes past the last plane of a wave hold none)
+    // (both pairs in one scan: counts of pair 1 in the upper 16 bits; n < 2^16 here)
     uint32_t V0 = 0u, V1 = 0u;
-    int32_t m0 = 0, m1 = 0;
+    int32_t mm;
+    const int32_t pre01 = block_exclusive_scan(__popc(q0) | (__popc(q1) << 16), red, &mm);
+    const int32_t m0 = mm & 0xFFFF, m1 = (int32_t)((uint32_t)mm >> 16);
     for (int p = 0; p < np; ++p) {
         const uint32_t qq0 = p ? q1 : q0;
         const int32_t cnt = __popc(qq0);
-        int32_t m;
-        const int32_t prefix = block_exclusive_scan(cnt, red, &m);
-        if (p) m1 = m; else m0 = m;
+        const int32_t m = p ? m1 : m0;
+        const int32_t prefix = p ? (int32_t)((uint32_t)pre01 >> 16) : (pre01 & 0xFFFF);
         if (m == 0) continue;
         const uint32_t w = p ? w01.z : w01.x;
         const int32_t k = (int32_t)(((uint64_t)w * (uint64_t)(uint32_t)m) >> 32);
