@@ -1524,6 +1524,86 @@ double sigma_of_moments(int64_t S1, int64_t S2, int64_t N)
 
 }  // namespace
 
+// The adaptive stage with 32 chains per word (adapt_kernel), for instances without
+// fields.  Returns false, having done nothing, when it does not apply; the caller then
+// runs the chains as APT slots.
+bool adaptive_packed(sg_ctx *c, const sg_adaptive_params *p, double *beta_out,
+                     double *sigma_out, int32_t *len_out)
+{
+    if (any_field(c) || c->ni > 64) return false;
+    int max_npad = 0, max_n = 0;
+    for (const InstDev &I : c->idev) {
+        max_npad = std::max(max_npad, I.npad);
+        max_n = std::max(max_n, I.n);
+    }
+    const int per_thread = 3 * ((max_n + kAdaptThreads - 1) / kAdaptThreads);
+    int planes = 1;
+    while ((1 << planes) <= per_thread) ++planes;
+    const size_t lds = sizeof(uint32_t) * (size_t)(max_npad + 1);
+    if (planes > kAdaptPlanes || lds + 16 * 1024 > kMaxLds) return false;
+    hipStream_t s = c->stream;
+    const int n_inst = c->n_inst, nc = p->n_chains, nw = (nc + 31) / 32;
+    AdaptArgs a{};
+    a.inst = c->d_inst.p;
+    a.rec_col = c->d_rec.p;
+    a.rec_j = c->d_recj.p;
+    a.wstride = max_npad + 1;
+    DevBuf<uint32_t> words;
+    words.alloc((size_t)n_inst * nw * (size_t)a.wstride, "adaptive chains");
+    DevBuf<int64_t> mom;
+    mom.alloc((size_t)n_inst * nc * 2, "moments");
+    a.words = words.p;
+    a.lut = c->d_lut.p;
+    a.mom = mom.p;
+    a.n_chains = nc;
+    a.nw = nw;
+    a.imax = c->imax;
+    a.ni = c->ni;
+    a.planes = planes;
+    a.key0 = c->key0;
+    a.key1 = c->key1;
+    hip_check(launch_adapt_init(a, n_inst, s), "adaptive init");
+    std::vector<double> bt(n_inst, p->beta0);
+    std::vector<int> len(n_inst, 0);
+    std::vector<char> active(n_inst, 1);
+    std::vector<uint32_t> lut((size_t)n_inst * c->ni);
+    std::vector<int64_t> m((size_t)n_inst * nc * 2);
+    uint32_t tglob = 0;
+    for (int step = 0; step < p->max_steps; ++step) {
+        bool any = false;
+        for (int i = 0; i < n_inst; ++i) any |= active[i] != 0;
+        if (!any) break;
+        for (int i = 0; i < n_inst; ++i)
+            for (int I2 = -c->imax; I2 <= c->imax; ++I2)
+                lut[(size_t)i * c->ni + (I2 + c->imax)] = heat_bath_threshold(bt[i], I2);
+        hip_check(hipStreamSynchronize(s), "adaptive");
+        c->d_lut.upload(lut.data(), lut.size(), s, "adaptive tables");
+        a.t0 = tglob;
+        a.n_sweeps = p->sweeps;
+        a.mom_from = p->sweeps - p->tail;
+        hip_check(launch_adapt(a, n_inst, lds, s), "adaptive sweeps");
+        tglob += (uint32_t)p->sweeps;
+        mom.download(m.data(), m.size(), s, "moments");
+        hip_check(hipStreamSynchronize(s), "adaptive");
+        for (int i = 0; i < n_inst; ++i) {
+            if (!active[i]) continue;
+            double sum = 0.0;
+            for (int k = 0; k < nc; ++k) {
+                const int64_t *mk = &m[((size_t)i * nc + k) * 2];
+                sum += sigma_of_moments(mk[0], mk[1], p->tail);
+            }
+            const double sigma = sum / (double)nc;
+            beta_out[(size_t)i * p->max_steps + step] = bt[i];
+            if (sigma_out) sigma_out[(size_t)i * p->max_steps + step] = sigma;
+            len[i] = step + 1;
+            if (sigma < p->tol) active[i] = 0;
+            else bt[i] = bt[i] + p->alpha / sigma;
+        }
+    }
+    for (int i = 0; i < n_inst; ++i) len_out[i] = len[i];
+    return true;
+}
+
 extern "C" sg_status sg_adaptive_ladder(const sg_lattice *inst, int32_t n_inst,
                                         const sg_adaptive_params *p, uint64_t seed,
                                         void *hip_stream, double *beta_out, double *sigma_out,
@@ -1557,6 +1637,10 @@ extern "C" sg_status sg_adaptive_ladder(const sg_lattice *inst, int32_t n_inst,
         cfg.seed = seed;
         cfg.hip_stream = hip_stream;
         create_apt(c, &cfg);
+        if (adaptive_packed(c, p, beta_out, sigma_out, len_out)) {
+            delete c;
+            return SG_OK;
+        }
         hipStream_t s = c->stream;
         const int nb4 = 4 * c->n_quads;
         // re-initialise with the adaptive-stage purpose tag

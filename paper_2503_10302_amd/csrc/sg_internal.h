@@ -157,6 +157,24 @@ struct SqaArgs {
     uint32_t key0, key1;
 };
 
+// Adaptive-ladder stage with the chains bit-packed: word w of a site holds chains
+// 32 w .. 32 w + 31 of its instance (bit b = chain 32 w + b; 1 = up), all at the
+// instance's current beta.  Fields must be zero (energies count unsatisfied bonds).
+constexpr int kAdaptThreads = 512;
+constexpr int kAdaptPlanes = 10;   // bits of the per-thread unsatisfied-bond counters
+struct AdaptArgs {
+    const InstDev *inst;
+    const uint4 *rec_col;      // colour-sorted site records
+    const uint4 *rec_j;        // site-ordered site records
+    uint32_t *words;           // [inst][nw][wstride]: the chains' spin words
+    const uint32_t *lut;       // [inst][ni]: heat-bath thresholds at the instance's beta
+    int64_t *mom;              // [inst][n_chains][2]: sum of E, sum of E^2 over the tail
+    int64_t wstride;           // words per (instance, word) block, >= npad + 1
+    uint32_t t0;               // sweep counter of the launch's first sweep
+    int32_t n_chains, nw, n_sweeps, mom_from, imax, ni, planes;
+    uint32_t key0, key1;
+};
+
 // Host-callable launch wrappers (defined in sg_kernels.hip).
 hipError_t launch_apt_init(const InstDev *inst_d, const QuadDesc *desc, int n_blocks,
                            uint8_t *spins, const int32_t *perm, uint32_t key0, uint32_t key1,
@@ -167,6 +185,8 @@ hipError_t launch_sqa_init(const SqaArgs &a, int n_inst, hipStream_t s);
 // DT-SQA kernel with a work-group of `threads` (a multiple of 64 in 128..1024).
 bool sqa_config_valid(int threads);
 hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, int threads, hipStream_t s);
+hipError_t launch_adapt_init(const AdaptArgs &a, int n_inst, hipStream_t s);
+hipError_t launch_adapt(const AdaptArgs &a, int n_inst, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 // ctr[i] += d[i] for the four counters (one thread; ordered by the stream).

@@ -1380,6 +1380,181 @@ __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n)
 }
 
 // ---------------------------------------------------------------------------
+// Adaptive-ladder stage (Methods, APT details): all chains of an instance run at the
+// instance's current beta, so 32 of them share one word per site and one threshold
+// row, and the aligned-neighbour count is summed bit-sliced as in the DT-SQA kernel.
+// One work-group per (instance, word of 32 chains); the words stay in LDS for all
+// sweeps of a launch.  Chain c = 32 w + 4 g + i takes word i of the Philox block
+// (site, sweep, 8 w + g, instance) -- the counter of slot c in the APT sweep.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kAdaptThreads) void adapt_init_kernel(AdaptArgs A)
+{
+    const int inst = blockIdx.x / A.nw, w = blockIdx.x - inst * A.nw;
+    const InstDev I = A.inst[inst];
+    const int nch = min(32, A.n_chains - 32 * w), ng = (nch + 3) >> 2;
+    const uint32_t c3 = ((uint32_t)inst << 4) | TAG_ADAPT_INIT;
+    uint32_t *g = A.words + (int64_t)blockIdx.x * A.wstride;
+    for (int j = threadIdx.x; j < (int)A.wstride; j += kAdaptThreads) {
+        uint32_t wd = 0u;
+        if (j < I.n)
+            for (int gq = 0; gq < ng; ++gq) {
+                const uint4 u = philox10((uint32_t)j, 0u, (uint32_t)(8 * w + gq), c3, A.key0, A.key1);
+                const uint32_t us[4] = {u.x, u.y, u.z, u.w};
+                for (int i = 0; i < 4; ++i)
+                    if (4 * gq + i < nch && us[i] < 0x80000000u) wd |= 1u << (4 * gq + i);
+            }
+        g[j] = wd;
+    }
+}
+
+__global__ __launch_bounds__(kAdaptThreads) void adapt_kernel(AdaptArgs A)
+{
+    // Static LDS: pair spread table of planes c0, c1 (256), spread table of c2 (16),
+    // threshold row (<= 64), per-thread counters for the energies, reduction scratch.
+    __shared__ uint32_t tabs[256 + 16 + 64];
+    __shared__ uint32_t vc[kAdaptPlanes * kAdaptThreads];
+    constexpr int kWaves = kAdaptThreads / 64;
+    __shared__ int32_t red[kWaves * 32 + 1];
+    extern __shared__ uint32_t sp[];   // npad + 1 words, the last one the zero dummy
+    const int inst = blockIdx.x / A.nw, w = blockIdx.x - inst * A.nw;
+    const InstDev I = A.inst[inst];
+    const int tid = threadIdx.x, n = I.n, npad = I.npad;
+    const int nch = min(32, A.n_chains - 32 * w), ng = (nch + 3) >> 2;
+    const uint32_t vmask = nch >= 32 ? 0xFFFFFFFFu : ((1u << nch) - 1u);
+    uint32_t *gw = A.words + (int64_t)blockIdx.x * A.wstride;
+    for (int i = tid; i <= npad; i += kAdaptThreads) sp[i] = i < npad ? gw[i] : 0u;
+    uint32_t *tab01 = tabs, *tab2 = tabs + 256, *lut = tabs + 272;
+    for (int e = tid; e < 272; e += kAdaptThreads) {
+        // bit i of a nibble -> byte i; table index = I + imax = 2 k + (h - d + imax), k =
+        // c0 + 2 c1 + 4 c2, stored times 4 (byte offsets into the threshold row)
+        auto spread = [](uint32_t nib) {
+            return (nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21);
+        };
+        const uint32_t lo = (uint32_t)e & 15u, hi = ((uint32_t)e >> 4) & 15u;
+        tabs[e] = e < 256 ? 8u * spread(lo) + 16u * spread(hi) : 32u * spread(lo);
+    }
+    for (int i = tid; i < A.ni; i += kAdaptThreads) lut[i] = A.lut[(int64_t)inst * A.ni + i];
+    // bonds along +x, +y, +z present (J != 0): E = 2 (unsatisfied) - bonds
+    if (tid == 0) red[kWaves * 32] = 0;
+    __syncthreads();
+    int32_t nbc = 0;
+    for (int j = tid; j < n; j += kAdaptThreads) {
+        const uint4 r = A.rec_j[I.recj_off + j];
+        nbc += ((r.y & 0xFFFFu) != (uint32_t)n) + ((r.z & 0xFFFFu) != (uint32_t)n) +
+               ((r.w & 0xFFFFu) != (uint32_t)n);
+    }
+    atomicAdd(&red[kWaves * 32], nbc);
+    __syncthreads();
+    const int32_t bonds = red[kWaves * 32];
+    const uint32_t c3 = ((uint32_t)inst << 4) | TAG_ADAPT_SWEEP;
+    int64_t S1 = 0, S2 = 0;   // moments of chain 32 w + tid (threads < nch)
+    for (int sw = 0; sw < A.n_sweeps; ++sw) {
+        const uint32_t t = A.t0 + (uint32_t)sw;
+        for (int c = 0; c < I.n_colours; ++c) {
+            const uint4 *rc = A.rec_col + I.rec_off + A.inst[inst].col_off[c];
+            const int cnt = A.inst[inst].col_cnt[c];
+            for (int i = tid; i < cnt; i += kAdaptThreads) {
+                const uint4 r = rc[i];
+                const uint32_t j = r.x & 0xFFFFu, jn = r.x >> 19;
+                // aligned words: bit b = 1 when J s_neighbour = +1 for chain b
+                const uint32_t a0 = sp[r.y & 0xFFFFu] ^ (0u - (jn & 1u));
+                const uint32_t a1 = sp[r.y >> 16] ^ (0u - ((jn >> 1) & 1u));
+                const uint32_t a2 = sp[r.z & 0xFFFFu] ^ (0u - ((jn >> 2) & 1u));
+                const uint32_t a3 = sp[r.z >> 16] ^ (0u - ((jn >> 3) & 1u));
+                const uint32_t a4 = sp[r.w & 0xFFFFu] ^ (0u - ((jn >> 4) & 1u));
+                const uint32_t a5 = sp[r.w >> 16] ^ (0u - ((jn >> 5) & 1u));
+                const uint32_t s1 = a0 ^ a1 ^ a2, k1 = (a0 & a1) | (a2 & (a0 ^ a1));
+                const uint32_t s2 = a3 ^ a4 ^ a5, k2 = (a3 & a4) | (a5 & (a3 ^ a4));
+                const uint32_t cy = s1 & s2;
+                const uint32_t c0 = s1 ^ s2, c1 = k1 ^ k2 ^ cy, c2 = (k1 & k2) | (cy & (k1 ^ k2));
+                // the site's part of the table index, h - d + imax, moves the row
+                const uint32_t *lsite = lut + ((int32_t)((r.x >> 25) & 63u) - 32 -
+                                               (int32_t)((r.x >> 16) & 7u) + A.imax);
+                uint32_t e01, o01;
+                pair_planes(c0, c1, e01, o01);
+                uint32_t res = 0u;
+                uint32_t s0v = lds_word(tab01, pair_off(e01, o01, ng - 1));
+                uint32_t s1v = lds_word(tab2, ((c2 >> (4 * (ng - 1))) & 15u) << 2);
+#pragma unroll
+                for (int g = 7; g >= 0; --g) {
+                    if (g >= ng) continue;
+                    const uint32_t idx4 = s0v + s1v;
+                    const uint32_t T3 = lds_word(lsite, idx4 >> 24);
+                    const uint32_t T2 = lds_word(lsite, (idx4 >> 16) & 0xFFu);
+                    const uint32_t T1 = lds_word(lsite, (idx4 >> 8) & 0xFFu);
+                    const uint32_t T0 = lds_word(lsite, idx4 & 0xFFu);
+                    if (g > 0) {
+                        s0v = lds_word(tab01, pair_off(e01, o01, g - 1));
+                        s1v = lds_word(tab2, nib_off(c2, g - 1));
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    const uint4 u = philox10(j, t, (uint32_t)(8 * w + g), c3, A.key0, A.key1);
+                    res = shift_in_lt(res, u.w, T3);
+                    res = shift_in_lt(res, u.z, T2);
+                    res = shift_in_lt(res, u.y, T1);
+                    res = shift_in_lt(res, u.x, T0);
+                }
+                sp[j] = res & vmask;
+            }
+            __syncthreads();
+        }
+        if (sw >= A.mom_from) {
+            // unsatisfied bonds per chain: each thread adds the +x, +y, +z bonds of its
+            // sites into a vertical counter (plane p = bit p of every chain's count)
+            uint32_t v[kAdaptPlanes];
+#pragma unroll
+            for (int p = 0; p < kAdaptPlanes; ++p) v[p] = 0u;
+            for (int j = tid; j < n; j += kAdaptThreads) {
+                const uint4 r = A.rec_j[I.recj_off + j];
+                const uint32_t jn = r.x >> 19, wj = sp[j];
+                const uint32_t nbf[3] = {r.y & 0xFFFFu, r.z & 0xFFFFu, r.w & 0xFFFFu};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    if (nbf[a] == (uint32_t)n) continue;
+                    uint32_t carry = wj ^ sp[nbf[a]] ^ (0u - ((jn >> (2 * a)) & 1u));
+#pragma unroll
+                    for (int p = 0; p < kAdaptPlanes; ++p) {
+                        if (p >= A.planes) break;
+                        const uint32_t cp = v[p] & carry;
+                        v[p] ^= carry;
+                        carry = cp;
+                    }
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < kAdaptPlanes; ++p)
+                if (p < A.planes) vc[p * kAdaptThreads + tid] = v[p];
+            __syncthreads();
+            // chain cc, sources part * 32 .. part * 32 + 31
+            const int cc = tid & 31, part = tid >> 5;
+            int32_t cntu = 0;
+            for (int src = part * 32; src < part * 32 + 32; ++src)
+#pragma unroll
+                for (int p = 0; p < kAdaptPlanes; ++p)
+                    if (p < A.planes) cntu += (int32_t)(((vc[p * kAdaptThreads + src] >> cc) & 1u) << p);
+            cntu += __shfl_xor(cntu, 32, 64);
+            if ((tid & 63) < 32) red[(tid >> 6) * 32 + cc] = cntu;
+            __syncthreads();
+            if (tid < nch) {
+                int32_t u = 0;
+#pragma unroll
+                for (int q = 0; q < kWaves; ++q) u += red[q * 32 + tid];
+                const int64_t e = 2 * (int64_t)u - bonds;
+                S1 += e;
+                S2 += e * e;
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < npad; i += kAdaptThreads) gw[i] = sp[i];
+    if (tid < nch) {
+        int64_t *m = A.mom + ((int64_t)inst * A.n_chains + 32 * w + tid) * 2;
+        m[0] = S1;
+        m[1] = S2;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
 hipError_t launch_apt_init(const InstDev *inst_d, const QuadDesc *desc, int n_blocks,
@@ -1438,6 +1613,20 @@ hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, int thread
                       : launch_sqa_t<8, false>(a, n_inst, lds_bytes, threads, s);
     return scaled ? launch_sqa_t<0, true>(a, n_inst, lds_bytes, threads, s)
                   : launch_sqa_t<0, false>(a, n_inst, lds_bytes, threads, s);
+}
+
+hipError_t launch_adapt_init(const AdaptArgs &a, int n_inst, hipStream_t s)
+{
+    hipLaunchKernelGGL(adapt_init_kernel, dim3(n_inst * a.nw), dim3(kAdaptThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adapt(const AdaptArgs &a, int n_inst, size_t lds_bytes, hipStream_t s)
+{
+    hipError_t e = allow_lds((const void *)adapt_kernel, lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(adapt_kernel, dim3(n_inst * a.nw), dim3(kAdaptThreads), lds_bytes, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_advance(uint32_t *ctr, uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3,

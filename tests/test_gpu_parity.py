@@ -319,6 +319,29 @@ def test_adaptive_ladder_matches_oracle():
         assert np.array_equal(res[i][1], osg)
 
 
+@pytest.mark.parametrize("n_chains", [37, 64])
+def test_adaptive_ladder_chain_words(n_chains):
+    """Chains 32 to a word: a partial last word with a partial group (37), two full words (64)."""
+    insts = [_inst((6, 6, 6), 7, 41), _inst((5, 4, 3), 0, 42), _inst((2, 3, 7), 5, 43)]
+    kw = dict(beta0=0.4, alpha=1.25, tol=2.0, n_chains=n_chains, sweeps=40, tail=20, max_steps=5)
+    res = sg.adaptive_ladder(insts, SEED + 1, **kw)
+    for i, inst in enumerate(insts):
+        ob, osg, _ = oracle.adaptive_ladder(_olat(inst), i, SEED + 1, **kw)
+        assert np.array_equal(res[i][0], ob), f"ladder {i}: {res[i][0]} vs {ob}"
+        assert np.array_equal(res[i][1], osg)
+
+
+def test_adaptive_ladder_with_fields():
+    """Instances with fields run the chains as APT slots (byte per spin)."""
+    insts = [_inst((4, 4, 4), 7, 44, hmax=2), _inst((3, 5, 4), 3, 45, hmax=1)]
+    kw = dict(beta0=0.5, alpha=1.25, tol=2.5, n_chains=6, sweeps=40, tail=20, max_steps=5)
+    res = sg.adaptive_ladder(insts, SEED + 2, **kw)
+    for i, inst in enumerate(insts):
+        ob, osg, _ = oracle.adaptive_ladder(_olat(inst), i, SEED + 2, **kw)
+        assert np.array_equal(res[i][0], ob), f"ladder {i}: {res[i][0]} vs {ob}"
+        assert np.array_equal(res[i][1], osg)
+
+
 def test_mlp_gradient_matches_fp64_oracle():
     import ctypes as C
     lib = sg.load()
