@@ -1541,8 +1541,14 @@ bool adaptive_packed(sg_ctx *c, const sg_adaptive_params *p, double *beta_out,
     while ((1 << planes) <= per_thread) ++planes;
     const size_t lds = sizeof(uint32_t) * (size_t)(max_npad + 1);
     if (planes > kAdaptPlanes || lds + 16 * 1024 > kMaxLds) return false;
-    hipStream_t s = c->stream;
     const int n_inst = c->n_inst, nc = p->n_chains, nw = (nc + 31) / 32;
+    // one work-group per (instance, chain word): with fewer work-groups than CUs the
+    // chains spread wider as APT slots (four per work-group)
+    int dev = 0, cus = 0;
+    hip_check(hipGetDevice(&dev), "device");
+    hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device");
+    if ((int64_t)n_inst * nw < cus) return false;
+    hipStream_t s = c->stream;
     AdaptArgs a{};
     a.inst = c->d_inst.p;
     a.rec_col = c->d_rec.p;

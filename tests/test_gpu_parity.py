@@ -310,6 +310,7 @@ def test_sqa_every_launch_config_matches_oracle(hmax, M):
 
 
 def test_adaptive_ladder_matches_oracle():
+    """Few instances: the chains run as APT slots, four per work-group."""
     insts = [_inst((4, 4, 4), 7, 31), _inst((5, 5, 5), 7, 32), _inst((3, 4, 5), 7, 33)]
     kw = dict(beta0=0.5, alpha=1.25, tol=2.5, n_chains=10, sweeps=60, tail=25, max_steps=8)
     res = sg.adaptive_ladder(insts, SEED, **kw)
@@ -319,14 +320,19 @@ def test_adaptive_ladder_matches_oracle():
         assert np.array_equal(res[i][1], osg)
 
 
-@pytest.mark.parametrize("n_chains", [37, 64])
+@pytest.mark.parametrize("n_chains", [37, 64, 100])
 def test_adaptive_ladder_chain_words(n_chains):
-    """Chains 32 to a word: a partial last word with a partial group (37), two full words (64)."""
-    insts = [_inst((6, 6, 6), 7, 41), _inst((5, 4, 3), 0, 42), _inst((2, 3, 7), 5, 43)]
-    kw = dict(beta0=0.4, alpha=1.25, tol=2.0, n_chains=n_chains, sweeps=40, tail=20, max_steps=5)
+    """Chains 32 to a word (one work-group per instance and word, used once there are at least
+    as many of them as CUs): a partial last word with a partial group (37), two full words (64),
+    the Methods' 100 chains (three full words and one of four chains)."""
+    nw = (n_chains + 31) // 32
+    n_inst = -(-256 // nw)
+    shapes = [((4, 4, 4), 7), ((5, 4, 3), 0), ((2, 3, 7), 5), ((3, 3, 3), 7), ((6, 2, 2), 6)]
+    insts = [_inst(shapes[i % 5][0], shapes[i % 5][1], 700 + i) for i in range(n_inst)]
+    kw = dict(beta0=0.4, alpha=1.25, tol=2.0, n_chains=n_chains, sweeps=30, tail=15, max_steps=4)
     res = sg.adaptive_ladder(insts, SEED + 1, **kw)
-    for i, inst in enumerate(insts):
-        ob, osg, _ = oracle.adaptive_ladder(_olat(inst), i, SEED + 1, **kw)
+    for i in sorted({0, 1, 2, 3, 4, n_inst - 1} | set(range(0, n_inst, 9))):
+        ob, osg, _ = oracle.adaptive_ladder(_olat(insts[i]), i, SEED + 1, **kw)
         assert np.array_equal(res[i][0], ob), f"ladder {i}: {res[i][0]} vs {ob}"
         assert np.array_equal(res[i][1], osg)
 
