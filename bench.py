@@ -228,6 +228,10 @@ def main():
                     help="time-to-target of plain, batched-adaptive and batched-learned APT+ICM "
                          "on 256 held-out L=15 instances (shipped network)")
     ap.add_argument("--plain-sample", type=int, default=16)
+    ap.add_argument("--adaptive", action="store_true",
+                    help="throughput of the adaptive-ladder stage: 256 L=15 instances x 100 chains, "
+                         "--adaptive-steps beta steps of 10^4 sweeps")
+    ap.add_argument("--adaptive-steps", type=int, default=3)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -240,6 +244,21 @@ def main():
 
     if args.ttt:
         print(json.dumps(time_to_target(e0_cycles=args.ttt_cycles)), flush=True)
+        return
+    if args.adaptive:
+        from paper_2503_10302_amd.inputs import ej_couplings
+        insts = [(ej_couplings(15, 7, seed=90000 + i)[0], 7, None) for i in range(256)]
+        kw = dict(beta0=0.5, alpha=1.25, tol=0.5, n_chains=100, sweeps=10000, tail=1000,
+                  max_steps=args.adaptive_steps)
+        t0 = time.perf_counter()
+        res = sg.adaptive_ladder(insts, 5, **kw)
+        dt = time.perf_counter() - t0
+        steps = max(len(b) for b, _ in res)   # every instance runs while any is active
+        flips = 256 * 100 * 15 ** 3 * 10000 * steps
+        print(json.dumps({"metric": "adaptive-ladder stage throughput (256 L=15 instances x 100 chains)",
+                          "unit": "flips/ns", "value": round(flips / dt / 1e9, 1),
+                          "wall_s": round(dt, 3), "beta_steps": steps,
+                          "first_ladder": [round(b, 6) for b in res[0][0]]}), flush=True)
         return
     if args.learned:
         from paper_2503_10302_amd import ladder
