@@ -828,6 +828,9 @@ __global__ __launch_bounds__(kQuadThreads) void apt_init_kernel(const InstDev *i
 // ---------------------------------------------------------------------------
 // APT replica kernel: n_sweeps sweeps, optional ICM, optional energies.
 // ---------------------------------------------------------------------------
+// SCALED: rows of at most 16 thresholds (no fields), so the four table offsets of a site
+// are bytes of one word.
+template <bool SCALED>
 __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
 {
     extern __shared__ uint32_t lds[];
@@ -884,7 +887,6 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
         bool full_energy = A.do_energy == 2;
         // threshold offsets: table of slot b at b * ni; with ni <= 16 the four byte offsets
         // of one site fit one word (index bytes + table starts, times 4)
-        const bool scaled = ni <= 16;
         const uint32_t soff4 = (uint32_t)ni * 0x03020100u;
         for (int sw = 0; sw < A.n_sweeps; ++sw) {
             const uint32_t t = t0 + (uint32_t)sw;
@@ -918,7 +920,7 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
                                           ((r.x >> 16) & 7u);
                     const uint32_t idx4 = (k4 << 1) + __builtin_amdgcn_perm(0u, base, 0u);   // base in every byte
                     uint32_t o0, o1, o2, o3;
-                    if (scaled) {
+                    if (SCALED) {
                         const uint32_t off4 = (idx4 + soff4) << 2;
                         o0 = off4 & 0xFFu;
                         o1 = (off4 >> 8) & 0xFFu;
@@ -1572,12 +1574,20 @@ static hipError_t allow_lds(const void *fn, size_t bytes)
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+template <bool SCALED>
+hipError_t launch_apt_quad_t(const AptArgs &a, size_t lds_bytes, hipStream_t s)
+{
+    hipError_t e = allow_lds((const void *)apt_quad_kernel<SCALED>, lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(apt_quad_kernel<SCALED>, dim3(a.n_blocks), dim3(kQuadThreads), lds_bytes, s,
+                       a);
+    return hipGetLastError();
+}
+
 hipError_t launch_apt_quad(const AptArgs &a, size_t lds_bytes, hipStream_t s)
 {
-    hipError_t e = allow_lds((const void *)apt_quad_kernel, lds_bytes);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(apt_quad_kernel, dim3(a.n_blocks), dim3(kQuadThreads), lds_bytes, s, a);
-    return hipGetLastError();
+    return a.ni <= 16 ? launch_apt_quad_t<true>(a, lds_bytes, s)
+                      : launch_apt_quad_t<false>(a, lds_bytes, s);
 }
 
 hipError_t launch_apt_swap(const SwapArgs &a, hipStream_t s)
