@@ -1618,9 +1618,13 @@ hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, int thread
 {
     if (!sqa_config_valid(threads)) return hipErrorInvalidValue;
     const bool scaled = a.nl <= 64;
-    if (((a.H + 3) >> 2) == 8)
+    const int ngrp = (a.H + 3) >> 2;
+    if (ngrp == 8)
         return scaled ? launch_sqa_t<8, true>(a, n_inst, lds_bytes, threads, s)
                       : launch_sqa_t<8, false>(a, n_inst, lds_bytes, threads, s);
+    // M = 32 and M = 16 with pre-scaled tables also run unrolled
+    if (ngrp == 4 && scaled) return launch_sqa_t<4, true>(a, n_inst, lds_bytes, threads, s);
+    if (ngrp == 2 && scaled) return launch_sqa_t<2, true>(a, n_inst, lds_bytes, threads, s);
     return scaled ? launch_sqa_t<0, true>(a, n_inst, lds_bytes, threads, s)
                   : launch_sqa_t<0, false>(a, n_inst, lds_bytes, threads, s);
 }

@@ -227,7 +227,7 @@ def test_checkpoint_resume_is_exact():
     assert c2.counters().tolist() == [40, 40, 40]
 
 
-@pytest.mark.parametrize("M", [8, 6, 2, 64])
+@pytest.mark.parametrize("M", [8, 6, 2, 16, 32, 64])
 def test_sqa_matches_oracle(M):
     insts = [_inst((4, 4, 4), 7, 21), _inst((5, 5, 5), 7, 22), _inst((3, 4, 6), 3, 23),
              _inst((6, 6, 6), 7, 24, hmax=2), _inst((5, 3, 2), 0, 25, p_absent=0.2)]
