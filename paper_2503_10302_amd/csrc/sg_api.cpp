@@ -622,6 +622,7 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
     a.ctr = c->d_ctr.p; a.key0 = c->key0; a.key1 = c->key1; a.tag = TAG_APT_SWEEP;
     a.do_energy = 2; a.mom_from = -1; a.reps = c->reps; a.imax = c->imax; a.ni = c->ni;
     a.n_blocks = c->n_blocks;
+    a.nb4 = 4 * c->n_quads;
     hip_check(launch_apt_quad(a, c->quad_lds, s), "initial energies");
 }
 
@@ -666,6 +667,7 @@ AptArgs apt_args(sg_ctx *c, int n_sweeps, int do_icm)
     a.ni = c->ni;
     a.cyc_k = 0;
     a.n_blocks = c->n_blocks;
+    a.nb4 = 4 * c->n_quads;
     a.fused_swap = 0;
     return a;
 }

@@ -127,6 +127,7 @@ struct AptArgs {
     int32_t imax;              // LUT covers fields -imax..imax
     int32_t ni;                // 2 * imax + 1
     int32_t n_blocks;
+    int32_t nb4;               // slots per instance padded to a multiple of 4 (= slot stride)
     int32_t cyc_k;             // cycle offset of this launch inside a captured graph: the
                                // kernel uses sweep counter ctr[0] + cyc_k * n_sweeps and ICM
                                // call ctr[1] + cyc_k + 1; counters advance only between graphs

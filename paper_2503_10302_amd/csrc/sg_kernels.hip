@@ -746,12 +746,15 @@ __device__ void swap_instance(const SwapArgs &A, int inst, int32_t *red)
 // logical slots (the work-group of a pair's lower slot counts it), and on quad 0 the
 // running minimum.  The new mapping and energies of the four slots go to lperm / lE
 // (LDS) and the mapping to A.perm.
-__device__ void fused_swap_quad(const SwapArgs &A, const InstDev &I, int inst, int q,
-                                int32_t *lperm, int32_t *lE)
+__device__ void fused_swap_quad(const SwapArgs &A, int slot_off, int inst, int q, int32_t *lperm,
+                                int32_t *lE)
 {
+    // the instance's slot range and swap tables follow from its index alone, so these
+    // reads need not wait for its descriptor
+    const int n_slots = A.n_beta * A.reps, swap_off = inst * (A.n_beta - 1);
     const int tid = threadIdx.x;
     const uint32_t a = A.ctr[2] + (uint32_t)A.cyc_k + 1u;
-    const int32_t *pin = A.perm_in + I.slot_off, *ein = A.E_in + I.slot_off;
+    const int32_t *pin = A.perm_in + slot_off, *ein = A.E_in + slot_off;
     if (tid < 4) {
         // every load of the decision is issued before any of it is used: the slot's and
         // its partner's mapping and energy, the pair's table bounds, and the random word
@@ -760,7 +763,7 @@ __device__ void fused_swap_quad(const SwapArgs &A, const InstDev &I, int inst, i
         const int b = s / R, l = s - b * R;
         const int first = (a & 1u) ? 0 : 1;
         int lo = -1;
-        if (s < I.n_slots) {
+        if (s < n_slots) {
             if (b >= first && ((b - first) & 1) == 0 && b + 1 < nb) lo = b;
             else if (b - 1 >= first && ((b - 1 - first) & 1) == 0) lo = b - 1;
         }
@@ -770,8 +773,8 @@ __device__ void fused_swap_quad(const SwapArgs &A, const InstDev &I, int inst, i
         const int32_t pp = pin[pt], ep = ein[pt];
         int32_t len = 0, off = 0;
         if (lo >= 0) {
-            len = A.tab_len[I.swap_off + lo];
-            off = A.tab_off[I.swap_off + lo];
+            len = A.tab_len[swap_off + lo];
+            off = A.tab_off[swap_off + lo];
         }
         const uint32_t u = philox10((uint32_t)s0, a, 0u, ((uint32_t)inst << 4) | TAG_SWAP, A.key0,
                                     A.key1).x;
@@ -785,14 +788,14 @@ __device__ void fused_swap_quad(const SwapArgs &A, const InstDev &I, int inst, i
             }
             if (s == s0) A.acc_count[(int64_t)inst * (nb - 1) * R + s0] += acc;
         }
-        A.perm[I.slot_off + s] = pv;
+        A.perm[slot_off + s] = pv;
         lperm[tid] = pv;
         lE[tid] = ev;
     }
     if (q == 0 && tid < 64) {
         // running minimum of the energies after the exchange (the same set as before it)
         int32_t m = 0x7FFFFFFF;
-        for (int i = tid; i < I.n_slots; i += 64) m = min(m, ein[i]);
+        for (int i = tid; i < n_slots; i += 64) m = min(m, ein[i]);
         m = wave_min(m);
         if (tid == 0) record_best(A, inst, m);
     }
@@ -848,18 +851,19 @@ __global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
         uint32_t *vis = Vr + 4 * I.n_rows;               // (npad + 31) / 32 + 1
         uint16_t *queue = (uint16_t *)(vis + ((npad + 31) >> 5) + 1);   // npad
         const int q = D.quad;
+        const int slot_off = D.inst * A.nb4;   // == I.slot_off, without waiting for I
         for (int e = tid; e < 4 * ni; e += kQuadThreads) {
             const int i = e / ni;
-            lut[e] = A.lut[(int64_t)A.slot_lut[I.slot_off + 4 * q + i] * ni + (e - i * ni)];
+            lut[e] = A.lut[(int64_t)A.slot_lut[slot_off + 4 * q + i] * ni + (e - i * ni)];
         }
         int32_t e_in = 0;   // fused exchange: this slot's energy after it (threads 0..3)
         int32_t pq[4];
         if (A.fused_swap) {
-            fused_swap_quad(A.sw, I, D.inst, q, red + 24, red + 28);
+            fused_swap_quad(A.sw, slot_off, D.inst, q, red + 24, red + 28);
             for (int i = 0; i < 4; ++i) pq[i] = red[24 + i];
             if (tid < 4) e_in = red[28 + tid];
         } else {
-            for (int i = 0; i < 4; ++i) pq[i] = A.perm[I.slot_off + 4 * q + i];
+            for (int i = 0; i < 4; ++i) pq[i] = A.perm[slot_off + 4 * q + i];
         }
         const int64_t b0 = (int64_t)pq[0] * npad, b1 = (int64_t)pq[1] * npad;
         const int64_t b2 = (int64_t)pq[2] * npad, b3 = (int64_t)pq[3] * npad;
