@@ -74,3 +74,14 @@ def test_binding_module_has_no_oracle_import():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 txt = open(os.path.join(root, f)).read()
                 assert "import oracle" not in txt and "sg_oracle" not in txt and "sgo_" not in txt, f
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs the whole path on one GPU and says so when asked for more."""
+    import subprocess
+    import sys
+    root = os.path.dirname(HEADER).rsplit(os.sep, 1)[0]
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
