@@ -468,3 +468,34 @@ def test_sqa_L15_M64_R64_sampled_replicas():
         assert np.array_equal(g[i, r], sp[0]), f"instance {i} replica {r}"
         assert np.array_equal(sE[i, r], osE[0])
     assert np.array_equal(bE, sE.reshape(32, -1).min(axis=1))
+
+
+def test_degenerate_lattices():
+    """A single site, axes of length one and two, and a lattice with every bond absent:
+    APT + ICM and DT-SQA against the oracle (and one small instance with fields, without ICM)."""
+    plain = [_inst((1, 1, 1), 7, 81), _inst((2, 1, 1), 1, 82), _inst((1, 5, 1), 2, 83),
+             _inst((3, 3, 3), 7, 84, p_absent=1.0)]
+    fields = [_inst((2, 2, 2), 7, 85, hmax=2)]
+    beta = geometric_ladder(4, 0.3, 2.0)
+    for insts, cut in ((plain, 0.5), (fields, float("inf"))):
+        ctx = sg.apt(insts, beta, SEED, reps_per_beta=2)
+        trace = ctx.run_apt(40, 1, cut, record_every=4)
+        g = ctx.spins()
+        for i, inst in enumerate(insts):
+            l = _olat(inst)
+            sp = oracle.apt_init(l, i, 8, SEED)
+            ctr = np.zeros(3, np.uint32)
+            E = np.zeros(8, np.int64)
+            b = np.array([np.iinfo(np.int64).max], np.int64)
+            rc, otr, _ = oracle.apt_run(l, i, beta, 2, SEED, 40, 1, cut, 4, ctr, sp, E, b)
+            assert rc == 0 and np.array_equal(g[i, :, :l.n], sp), f"instance {i}"
+            assert np.array_equal(trace[i], otr), f"instance {i}"
+    insts = plain + fields
+    q = sg.sqa(insts, 8, 2, 2.0, SEED)
+    gam = linear_gamma(6)
+    bE, _ = q.sqa_anneal(gam)
+    for i, inst in enumerate(insts):
+        l = _olat(inst)
+        s5 = oracle.sqa_init(l, i, 8, 2, SEED)
+        obE, _, _ = oracle.sqa_anneal(l, i, 8, 2, 2.0, gam, SEED, 0, s5)
+        assert np.array_equal(q.spins()[i, :, :, :l.n], s5) and bE[i] == obE, f"instance {i}"
