@@ -463,17 +463,35 @@ void apt_rows(const Lat &L, std::vector<uint4> &rowA, std::vector<uint4> &rowB,
 // Work-group tasks, grouped so that all quads of an instance run on one
 // XCD (blocks are dispatched round-robin over the 8 XCDs; each XCD has its own
 // L2 holding that instance's records and tables).  Largest instances first.
-std::vector<QuadDesc> make_quad_descs(const std::vector<Lat> &lat, int n_quads)
+// Work-group order of the APT replica kernel.  Instances are spread over the eight XCDs by
+// size (an instance's quads share one XCD's L2 for its site records); within an XCD, quads
+// are ordered by estimated cost, largest first: sites, doubled for quads holding a
+// temperature >= 1 (where the cluster moves usually run).
+std::vector<QuadDesc> make_quad_descs(const std::vector<Lat> &lat, int n_quads,
+                                      const std::vector<double> &beta, int n_beta, int reps)
 {
     const int ni = (int)lat.size();
     std::vector<int> order(ni);
     for (int i = 0; i < ni; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lat[a].n > lat[b].n; });
+    auto cost = [&](const QuadDesc &d) {
+        bool icm = false;
+        for (int k = 0; k < 4 && reps >= 2; ++k) {
+            const int b = std::min(4 * d.quad + k, n_beta * reps - 1) / reps;
+            icm |= beta[(size_t)d.inst * n_beta + b] >= 1.0;
+        }
+        return (int64_t)lat[d.inst].n * (icm ? 2 : 1);
+    };
+    auto by_cost = [&](std::vector<QuadDesc> &v) {
+        std::stable_sort(v.begin(), v.end(),
+                         [&](const QuadDesc &a, const QuadDesc &b) { return cost(a) > cost(b); });
+    };
     std::vector<QuadDesc> out;
-    // within an instance the last quads hold the largest betas, where ICM runs: start them first
+    // within an instance the last quads hold the largest betas: start them first
     if (ni < 8) {
         for (int i : order)
             for (int q = n_quads - 1; q >= 0; --q) out.push_back({i, q});
+        by_cost(out);
         return out;
     }
     const int X = 8;
@@ -484,6 +502,7 @@ std::vector<QuadDesc> make_quad_descs(const std::vector<Lat> &lat, int n_quads)
         load[x] += (int64_t)lat[i].n;
         for (int q = n_quads - 1; q >= 0; --q) qs[x].push_back({i, q});
     }
+    for (auto &v : qs) by_cost(v);
     size_t len = 0;
     for (auto &v : qs) len = std::max(len, v.size());
     out.assign(len * X, QuadDesc{-1, 0});
@@ -595,7 +614,7 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
     c->d_icm_info.alloc((size_t)c->n_inst * c->n_beta * std::max(1, c->reps / 2) * 4, "icm info");
     c->d_icm_on.alloc((size_t)c->n_inst * c->n_beta, "icm flags");
     c->d_ctr.alloc(8, "counters");
-    std::vector<QuadDesc> desc = make_quad_descs(c->lat, c->n_quads);
+    std::vector<QuadDesc> desc = make_quad_descs(c->lat, c->n_quads, c->beta, c->n_beta, c->reps);
     c->n_blocks = (int)desc.size();
     c->d_desc.upload(desc, s, "tasks");
     c->quad_lds = 0;
