@@ -465,8 +465,9 @@ void apt_rows(const Lat &L, std::vector<uint4> &rowA, std::vector<uint4> &rowB,
 // L2 holding that instance's records and tables).  Largest instances first.
 // Work-group order of the APT replica kernel.  Instances are spread over the eight XCDs by
 // size (an instance's quads share one XCD's L2 for its site records); within an XCD, quads
-// are ordered by estimated cost, largest first: sites, doubled for quads holding a
-// temperature >= 1 (where the cluster moves usually run).
+// are ordered by estimated cost, largest first: sites, tripled for quads holding a
+// temperature >= 1 (where the cluster moves usually run; the weight measured best among
+// 1.5, 2, 3 and 4 on a batch of mixed sizes).
 std::vector<QuadDesc> make_quad_descs(const std::vector<Lat> &lat, int n_quads,
                                       const std::vector<double> &beta, int n_beta, int reps)
 {
@@ -480,7 +481,7 @@ std::vector<QuadDesc> make_quad_descs(const std::vector<Lat> &lat, int n_quads,
             const int b = std::min(4 * d.quad + k, n_beta * reps - 1) / reps;
             icm |= beta[(size_t)d.inst * n_beta + b] >= 1.0;
         }
-        return (int64_t)lat[d.inst].n * (icm ? 2 : 1);
+        return (int64_t)lat[d.inst].n * (icm ? 3 : 1);
     };
     auto by_cost = [&](std::vector<QuadDesc> &v) {
         std::stable_sort(v.begin(), v.end(),
