@@ -832,9 +832,11 @@ __global__ __launch_bounds__(kQuadThreads) void apt_init_kernel(const InstDev *i
 // APT replica kernel: n_sweeps sweeps, optional ICM, optional energies.
 // ---------------------------------------------------------------------------
 // SCALED: rows of at most 16 thresholds (no fields), so the four table offsets of a site
-// are bytes of one word.
+// are bytes of one word.  At most 72 VGPRs, seven waves per SIMD (measured faster than six
+// with more registers and than eight with spills).
 template <bool SCALED>
-__global__ __launch_bounds__(kQuadThreads) void apt_quad_kernel(AptArgs A)
+__global__ __launch_bounds__(kQuadThreads) __attribute__((amdgpu_waves_per_eu(7, 8)))
+void apt_quad_kernel(AptArgs A)
 {
     extern __shared__ uint32_t lds[];
     const QuadDesc D = A.desc[blockIdx.x];
