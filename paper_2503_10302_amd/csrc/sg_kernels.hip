@@ -38,24 +38,60 @@ __device__ __forceinline__ uint4 philox10(uint32_t x0, uint32_t x1, uint32_t x2,
     return make_uint4(x0, x1, x2, x3);
 }
 
-// Rounds [r0, r1) of Philox4x32-10 on the state x with the key k of round r0 (the key
-// is advanced): philox10 split in two so that other work can sit between the halves.
+// a ^ b ^ k as one vector operation; k must be wave-uniform (it is read from a scalar
+// register).  On gfx950 a two-operand XOR that reads a scalar register issues at half
+// rate, so the pair of XORs of a Philox round costs three full-rate slots and this
+// three-input form two.
+__device__ __forceinline__ uint32_t xor3_vvs(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t d;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(d) : "v"(a), "v"(b), "s"(k));
+    return d;
+}
+
+// Round R of Philox4x32-10 for a counter whose words 1..3 are wave-uniform and word 0
+// varies between lanes: words that are still uniform after round R - 1 (all of x1..x3
+// before round 0; x0, x1 and x3 before round 1; x3 before round 2) are left to plain
+// code, which keeps them on the scalar unit; from round 2 (x0 side) and round 3 (x2
+// side) on, both operands of each XOR pair vary and the pair is one three-input
+// operation with the round key.  The result is Philox4x32-10 whatever the counter.
+template <int R>
+__device__ __forceinline__ void philox_round_v(uint32_t x[4], uint32_t k[2])
+{
+    const uint64_t p0 = (uint64_t)0xD2511F53u * x[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * x[2];
+    const uint32_t n0 = R >= 2 ? xor3_vvs((uint32_t)(p1 >> 32), x[1], k[0])
+                               : (uint32_t)(p1 >> 32) ^ x[1] ^ k[0];
+    const uint32_t n2 = R >= 3 ? xor3_vvs((uint32_t)(p0 >> 32), x[3], k[1])
+                               : (uint32_t)(p0 >> 32) ^ x[3] ^ k[1];
+    x[1] = (uint32_t)p1;
+    x[3] = (uint32_t)p0;
+    x[0] = n0;
+    x[2] = n2;
+    k[0] += 0x9E3779B9u;
+    k[1] += 0xBB67AE85u;
+}
+
+// Rounds [R0, R1) of Philox4x32-10 on the state x with the key k of round R0 (the key
+// is advanced): the block split in two so that other work can sit between the halves.
+// For counters laid out as philox_round_v expects.
 template <int R0, int R1>
 __device__ __forceinline__ void philox_rounds(uint32_t x[4], uint32_t k[2])
 {
-#pragma unroll
-    for (int r = R0; r < R1; ++r) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * x[0];
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * x[2];
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ x[1] ^ k[0];
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ x[3] ^ k[1];
-        x[1] = (uint32_t)p1;
-        x[3] = (uint32_t)p0;
-        x[0] = n0;
-        x[2] = n2;
-        k[0] += 0x9E3779B9u;
-        k[1] += 0xBB67AE85u;
+    if constexpr (R0 < R1) {
+        philox_round_v<R0>(x, k);
+        philox_rounds<R0 + 1, R1>(x, k);
     }
+}
+
+// Philox4x32-10 of (x0, x1, x2, x3) under (k0, k1), for a counter whose words 1..3 are
+// wave-uniform (the sweep kernels' layout).
+__device__ __forceinline__ uint4 philox10v(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                           uint32_t k0, uint32_t k1)
+{
+    uint32_t x[4] = {x0, x1, x2, x3}, k[2] = {k0, k1};
+    philox_rounds<0, 10>(x, k);
+    return make_uint4(x[0], x[1], x[2], x[3]);
 }
 
 __device__ __forceinline__ uint32_t lds_word(const uint32_t *base, uint32_t byte_off)
@@ -1212,7 +1248,7 @@ __device__ __forceinline__ uint32_t sqa_slices(const uint32_t *lut, const uint32
             s2 = lds_word(tab1, nib_off(t1b, g - 1));
         }
         __builtin_amdgcn_sched_barrier(0);
-        const uint4 u = philox10(jp, t, x2 | (uint32_t)g, c3, k0, k1);
+        const uint4 u = philox10v(jp, t, x2 | (uint32_t)g, c3, k0, k1);
         res = shift_in_lt(res, u.w, T3);
         res = shift_in_lt(res, u.z, T2);
         res = shift_in_lt(res, u.y, T1);
@@ -1496,7 +1532,7 @@ __global__ __launch_bounds__(kAdaptThreads) void adapt_kernel(AdaptArgs A)
                         s1v = lds_word(tab2, nib_off(c2, g - 1));
                     }
                     __builtin_amdgcn_sched_barrier(0);
-                    const uint4 u = philox10(j, t, (uint32_t)(8 * w + g), c3, A.key0, A.key1);
+                    const uint4 u = philox10v(j, t, (uint32_t)(8 * w + g), c3, A.key0, A.key1);
                     res = shift_in_lt(res, u.w, T3);
                     res = shift_in_lt(res, u.z, T2);
                     res = shift_in_lt(res, u.y, T1);
