@@ -1583,6 +1583,7 @@ bool adaptive_packed(sg_ctx *c, const sg_adaptive_params *p, double *beta_out,
     a.words = words.p;
     a.lut = c->d_lut.p;
     a.mom = mom.p;
+    a.n_inst = n_inst;
     a.n_chains = nc;
     a.nw = nw;
     a.imax = c->imax;

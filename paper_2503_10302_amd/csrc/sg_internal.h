@@ -172,7 +172,7 @@ struct AdaptArgs {
     int64_t *mom;              // [inst][n_chains][2]: sum of E, sum of E^2 over the tail
     int64_t wstride;           // words per (instance, word) block, >= npad + 1
     uint32_t t0;               // sweep counter of the launch's first sweep
-    int32_t n_chains, nw, n_sweeps, mom_from, imax, ni, planes;
+    int32_t n_inst, n_chains, nw, n_sweeps, mom_from, imax, ni, planes;
     uint32_t key0, key1;
 };
 

@@ -1431,13 +1431,107 @@ __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n)
 // sweeps of a launch.  Chain c = 32 w + 4 g + i takes word i of the Philox block
 // (site, sweep, 8 w + g, instance) -- the counter of slot c in the APT sweep.
 // ---------------------------------------------------------------------------
+// New states of the chains of one word at one site (heat-bath rule of Eq. 6 at the
+// instance's beta): chain 4 g + i takes word i of the Philox block (j, t, 8 w + g,
+// instance) of group g; its threshold index is a byte of the sum of a pair-table read
+// (planes c0, c1) and a 16-entry table read (plane c2), relative to lsite, the row moved
+// by the site's field and degree.  Groups run from the highest to the lowest so that the
+// borrow chain leaves chain b at bit b; the table reads of group g - 1 and the threshold
+// reads of group g are issued before group g's Philox block.  NG > 0: NG groups,
+// unrolled; NG == 0: ngrp groups, not unrolled.
+template <int NG>
+__device__ __forceinline__ uint32_t adapt_groups(const uint32_t *lsite, const uint32_t *tab01,
+                                                 const uint32_t *tab2, uint32_t e01, uint32_t o01,
+                                                 uint32_t c2, uint32_t j, uint32_t t, uint32_t x2,
+                                                 uint32_t c3, uint32_t k0, uint32_t k1, int ngrp)
+{
+    const int ng = NG > 0 ? NG : ngrp;
+    uint32_t res = 0u;
+    uint32_t s0v = lds_word(tab01, pair_off(e01, o01, ng - 1));
+    uint32_t s1v = lds_word(tab2, nib_off(c2, ng - 1));
+#pragma unroll
+    for (int g = ng - 1; g >= 0; --g) {
+        const uint32_t idx4 = s0v + s1v;
+        const uint32_t T3 = lds_word(lsite, idx4 >> 24);
+        const uint32_t T2 = lds_word(lsite, (idx4 >> 16) & 0xFFu);
+        const uint32_t T1 = lds_word(lsite, (idx4 >> 8) & 0xFFu);
+        const uint32_t T0 = lds_word(lsite, idx4 & 0xFFu);
+        if (g > 0) {
+            s0v = lds_word(tab01, pair_off(e01, o01, g - 1));
+            s1v = lds_word(tab2, nib_off(c2, g - 1));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const uint4 u = philox10v(j, t, x2 | (uint32_t)g, c3, k0, k1);
+        res = shift_in_lt(res, u.w, T3);
+        res = shift_in_lt(res, u.z, T2);
+        res = shift_in_lt(res, u.y, T1);
+        res = shift_in_lt(res, u.x, T0);
+    }
+    return res;
+}
+
+// One colour phase of the adaptive stage's sweep: the sites of the phase are split over
+// the work-group's threads; each updates all chains of the word at its sites.
+template <int NG>
+__device__ __forceinline__ void adapt_phase(const AdaptArgs &A, const uint4 *rc, int cnt,
+                                            uint32_t *sp, const uint32_t *tab01,
+                                            const uint32_t *tab2, const uint32_t *lut,
+                                            uint32_t t, uint32_t x2, uint32_t c3, int ng,
+                                            uint32_t vmask)
+{
+    for (int i = threadIdx.x; i < cnt; i += kAdaptThreads) {
+        const uint4 r = rc[i];
+        const uint32_t j = r.x & 0xFFFFu, jn = r.x >> 19;
+        // aligned words: bit b = 1 when J s_neighbour = +1 for chain b
+        const uint32_t a0 = sp[r.y & 0xFFFFu] ^ (0u - (jn & 1u));
+        const uint32_t a1 = sp[r.y >> 16] ^ (0u - ((jn >> 1) & 1u));
+        const uint32_t a2 = sp[r.z & 0xFFFFu] ^ (0u - ((jn >> 2) & 1u));
+        const uint32_t a3 = sp[r.z >> 16] ^ (0u - ((jn >> 3) & 1u));
+        const uint32_t a4 = sp[r.w & 0xFFFFu] ^ (0u - ((jn >> 4) & 1u));
+        const uint32_t a5 = sp[r.w >> 16] ^ (0u - ((jn >> 5) & 1u));
+        const uint32_t s1 = a0 ^ a1 ^ a2, k1 = (a0 & a1) | (a2 & (a0 ^ a1));
+        const uint32_t s2 = a3 ^ a4 ^ a5, k2 = (a3 & a4) | (a5 & (a3 ^ a4));
+        const uint32_t cy = s1 & s2;
+        const uint32_t c0 = s1 ^ s2, c1 = k1 ^ k2 ^ cy, c2 = (k1 & k2) | (cy & (k1 ^ k2));
+        // the site's part of the table index, h - d + imax, moves the row
+        const uint32_t *lsite = lut + ((int32_t)((r.x >> 25) & 63u) - 32 -
+                                       (int32_t)((r.x >> 16) & 7u) + A.imax);
+        uint32_t e01, o01;
+        pair_planes(c0, c1, e01, o01);
+        const uint32_t res = adapt_groups<NG>(lsite, tab01, tab2, e01, o01, c2, j, t, x2, c3,
+                                              A.key0, A.key1, ng);
+        sp[j] = res & vmask;
+    }
+}
+
+// Work-group -> (instance, chain word).  When the last word of each instance holds fewer
+// than 32 chains (one to seven Philox groups against eight), the full words come first
+// and the short ones last: work-groups are handed to the eight XCDs in turn, so with the
+// natural order (instance-major) every short word of a four-word instance would land on
+// two of the eight XCDs and the full ones on the other six.
+__device__ __forceinline__ void adapt_block(const AdaptArgs &A, int b, int &inst, int &w)
+{
+    const int nf = A.nw - 1;
+    if ((A.n_chains & 31) == 0 || nf == 0) {
+        inst = b / A.nw;
+        w = b - inst * A.nw;
+    } else if (b < A.n_inst * nf) {
+        inst = b / nf;
+        w = b - inst * nf;
+    } else {
+        inst = b - A.n_inst * nf;
+        w = nf;
+    }
+}
+
 __global__ __launch_bounds__(kAdaptThreads) void adapt_init_kernel(AdaptArgs A)
 {
-    const int inst = blockIdx.x / A.nw, w = blockIdx.x - inst * A.nw;
+    int inst, w;
+    adapt_block(A, blockIdx.x, inst, w);
     const InstDev I = A.inst[inst];
     const int nch = min(32, A.n_chains - 32 * w), ng = (nch + 3) >> 2;
     const uint32_t c3 = ((uint32_t)inst << 4) | TAG_ADAPT_INIT;
-    uint32_t *g = A.words + (int64_t)blockIdx.x * A.wstride;
+    uint32_t *g = A.words + ((int64_t)inst * A.nw + w) * A.wstride;
     for (int j = threadIdx.x; j < (int)A.wstride; j += kAdaptThreads) {
         uint32_t wd = 0u;
         if (j < I.n)
@@ -1460,12 +1554,13 @@ __global__ __launch_bounds__(kAdaptThreads) void adapt_kernel(AdaptArgs A)
     constexpr int kWaves = kAdaptThreads / 64;
     __shared__ int32_t red[kWaves * 32 + 1];
     extern __shared__ uint32_t sp[];   // npad + 1 words, the last one the zero dummy
-    const int inst = blockIdx.x / A.nw, w = blockIdx.x - inst * A.nw;
+    int inst, w;
+    adapt_block(A, blockIdx.x, inst, w);
     const InstDev I = A.inst[inst];
     const int tid = threadIdx.x, n = I.n, npad = I.npad;
     const int nch = min(32, A.n_chains - 32 * w), ng = (nch + 3) >> 2;
     const uint32_t vmask = nch >= 32 ? 0xFFFFFFFFu : ((1u << nch) - 1u);
-    uint32_t *gw = A.words + (int64_t)blockIdx.x * A.wstride;
+    uint32_t *gw = A.words + ((int64_t)inst * A.nw + w) * A.wstride;
     for (int i = tid; i <= npad; i += kAdaptThreads) sp[i] = i < npad ? gw[i] : 0u;
     uint32_t *tab01 = tabs, *tab2 = tabs + 256, *lut = tabs + 272;
     for (int e = tid; e < 272; e += kAdaptThreads) {
@@ -1497,49 +1592,10 @@ __global__ __launch_bounds__(kAdaptThreads) void adapt_kernel(AdaptArgs A)
         for (int c = 0; c < I.n_colours; ++c) {
             const uint4 *rc = A.rec_col + I.rec_off + A.inst[inst].col_off[c];
             const int cnt = A.inst[inst].col_cnt[c];
-            for (int i = tid; i < cnt; i += kAdaptThreads) {
-                const uint4 r = rc[i];
-                const uint32_t j = r.x & 0xFFFFu, jn = r.x >> 19;
-                // aligned words: bit b = 1 when J s_neighbour = +1 for chain b
-                const uint32_t a0 = sp[r.y & 0xFFFFu] ^ (0u - (jn & 1u));
-                const uint32_t a1 = sp[r.y >> 16] ^ (0u - ((jn >> 1) & 1u));
-                const uint32_t a2 = sp[r.z & 0xFFFFu] ^ (0u - ((jn >> 2) & 1u));
-                const uint32_t a3 = sp[r.z >> 16] ^ (0u - ((jn >> 3) & 1u));
-                const uint32_t a4 = sp[r.w & 0xFFFFu] ^ (0u - ((jn >> 4) & 1u));
-                const uint32_t a5 = sp[r.w >> 16] ^ (0u - ((jn >> 5) & 1u));
-                const uint32_t s1 = a0 ^ a1 ^ a2, k1 = (a0 & a1) | (a2 & (a0 ^ a1));
-                const uint32_t s2 = a3 ^ a4 ^ a5, k2 = (a3 & a4) | (a5 & (a3 ^ a4));
-                const uint32_t cy = s1 & s2;
-                const uint32_t c0 = s1 ^ s2, c1 = k1 ^ k2 ^ cy, c2 = (k1 & k2) | (cy & (k1 ^ k2));
-                // the site's part of the table index, h - d + imax, moves the row
-                const uint32_t *lsite = lut + ((int32_t)((r.x >> 25) & 63u) - 32 -
-                                               (int32_t)((r.x >> 16) & 7u) + A.imax);
-                uint32_t e01, o01;
-                pair_planes(c0, c1, e01, o01);
-                uint32_t res = 0u;
-                uint32_t s0v = lds_word(tab01, pair_off(e01, o01, ng - 1));
-                uint32_t s1v = lds_word(tab2, ((c2 >> (4 * (ng - 1))) & 15u) << 2);
-#pragma unroll
-                for (int g = 7; g >= 0; --g) {
-                    if (g >= ng) continue;
-                    const uint32_t idx4 = s0v + s1v;
-                    const uint32_t T3 = lds_word(lsite, idx4 >> 24);
-                    const uint32_t T2 = lds_word(lsite, (idx4 >> 16) & 0xFFu);
-                    const uint32_t T1 = lds_word(lsite, (idx4 >> 8) & 0xFFu);
-                    const uint32_t T0 = lds_word(lsite, idx4 & 0xFFu);
-                    if (g > 0) {
-                        s0v = lds_word(tab01, pair_off(e01, o01, g - 1));
-                        s1v = lds_word(tab2, nib_off(c2, g - 1));
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                    const uint4 u = philox10v(j, t, (uint32_t)(8 * w + g), c3, A.key0, A.key1);
-                    res = shift_in_lt(res, u.w, T3);
-                    res = shift_in_lt(res, u.z, T2);
-                    res = shift_in_lt(res, u.y, T1);
-                    res = shift_in_lt(res, u.x, T0);
-                }
-                sp[j] = res & vmask;
-            }
+            if (ng == 8)
+                adapt_phase<8>(A, rc, cnt, sp, tab01, tab2, lut, t, 8u * (uint32_t)w, c3, ng, vmask);
+            else
+                adapt_phase<0>(A, rc, cnt, sp, tab01, tab2, lut, t, 8u * (uint32_t)w, c3, ng, vmask);
             __syncthreads();
         }
         if (sw >= A.mom_from) {
