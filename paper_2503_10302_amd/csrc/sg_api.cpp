@@ -623,7 +623,7 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
         const size_t need = apt_lds_bytes(I.npad, I.n_rows, c->ni, I.row_off < 0);
         c->quad_lds = std::max(c->quad_lds, need);
     }
-    if (c->quad_lds > kMaxLds)
+    if (c->quad_lds + 64 * sizeof(uint32_t) > kMaxLds)   // + the kernel's static threshold tables
         fail(SG_EUNSUPPORTED, "instance too large for one work-group's LDS (%zu bytes)", c->quad_lds);
     hip_check(launch_fill_u32(c->d_ctr.p, 0u, 8, s), "init");
     hip_check(launch_fill_i64(c->d_best.p, std::numeric_limits<int64_t>::max(), c->n_inst, s), "init");

@@ -874,6 +874,9 @@ template <bool SCALED>
 __global__ __launch_bounds__(kQuadThreads) __attribute__((amdgpu_waves_per_eu(7, 8)))
 void apt_quad_kernel(AptArgs A)
 {
+    // SCALED (at most 16 threshold entries per slot): the four tables sit in static LDS at
+    // a constant address, so that a threshold read needs no base register.
+    __shared__ uint32_t lut_static[SCALED ? 64 : 1];
     extern __shared__ uint32_t lds[];
     const QuadDesc D = A.desc[blockIdx.x];
     if (D.inst >= 0) {
@@ -881,8 +884,8 @@ void apt_quad_kernel(AptArgs A)
         const int tid = threadIdx.x;
         const int n = I.n, npad = I.npad, ni = A.ni;
         uint32_t *sp = lds;                              // npad + 4 words
-        uint32_t *lut = sp + npad + 4;                   // 4 * ni
-        int32_t *red = (int32_t *)(lut + 4 * ni);        // 32
+        uint32_t *lut = SCALED ? lut_static : sp + npad + 4;   // 4 * ni
+        int32_t *red = (int32_t *)(sp + npad + 4 + 4 * ni);    // 32
         uint32_t *Qr = (uint32_t *)(red + 32);           // 2 * n_rows
         uint32_t *Vr = Qr + 2 * I.n_rows;                // 2 * n_rows, then S rows 2 * n_rows
         // queue search only (rows longer than 32 sites): allocated when some instance needs it
@@ -926,6 +929,13 @@ void apt_quad_kernel(AptArgs A)
         const uint32_t c3 = ((uint32_t)D.inst << 4) | A.tag;
         // this thread's share of each slot's energy change in this launch
         int32_t dE[4] = {0, 0, 0, 0};
+        // Within a sweep the changes are summed in packed form: every flip of slot b adds
+        // v = idx_b (a 1 -> 0 flip) or 2 imax - idx_b (0 -> 1) to 16-bit lane b of V02 (b = 0, 2)
+        // or V13 (b = 1, 3), and 1 to byte b of C4; the slot's energy change is then
+        // 2 (sum v - imax * flips) (Eq. 8 with I_j = idx_b - imax).  A thread updates at most
+        // about 131 sites per sweep, so lanes and bytes do not overflow before the flush.
+        uint32_t V02 = 0u, V13 = 0u, C4 = 0u;
+        const uint32_t rev4 = 2u * (uint32_t)A.imax * 0x01010101u;
         bool full_energy = A.do_energy == 2;
         // threshold offsets: table of slot b at b * ni; with ni <= 16 the four byte offsets
         // of one site fit one word (index bytes + table starts, times 4)
@@ -985,19 +995,25 @@ void apt_quad_kernel(AptArgs A)
                     acc = shift_in_lt(acc, u.y, T1);
                     acc = shift_in_lt(acc, u.x, T0);
                     const uint32_t nw = __umul24(acc, 0x00204081u) & 0x01010101u;   // bit b -> byte b
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        // Eq. (8): the update changes E by -(s_new - s_old) I_j = 2 (o - n) I_j,
-                        // with o, n the old and new states (0/1) and I_j = index - imax
-                        const int32_t ob = (int32_t)((old >> (8 * b)) & 1u);
-                        const int32_t nb = (int32_t)((acc >> b) & 1u);
-                        const int32_t Ij = (int32_t)((idx4 >> (8 * b)) & 0xFFu) - A.imax;
-                        dE[b] += __mul24(ob - nb, 2 * Ij);
-                    }
+                    // Eq. (8): the update changes E by -(s_new - s_old) I_j = 2 (o - n) I_j,
+                    // with o, n the old and new states (0/1) and I_j = index - imax
+                    const uint32_t fl = old ^ nw;                    // flipped slots, bytes 0/1
+                    // byte 1 -> 0xFF, 0 -> 0x00 (two full-rate operations, no carries)
+                    const uint32_t mo = (old + 0x7F7F7F7Fu) ^ 0x7F7F7F7Fu;   // where o = 1
+                    const uint32_t mf = (fl + 0x7F7F7F7Fu) ^ 0x7F7F7F7Fu;    // where flipped
+                    const uint32_t v4 = (((idx4 ^ (rev4 - idx4)) & mo) ^ (rev4 - idx4)) & mf;
+                    V02 += v4 & 0x00FF00FFu;
+                    V13 += (v4 >> 8) & 0x00FF00FFu;
+                    C4 += fl;
                     sp[j] = nw;
                 }
                 __syncthreads();
             }
+            dE[0] += 2 * ((int32_t)(V02 & 0xFFFFu) - A.imax * (int32_t)(C4 & 0xFFu));
+            dE[1] += 2 * ((int32_t)(V13 & 0xFFFFu) - A.imax * (int32_t)((C4 >> 8) & 0xFFu));
+            dE[2] += 2 * ((int32_t)(V02 >> 16) - A.imax * (int32_t)((C4 >> 16) & 0xFFu));
+            dE[3] += 2 * ((int32_t)(V13 >> 16) - A.imax * (int32_t)(C4 >> 24));
+            V02 = V13 = C4 = 0u;
             if (A.mom_from >= 0 && sw >= A.mom_from) {
                 int32_t e[4] = {dE[0], dE[1], dE[2], dE[3]};
                 block_sum4(e, red);
