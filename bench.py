@@ -30,8 +30,9 @@ sys.path.insert(0, ROOT)
 METRIC = "spin flips/ns at L=15; time-to-target residual energy/spin, plain vs batched"
 # MI355X VALU: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6e12 lane-operations/s for
 # full-rate 32-bit operations (the published 157.3 TFLOP/s FP32 vector rate is this
-# figure times two flops per FMA).  Three-operand (VOP3) integer operations such as the
-# 32x32->64 multiply-add issue at half that rate (two slots).
+# figure times two flops per FMA).  Three-source integer operations such as the
+# 32x32->64 multiply-add and the three-input XOR, and operations that read a scalar
+# register or write VCC, issue at half that rate (two slots).
 VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 # Algorithmic VALU work per DT-SQA spin-update attempt, in full-rate slots.  One
 # Philox4x32-10 block (10 rounds, each two 32x32->64 multiply-adds at 2 slots and four
@@ -211,6 +212,53 @@ def time_to_target(rho0=0.007, e0_cycles=30000, max_cycles=100000, chunk=250, bc
     return out
 
 
+def sqa_study(Rs=(64, 256, 1024), lengths=(1000, 3000, 10000), e0_cycles=30000,
+              e0_seeds=(101, 202)):
+    """Residual energy per spin of DT-SQA against the number R of independent replicas and the
+    annealing length, on the extreme-value workload (32 periodic 15^3 +-J instances, M = 64,
+    beta = 32, Gamma linear 3.0 -> 0.01; Supplementary DT-SQA study).  Per instance the result
+    of a run is the lowest slice energy over its R replicas at the end of the anneal; rho =
+    (that energy - E0) / n (Eq. 2), averaged over the instances.  E0 per instance is the lowest
+    energy seen in any of these runs and in long batched APT+ICM runs on the same instances
+    (the paper's instances and ground energies are not available)."""
+    from paper_2503_10302_amd import sg
+    from paper_2503_10302_amd.inputs import geometric_ladder, linear_gamma
+    insts, M, _, beta = sqa_workload(64)
+    n = 15 ** 3
+    E0 = np.full(len(insts), np.iinfo(np.int64).max)
+    for sd in e0_seeds:
+        c = sg.apt(insts, geometric_ladder(32, 0.2, 3.0), seed=sd, reps_per_beta=2)
+        c.run_apt(e0_cycles, 1, 1.0)
+        E0 = np.minimum(E0, c.best())
+        c.close()
+        print(f"sqa-study: APT+ICM reference run (seed {sd}, {e0_cycles} cycles) done", file=sys.stderr,
+              flush=True)
+    runs = []
+    for T in lengths:
+        gam = linear_gamma(T)
+        for R in Rs:
+            ctx = sg.sqa(insts, M, R, beta, seed=5000 + R + T)
+            ctx.synchronize()
+            ctx.timer_start()
+            bE, _ = ctx.sqa_anneal(gam)
+            ms = ctx.timer_stop()
+            ctx.close()
+            runs.append((R, T, bE, ms))
+            E0 = np.minimum(E0, bE)
+            print(f"sqa-study: R={R} steps={T} done in {ms / 1e3:.2f} s", file=sys.stderr, flush=True)
+    table = {}
+    for R, T, bE, ms in runs:
+        rho = (bE - E0) / n
+        table[f"R{R}_steps{T}"] = {"rho_mean": round(float(rho.mean()), 6),
+                                   "rho_median": round(float(np.median(rho)), 6),
+                                   "at_E0": int((bE == E0).sum()), "wall_s": round(ms / 1e3, 3),
+                                   "flips_per_ns": round(len(insts) * R * M * n * T / (ms * 1e6), 1)}
+    return {"metric": "DT-SQA residual energy per spin vs replicas R and annealing steps "
+                      "(32 periodic L=15 instances, M=64, beta=32)",
+            "e0": f"min over every run here and {len(e0_seeds)} x {e0_cycles}-cycle batched APT+ICM runs",
+            "mean_E0_per_spin": round(float(E0.mean()) / n, 6), "runs": table}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +280,9 @@ def main():
                     help="throughput of the adaptive-ladder stage: 256 L=15 instances x 100 chains, "
                          "--adaptive-steps beta steps of 10^4 sweeps")
     ap.add_argument("--adaptive-steps", type=int, default=3)
+    ap.add_argument("--sqa-study", action="store_true",
+                    help="DT-SQA residual energy per spin against R (64, 256, 1024) and annealing "
+                         "steps (1e3, 3e3, 1e4) on the L=15 extreme-value workload")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -244,6 +295,9 @@ def main():
 
     if args.ttt:
         print(json.dumps(time_to_target(e0_cycles=args.ttt_cycles)), flush=True)
+        return
+    if args.sqa_study:
+        print(json.dumps(sqa_study(e0_cycles=args.ttt_cycles)), flush=True)
         return
     if args.adaptive:
         from paper_2503_10302_amd.inputs import ej_couplings
