@@ -138,6 +138,26 @@ def test_apt_with_fields_and_open_axes():
     assert e.value.code == sg.SG_EUNSUPPORTED
 
 
+def test_apt_largest_lattices_multi_sweep_energy_sums():
+    """Lattices near the 32767-site limit, one with fields up to 31 (75 threshold entries per
+    slot) and one without (16 or fewer, tables in static LDS): one launch of three sweeps,
+    whose per-sweep packed energy sums are at their largest (about 124 sites per thread)."""
+    insts = [_inst((31, 32, 32), 7, 51, hmax=31), _inst((32, 32, 31), 7, 52)]
+    beta = geometric_ladder(4, 0.3, 2.5)
+    ctx = sg.apt(insts, beta, SEED, reps_per_beta=2)
+    sb = np.repeat(beta, 2)
+    ctx.sweep(3)
+    g = ctx.spins()
+    E = ctx.energy()
+    for i, inst in enumerate(insts):
+        l = _olat(inst)
+        sp = oracle.apt_init(l, i, 8, SEED)
+        for t in range(3):
+            oracle.apt_sweep(l, i, sb, SEED, t, sp)
+        assert np.array_equal(g[i, :, :l.n], sp), f"instance {i}"
+        assert E[i].tolist() == [oracle.energy(l, s) for s in sp], f"instance {i}"
+
+
 def test_apt_long_rows_use_queue_search():
     """x extent above 32 sites: the cluster search falls back to the breadth-first queue."""
     insts = [_inst((40, 3, 3), 7, 41), _inst((37, 2, 4), 5, 42), _inst((6, 6, 6), 7, 43)]
