@@ -398,20 +398,26 @@ void sqa_records(const Lat &L, std::vector<uint4> &rec, std::vector<uint4> &recj
     for (int c = 0; c < 3; ++c) {
         I.col_off[c] = off;
         I.col_cnt[c] = 0;
+        I.col_p1[c] = 0;
         if (c >= C) continue;
-        for (int j = 0; j < L.n; ++j) {
-            const int p = ((c - L.label_sum(j, three)) % C + C) % C;
-            if (p > 1) continue;
-            uint4 rr = make_record(L, j, (uint32_t)p);
-            // neighbour fields -> word offsets 2 nb + p into the replica's spin words
-            auto wo = [p](uint32_t f) {
-                return (2u * (f & 0xFFFFu) + (uint32_t)p) | ((2u * (f >> 16) + (uint32_t)p) << 16);
-            };
-            rr.y = wo(rr.y);
-            rr.z = wo(rr.z);
-            rr.w = wo(rr.w);
-            rec.push_back(rr);
-            ++I.col_cnt[c];
+        // the phase's sites of parity 0 first (col_p1[c] of them), then those of parity 1,
+        // so that the kernel sweeps each part with the parity fixed
+        for (int pp = 0; pp < 2; ++pp) {
+            if (pp == 1) I.col_p1[c] = I.col_cnt[c];
+            for (int j = 0; j < L.n; ++j) {
+                const int p = ((c - L.label_sum(j, three)) % C + C) % C;
+                if (p != pp) continue;
+                uint4 rr = make_record(L, j, (uint32_t)p);
+                // neighbour fields -> word offsets 2 nb + p into the replica's spin words
+                auto wo = [p](uint32_t f) {
+                    return (2u * (f & 0xFFFFu) + (uint32_t)p) | ((2u * (f >> 16) + (uint32_t)p) << 16);
+                };
+                rr.y = wo(rr.y);
+                rr.z = wo(rr.z);
+                rr.w = wo(rr.w);
+                rec.push_back(rr);
+                ++I.col_cnt[c];
+            }
         }
         off += I.col_cnt[c];
     }

@@ -49,6 +49,8 @@ struct InstDev {
     int32_t n_slots;     // APT: n_beta * reps; DT-SQA: M
     int32_t col_off[3];  // first record of each colour class / phase (relative)
     int32_t col_cnt[3];  // records in each class / phase
+    int32_t col_p1[3];   // DT-SQA: records of parity 0 at the start of each phase (the rest
+                         // have parity 1)
     int64_t rec_off;     // colour-sorted (or phase) records
     int64_t recj_off;    // site-ordered records
     int64_t spin_off;    // APT: byte offset of replica buffer 0; DT-SQA: word offset

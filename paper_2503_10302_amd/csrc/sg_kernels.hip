@@ -1273,6 +1273,58 @@ __device__ __forceinline__ uint32_t sqa_slices(const uint32_t *lut, const uint32
     return res;
 }
 
+// Heat-bath update of the slices of parity P (slice 2 h + P at bit h) at the site of record
+// rr (Supplementary Eq. S.3): the aligned-neighbour count of every slice, bit-sliced over the
+// six spatial neighbours, the number of up Trotter neighbours from the other parity's word,
+// then sqa_slices.
+template <int NG, bool SCALED, int P>
+__device__ __forceinline__ void sqa_site(const SqaArgs &A, const uint4 rr, uint32_t *sp,
+                                         const uint32_t *lrow, const uint32_t *tab01,
+                                         const uint32_t *tab2t, const uint32_t *tab1,
+                                         uint32_t mask, int H, uint32_t t, int r, uint32_t c3,
+                                         int ngrp)
+{
+    const uint32_t j = rr.x & 0xFFFFu;
+    const uint32_t jn = rr.x >> 19;
+    // aligned words: bit h = 1 when J * s_neighbour = +1 in slice 2h + P
+    // (the record holds the neighbours' word offsets 2 nb + P)
+    const uint32_t a0 = sp[rr.y & 0xFFFFu] ^ (0u - (jn & 1u));
+    const uint32_t a1 = sp[rr.y >> 16] ^ (0u - ((jn >> 1) & 1u));
+    const uint32_t a2 = sp[rr.z & 0xFFFFu] ^ (0u - ((jn >> 2) & 1u));
+    const uint32_t a3 = sp[rr.z >> 16] ^ (0u - ((jn >> 3) & 1u));
+    const uint32_t a4 = sp[rr.w & 0xFFFFu] ^ (0u - ((jn >> 4) & 1u));
+    const uint32_t a5 = sp[rr.w >> 16] ^ (0u - ((jn >> 5) & 1u));
+    // bit-sliced 6-input count: k = c0 + 2 c1 + 4 c2 per slice
+    const uint32_t s1 = a0 ^ a1 ^ a2, k1 = (a0 & a1) | (a2 & (a0 ^ a1));
+    const uint32_t s2 = a3 ^ a4 ^ a5, k2 = (a3 & a4) | (a5 & (a3 ^ a4));
+    const uint32_t cy = s1 & s2;
+    const uint32_t c0 = (s1 ^ s2) & mask;
+    const uint32_t c1 = (k1 ^ k2 ^ cy) & mask;
+    const uint32_t c2 = ((k1 & k2) | (cy & (k1 ^ k2))) & mask;
+    // Trotter neighbours 2h + P - 1 and 2h + P + 1 from the other parity's word
+    uint32_t up, dn;
+    if (P) {
+        const uint32_t ev = sp[2 * j];
+        up = ev;
+        dn = rotr_h(ev, H, mask);
+    } else {
+        const uint32_t od = sp[2 * j + 1];
+        up = rotl_h(od, H, mask);
+        dn = od;
+    }
+    const uint32_t t0b = up ^ dn, t1b = up & dn;
+    // the site's part of the threshold index, 3 (h - d + smax), moves the row
+    const uint32_t *lsite = lrow + 3 * ((int32_t)((rr.x >> 25) & 63u) - 32 -
+                                        (int32_t)((rr.x >> 16) & 7u) + A.smax);
+    uint32_t e01, o01, e2t, o2t;
+    pair_planes(c0, c1, e01, o01);
+    pair_planes(c2, t0b, e2t, o2t);
+    const uint32_t res = sqa_slices<NG, SCALED>(lsite, tab01, tab2t, tab1, e01, o01, e2t, o2t,
+                                                t1b, (j << 1) | (uint32_t)P, t, (uint32_t)r << 16,
+                                                c3, A.key0, A.key1, ngrp);
+    sp[2 * j + P] = res & mask;
+}
+
 // The work-group size is a launch-time choice (a multiple of 64, at most 1024);
 // waves are limited to 64 VGPRs (8 waves per SIMD).
 template <int NG, bool SCALED>
@@ -1341,42 +1393,16 @@ void sqa_kernel(SqaArgs A)
                     lut[128 * ((st + 1) & 1) + i] = A.lut[(int64_t)(A.lut_step0 + st + 1) * A.nl + i];
             const uint4 *rc = A.rec + I.rec_off + A.inst[inst].col_off[c];
             const int cnt = A.inst[inst].col_cnt[c];
-            for (int i = tid; i < cnt; i += THREADS) {
-                const uint4 rr = rc[i];
-                const uint32_t j = rr.x & 0xFFFFu;
-                const uint32_t p = rr.x >> 31;
-                const uint32_t jn = rr.x >> 19;
-                // aligned words: bit h = 1 when J * s_neighbour = +1 in slice 2h + p
-                // (the record holds the neighbours' word offsets 2 nb + p)
-                const uint32_t a0 = sp[rr.y & 0xFFFFu] ^ (0u - (jn & 1u));
-                const uint32_t a1 = sp[rr.y >> 16] ^ (0u - ((jn >> 1) & 1u));
-                const uint32_t a2 = sp[rr.z & 0xFFFFu] ^ (0u - ((jn >> 2) & 1u));
-                const uint32_t a3 = sp[rr.z >> 16] ^ (0u - ((jn >> 3) & 1u));
-                const uint32_t a4 = sp[rr.w & 0xFFFFu] ^ (0u - ((jn >> 4) & 1u));
-                const uint32_t a5 = sp[rr.w >> 16] ^ (0u - ((jn >> 5) & 1u));
-                // bit-sliced 6-input count: k = c0 + 2 c1 + 4 c2 per slice
-                const uint32_t s1 = a0 ^ a1 ^ a2, k1 = (a0 & a1) | (a2 & (a0 ^ a1));
-                const uint32_t s2 = a3 ^ a4 ^ a5, k2 = (a3 & a4) | (a5 & (a3 ^ a4));
-                const uint32_t cy = s1 & s2;
-                const uint32_t c0 = (s1 ^ s2) & mask;
-                const uint32_t c1 = (k1 ^ k2 ^ cy) & mask;
-                const uint32_t c2 = ((k1 & k2) | (cy & (k1 ^ k2))) & mask;
-                const uint32_t ev = sp[2 * j], od = sp[2 * j + 1];
-                const uint32_t up = p ? ev : rotl_h(od, H, mask);
-                const uint32_t dn = p ? rotr_h(ev, H, mask) : od;
-                const uint32_t t0b = up ^ dn, t1b = up & dn;
-                // the site's part of the threshold index, 3 (h - d + smax), moves the row
-                const uint32_t *lsite = lrow + 3 * ((int32_t)((rr.x >> 25) & 63u) - 32 -
-                                                    (int32_t)((rr.x >> 16) & 7u) + A.smax);
-                uint32_t e01, o01, e2t, o2t;
-                pair_planes(c0, c1, e01, o01);
-                pair_planes(c2, t0b, e2t, o2t);
-                const uint32_t res = sqa_slices<NG, SCALED>(lsite, tab01, tab2t, tab1, e01, o01, e2t,
-                                                            o2t, t1b, (j << 1) | p, t,
-                                                            (uint32_t)r << 16, c3, A.key0,
-                                                            A.key1, ngrp);
-                sp[2 * j + p] = res & mask;
-            }
+            // parity 0 sites first, then parity 1 (each thread continues its stride across
+            // the boundary, so only the wave that straddles it runs both bodies)
+            const int n0 = A.inst[inst].col_p1[c];
+            int i = tid;
+            for (; i < n0; i += THREADS)
+                sqa_site<NG, SCALED, 0>(A, rc[i], sp, lrow, tab01, tab2t, tab1, mask, H, t, r, c3,
+                                        ngrp);
+            for (; i < cnt; i += THREADS)
+                sqa_site<NG, SCALED, 1>(A, rc[i], sp, lrow, tab01, tab2t, tab1, mask, H, t, r, c3,
+                                        ngrp);
             __syncthreads();
         }
     }
