@@ -85,3 +85,25 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_bench_roofline_accounting():
+    """The roofline inputs of the benchmark: 17.4 algorithmic slots per DT-SQA flip at 64
+    slices (65 per four-slice group, 5 per site and parity shared by the eight groups, one
+    compare per slice), the MI355X VALU peak, and HBM counters reported only for the kernel
+    source, replica count and step count they were measured on."""
+    import importlib.util
+    root = os.path.dirname(HEADER).rsplit(os.sep, 1)[0]
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    assert abs(b.alg_ops_per_flip(8) - (65 / 4 + 5 / 32 + 1)) < 1e-12
+    assert abs(b.VALU_PEAK_TOPS - 78.6432) < 1e-9
+    t = b.SQA_TRAFFIC
+    ok = b.sqa_traffic(t["R"], t["steps"])
+    if b.sqa_kernel_source_hash() == t["kernel_src_sha256_16"]:
+        assert ok == round((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024)
+    else:
+        assert ok is None   # counters taken on another version of the kernel are not reported
+    assert b.sqa_traffic(t["R"] // 2, t["steps"]) is None
+    assert b.sqa_traffic(t["R"], t["steps"] + 1) is None
