@@ -1746,7 +1746,7 @@ template <int NG, bool SCALED>
 hipError_t launch_sqa_t(const SqaArgs &a, int n_inst, size_t lds_bytes, int threads, hipStream_t s)
 {
     const void *k = (const void *)sqa_kernel<NG, SCALED>;
-    hipError_t e = allow_lds(k, lds_bytes + sizeof(uint32_t) * kSqaTabWords);
+    hipError_t e = allow_lds(k, lds_bytes);   // the dynamic part (the tables are static)
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((sqa_kernel<NG, SCALED>), dim3(n_inst * a.R), dim3(threads), lds_bytes, s, a);
     return hipGetLastError();

@@ -272,6 +272,28 @@ def test_sqa_matches_oracle(M):
     assert ctx.counters()[0] == 12
 
 
+def test_sqa_largest_lattice_in_lds():
+    """A DT-SQA replica that nearly fills one work-group's LDS (19656 sites, 2 x 19665 words),
+    with an open axis and fields, next to a small instance: spins, slice energies and the
+    minimum after three steps; beyond the limit the context is refused."""
+    insts = [_inst((28, 27, 26), 5, 61, hmax=3), _inst((4, 4, 4), 7, 62)]
+    M, R, beta = 64, 2, 32.0
+    gam = linear_gamma(3, 3.0, 0.01)
+    ctx = sg.sqa(insts, M, R, beta, SEED)
+    bE, _ = ctx.sqa_anneal(gam)
+    g = ctx.spins()
+    sE = ctx.energy()
+    for i, inst in enumerate(insts):
+        l = _olat(inst)
+        sp = oracle.sqa_init(l, i, M, R, SEED)
+        obE, _, osE = oracle.sqa_anneal(l, i, M, R, beta, gam, SEED, 0, sp)
+        assert np.array_equal(g[i, :, :, :l.n], sp), f"instance {i}"
+        assert np.array_equal(sE[i], osE) and bE[i] == obE
+    with pytest.raises(sg.SGError) as e:
+        sg.sqa([_inst((28, 28, 26), 5, 63)], M, R, beta, SEED)
+    assert e.value.code == sg.SG_EUNSUPPORTED
+
+
 def test_sqa_energy_without_schedule():
     """Slice energies right after creation and after a zero-step anneal: the kernel runs
     its energy pass with no threshold table."""
