@@ -1568,7 +1568,10 @@ bool adaptive_packed(sg_ctx *c, const sg_adaptive_params *p, double *beta_out,
     int planes = 1;
     while ((1 << planes) <= per_thread) ++planes;
     const size_t lds = sizeof(uint32_t) * (size_t)(max_npad + 1);
-    if (planes > kAdaptPlanes || lds + 16 * 1024 > kMaxLds) return false;
+    // + the kernel's static LDS: tables, energy counters, reduction scratch
+    const size_t lds_static =
+        sizeof(uint32_t) * (kAdaptTabWords + kAdaptPlanes * kAdaptThreads + kAdaptRedWords);
+    if (planes > kAdaptPlanes || lds + lds_static > kMaxLds) return false;
     const int n_inst = c->n_inst, nc = p->n_chains, nw = (nc + 31) / 32;
     // one work-group per (instance, chain word): with fewer work-groups than CUs the
     // chains spread wider as APT slots (four per work-group)

@@ -165,6 +165,8 @@ struct SqaArgs {
 // instance's current beta.  Fields must be zero (energies count unsatisfied bonds).
 constexpr int kAdaptThreads = 512;
 constexpr int kAdaptPlanes = 10;   // bits of the per-thread unsatisfied-bond counters
+constexpr int kAdaptTabWords = 256 + 16 + 64;            // static tables of adapt_kernel
+constexpr int kAdaptRedWords = kAdaptThreads / 64 * 32 + 1;   // its reduction scratch
 struct AdaptArgs {
     const InstDev *inst;
     const uint4 *rec_col;      // colour-sorted site records

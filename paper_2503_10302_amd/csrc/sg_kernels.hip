@@ -1591,10 +1591,10 @@ __global__ __launch_bounds__(kAdaptThreads) void adapt_kernel(AdaptArgs A)
 {
     // Static LDS: pair spread table of planes c0, c1 (256), spread table of c2 (16),
     // threshold row (<= 64), per-thread counters for the energies, reduction scratch.
-    __shared__ uint32_t tabs[256 + 16 + 64];
+    __shared__ uint32_t tabs[kAdaptTabWords];
     __shared__ uint32_t vc[kAdaptPlanes * kAdaptThreads];
     constexpr int kWaves = kAdaptThreads / 64;
-    __shared__ int32_t red[kWaves * 32 + 1];
+    __shared__ int32_t red[kAdaptRedWords];
     extern __shared__ uint32_t sp[];   // npad + 1 words, the last one the zero dummy
     int inst, w;
     adapt_block(A, blockIdx.x, inst, w);
