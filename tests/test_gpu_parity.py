@@ -175,6 +175,25 @@ def test_apt_long_rows_use_queue_search():
         assert rc == 0 and np.array_equal(g[i, :, :l.n], sp) and np.array_equal(trace[i], otr)
 
 
+def test_apt_queue_search_large_lattice():
+    """Rows longer than 32 sites at a size where the LDS queue, the visited bits and the tile
+    take about two thirds of the work-group's LDS (40 x 20 x 20 = 16000 sites), two labels."""
+    insts = [_inst((40, 20, 20), 7, 71), _inst((33, 4, 5), 3, 72)]
+    beta = geometric_ladder(4, 0.5, 3.0)
+    ctx = sg.apt(insts, beta, SEED, reps_per_beta=2)
+    trace = ctx.run_apt(6, 1, 0.5, record_every=2)
+    g = ctx.spins()
+    for i, inst in enumerate(insts):
+        l = _olat(inst)
+        sp = oracle.apt_init(l, i, 8, SEED)
+        ctr = np.zeros(3, np.uint32)
+        E = np.zeros(8, np.int64)
+        b = np.array([np.iinfo(np.int64).max], np.int64)
+        rc, otr, _ = oracle.apt_run(l, i, beta, 2, SEED, 6, 1, 0.5, 2, ctr, sp, E, b)
+        assert rc == 0 and np.array_equal(g[i, :, :l.n], sp) and np.array_equal(trace[i], otr)
+    assert ctx.energy()[0].tolist() == [oracle.energy(_olat(insts[0]), s) for s in g[0, :, :16000]]
+
+
 @pytest.mark.parametrize("reps", [2, 4])
 def test_apt_cluster_search_layouts(reps):
     """Row-bitset cluster search in both layouts: whole y-z planes per wave (wave-local fill:
