@@ -381,11 +381,12 @@ def test_adaptive_ladder_matches_oracle():
         assert np.array_equal(res[i][1], osg)
 
 
-@pytest.mark.parametrize("n_chains", [37, 64, 100])
+@pytest.mark.parametrize("n_chains", [37, 64, 100, 32, 33])
 def test_adaptive_ladder_chain_words(n_chains):
     """Chains 32 to a word (one work-group per instance and word, used once there are at least
     as many of them as CUs): a partial last word with a partial group (37), two full words (64),
-    the Methods' 100 chains (three full words and one of four chains)."""
+    the Methods' 100 chains (three full words and one of four chains), one full word (32), and
+    a full word with a last word of one chain (33)."""
     nw = (n_chains + 31) // 32
     n_inst = -(-256 // nw)
     shapes = [((4, 4, 4), 7), ((5, 4, 3), 0), ((2, 3, 7), 5), ((3, 3, 3), 7), ((6, 2, 2), 6)]
