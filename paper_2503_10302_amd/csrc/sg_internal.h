@@ -25,7 +25,7 @@ constexpr int kMaxH = 31;      // |h| bound, so that h + 32 fits 6 bits of a sit
 constexpr int kMaxN = 32767;   // sites per instance (16-bit site and neighbour indices)
 constexpr int kQuadThreads = 256;
 constexpr int kSqaThreads = 512;
-constexpr int kSqaTabWords = 912;        // static LDS of the DT-SQA kernel (tables)
+constexpr int kSqaTabWords = 976;        // static LDS of the DT-SQA kernel (tables)
 constexpr size_t kMaxLds = 160 * 1024;   // LDS per CU on gfx950
 
 // Site record (uint4), one per site:

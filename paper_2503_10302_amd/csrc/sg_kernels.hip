@@ -1219,18 +1219,19 @@ __device__ __forceinline__ uint32_t pair_off(uint32_t ev, uint32_t od, int g)
 // neighbours (t0, t1), read from two pair tables (planes c0, c1 and c2, t0, indexed by
 // a byte of pair_planes) and one 16-entry table (t1).  Groups run from the
 // highest to the lowest so that the borrow chain leaves slice h at bit h.  The block
-// counter is (2 j + p, step, r << 16 | g, instance): only its first word differs
-// between the lanes, so the products of the other half in the first two rounds are
-// work-group uniform (scalar unit) and the first-round product of 2 j + p is shared by
-// all groups.  SCALED: table indices are stored pre-multiplied by 4 (byte offsets),
-// possible when the table has <= 64 rows.  NG > 0: NG groups, unrolled; NG == 0: ngrp
-// groups, not unrolled.
+// counter is (2 j + p, step, r << 16 | g, instance): the groups of a site differ only in
+// word 2, so the first two rounds split into a part of the site (D, C, E: the products
+// of 2 j + p and of round 0's second output word, see sqa_site) and a part of the group
+// and step, U = {U1, U2, U3} from ug[g] (sqa_group_words), after which the state of round 2
+// is (D ^ U1, E, C ^ U2, .) and round 2's second XOR pair takes U3.  SCALED: table indices
+// are stored pre-multiplied by 4 (byte offsets), possible when the table has <= 64 rows.
+// NG > 0: NG groups, unrolled; NG == 0: ngrp groups, not unrolled.
 template <int NG, bool SCALED>
 __device__ __forceinline__ uint32_t sqa_slices(const uint32_t *lut, const uint32_t *tab01,
                                                const uint32_t *tab2t, const uint32_t *tab1,
                                                uint32_t e01, uint32_t o01, uint32_t e2t,
-                                               uint32_t o2t, uint32_t t1b, uint32_t jp,
-                                               uint32_t t, uint32_t x2, uint32_t c3,
+                                               uint32_t o2t, uint32_t t1b, uint32_t D,
+                                               uint32_t C, uint32_t E, const uint4 *ug,
                                                uint32_t k0, uint32_t k1, int ngrp)
 {
     uint32_t res = 0u;
@@ -1241,6 +1242,7 @@ __device__ __forceinline__ uint32_t sqa_slices(const uint32_t *lut, const uint32
     uint32_t s0 = lds_word(tab01, pair_off(e01, o01, ng - 1));
     uint32_t s1 = lds_word(tab2t, pair_off(e2t, o2t, ng - 1));
     uint32_t s2 = lds_word(tab1, nib_off(t1b, ng - 1));
+    uint4 U = ug[ng - 1];
 #pragma unroll
     for (int g = ng - 1; g >= 0; --g) {
         const uint32_t idx4 = s0 + s1 + s2;
@@ -1258,19 +1260,41 @@ __device__ __forceinline__ uint32_t sqa_slices(const uint32_t *lut, const uint32
         }
         const uint32_t T3 = lds_word(lut, o3), T2 = lds_word(lut, o2);
         const uint32_t T1 = lds_word(lut, o1), T0 = lds_word(lut, o0);
+        const uint4 Ug = U;
         if (g > 0) {
             s0 = lds_word(tab01, pair_off(e01, o01, g - 1));
             s1 = lds_word(tab2t, pair_off(e2t, o2t, g - 1));
             s2 = lds_word(tab1, nib_off(t1b, g - 1));
+            U = ug[g - 1];
         }
         __builtin_amdgcn_sched_barrier(0);
-        const uint4 u = philox10v(jp, t, x2 | (uint32_t)g, c3, k0, k1);
-        res = shift_in_lt(res, u.w, T3);
-        res = shift_in_lt(res, u.z, T2);
-        res = shift_in_lt(res, u.y, T1);
-        res = shift_in_lt(res, u.x, T0);
+        // round 2 (key k + 2 W) on the state after round 1, then rounds 3..9
+        const uint32_t x0 = D ^ Ug.x, x2 = C ^ Ug.y;
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+        uint32_t x[4] = {xor3_vvs((uint32_t)(p1 >> 32), E, k0 + 2u * 0x9E3779B9u), (uint32_t)p1,
+                         (uint32_t)(p0 >> 32) ^ Ug.z, (uint32_t)p0};
+        uint32_t key[2] = {k0 + 3u * 0x9E3779B9u, k1 + 3u * 0xBB67AE85u};
+        philox_rounds<3, 10>(x, key);
+        res = shift_in_lt(res, x[3], T3);
+        res = shift_in_lt(res, x[2], T2);
+        res = shift_in_lt(res, x[1], T1);
+        res = shift_in_lt(res, x[0], T0);
     }
     return res;
+}
+
+// The group-and-step part of the first two Philox rounds of sqa_slices for counter
+// (., t, r << 16 | g, c3) under (k0, k1): U1 = lo(M1 x2) ^ (k0 + W0), and with
+// A = hi(M1 x2) ^ t ^ k0 (round 0's first output word), U2 = hi(M0 A) ^ (k1 + W1) and
+// U3 = lo(M0 A) ^ (k1 + 2 W1).
+__device__ __forceinline__ uint4 sqa_group_words(uint32_t t, uint32_t x2, uint32_t k0, uint32_t k1)
+{
+    const uint64_t q = (uint64_t)0xCD9E8D57u * x2;
+    const uint32_t A = (uint32_t)(q >> 32) ^ t ^ k0;
+    const uint64_t pa = (uint64_t)0xD2511F53u * A;
+    return make_uint4((uint32_t)q ^ (k0 + 0x9E3779B9u), (uint32_t)(pa >> 32) ^ (k1 + 0xBB67AE85u),
+                      (uint32_t)pa ^ (k1 + 2u * 0xBB67AE85u), 0u);
 }
 
 // Heat-bath update of the slices of parity P (slice 2 h + P at bit h) at the site of record
@@ -1281,7 +1305,7 @@ template <int NG, bool SCALED, int P>
 __device__ __forceinline__ void sqa_site(const SqaArgs &A, const uint4 rr, uint32_t *sp,
                                          const uint32_t *lrow, const uint32_t *tab01,
                                          const uint32_t *tab2t, const uint32_t *tab1,
-                                         uint32_t mask, int H, uint32_t t, int r, uint32_t c3,
+                                         uint32_t mask, int H, const uint4 *ug, uint32_t c3,
                                          int ngrp)
 {
     const uint32_t j = rr.x & 0xFFFFu;
@@ -1319,9 +1343,13 @@ __device__ __forceinline__ void sqa_site(const SqaArgs &A, const uint4 rr, uint3
     uint32_t e01, o01, e2t, o2t;
     pair_planes(c0, c1, e01, o01);
     pair_planes(c2, t0b, e2t, o2t);
+    // the site's part of Philox rounds 0 and 1 (word 0 of the counter is 2 j + P)
+    const uint64_t pj = (uint64_t)0xD2511F53u * ((j << 1) | (uint32_t)P);
+    const uint32_t B = (uint32_t)(pj >> 32) ^ c3 ^ A.key1;
+    const uint64_t pb = (uint64_t)0xCD9E8D57u * B;
     const uint32_t res = sqa_slices<NG, SCALED>(lsite, tab01, tab2t, tab1, e01, o01, e2t, o2t,
-                                                t1b, (j << 1) | (uint32_t)P, t, (uint32_t)r << 16,
-                                                c3, A.key0, A.key1, ngrp);
+                                                t1b, (uint32_t)(pb >> 32), (uint32_t)pj,
+                                                (uint32_t)pb, ug, A.key0, A.key1, ngrp);
     sp[2 * j + P] = res & mask;
 }
 
@@ -1335,7 +1363,7 @@ void sqa_kernel(SqaArgs A)
     // Tables at fixed (static) LDS addresses, so that table offsets need no base
     // register: thresholds (<= 256 entries), spread tables, reduction scratch.  The
     // replica lives in dynamic LDS.
-    __shared__ uint32_t tabs[kSqaTabWords];
+    __shared__ __align__(16) uint32_t tabs[kSqaTabWords];
     extern __shared__ uint32_t lds[];
     const int inst = blockIdx.x / A.R, r = blockIdx.x - inst * A.R;
     const InstDev I = A.inst[inst];
@@ -1352,6 +1380,8 @@ void sqa_kernel(SqaArgs A)
     uint32_t *tab2t = tabs + 512;               // 256
     uint32_t *tab1 = tabs + 768;                // 16
     int32_t *red = (int32_t *)(tabs + 784);     // 2 * 64
+    uint4 *ugrp = (uint4 *)(tabs + 912);        // [2][8] group words of the Philox rounds
+                                                // 0-1 (sqa_group_words), by step parity
     uint32_t *sp = lds;                         // 2 * (npad + 1)
     uint32_t *g = A.spins + I.spin_off + (int64_t)r * npad * 2;
     for (int i = tid; i < 2 * npad; i += THREADS) sp[i] = g[i];
@@ -1369,6 +1399,9 @@ void sqa_kernel(SqaArgs A)
     }
     const uint32_t c3 = ((uint32_t)inst << 4) | TAG_SQA_SWEEP;
     const int ngrp = (H + 3) >> 2;
+    if (A.n_steps > 0 && tid < ngrp)
+        ugrp[tid] = sqa_group_words((uint32_t)A.t0, ((uint32_t)r << 16) | (uint32_t)tid, A.key0,
+                                    A.key1);
     // Threshold rows: a table of <= 128 entries is double-buffered, the next step's
     // row written during the current step's first phase (no extra barrier); a larger
     // table is reloaded between steps.
@@ -1380,6 +1413,7 @@ void sqa_kernel(SqaArgs A)
     for (int st = 0; st < A.n_steps; ++st) {
         const uint32_t t = (uint32_t)(A.t0 + st);
         const uint32_t *lrow = lut + (dbuf ? 128 * (st & 1) : 0);
+        const uint4 *ug = ugrp + 8 * (st & 1);
         if (!dbuf) {
             for (int i = tid; i < A.nl; i += THREADS)
                 lut[i] = A.lut[(int64_t)(A.lut_step0 + st) * A.nl + i];
@@ -1391,6 +1425,9 @@ void sqa_kernel(SqaArgs A)
             if (dbuf && c == 0 && st + 1 < A.n_steps)
                 for (int i = tid; i < A.nl; i += THREADS)
                     lut[128 * ((st + 1) & 1) + i] = A.lut[(int64_t)(A.lut_step0 + st + 1) * A.nl + i];
+            if (c == 0 && st + 1 < A.n_steps && tid < ngrp)
+                ugrp[8 * ((st + 1) & 1) + tid] = sqa_group_words(
+                    t + 1u, ((uint32_t)r << 16) | (uint32_t)tid, A.key0, A.key1);
             const uint4 *rc = A.rec + I.rec_off + A.inst[inst].col_off[c];
             const int cnt = A.inst[inst].col_cnt[c];
             // parity 0 sites first, then parity 1 (each thread continues its stride across
@@ -1398,10 +1435,10 @@ void sqa_kernel(SqaArgs A)
             const int n0 = A.inst[inst].col_p1[c];
             int i = tid;
             for (; i < n0; i += THREADS)
-                sqa_site<NG, SCALED, 0>(A, rc[i], sp, lrow, tab01, tab2t, tab1, mask, H, t, r, c3,
+                sqa_site<NG, SCALED, 0>(A, rc[i], sp, lrow, tab01, tab2t, tab1, mask, H, ug, c3,
                                         ngrp);
             for (; i < cnt; i += THREADS)
-                sqa_site<NG, SCALED, 1>(A, rc[i], sp, lrow, tab01, tab2t, tab1, mask, H, t, r, c3,
+                sqa_site<NG, SCALED, 1>(A, rc[i], sp, lrow, tab01, tab2t, tab1, mask, H, ug, c3,
                                         ngrp);
             __syncthreads();
         }
