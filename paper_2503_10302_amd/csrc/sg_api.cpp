@@ -1570,7 +1570,7 @@ bool adaptive_packed(sg_ctx *c, const sg_adaptive_params *p, double *beta_out,
     const size_t lds = sizeof(uint32_t) * (size_t)(max_npad + 1);
     // + the kernel's static LDS: tables, energy counters, reduction scratch
     const size_t lds_static =
-        sizeof(uint32_t) * (kAdaptTabWords + kAdaptPlanes * kAdaptThreads + kAdaptRedWords);
+        sizeof(uint32_t) * (kAdaptTabWords + kAdaptPlanes * kAdaptThreads + kAdaptRedWords + 64);
     if (planes > kAdaptPlanes || lds + lds_static > kMaxLds) return false;
     const int n_inst = c->n_inst, nc = p->n_chains, nw = (nc + 31) / 32;
     // one work-group per (instance, chain word): with fewer work-groups than CUs the

@@ -1512,7 +1512,8 @@ __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n)
 // ---------------------------------------------------------------------------
 // New states of the chains of one word at one site (heat-bath rule of Eq. 6 at the
 // instance's beta): chain 4 g + i takes word i of the Philox block (j, t, 8 w + g,
-// instance) of group g; its threshold index is a byte of the sum of a pair-table read
+// instance) of group g (rounds 0-1 split as in sqa_slices: D, C, E of the site, ug[g] of the
+// group and sweep); its threshold index is a byte of the sum of a pair-table read
 // (planes c0, c1) and a 16-entry table read (plane c2), relative to lsite, the row moved
 // by the site's field and degree.  Groups run from the highest to the lowest so that the
 // borrow chain leaves chain b at bit b; the table reads of group g - 1 and the threshold
@@ -1521,13 +1522,15 @@ __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n)
 template <int NG>
 __device__ __forceinline__ uint32_t adapt_groups(const uint32_t *lsite, const uint32_t *tab01,
                                                  const uint32_t *tab2, uint32_t e01, uint32_t o01,
-                                                 uint32_t c2, uint32_t j, uint32_t t, uint32_t x2,
-                                                 uint32_t c3, uint32_t k0, uint32_t k1, int ngrp)
+                                                 uint32_t c2, uint32_t D, uint32_t C, uint32_t E,
+                                                 const uint4 *ug, uint32_t k0, uint32_t k1,
+                                                 int ngrp)
 {
     const int ng = NG > 0 ? NG : ngrp;
     uint32_t res = 0u;
     uint32_t s0v = lds_word(tab01, pair_off(e01, o01, ng - 1));
     uint32_t s1v = lds_word(tab2, nib_off(c2, ng - 1));
+    uint4 U = ug[ng - 1];
 #pragma unroll
     for (int g = ng - 1; g >= 0; --g) {
         const uint32_t idx4 = s0v + s1v;
@@ -1535,16 +1538,25 @@ __device__ __forceinline__ uint32_t adapt_groups(const uint32_t *lsite, const ui
         const uint32_t T2 = lds_word(lsite, (idx4 >> 16) & 0xFFu);
         const uint32_t T1 = lds_word(lsite, (idx4 >> 8) & 0xFFu);
         const uint32_t T0 = lds_word(lsite, idx4 & 0xFFu);
+        const uint4 Ug = U;
         if (g > 0) {
             s0v = lds_word(tab01, pair_off(e01, o01, g - 1));
             s1v = lds_word(tab2, nib_off(c2, g - 1));
+            U = ug[g - 1];
         }
         __builtin_amdgcn_sched_barrier(0);
-        const uint4 u = philox10v(j, t, x2 | (uint32_t)g, c3, k0, k1);
-        res = shift_in_lt(res, u.w, T3);
-        res = shift_in_lt(res, u.z, T2);
-        res = shift_in_lt(res, u.y, T1);
-        res = shift_in_lt(res, u.x, T0);
+        // round 2 (key k + 2 W) on the state after round 1, then rounds 3..9
+        const uint32_t x0 = D ^ Ug.x, x2 = C ^ Ug.y;
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+        uint32_t x[4] = {xor3_vvs((uint32_t)(p1 >> 32), E, k0 + 2u * 0x9E3779B9u), (uint32_t)p1,
+                         (uint32_t)(p0 >> 32) ^ Ug.z, (uint32_t)p0};
+        uint32_t key[2] = {k0 + 3u * 0x9E3779B9u, k1 + 3u * 0xBB67AE85u};
+        philox_rounds<3, 10>(x, key);
+        res = shift_in_lt(res, x[3], T3);
+        res = shift_in_lt(res, x[2], T2);
+        res = shift_in_lt(res, x[1], T1);
+        res = shift_in_lt(res, x[0], T0);
     }
     return res;
 }
@@ -1555,8 +1567,7 @@ template <int NG>
 __device__ __forceinline__ void adapt_phase(const AdaptArgs &A, const uint4 *rc, int cnt,
                                             uint32_t *sp, const uint32_t *tab01,
                                             const uint32_t *tab2, const uint32_t *lut,
-                                            uint32_t t, uint32_t x2, uint32_t c3, int ng,
-                                            uint32_t vmask)
+                                            const uint4 *ug, uint32_t c3, int ng, uint32_t vmask)
 {
     for (int i = threadIdx.x; i < cnt; i += kAdaptThreads) {
         const uint4 r = rc[i];
@@ -1577,7 +1588,12 @@ __device__ __forceinline__ void adapt_phase(const AdaptArgs &A, const uint4 *rc,
                                        (int32_t)((r.x >> 16) & 7u) + A.imax);
         uint32_t e01, o01;
         pair_planes(c0, c1, e01, o01);
-        const uint32_t res = adapt_groups<NG>(lsite, tab01, tab2, e01, o01, c2, j, t, x2, c3,
+        // the site's part of Philox rounds 0 and 1 (word 0 of the counter is j)
+        const uint64_t pj = (uint64_t)0xD2511F53u * j;
+        const uint32_t B = (uint32_t)(pj >> 32) ^ c3 ^ A.key1;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * B;
+        const uint32_t res = adapt_groups<NG>(lsite, tab01, tab2, e01, o01, c2,
+                                              (uint32_t)(pb >> 32), (uint32_t)pj, (uint32_t)pb, ug,
                                               A.key0, A.key1, ng);
         sp[j] = res & vmask;
     }
@@ -1632,6 +1648,8 @@ __global__ __launch_bounds__(kAdaptThreads) void adapt_kernel(AdaptArgs A)
     __shared__ uint32_t vc[kAdaptPlanes * kAdaptThreads];
     constexpr int kWaves = kAdaptThreads / 64;
     __shared__ int32_t red[kAdaptRedWords];
+    // group words of Philox rounds 0-1 (sqa_group_words) by sweep parity and group
+    __shared__ __align__(16) uint4 ugrp[2 * 8];
     extern __shared__ uint32_t sp[];   // npad + 1 words, the last one the zero dummy
     int inst, w;
     adapt_block(A, blockIdx.x, inst, w);
@@ -1661,6 +1679,8 @@ __global__ __launch_bounds__(kAdaptThreads) void adapt_kernel(AdaptArgs A)
         nbc += ((r.y & 0xFFFFu) != (uint32_t)n) + ((r.z & 0xFFFFu) != (uint32_t)n) +
                ((r.w & 0xFFFFu) != (uint32_t)n);
     }
+    if (A.n_sweeps > 0 && tid < ng)
+        ugrp[tid] = sqa_group_words(A.t0, 8u * (uint32_t)w + (uint32_t)tid, A.key0, A.key1);
     atomicAdd(&red[kWaves * 32], nbc);
     __syncthreads();
     const int32_t bonds = red[kWaves * 32];
@@ -1668,13 +1688,19 @@ __global__ __launch_bounds__(kAdaptThreads) void adapt_kernel(AdaptArgs A)
     int64_t S1 = 0, S2 = 0;   // moments of chain 32 w + tid (threads < nch)
     for (int sw = 0; sw < A.n_sweeps; ++sw) {
         const uint32_t t = A.t0 + (uint32_t)sw;
+        const uint4 *ug = ugrp + 8 * (sw & 1);
         for (int c = 0; c < I.n_colours; ++c) {
+            // the next sweep's group words into the other buffer (its readers, the previous
+            // sweep's phases, are past a barrier)
+            if (c == 0 && sw + 1 < A.n_sweeps && tid < ng)
+                ugrp[8 * ((sw + 1) & 1) + tid] =
+                    sqa_group_words(t + 1u, 8u * (uint32_t)w + (uint32_t)tid, A.key0, A.key1);
             const uint4 *rc = A.rec_col + I.rec_off + A.inst[inst].col_off[c];
             const int cnt = A.inst[inst].col_cnt[c];
             if (ng == 8)
-                adapt_phase<8>(A, rc, cnt, sp, tab01, tab2, lut, t, 8u * (uint32_t)w, c3, ng, vmask);
+                adapt_phase<8>(A, rc, cnt, sp, tab01, tab2, lut, ug, c3, ng, vmask);
             else
-                adapt_phase<0>(A, rc, cnt, sp, tab01, tab2, lut, t, 8u * (uint32_t)w, c3, ng, vmask);
+                adapt_phase<0>(A, rc, cnt, sp, tab01, tab2, lut, ug, c3, ng, vmask);
             __syncthreads();
         }
         if (sw >= A.mom_from) {
