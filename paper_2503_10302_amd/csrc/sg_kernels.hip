@@ -870,6 +870,9 @@ __global__ __launch_bounds__(kQuadThreads) void apt_init_kernel(const InstDev *i
 // SCALED: rows of at most 16 thresholds (no fields), so the four table offsets of a site
 // are bytes of one word.  At most 72 VGPRs, seven waves per SIMD (measured faster than six
 // with more registers and than eight with spills).
+// defined with the DT-SQA kernel
+__device__ __forceinline__ uint4 sqa_group_words(uint32_t t, uint32_t x2, uint32_t k0, uint32_t k1);
+
 template <bool SCALED>
 __global__ __launch_bounds__(kQuadThreads) __attribute__((amdgpu_waves_per_eu(7, 8)))
 void apt_quad_kernel(AptArgs A)
@@ -942,6 +945,10 @@ void apt_quad_kernel(AptArgs A)
         const uint32_t soff4 = (uint32_t)ni * 0x03020100u;
         for (int sw = 0; sw < A.n_sweeps; ++sw) {
             const uint32_t t = t0 + (uint32_t)sw;
+            // the work-group's words of Philox rounds 0-1 for this sweep, held in vector
+            // registers so that the XORs with a site's words are two-operand vector ones
+            uint4 uq = sqa_group_words(t, (uint32_t)q, A.key0, A.key1);
+            asm volatile("" : "+v"(uq.x), "+v"(uq.y), "+v"(uq.z));
             for (int c = 0; c < I.n_colours; ++c) {
                 const uint4 *rc = A.rec_col + I.rec_off + A.inst[D.inst].col_off[c];
                 const int cnt = A.inst[D.inst].col_cnt[c];
@@ -958,8 +965,20 @@ void apt_quad_kernel(AptArgs A)
                     const uint32_t nb4 = sp[r.w & 0xFFFFu], nb5 = sp[r.w >> 16];
                     const uint32_t old = sp[j];
                     __builtin_amdgcn_sched_barrier(0);
-                    uint32_t x[4] = {j, t, (uint32_t)q, c3}, key[2] = {A.key0, A.key1};
-                    philox_rounds<0, 5>(x, key);
+                    // Philox block (j, t, q, instance): rounds 0-1 split into the site's part
+                    // and the work-group's per-sweep words (uq, as in sqa_slices), then
+                    // round 2 and rounds 3-4
+                    const uint64_t pj = (uint64_t)0xD2511F53u * j;
+                    const uint32_t B = (uint32_t)(pj >> 32) ^ c3 ^ A.key1;
+                    const uint64_t pb = (uint64_t)0xCD9E8D57u * B;
+                    const uint32_t x0r = (uint32_t)(pb >> 32) ^ uq.x, x2r = (uint32_t)pj ^ uq.y;
+                    const uint64_t p0r = (uint64_t)0xD2511F53u * x0r;
+                    const uint64_t p1r = (uint64_t)0xCD9E8D57u * x2r;
+                    uint32_t x[4] = {xor3_vvs((uint32_t)(p1r >> 32), (uint32_t)pb,
+                                              A.key0 + 2u * 0x9E3779B9u),
+                                     (uint32_t)p1r, (uint32_t)(p0r >> 32) ^ uq.z, (uint32_t)p0r};
+                    uint32_t key[2] = {A.key0 + 3u * 0x9E3779B9u, A.key1 + 3u * 0xBB67AE85u};
+                    philox_rounds<3, 5>(x, key);
                     __builtin_amdgcn_sched_barrier(0);
                     // per byte (slot): number of present bonds whose J * s_neighbour = +1
                     const uint32_t k4 = (nb0 ^ bytemask(jn & 1u)) + (nb1 ^ bytemask((jn >> 1) & 1u)) +
