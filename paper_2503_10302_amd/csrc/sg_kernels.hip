@@ -126,11 +126,17 @@ __device__ __forceinline__ uint32_t aligned_count(const uint32_t *sp, const uint
     return k;
 }
 
+// Sum over the 64 lanes of a wave (all lanes active): DPP exchanges inside each row of 16
+// lanes (pairs, quads, half rows, rows: no LDS round trips), then the four row sums read
+// from lanes 0, 16, 32 and 48.  The result is wave-uniform.
 __device__ __forceinline__ int32_t wave_sum(int32_t v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);    // quad_perm [1,0,3,2]
+    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);    // quad_perm [2,3,0,1]
+    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);   // row_half_mirror
+    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);   // row_mirror
+    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+           __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
 }
 
 __device__ __forceinline__ int32_t wave_min(int32_t v)
