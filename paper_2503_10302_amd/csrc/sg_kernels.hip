@@ -160,6 +160,21 @@ __device__ __forceinline__ void block_sum4(int32_t v[4], int32_t *red)
     __syncthreads();
 }
 
+// block_sum4 for the work-group's last use of red: the totals are read by threads 0..3
+// only (into v), and there is no trailing barrier.
+__device__ __forceinline__ void block_sum4_last(int32_t v[4], int32_t *red)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = wave_sum(v[i]);
+    if (lane == 0)
+        for (int i = 0; i < 4; ++i) red[wv * 4 + i] = v[i];
+    __syncthreads();
+    if (threadIdx.x < 4)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = red[i] + red[4 + i] + red[8 + i] + red[12 + i];
+}
+
 // Exclusive prefix of v over the block in thread order; returns it and the total.
 __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *red, int32_t *total)
 {
@@ -1134,7 +1149,7 @@ void apt_quad_kernel(AptArgs A)
                 if (s < I.n_slots) A.E[I.slot_off + s] = e[tid];
             }
         } else if (A.do_energy) {
-            block_sum4(dE, red);
+            block_sum4_last(dE, red);
             if (tid < 4) {
                 const int s = 4 * q + tid;
                 if (s < I.n_slots) {
