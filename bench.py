@@ -52,8 +52,8 @@ def alg_ops_per_flip(groups):
 # runs, FETCH_SIZE then WRITE_SIZE (KiB per dispatch), each scaled by what the same
 # counter reads for a plain 256 MiB copy (fetch x 2.0, write x 1.0).  Reported only
 # while the DT-SQA kernel source is the one measured.
-SQA_TRAFFIC = {"kernel_src_sha256_16": "1255f77c565640db", "R": 1024, "steps": 200,
-               "fetch_kib": 452691.3125, "write_kib": 872448.0, "fetch_scale": 2.0, "write_scale": 1.0}
+SQA_TRAFFIC = {"kernel_src_sha256_16": "b2cea33a7749ac69", "R": 1024, "steps": 200,
+               "fetch_kib": 452678.1875, "write_kib": 872448.0, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def sqa_kernel_source_hash():

@@ -84,16 +84,6 @@ __device__ __forceinline__ void philox_rounds(uint32_t x[4], uint32_t k[2])
     }
 }
 
-// Philox4x32-10 of (x0, x1, x2, x3) under (k0, k1), for a counter whose words 1..3 are
-// wave-uniform (the sweep kernels' layout).
-__device__ __forceinline__ uint4 philox10v(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
-                                           uint32_t k0, uint32_t k1)
-{
-    uint32_t x[4] = {x0, x1, x2, x3}, k[2] = {k0, k1};
-    philox_rounds<0, 10>(x, k);
-    return make_uint4(x[0], x[1], x[2], x[3]);
-}
-
 __device__ __forceinline__ uint32_t lds_word(const uint32_t *base, uint32_t byte_off)
 {
     return *(const uint32_t *)((const uint8_t *)base + byte_off);
