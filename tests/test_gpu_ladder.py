@@ -5,7 +5,7 @@ import time
 import numpy as np
 import pytest
 
-from paper_2503_10302_amd import ladder
+from paper_2503_10302_amd import ladder, sg
 
 pytestmark = pytest.mark.gpu
 
@@ -52,3 +52,36 @@ def test_band_violation_falls_back_to_the_adaptive_stage():
     for i in range(4):
         np.testing.assert_array_equal(lad[i], ladder.resample(ref[i][0]))
         assert lad[i, 0] == 0.5 and np.all(np.diff(lad[i]) > 0)
+
+
+def test_predicted_ladder_matches_the_fp64_oracle_forward_pass():
+    """sg_ladder_predict against the oracle on 64 instances of every training size and two
+    held-out geometries: the features are the oracle's bit for bit, and the predicted log
+    betas and log cutoff agree with the oracle's FP64 forward pass of the same parameters
+    (standardised the same way) to 1e-5.  Tolerance: the FP32 kernel rounds the features
+    (relative 6e-8, at most 4e-7 after standardisation), sums 4, 64 and 64 products per
+    layer and 31 softplus increments; with weights of order 1 the accumulated error is a
+    few 1e-6, well inside 1e-5 (a float32 emulation of the layers stays below 3e-7)."""
+    import oracle
+    from paper_2503_10302_amd.inputs import diluted_couplings, ej_couplings
+    p = ladder.default_params()
+    NP = sg.MLP_NPARAM
+    inst = ladder._instances(range(48), (8, 10, 12, 15), 95000)
+    inst += [(ej_couplings((15, 15, 12), 4, seed=96000 + k)[0], 4, None) for k in range(8)]
+    inst += [(diluted_couplings((12, 12, 12), 7, seed=97000 + k, p_absent=0.1), 7, None)
+             for k in range(8)]
+    feats = ladder.features(inst)
+    of = np.stack([oracle.instance_features(oracle.Lattice(J, per, h)) for J, per, h in inst])
+    np.testing.assert_array_equal(feats, of)
+    m = ladder.Predictor(p)
+    beta, cut = m.predict(inst)
+    m.close()
+    mean = p[NP:NP + 4].astype(np.float64)
+    std = p[NP + 4:NP + 8].astype(np.float64)
+    x = (of.astype(np.float32).astype(np.float64) - mean) / std
+    _, _, out = oracle.mlp_loss_grad(p[:NP].astype(np.float64), x)
+    err_b = np.abs(np.log(beta) - out[:, :32]).max()
+    err_c = np.abs(np.log(cut) - out[:, 32]).max()
+    print(f"max |log beta - oracle| = {err_b:.2e}, cutoff {err_c:.2e}", flush=True)
+    assert err_b < 1e-5 and err_c < 1e-5
+    assert np.all(np.diff(beta, axis=1) > 0)

@@ -107,3 +107,23 @@ def test_bench_roofline_accounting():
         assert ok is None   # counters taken on another version of the kernel are not reported
     assert b.sqa_traffic(t["R"] // 2, t["steps"]) is None
     assert b.sqa_traffic(t["R"], t["steps"] + 1) is None
+
+
+def test_instance_features_equal_the_oracle():
+    """sg_instance_features (host code of the library, input of the ladder network) against
+    the oracle's sgo_instance_features, exactly: periodic, open, mixed-boundary, diluted and
+    thin lattices, with and without fields (fields are not features)."""
+    import oracle
+    from paper_2503_10302_amd import ladder
+    from paper_2503_10302_amd.inputs import diluted_couplings
+    cases = []
+    for k, (shape, per) in enumerate([((8, 8, 8), 7), ((15, 15, 15), 7), ((15, 15, 12), 4),
+                                      ((6, 7, 5), 0), ((9, 4, 3), 5), ((2, 2, 2), 7),
+                                      ((1, 1, 6), 4), ((10, 10, 10), 3)]):
+        J, h = ej_couplings(shape, per, seed=300 + k, h_max=3 if k % 3 == 0 else 0)
+        cases.append((J, per, h))
+        cases.append((diluted_couplings(shape, per, seed=400 + k, p_absent=0.2), per, None))
+    got = ladder.features(cases)
+    for i, (J, per, h) in enumerate(cases):
+        want = oracle.instance_features(oracle.Lattice(J, per, h))
+        assert got[i].tolist() == want.tolist(), (i, got[i], want)

@@ -199,3 +199,55 @@ def test_swap_rule_closed_form():
     u = rng.integers(0, 2 ** 32, size=20000, dtype=np.uint64)
     acc = np.mean([oracle.swap_accept(1.0, 1.25, -40, -44, int(v)) for v in u])
     assert abs(acc - math.exp(-1.0)) < 0.012
+
+
+def _fair(x, N, z=5.0):
+    """|x - N/2| within z standard deviations of a Binomial(N, 1/2) count."""
+    return abs(x - N / 2) <= z * 0.5 * math.sqrt(N)
+
+
+def test_apt_initial_state_is_fair_and_independent():
+    """Algorithm S2 starts every replica "in a random state": i.i.d. fair spins.  The oracle
+    draws spin (j, slot s) from word s & 3 of the Philox block (j, 0, s >> 2): pinned here by
+    the law itself -- the up fraction over 2.6e5 spins and the agreement of every pair of
+    slots that share a block, of neighbouring blocks and of neighbouring sites, all within
+    5 sigma of 1/2 -- and by two instances and the two purposes giving unrelated states."""
+    J, _ = ej_couplings((20, 20, 20), 7, seed=3)
+    lat = oracle.Lattice(J, 7)
+    n, S = lat.n, 32
+    s = oracle.apt_init(lat, 0, S, 1234)
+    up = (s > 0)
+    assert _fair(int(up.sum()), up.size)
+    for q in range(S // 4):
+        for i in range(4):
+            for k in range(i + 1, 4):   # slots of one Philox block
+                assert _fair(int((s[4 * q + i] == s[4 * q + k]).sum()), n), (q, i, k)
+    for a in range(S - 4):              # same word of neighbouring blocks
+        assert _fair(int((s[a] == s[a + 4]).sum()), n), a
+    for a in range(S):                  # neighbouring sites within a slot
+        assert _fair(int((s[a, 1:] == s[a, :-1]).sum()), n - 1), a
+    other = oracle.apt_init(lat, 1, S, 1234)
+    adapt = oracle.apt_init(lat, 0, S, 1234, tag=oracle.TAG_ADAPT_INIT)
+    for t in (other, adapt):
+        assert _fair(int((t == s).sum()), s.size)
+
+
+def test_sqa_initial_state_is_fair_and_independent():
+    """Algorithm S1 initialises every Trotter replica at random: i.i.d. fair spins.  Slice
+    k = 2h + p at site j takes word (h mod 4) of the block (2j + p, 0, r << 16 | h >> 2), so the
+    pins cover the four slices sharing a block, the two parities of a site, neighbouring
+    block groups, replicas and sites."""
+    J, _ = ej_couplings((16, 16, 16), 7, seed=4)
+    lat = oracle.Lattice(J, 7)
+    n, M, R = lat.n, 16, 4
+    s = oracle.sqa_init(lat, 0, M, R, 99)
+    assert _fair(int((s > 0).sum()), s.size)
+    for r in range(R):
+        for k in range(M):
+            for k2 in range(k + 1, M):
+                assert _fair(int((s[r, k] == s[r, k2]).sum()), n), (r, k, k2)
+            assert _fair(int((s[r, k, 1:] == s[r, k, :-1]).sum()), n - 1), (r, k)
+        if r + 1 < R:
+            assert _fair(int((s[r] == s[r + 1]).sum()), M * n), r
+    other = oracle.sqa_init(lat, 0, M, R, 99, r0=R)
+    assert _fair(int((other == s).sum()), s.size)

@@ -40,6 +40,14 @@ MUTANTS = [
      "double sigma = 1.05 * sum / (double)nc;"),
     ("adaptive_variance_for_std", "    return sqrt(var);", "    return var;"),
     ("mlp_drops_softplus_slope", "dO[i] = sigmoid(o[i]) * suffix;", "dO[i] = suffix;"),
+    ("apt_init_biased_threshold", "spins[(int64_t)s * n + j] = (w < 0x80000000u) ? 1 : -1;",
+     "spins[(int64_t)s * n + j] = (w < 0x40000000u) ? 1 : -1;"),
+    ("apt_init_one_word_per_block",
+     "uint32_t w = sgo_word(seed, (uint32_t)j, 0u, (uint32_t)s >> 2, inst, tag, s & 3);",
+     "uint32_t w = sgo_word(seed, (uint32_t)j, 0u, (uint32_t)s >> 2, inst, tag, 0);"),
+    ("sqa_init_biased_threshold", "spins[((int64_t)r * M + k) * n + j] = (w < 0x80000000u) ? 1 : -1;",
+     "spins[((int64_t)r * M + k) * n + j] = (w < 0x40000000u) ? 1 : -1;"),
+    ("sqa_init_one_word_per_block", "SGO_TAG_SQA_INIT, (k >> 1) & 3);", "SGO_TAG_SQA_INIT, 0);"),
 ]
 
 
