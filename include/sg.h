@@ -223,6 +223,20 @@ sg_status sg_mlp_get_params(sg_mlp *m, float *params /*[6625 + 8]*/);
 sg_status sg_ladder_predict(sg_mlp *m, const sg_lattice *inst, int32_t n_inst, double *beta_out,
                             double *cutoff_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): sg_ladder_predict without any
+ * allocation.  Same arguments, same results bit for bit.  The network inputs and outputs
+ * are staged in a static device array of the library (one per GPU, about 0.6 MB, held until
+ * the process ends, its address resolved by sg_mlp_create on the network's device) and, on
+ * the host, inside beta_out itself; the call allocates nothing, host or device.
+ * n_inst must be 1..SG_PREDICT_NOALLOC_MAX, otherwise SG_EINVAL with a message in
+ * sg_last_error(NULL).  Every call on one GPU shares that GPU's array: calls that overlap
+ * in time on one GPU (two threads, two streams) race and must be serialised by the caller.
+ * The call synchronises the network's stream before returning. */
+#define SG_PREDICT_NOALLOC_MAX 4096
+sg_status sg_ladder_predict_noalloc(sg_mlp *m, const sg_lattice *inst, int32_t n_inst,
+                                    double *beta_out, double *cutoff_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -936,6 +936,8 @@ thread_local std::string g_create_error;
 
 }  // namespace
 
+void sg::set_global_error(const char *msg) { g_create_error = msg ? msg : ""; }
+
 // ====================================================================== C ABI
 extern "C" {
 

@@ -204,5 +204,15 @@ hipError_t launch_mlp_pass(const float *P, const float *x, const float *y, const
                            float *grad, hipStream_t s);
 hipError_t launch_mlp_adam2(float *P, const float *g, float *m, float *v, float lr, float b1,
                             float b2, float eps, int step, hipStream_t s);
+// Allocation-free prediction: at most kPredictMax instances per call; the staging area
+// (raw features [kPredictMax][4], then outputs [kPredictMax][33]) is a static device array
+// of the library, one per GPU.  mlp_scratch gives its address on the current device
+// (resolved once per device, then cached).
+constexpr int kPredictMax = 4096;
+constexpr int kPredictScratchFloats = kPredictMax * (4 + 33);
+constexpr int kMaxDevices = 64;
+hipError_t mlp_scratch(float **p);
+// Message returned by sg_last_error(NULL) (calls without a context).
+void set_global_error(const char *msg);
 
 }  // namespace sg

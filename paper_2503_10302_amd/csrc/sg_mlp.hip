@@ -2,6 +2,8 @@
 // (4 -> 64 -> 64 -> 33, ReLU; outputs: log beta_0, softplus increments of
 // log beta_1..31, log ICM cutoff).  Tiny dense layers: plain VALU FMAs, one
 // 64-lane work-group per sample chunk, no matrix cores.
+#include <mutex>
+
 #include "sg_internal.h"
 
 namespace sg {
@@ -141,6 +143,37 @@ hipError_t launch_mlp_pass(const float *P, const float *x, const float *y, const
     hipLaunchKernelGGL(mlp_reduce_kernel, dim3((NPARAM + 255) / 256), dim3(256), 0, s, grad_acc,
                        nblk, grad);
     return hipGetLastError();
+}
+
+// Device memory of the allocation-free prediction entry point: the staging area of the
+// network inputs (raw features, [kPredictMax][NI]) followed by the network outputs
+// ([kPredictMax][NO]).  One copy per GPU, held until the process ends.  In host code the
+// name below is only a stand-in: every host-side use goes through the address that
+// hipGetSymbolAddress returns for the current device (mlp_scratch).
+static __device__ __align__(256) float scratch[kPredictMax * (NI + NO)];
+static_assert(kPredictScratchFloats == kPredictMax * (NI + NO), "scratch layout");
+
+namespace {
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t mlp_scratch(float **p)
+{
+    *p = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *a = nullptr;
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (float *)a;
+    }
+    *p = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_mlp_adam2(float *P, const float *g, float *m, float *v, float lr, float b1,

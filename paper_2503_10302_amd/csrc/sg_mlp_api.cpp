@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 #include <random>
@@ -110,6 +111,7 @@ struct sg_mlp {
     float *P = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *gacc = nullptr, *loss = nullptr;
     int step = 0;
     uint64_t seed = 0;
+    float *scratch = nullptr;   // the library's static staging area on this network's GPU
     ~sg_mlp()
     {
         for (float *p : {P, m, v, grad, gacc, loss})
@@ -148,6 +150,9 @@ sg_status sg_mlp_create(const float *params, uint64_t seed, void *hip_stream, sg
             m->own = true;
         }
         m->seed = seed;
+        // address of the allocation-free entry point's staging area on this GPU (once per
+        // device, with the device current)
+        chk(mlp_scratch(&m->scratch));
         std::vector<float> h(NPX, 0.f);
         if (params) {
             std::memcpy(h.data(), params, sizeof(float) * NPX);
@@ -319,6 +324,64 @@ sg_status sg_ladder_predict(sg_mlp *m, const sg_lattice *inst, int32_t n_inst, d
         for (int k = 0; k < 32; ++k) beta_out[(size_t)i * 32 + k] = std::exp((double)out[(size_t)i * 33 + k]);
         if (cutoff_out) cutoff_out[i] = std::exp((double)out[(size_t)i * 33 + 32]);
     }
+    return SG_OK;
+}
+
+sg_status sg_ladder_predict_noalloc(sg_mlp *m, const sg_lattice *inst, int32_t n_inst,
+                                    double *beta_out, double *cutoff_out)
+{
+    if (!m || !inst || n_inst < 1 || !beta_out) {
+        set_global_error("sg_ladder_predict_noalloc: NULL argument or n_inst < 1");
+        return SG_EINVAL;
+    }
+    if (n_inst > kPredictMax) {
+        char msg[128];
+        std::snprintf(msg, sizeof msg, "sg_ladder_predict_noalloc: n_inst = %d exceeds the limit of %d",
+                      (int)n_inst, kPredictMax);
+        set_global_error(msg);
+        return SG_EINVAL;
+    }
+    for (int i = 0; i < n_inst; ++i) {
+        const sg_lattice &L = inst[i];
+        if (L.Lx < 1 || L.Ly < 1 || L.Lz < 1 || !L.J || (int64_t)L.Lx * L.Ly * L.Lz > kMaxN) {
+            set_global_error("sg_ladder_predict_noalloc: invalid lattice");
+            return SG_EINVAL;
+        }
+    }
+    if (!m->scratch) {
+        set_global_error("sg_ladder_predict_noalloc: no staging area on this device");
+        return SG_EHIP;
+    }
+    // Host staging lives in beta_out itself (256 bytes per instance): the float features
+    // in its first 16 n bytes, the 33 float outputs in its last 132 n bytes.  Expanding
+    // instance i's outputs to doubles writes bytes [256 i, 256 i + 256), which lie below
+    // the outputs of every later instance (124 n + 132 (i + 1) >= 256 (i + 1) for i < n).
+    const size_t n = (size_t)n_inst;
+    float *hx = reinterpret_cast<float *>(beta_out);
+    float *hout = reinterpret_cast<float *>(beta_out) + 31 * n;
+    for (size_t i = 0; i < n; ++i) {
+        double f[4];
+        features_of(inst[i], f);
+        for (int k = 0; k < 4; ++k) hx[4 * i + k] = (float)f[k];
+    }
+    float *dx = m->scratch, *dout = m->scratch + (size_t)kPredictMax * 4;
+    try {
+        chk(hipMemcpyAsync(dx, hx, sizeof(float) * 4 * n, hipMemcpyHostToDevice, m->stream));
+        chk(launch_mlp_pass(m->P, dx, nullptr, nullptr, n_inst, std::min(NBLK, (int)n_inst), nullptr,
+                            nullptr, dout, nullptr, m->stream));
+        chk(hipMemcpyAsync(hout, dout, sizeof(float) * 33 * n, hipMemcpyDeviceToHost, m->stream));
+        chk(hipStreamSynchronize(m->stream));
+    } catch (const Err &e) {
+        set_global_error("sg_ladder_predict_noalloc: HIP error");
+        return e.code;
+    }
+    for (size_t i = 0; i < n; ++i) {
+        float o[33];
+        std::memcpy(o, hout + 33 * i, sizeof o);
+        for (int k = 0; k < 32; ++k) beta_out[i * 32 + k] = std::exp((double)o[k]);
+        if (cutoff_out) cutoff_out[i] = std::exp((double)o[32]);
+    }
+    set_global_error("");
     return SG_OK;
 }
 

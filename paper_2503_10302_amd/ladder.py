@@ -146,6 +146,19 @@ class Predictor:
             raise sg.SGError(rc, "sg_ladder_predict")
         return b, c
 
+    def predict_noalloc(self, instances):
+        """The same prediction through the allocation-free entry point (at most
+        sg.PREDICT_NOALLOC_MAX instances per call)."""
+        arr, keep = sg._lattices(instances)
+        b = np.zeros((len(instances), N_RUNGS), np.float64)
+        c = np.zeros(len(instances), np.float64)
+        rc = self.lib.sg_ladder_predict_noalloc(self.h, arr, len(instances),
+                                                b.ctypes.data_as(C.c_void_p),
+                                                c.ctypes.data_as(C.c_void_p))
+        if rc != sg.SG_OK:
+            raise sg.SGError(rc, self.lib.sg_last_error(None).decode())
+        return b, c
+
 
 OFF_B3 = sg.MLP_NPARAM - (N_RUNGS + 1)
 OFF_W3 = OFF_B3 - (N_RUNGS + 1) * 64

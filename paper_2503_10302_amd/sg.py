@@ -18,6 +18,7 @@ SO_PATH = os.path.join(_PKG, "libsg.so")
 SG_OK, SG_EINVAL, SG_ENOMEM, SG_EHIP, SG_ESTATE, SG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 SG_APT, SG_SQA = 1, 2
 MLP_NPARAM = 6625
+PREDICT_NOALLOC_MAX = 4096
 _NAMES = {SG_EINVAL: "SG_EINVAL", SG_ENOMEM: "SG_ENOMEM", SG_EHIP: "SG_EHIP",
           SG_ESTATE: "SG_ESTATE", SG_EUNSUPPORTED: "SG_EUNSUPPORTED"}
 
@@ -53,7 +54,7 @@ EXPORTS = [
     "sg_get_counters", "sg_get_state", "sg_set_state", "sg_timer_start", "sg_timer_stop",
     "sg_synchronize", "sg_kernel_timing", "sg_kernel_time", "sg_adaptive_ladder", "sg_mlp_create", "sg_mlp_destroy",
     "sg_instance_features", "sg_mlp_set_standardisation", "sg_mlp_loss_grad", "sg_mlp_train",
-    "sg_mlp_get_params", "sg_ladder_predict",
+    "sg_mlp_get_params", "sg_ladder_predict", "sg_ladder_predict_noalloc",
 ]
 
 _lib = None
@@ -102,6 +103,7 @@ def load():
         "sg_mlp_train": (i32, [P, P, P, i32, i32, i32, C.c_float, P]),
         "sg_mlp_get_params": (i32, [P, P]),
         "sg_ladder_predict": (i32, [P, C.POINTER(_Lattice), i32, P, P]),
+        "sg_ladder_predict_noalloc": (i32, [P, C.POINTER(_Lattice), i32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
