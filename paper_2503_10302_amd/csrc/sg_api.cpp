@@ -151,6 +151,13 @@ struct Lat {
             if (v) return true;
         return false;
     }
+    int bonds() const
+    {
+        int b = 0;
+        for (int j = 0; j < n; ++j)
+            for (int a = 0; a < 3; ++a) b += coupling(j, a, +1) != 0;
+        return b;
+    }
     int64_t max_energy_gap() const
     {
         int64_t s = 0;
@@ -308,6 +315,8 @@ struct sg_ctx {
     double sqa_beta = 0.0;
     DevBuf<uint32_t> d_sqa, d_sqa_lut;
     DevBuf<int32_t> d_slice_E;
+    DevBuf<int64_t> d_best_key;   // per instance: (E + 2^30) << 32 | (r M + k) of the lowest slice
+    DevBuf<int8_t> d_best_state;  // per instance: that slice, +1/-1 [n_max]
     size_t sqa_lds = 0;
     uint32_t sqa_steps = 0;
     int sqa_threads = 0;   // work-group size; 0: chosen by the autotuner on the next anneal
@@ -570,6 +579,7 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
         I.npad = round_up(L.n, 16);
         I.n_slots = c->n_slots;
         apt_records(L, rec, recj, I);
+        I.n_bonds = L.bonds();
         apt_rows(L, rowA, rowB, rowC, I);
         I.spin_off = spin_bytes;
         spin_bytes += (int64_t)nb4 * I.npad;
@@ -774,6 +784,7 @@ void create_sqa(sg_ctx *c, const sg_config *cfg)
         I.npad = round_up(L.n, 16);
         I.n_slots = c->M;
         sqa_records(L, rec, recj, I);
+        I.n_bonds = L.bonds();
         I.spin_off = words;
         words += (int64_t)c->R * I.npad * 2;
         npad_max = std::max(npad_max, I.npad);
@@ -784,6 +795,8 @@ void create_sqa(sg_ctx *c, const sg_config *cfg)
     c->d_recj.upload(recj, s, "records");
     c->d_sqa.alloc((size_t)words, "spins");
     c->d_slice_E.alloc((size_t)c->n_inst * c->R * c->M, "slice energies");
+    c->d_best_key.alloc((size_t)c->n_inst, "best slices");
+    c->d_best_state.alloc((size_t)c->n_inst * c->n_max, "best slices");
     c->d_ctr.alloc(8, "counters");
     hip_check(launch_fill_u32(c->d_ctr.p, 0u, 8, s), "init");
     if (c->nl > 256) fail(SG_EUNSUPPORTED, "field range too large for the threshold table");
@@ -815,6 +828,7 @@ SqaArgs sqa_args(sg_ctx *c)
     a.H = c->H;
     a.smax = c->smax;
     a.nl = c->nl;
+    a.no_field = c->hmax == 0 ? 1 : 0;
     a.key0 = c->key0;
     a.key1 = c->key1;
     return a;
@@ -1226,6 +1240,10 @@ sg_status sg_sqa_anneal(sg_ctx *c, const double *gamma, int32_t n_steps, int64_t
             a.lut_step0 = 0;
             a.do_energy = (done + ns == n_steps) ? 1 : 0;
             if (c->sqa_threads == 0) sqa_autotune(c, a, ns);
+            if (a.do_energy) {
+                hip_check(launch_fill_i64(c->d_best_key.p, -1, c->n_inst, c->stream), "anneal");
+                a.best_key = (uint64_t *)c->d_best_key.p;
+            }
             kernel_event(c, true);
             hip_check(launch_sqa(a, c->n_inst, c->sqa_lds, c->sqa_threads, c->stream),
                       "anneal");
@@ -1234,37 +1252,31 @@ sg_status sg_sqa_anneal(sg_ctx *c, const double *gamma, int32_t n_steps, int64_t
             done += ns;
         }
         if (n_steps == 0) {
+            hip_check(launch_fill_i64(c->d_best_key.p, -1, c->n_inst, c->stream), "anneal");
             SqaArgs a = sqa_args(c);
             a.n_steps = 0;
             a.do_energy = 1;
+            a.best_key = (uint64_t *)c->d_best_key.p;
             hip_check(launch_sqa(a, c->n_inst, c->sqa_lds, sqa_threads_or_default(c), c->stream),
                       "anneal");
         }
+        // Alg. S1, last lines: the lowest slice energy of every instance and its state, both
+        // reduced on the device (the energy pass keeps an atomic minimum per instance)
         if (best_E || best_state) {
-            const int RM = c->R * c->M;
-            std::vector<int32_t> e((size_t)c->n_inst * RM);
-            c->d_slice_E.download(e.data(), e.size(), c->stream, "anneal");
-            hip_check(hipStreamSynchronize(c->stream), "anneal");
-            for (int i = 0; i < c->n_inst; ++i) {
-                int arg = 0;
-                for (int q = 1; q < RM; ++q)
-                    if (e[(size_t)i * RM + q] < e[(size_t)i * RM + arg]) arg = q;
-                if (best_E) best_E[i] = e[(size_t)i * RM + arg];
-                if (best_state) {
-                    const InstDev &I = c->idev[i];
-                    const int r = arg / c->M, k = arg % c->M;
-                    std::vector<uint32_t> w((size_t)I.npad * 2);
-                    hip_check(hipMemcpyAsync(w.data(),
-                                             c->d_sqa.p + I.spin_off + (int64_t)r * I.npad * 2,
-                                             w.size() * 4, hipMemcpyDeviceToHost, c->stream),
-                              "best state");
-                    hip_check(hipStreamSynchronize(c->stream), "best state");
-                    int8_t *o = best_state + (size_t)i * c->n_max;
-                    std::memset(o, 0, (size_t)c->n_max);
-                    for (int j = 0; j < I.n; ++j)
-                        o[j] = ((w[2 * j + (k & 1)] >> (k >> 1)) & 1u) ? 1 : -1;
-                }
+            if (best_state) {
+                SqaArgs a = sqa_args(c);
+                a.best_key = (uint64_t *)c->d_best_key.p;
+                hip_check(launch_sqa_best_state(a, c->n_inst, c->n_max, c->d_best_state.p, c->stream),
+                          "best state");
+                c->d_best_state.download(best_state, (size_t)c->n_inst * c->n_max, c->stream,
+                                         "best state");
             }
+            std::vector<int64_t> key((size_t)c->n_inst);
+            c->d_best_key.download(key.data(), key.size(), c->stream, "anneal");
+            hip_check(hipStreamSynchronize(c->stream), "anneal");
+            if (best_E)
+                for (int i = 0; i < c->n_inst; ++i)
+                    best_E[i] = (int64_t)(uint32_t)((uint64_t)key[i] >> 32) - 0x40000000;
         }
     });
 }

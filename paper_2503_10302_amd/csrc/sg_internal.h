@@ -63,6 +63,7 @@ struct InstDev {
     int32_t ly, lz;      // y and z extents (rows are r = y + ly z)
     int32_t planes;      // 1: every y-z plane's rows fit one per lane in one wave and all
                          //    planes in the work-group's waves (wave-local cluster search)
+    int32_t n_bonds;     // bonds with J != 0 (each counted once)
 };
 
 // Row tables of an instance for the cluster search (rows of lx <= 32 sites):
@@ -157,8 +158,13 @@ struct SqaArgs {
     int32_t n_steps;
     int32_t lut_step0;         // row of lut used for the first step
     int32_t do_energy;
+    int32_t no_field;          // 1: every field is zero (bit-sliced energy readout)
+    uint64_t *best_key;        // [inst] or null: atomic minimum of (E + 2^30) << 32 | (r M + k)
+                               // over the slices of the energy pass (ties: lowest r M + k)
     uint32_t key0, key1;
 };
+
+constexpr int kSqaPlanes = 10;   // bits of the readout's per-thread unsatisfied-bond counters
 
 // Adaptive-ladder stage with the chains bit-packed: word w of a site holds chains
 // 32 w .. 32 w + 31 of its instance (bit b = chain 32 w + b; 1 = up), all at the
@@ -190,6 +196,9 @@ hipError_t launch_sqa_init(const SqaArgs &a, int n_inst, hipStream_t s);
 // DT-SQA kernel with a work-group of `threads` (a multiple of 64 in 128..1024).
 bool sqa_config_valid(int threads);
 hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, int threads, hipStream_t s);
+// The slice chosen by best_key[i] of every instance as +1/-1 bytes, out[i][n_max].
+hipError_t launch_sqa_best_state(const SqaArgs &a, int n_inst, int n_max, int8_t *out,
+                                 hipStream_t s);
 hipError_t launch_adapt_init(const AdaptArgs &a, int n_inst, hipStream_t s);
 hipError_t launch_adapt(const AdaptArgs &a, int n_inst, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);

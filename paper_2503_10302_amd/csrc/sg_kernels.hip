@@ -1383,6 +1383,56 @@ __device__ __forceinline__ void sqa_site(const SqaArgs &A, const uint4 rr, uint3
     sp[2 * j + P] = res & mask;
 }
 
+// Unsatisfied bonds of every slice of one replica (no fields): the calling thread folds the
+// forward bonds of its sites (j = tid, tid + threads, ...), 32 slices per parity word, into
+// P-bit vertical counters (plane q = bit q of every slice's count); the wave then reads plane
+// q of slice bit h across its 64 lanes with one ballot.  Returns, in lane k = 2h + p of each
+// wave, that wave's count for slice k (0 in lanes >= 2H).
+template <int P>
+__device__ __forceinline__ int32_t sqa_unsat_counts(const uint4 *recj, const uint32_t *sp, int n,
+                                                    int threads, uint32_t mask, int H)
+{
+    uint32_t v0[P], v1[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) v0[q] = v1[q] = 0u;
+    for (int j = threadIdx.x; j < n; j += threads) {
+        const uint4 rr = recj[j];
+        const uint32_t jn = rr.x >> 19, w0 = sp[2 * j], w1 = sp[2 * j + 1];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const uint32_t nb = a == 0 ? (rr.y & 0xFFFFu) : (a == 1 ? (rr.z & 0xFFFFu) : (rr.w & 0xFFFFu));
+            // no bond (dummy neighbour): nothing to count
+            const uint32_t live = nb == (uint32_t)n ? 0u : mask;
+            const uint32_t neg = 0u - ((jn >> (2 * a)) & 1u);
+            uint32_t c0 = (w0 ^ sp[2 * nb] ^ neg) & live;
+            uint32_t c1 = (w1 ^ sp[2 * nb + 1] ^ neg) & live;
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                const uint32_t d0 = v0[q] & c0, d1 = v1[q] & c1;
+                v0[q] ^= c0;
+                v1[q] ^= c1;
+                c0 = d0;
+                c1 = d1;
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63;
+    int32_t mine = 0;
+#pragma unroll
+    for (int h = 0; h < 32; ++h) {
+        if (h >= H) break;
+        int32_t u0 = 0, u1 = 0;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            u0 += (int32_t)__popcll(__ballot((v0[q] >> h) & 1u)) << q;
+            u1 += (int32_t)__popcll(__ballot((v1[q] >> h) & 1u)) << q;
+        }
+        mine = lane == 2 * h ? u0 : mine;
+        mine = lane == 2 * h + 1 ? u1 : mine;
+    }
+    return mine;
+}
+
 // The work-group size is a launch-time choice (a multiple of 64, at most 1024);
 // waves are limited to 64 VGPRs (8 waves per SIMD).
 template <int NG, bool SCALED>
@@ -1475,7 +1525,26 @@ void sqa_kernel(SqaArgs A)
     }
     __syncthreads();
     for (int i = tid; i < 2 * npad; i += THREADS) g[i] = sp[i];
-    if (A.do_energy) {
+    if (A.do_energy && A.no_field) {
+        // Energy (Eq. 8, original couplings, no fields) of every slice k = 2h + p:
+        // E_k = 2 U_k - bonds with U_k the number of unsatisfied bonds, counted bit-sliced
+        // per wave (sqa_unsat_counts) and summed over the waves in red[k].
+        const int M = A.M;
+        for (int k = tid; k < M; k += THREADS) red[k] = 0;
+        const int per = 3 * ((n + THREADS - 1) / THREADS);
+        const int lane = tid & 63;
+        const uint4 *recj = A.rec_j + I.recj_off;
+        const int32_t mine = per < 32 ? sqa_unsat_counts<5>(recj, sp, n, THREADS, mask, H)
+                                      : sqa_unsat_counts<kSqaPlanes>(recj, sp, n, THREADS, mask, H);
+        __syncthreads();
+        if (lane < M) atomicAdd(&red[lane], mine);
+        __syncthreads();
+        for (int k = tid; k < M; k += THREADS) {
+            const int32_t e = 2 * red[k] - I.n_bonds;
+            A.slice_E[((int64_t)inst * A.R + r) * M + k] = e;
+            red[64 + k] = e;
+        }
+    } else if (A.do_energy) {
         // Energy (Eq. 8, original couplings) of every slice k, threads split over (k, sites).
         const int M = A.M;
         for (int k = tid; k < 2 * M; k += THREADS) red[k] = 0;
@@ -1503,9 +1572,42 @@ void sqa_kernel(SqaArgs A)
             atomicAdd(&red[k], acc);
         }
         __syncthreads();
-        for (int k = tid; k < M; k += THREADS)
-            A.slice_E[((int64_t)inst * A.R + r) * M + k] = -red[k] / 2;
+        for (int k = tid; k < M; k += THREADS) {
+            const int32_t e = -red[k] / 2;
+            A.slice_E[((int64_t)inst * A.R + r) * M + k] = e;
+            red[64 + k] = e;
+        }
     }
+    if (A.do_energy && A.best_key) {
+        // this replica's lowest slice energy (ties: lowest slice), then the instance minimum
+        __syncthreads();
+        if (tid < 64) {
+            uint64_t key = ~0ull;
+            if (tid < A.M)
+                key = ((uint64_t)(uint32_t)(red[64 + tid] + 0x40000000) << 32) |
+                      (uint32_t)(r * A.M + tid);
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) {
+                const uint64_t o = __shfl_xor(key, d, 64);
+                key = o < key ? o : key;
+            }
+            if (tid == 0) atomicMin((unsigned long long *)&A.best_key[inst], (unsigned long long)key);
+        }
+    }
+}
+
+// Spins of the slice that best_key[i] names (replica r, slice k = 2h + p: bit h of word p),
+// as +1/-1, one work-group per instance.
+__global__ __launch_bounds__(256) void sqa_best_state_kernel(SqaArgs A, int n_max, int8_t *out)
+{
+    const int inst = blockIdx.x;
+    const InstDev I = A.inst[inst];
+    const uint32_t q = (uint32_t)A.best_key[inst];
+    const int r = (int)(q / (uint32_t)A.M), k = (int)(q % (uint32_t)A.M);
+    const uint32_t *g = A.spins + I.spin_off + (int64_t)r * I.npad * 2;
+    int8_t *o = out + (int64_t)inst * n_max;
+    for (int j = threadIdx.x; j < n_max; j += 256)
+        o[j] = j < I.n ? (((g[2 * j + (k & 1)] >> (k >> 1)) & 1u) ? 1 : -1) : 0;
 }
 
 __global__ void advance_kernel(uint32_t *ctr, uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3)
@@ -1860,6 +1962,13 @@ hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, int thread
     if (ngrp == 2 && scaled) return launch_sqa_t<2, true>(a, n_inst, lds_bytes, threads, s);
     return scaled ? launch_sqa_t<0, true>(a, n_inst, lds_bytes, threads, s)
                   : launch_sqa_t<0, false>(a, n_inst, lds_bytes, threads, s);
+}
+
+hipError_t launch_sqa_best_state(const SqaArgs &a, int n_inst, int n_max, int8_t *out,
+                                 hipStream_t s)
+{
+    hipLaunchKernelGGL(sqa_best_state_kernel, dim3(n_inst), dim3(256), 0, s, a, n_max, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_adapt_init(const AdaptArgs &a, int n_inst, hipStream_t s)

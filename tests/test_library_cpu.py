@@ -100,13 +100,15 @@ def test_bench_roofline_accounting():
     assert abs(b.alg_ops_per_flip(8) - (65 / 4 + 5 / 32 + 1)) < 1e-12
     assert abs(b.VALU_PEAK_TOPS - 78.6432) < 1e-9
     t = b.SQA_TRAFFIC
-    ok = b.sqa_traffic(t["R"], t["steps"])
-    if b.sqa_kernel_source_hash() == t["kernel_src_sha256_16"]:
-        assert ok == round((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024)
-    else:
-        assert ok is None   # counters taken on another version of the kernel are not reported
-    assert b.sqa_traffic(t["R"] // 2, t["steps"]) is None
-    assert b.sqa_traffic(t["R"], t["steps"] + 1) is None
+    current = b.sqa_kernel_source_hash() == t["kernel_src_sha256_16"]
+    for steps, m in t["by_steps"].items():
+        v = b.sqa_traffic(t["R"], steps)
+        if current:
+            assert v == round((m["fetch_kib"] * t["fetch_scale"] + m["write_kib"] * t["write_scale"]) * 1024)
+        else:
+            assert v is None   # counters taken on another version of the kernel are not reported
+        assert b.sqa_traffic(t["R"] // 2, steps) is None
+    assert b.sqa_traffic(t["R"], 1 + max([0] + list(t["by_steps"]))) is None
 
 
 def test_instance_features_equal_the_oracle():
