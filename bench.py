@@ -322,6 +322,64 @@ def sqa_study(Rs=(64, 256, 1024), lengths=(1000, 3000, 10000), e0_cycles=30000,
             "mean_E0_per_spin": round(float(E0.mean()) / n, 6), "runs": table}
 
 
+def apt_ablation(n_inst=128, L=8, budget=100000,
+                 points=(100, 300, 1000, 3000, 10000, 30000, 100000), seed0=60000):
+    """Supplementary APT+ICM ablations on instances of the plain-APT shape (L = 8 periodic +-J,
+    32 betas geometric in [0.2, 3.0], ICM at beta >= 1): the residual energy per spin (Eq. 2)
+    rho(t_a) = mean over instances of (lowest energy seen up to t_a MCS - E0) / n, for
+      * APT with and without ICM, four labels; two vs four labels (Fig. S14);
+      * zero, one and two Houdayer moves per temperature per sweep, four labels, and two
+        labels (Fig. S15);
+      * sweep-to-swap ratios 1, 10 and 516, four labels (Fig. S16).
+    Every variant runs all instances in one batched context for `budget` sweeps per replica;
+    energies are recorded at every swap attempt, so the ratio-516 runs have no record before
+    516 MCS.  E0 per instance: the lowest energy of every run here and of one reference run of
+    3 x budget sweeps (four labels, two moves); the paper's instances are not available."""
+    from paper_2503_10302_amd import sg
+    from paper_2503_10302_amd.inputs import ej_couplings, geometric_ladder
+    insts = [(ej_couplings(L, 7, seed=seed0 + i)[0], 7, None) for i in range(n_inst)]
+    beta = geometric_ladder(32, 0.2, 3.0)
+    n = L ** 3
+    variants = [("4 labels, 2 ICM per sweep, ratio 1", 4, 2, 1.0, 1),
+                ("4 labels, 1 ICM per sweep, ratio 1", 4, 1, 1.0, 1),
+                ("4 labels, no ICM, ratio 1", 4, 2, float("inf"), 1),
+                ("2 labels, ICM, ratio 1", 2, 2, 1.0, 1),
+                ("2 labels, no ICM, ratio 1", 2, 2, float("inf"), 1),
+                ("4 labels, 2 ICM per sweep, ratio 10", 4, 2, 1.0, 10),
+                ("4 labels, 2 ICM per sweep, ratio 516", 4, 2, 1.0, 516)]
+    runs = {}
+    for k, (name, reps, pairs, cut, S) in enumerate(variants):
+        c = sg.apt(insts, beta, seed=7000 + k, reps_per_beta=reps)
+        cycles = budget // S
+        c.synchronize()
+        c.timer_start()
+        tr = c.run_apt_ex(cycles, S, cut, pairs, record_every=1)
+        ms = c.timer_stop()
+        c.close()
+        runs[name] = (S, tr, ms)
+        print(f"ablation: {name} done ({ms / 1e3:.2f} s)", file=sys.stderr, flush=True)
+    c = sg.apt(insts, beta, seed=6999, reps_per_beta=4)
+    c.run_apt_ex(3 * budget, 1, 1.0, 2)
+    E0 = c.best()
+    c.close()
+    for S, tr, _ in runs.values():
+        E0 = np.minimum(E0, tr[:, -1])
+    table = {}
+    for name, (S, tr, ms) in runs.items():
+        row = {}
+        for ta in points:
+            k = ta // S
+            row[str(ta)] = None if k < 1 else round(float(np.mean((tr[:, k - 1] - E0) / n)), 6)
+        row["at_E0"] = int((tr[:, -1] == E0).sum())
+        row["wall_s"] = round(ms / 1e3, 3)
+        table[name] = row
+    return {"metric": "APT+ICM ablations: residual energy per spin rho(t_a) at t_a MCS "
+                      f"({n_inst} periodic L={L} +-J instances, 32 geometric betas in [0.2, 3.0], "
+                      "ICM at beta >= 1)",
+            "e0": f"min over every run and a {3 * budget}-sweep reference run (4 labels, 2 ICM)",
+            "rho": table}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -348,6 +406,9 @@ def main():
     ap.add_argument("--sqa-study", action="store_true",
                     help="DT-SQA residual energy per spin against R (64, 256, 1024) and annealing "
                          "steps (1e3, 3e3, 1e4) on the L=15 extreme-value workload")
+    ap.add_argument("--ablation", action="store_true",
+                    help="APT+ICM ablations: ICM on/off, labels, ICMs per sweep, sweep-to-swap ratio")
+    ap.add_argument("--ablation-L", type=int, default=8)
     ap.add_argument("--valu-rates", action="store_true",
                     help="compile and run bench_valu.hip: issue rate of single VALU instruction "
                          "forms (the evidence for the ALU peak)")
@@ -374,6 +435,9 @@ def main():
 
     if args.ttt:
         print(json.dumps(time_to_target(e0_cycles=args.ttt_cycles)), flush=True)
+        return
+    if args.ablation:
+        print(json.dumps(apt_ablation(L=args.ablation_L)), flush=True)
         return
     if args.sqa_study:
         print(json.dumps(sqa_study(e0_cycles=args.ttt_cycles)), flush=True)

@@ -125,6 +125,26 @@ sg_status sg_swap(sg_ctx *ctx, int32_t *accepted_host);
 sg_status sg_run_apt(sg_ctx *ctx, int64_t n_cycles, int32_t sweeps_per_swap, double icm_cutoff,
                      int32_t record_every, int64_t *best_trace);
 
+/* Options of the APT main loop and of the ICM call beyond those of sg_run_apt / sg_icm:
+ * per-instance ICM cutoffs (a learned ladder predicts one per instance) and the number
+ * of Houdayer moves per temperature per call with four labels (Supplementary comparison
+ * of APT with zero, one and two ICMs per sweep: two moves both pairs of the drawn
+ * matching, one moves one of them, chosen at random).  With two labels there is one
+ * pair and both values give one move; no ICM is icm_cutoff = +inf. */
+typedef struct {
+    int32_t sweeps_per_swap;            /* >= 1 (sg_run_apt_ex only) */
+    int32_t icm_pairs;                  /* 2 or 1 */
+    double icm_cutoff;                  /* ICM at beta >= icm_cutoff, all instances ... */
+    const double *icm_cutoff_per_inst;  /* ... or [n_inst] per instance (nullable) */
+    int32_t record_every;               /* as in sg_run_apt (sg_run_apt_ex only) */
+} sg_apt_options;
+/* sg_run_apt with these options; sg_run_apt(c, n, s, cut, r, t) equals sg_run_apt_ex with
+ * {s, 2, cut, NULL, r}.  SG_EINVAL for icm_pairs outside {1, 2} or a NaN cutoff. */
+sg_status sg_run_apt_ex(sg_ctx *ctx, int64_t n_cycles, const sg_apt_options *opt,
+                        int64_t *best_trace);
+/* sg_icm with these options (sweeps_per_swap and record_every are ignored). */
+sg_status sg_icm_ex(sg_ctx *ctx, const sg_apt_options *opt, int32_t *info_host);
+
 /* APT: running minimum energy per instance since creation [n_inst]. */
 sg_status sg_best(sg_ctx *ctx, int64_t *best_host);
 

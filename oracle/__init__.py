@@ -78,10 +78,10 @@ def lib():
             "sgo_swap_accept": (i32, [dbl, dbl, i64, i64, u32]),
             "sgo_apt_init": (None, [LP, u32, i32, u64, u32, P]),
             "sgo_apt_sweep": (None, [LP, u32, i32, P, u64, u32, u32, P]),
-            "sgo_apt_icm": (i32, [LP, u32, i32, i32, P, dbl, u64, u32, P, P]),
+            "sgo_apt_icm": (i32, [LP, u32, i32, i32, P, dbl, i32, u64, u32, P, P]),
             "sgo_apt_swap": (None, [u32, i32, i32, P, u64, u32, i32, P, P, P]),
-            "sgo_apt_run": (i32, [LP, u32, i32, i32, P, u64, i64, i32, dbl, i32, P, P, P, P,
-                                  P, P]),
+            "sgo_apt_run": (i32, [LP, u32, i32, i32, P, u64, i64, i32, dbl, i32, i32, P, P, P,
+                                  P, P, P]),
             "sgo_sqa_init": (None, [LP, u32, i32, i32, i32, u64, P]),
             "sgo_sqa_step": (None, [LP, u32, i32, i32, i32, dbl, dbl, u64, u32, P]),
             "sgo_sqa_anneal": (None, [LP, u32, i32, i32, i32, dbl, P, i32, u64, u32, P, P, P, P]),
@@ -184,12 +184,12 @@ def apt_sweep(lat, inst, slot_beta, seed, t, spins, tag=TAG_APT_SWEEP):
     return spins
 
 
-def apt_icm(lat, inst, beta, R_lab, cutoff, seed, a, spins):
+def apt_icm(lat, inst, beta, R_lab, cutoff, seed, a, spins, pairs_per_call=2):
     b = np.ascontiguousarray(beta, dtype=np.float64)
     npair = max(1, R_lab // 2)
     info = np.full((b.size, npair, 4), -7, np.int32)
-    rc = lib().sgo_apt_icm(lat.c, inst, b.size, R_lab, _ptr(b), float(cutoff), seed, a,
-                           _ptr(spins), _ptr(info))
+    rc = lib().sgo_apt_icm(lat.c, inst, b.size, R_lab, _ptr(b), float(cutoff), int(pairs_per_call),
+                           seed, a, _ptr(spins), _ptr(info))
     return rc, info
 
 
@@ -202,14 +202,14 @@ def apt_swap(inst, beta, R_lab, seed, a, spins, E):
 
 
 def apt_run(lat, inst, beta, R_lab, seed, n_cycles, sweeps_per_swap, cutoff, record_every,
-            counters, spins, E, best):
+            counters, spins, E, best, icm_pairs=2):
     """APT cycles in place.  counters: uint32[3]; E: int64[n_slots]; best: int64[1]."""
     b = np.ascontiguousarray(beta, dtype=np.float64)
     ntr = n_cycles // record_every if record_every > 0 else 0
     trace = np.zeros(max(ntr, 1), np.int64)
     accc = np.zeros(max((b.size - 1) * R_lab, 1), np.int64)
     rc = lib().sgo_apt_run(lat.c, inst, b.size, R_lab, _ptr(b), seed, n_cycles, sweeps_per_swap,
-                           float(cutoff), record_every, _ptr(counters), _ptr(spins), _ptr(E),
+                           float(cutoff), int(icm_pairs), record_every, _ptr(counters), _ptr(spins), _ptr(E),
                            _ptr(best), _ptr(trace), _ptr(accc))
     return rc, trace[:ntr], accc
 

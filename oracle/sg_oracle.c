@@ -243,6 +243,9 @@ void sgo_apt_sweep(const sgo_lattice *lat, uint32_t inst, int32_t n_slots,
  * replicas or, when it holds more than half of the sites, one replica chosen
  * at random is flipped entirely.  Pairs: 2 labels -> (0,1); 4 labels -> one
  * of the three perfect matchings drawn at random (Methods, "APT details").
+ * pairs_per_call (4 labels): 2 moves both pairs of the matching, 1 moves one of
+ * the two, drawn at random (the Supplementary comparison of one and two ICMs per
+ * sweep); the pair not moved gets the "not applied" record.
  * info[(b * npair + pi) * 4 + {0..3}] = (m, seed site, |C|, branch) with
  * branch 0 = cluster, 1 = whole first replica, 2 = whole second; -1 when the
  * temperature is below the cutoff.  Returns 0, or -5 when some pair would be
@@ -251,8 +254,8 @@ void sgo_apt_sweep(const sgo_lattice *lat, uint32_t inst, int32_t n_slots,
 static const int32_t PAIRINGS[3][2][2] = {{{0, 1}, {2, 3}}, {{0, 2}, {1, 3}}, {{0, 3}, {1, 2}}};
 
 int32_t sgo_apt_icm(const sgo_lattice *lat, uint32_t inst, int32_t n_beta, int32_t R_lab,
-                    const double *beta, double cutoff, uint64_t seed, uint32_t a,
-                    int8_t *spins, int32_t *info)
+                    const double *beta, double cutoff, int32_t pairs_per_call, uint64_t seed,
+                    uint32_t a, int8_t *spins, int32_t *info)
 {
     int32_t n = sgo_n_sites(lat);
     if (R_lab != 2 && R_lab != 4) return 0;
@@ -265,14 +268,16 @@ int32_t sgo_apt_icm(const sgo_lattice *lat, uint32_t inst, int32_t n_beta, int32
     int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     char *inC = (char *)malloc((size_t)n);
     for (int32_t b = 0; b < n_beta; ++b) {
-        int32_t pairing = 0;
+        int32_t pairing = 0, only = -1;
         if (R_lab == 4) {
             uint32_t w = sgo_word(seed, (uint32_t)b, a, 0u, inst, SGO_TAG_ICM_PAIR, 0);
             pairing = (int32_t)(((uint64_t)w * 3u) >> 32);
+            if (pairs_per_call == 1)
+                only = (int32_t)(sgo_word(seed, (uint32_t)b, a, 0u, inst, SGO_TAG_ICM_PAIR, 1) >> 31);
         }
         for (int32_t pi = 0; pi < npair; ++pi) {
             int32_t *rec = info ? info + ((int64_t)b * npair + pi) * 4 : NULL;
-            if (!(beta[b] >= cutoff)) {
+            if (!(beta[b] >= cutoff) || (only >= 0 && pi != only)) {
                 if (rec) rec[0] = rec[1] = rec[2] = rec[3] = -1;
                 continue;
             }
@@ -362,15 +367,16 @@ void sgo_apt_swap(uint32_t inst, int32_t n_beta, int32_t R_lab, const double *be
 }
 
 /* APT main loop of Algorithm S2 for one instance.  One cycle =
- * sweeps_per_swap sweeps, one ICM call (pairs at beta >= cutoff), energies,
+ * sweeps_per_swap sweeps, one ICM call (pairs at beta >= cutoff, icm_pairs as
+ * in sgo_apt_icm), energies,
  * one swap attempt, then the running minimum energy.  counters =
  * {sweeps done, ICM calls done, swap attempts done} are read and advanced.
  * accept_count[(n_beta-1) * R_lab] accumulates accepted swaps (nullable). */
 int32_t sgo_apt_run(const sgo_lattice *lat, uint32_t inst, int32_t n_beta, int32_t R_lab,
                     const double *beta, uint64_t seed, int64_t n_cycles,
-                    int32_t sweeps_per_swap, double icm_cutoff, int32_t record_every,
-                    uint32_t *counters, int8_t *spins, int64_t *E, int64_t *best,
-                    int64_t *best_trace, int64_t *accept_count)
+                    int32_t sweeps_per_swap, double icm_cutoff, int32_t icm_pairs,
+                    int32_t record_every, uint32_t *counters, int8_t *spins, int64_t *E,
+                    int64_t *best, int64_t *best_trace, int64_t *accept_count)
 {
     int32_t n = sgo_n_sites(lat);
     int32_t n_slots = n_beta * R_lab;
@@ -382,8 +388,8 @@ int32_t sgo_apt_run(const sgo_lattice *lat, uint32_t inst, int32_t n_beta, int32
         for (int32_t i = 0; i < sweeps_per_swap; ++i)
             sgo_apt_sweep(lat, inst, n_slots, slot_beta, seed, SGO_TAG_APT_SWEEP,
                           counters[0]++, spins);
-        rc = sgo_apt_icm(lat, inst, n_beta, R_lab, beta, icm_cutoff, seed, ++counters[1],
-                         spins, NULL);
+        rc = sgo_apt_icm(lat, inst, n_beta, R_lab, beta, icm_cutoff, icm_pairs, seed,
+                         ++counters[1], spins, NULL);
         if (rc) break;
         for (int32_t s = 0; s < n_slots; ++s) E[s] = sgo_energy(lat, spins + (int64_t)s * n);
         sgo_apt_swap(inst, n_beta, R_lab, beta, seed, ++counters[2], n, spins, E, acc);

@@ -73,16 +73,16 @@ void sgo_apt_sweep(const sgo_lattice *lat, uint32_t inst, int32_t n_slots,
                    const double *slot_beta, uint64_t seed, uint32_t tag, uint32_t t,
                    int8_t *spins);
 int32_t sgo_apt_icm(const sgo_lattice *lat, uint32_t inst, int32_t n_beta, int32_t R_lab,
-                    const double *beta, double cutoff, uint64_t seed, uint32_t a,
-                    int8_t *spins, int32_t *info);
+                    const double *beta, double cutoff, int32_t pairs_per_call, uint64_t seed,
+                    uint32_t a, int8_t *spins, int32_t *info);
 void sgo_apt_swap(uint32_t inst, int32_t n_beta, int32_t R_lab, const double *beta,
                   uint64_t seed, uint32_t a, int32_t n, int8_t *spins, int64_t *E,
                   int32_t *accepted);
 int32_t sgo_apt_run(const sgo_lattice *lat, uint32_t inst, int32_t n_beta, int32_t R_lab,
                     const double *beta, uint64_t seed, int64_t n_cycles,
-                    int32_t sweeps_per_swap, double icm_cutoff, int32_t record_every,
-                    uint32_t *counters, int8_t *spins, int64_t *E, int64_t *best,
-                    int64_t *best_trace, int64_t *accept_count);
+                    int32_t sweeps_per_swap, double icm_cutoff, int32_t icm_pairs,
+                    int32_t record_every, uint32_t *counters, int8_t *spins, int64_t *E,
+                    int64_t *best, int64_t *best_trace, int64_t *accept_count);
 
 /* ---- DT-SQA (one instance, replicas r0 .. r0+R-1, spins [R][M][n]) ---- */
 void sgo_sqa_init(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t r0, int32_t R,

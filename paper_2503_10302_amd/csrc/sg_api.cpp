@@ -303,10 +303,10 @@ struct sg_ctx {
     DevBuf<uint4> d_rowA, d_rowB, d_rowC;
     int n_blocks = 0;
     size_t quad_lds = 0;
-    double icm_cutoff_loaded = std::numeric_limits<double>::quiet_NaN();
+    std::vector<double> icm_cutoff_loaded;   // per instance, as last uploaded into d_icm_on
     // graph cache for APT cycles
     hipGraphExec_t gexec = nullptr;
-    int g_sweeps = -1, g_icm = -1, g_record = -1, g_cycles = 0;
+    int g_sweeps = -1, g_icm = -1, g_record = -1, g_cycles = 0, g_pairs = -1;
     int64_t *g_trace = nullptr;
     int g_trace_cap = 0;
 
@@ -662,11 +662,12 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
     hip_check(launch_apt_quad(a, c->quad_lds, s), "initial energies");
 }
 
-void upload_icm_flags(sg_ctx *c, double cutoff)
+// ICM applies at (instance i, temperature b) when beta[i][b] >= cutoff[i].
+void upload_icm_flags(sg_ctx *c, const std::vector<double> &cutoff)
 {
     if (c->icm_cutoff_loaded == cutoff) return;
     std::vector<uint8_t> on((size_t)c->n_inst * c->n_beta);
-    for (size_t i = 0; i < on.size(); ++i) on[i] = c->beta[i] >= cutoff ? 1 : 0;
+    for (size_t i = 0; i < on.size(); ++i) on[i] = c->beta[i] >= cutoff[i / c->n_beta] ? 1 : 0;
     c->d_icm_on.upload(on.data(), on.size(), c->stream, "icm flags");
     hip_check(hipStreamSynchronize(c->stream), "icm flags");
     c->icm_cutoff_loaded = cutoff;
@@ -699,6 +700,7 @@ AptArgs apt_args(sg_ctx *c, int n_sweeps, int do_icm)
     a.do_energy = 1;
     a.mom_from = -1;
     a.reps = c->reps;
+    a.icm_pairs = 2;
     a.imax = c->imax;
     a.ni = c->ni;
     a.cyc_k = 0;
@@ -741,13 +743,23 @@ void require(sg_ctx *c, int mode)
     if (c->mode != mode) fail(SG_ESTATE, "call does not match the context mode");
 }
 
-// ICM would move some pair: two or more labels and a temperature >= cutoff.
-bool icm_applies(const sg_ctx *c, double cutoff)
+// ICM would move some pair: two or more labels and a temperature >= its instance's cutoff.
+bool icm_applies(const sg_ctx *c, const std::vector<double> &cutoff)
 {
     if (c->reps < 2) return false;
-    for (double b : c->beta)
-        if (b >= cutoff) return true;
+    for (size_t i = 0; i < c->beta.size(); ++i)
+        if (c->beta[i] >= cutoff[i / c->n_beta]) return true;
     return false;
+}
+
+// Per-instance ICM cutoffs from one value or an array (validated: no NaN).
+std::vector<double> cutoffs_of(const sg_ctx *c, double all, const double *per_inst)
+{
+    std::vector<double> v((size_t)c->n_inst, all);
+    if (per_inst) v.assign(per_inst, per_inst + c->n_inst);
+    for (double x : v)
+        if (std::isnan(x)) fail(SG_EINVAL, "ICM cutoff is NaN");
+    return v;
 }
 
 bool any_field(const sg_ctx *c)
@@ -1007,26 +1019,50 @@ sg_status sg_sweep(sg_ctx *c, int32_t n_sweeps)
     });
 }
 
+}  // extern "C"
+
+namespace {
+
+void icm_call(sg_ctx *c, const std::vector<double> &cut, int icm_pairs, int32_t *info_host)
+{
+    if (icm_pairs != 1 && icm_pairs != 2) fail(SG_EINVAL, "icm_pairs must be 1 or 2");
+    if (icm_applies(c, cut) && any_field(c))
+        fail(SG_EUNSUPPORTED, "ICM with non-zero fields is not supported");
+    upload_icm_flags(c, cut);
+    hip_check(launch_fill_u32((uint32_t *)c->d_icm_info.p, 0xFFFFFFFFu, (int64_t)c->d_icm_info.n,
+                              c->stream),
+              "icm");
+    AptArgs a = apt_args(c, 0, 1);
+    a.icm_pairs = icm_pairs;
+    hip_check(launch_apt_quad(a, c->quad_lds, c->stream), "icm");
+    hip_check(launch_advance(c->d_ctr.p, 0u, 1u, 0u, 0u, c->stream), "icm");
+    if (info_host) {
+        c->d_icm_info.download(info_host, c->d_icm_info.n, c->stream, "icm info");
+        hip_check(hipStreamSynchronize(c->stream), "icm");
+        if (c->reps == 1)
+            for (size_t i = 0; i < c->d_icm_info.n; ++i) info_host[i] = -1;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
 sg_status sg_icm(sg_ctx *c, double cutoff, int32_t *info_host)
 {
     return guarded(c, [&] {
         require(c, SG_APT);
-        if (std::isnan(cutoff)) fail(SG_EINVAL, "cutoff is NaN");
-        if (icm_applies(c, cutoff) && any_field(c))
-            fail(SG_EUNSUPPORTED, "ICM with non-zero fields is not supported");
-        upload_icm_flags(c, cutoff);
-        hip_check(launch_fill_u32((uint32_t *)c->d_icm_info.p, 0xFFFFFFFFu, (int64_t)c->d_icm_info.n,
-                                  c->stream),
-                  "icm");
-        AptArgs a = apt_args(c, 0, 1);
-        hip_check(launch_apt_quad(a, c->quad_lds, c->stream), "icm");
-        hip_check(launch_advance(c->d_ctr.p, 0u, 1u, 0u, 0u, c->stream), "icm");
-        if (info_host) {
-            c->d_icm_info.download(info_host, c->d_icm_info.n, c->stream, "icm info");
-            hip_check(hipStreamSynchronize(c->stream), "icm");
-            if (c->reps == 1)
-                for (size_t i = 0; i < c->d_icm_info.n; ++i) info_host[i] = -1;
-        }
+        icm_call(c, cutoffs_of(c, cutoff, nullptr), 2, info_host);
+    });
+}
+
+sg_status sg_icm_ex(sg_ctx *c, const sg_apt_options *opt, int32_t *info_host)
+{
+    return guarded(c, [&] {
+        require(c, SG_APT);
+        if (!opt) fail(SG_EINVAL, "options are NULL");
+        icm_call(c, cutoffs_of(c, opt->icm_cutoff, opt->icm_cutoff_per_inst), opt->icm_pairs,
+                 info_host);
     });
 }
 
@@ -1073,19 +1109,23 @@ sg_status sg_swap(sg_ctx *c, int32_t *accepted_host)
     });
 }
 
-sg_status sg_run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, double icm_cutoff,
-                     int32_t record_every, int64_t *best_trace)
+}  // extern "C"
+
+namespace {
+
+void run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, const std::vector<double> &cut,
+             int32_t icm_pairs, int32_t record_every, int64_t *best_trace)
 {
-    return guarded(c, [&] {
-        require(c, SG_APT);
+    {
         if (n_cycles < 0 || sweeps_per_swap < 1) fail(SG_EINVAL, "bad cycle or sweep count");
-        if (std::isnan(icm_cutoff)) fail(SG_EINVAL, "cutoff is NaN");
+        if (icm_pairs != 1 && icm_pairs != 2) fail(SG_EINVAL, "icm_pairs must be 1 or 2");
         if (record_every < 0 || (best_trace && record_every == 0))
             fail(SG_EINVAL, "record_every must be > 0 with a trace");
-        const bool icm = icm_applies(c, icm_cutoff);
+        const bool icm = icm_applies(c, cut);
         if (icm && any_field(c)) fail(SG_EUNSUPPORTED, "ICM with non-zero fields is not supported");
         if (n_cycles == 0) return;
-        upload_icm_flags(c, icm ? icm_cutoff : std::numeric_limits<double>::infinity());
+        upload_icm_flags(c, icm ? cut : std::vector<double>((size_t)c->n_inst,
+                                                              std::numeric_limits<double>::infinity()));
         const int cap = best_trace ? (int)(n_cycles / record_every) : 0;
         if (best_trace) {
             if ((size_t)c->n_inst * cap > c->d_trace.n) c->d_trace.alloc((size_t)c->n_inst * cap, "trace");
@@ -1094,6 +1134,7 @@ sg_status sg_run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, doubl
         const int rec = best_trace ? record_every : 0;
         hip_check(launch_fill_u32(c->d_ctr.p + 3, 0u, 1, c->stream), "cycle counter");
         AptArgs qa = apt_args(c, sweeps_per_swap, icm ? 1 : 0);
+        qa.icm_pairs = icm_pairs;
         SwapArgs sa = swap_args(c, nullptr, trace, cap, rec);
         const uint32_t S = (uint32_t)sweeps_per_swap;
         // Replay a captured graph of K cycles.  Inside the graph cycle k reads
@@ -1105,7 +1146,7 @@ sg_status sg_run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, doubl
         // exchange launch after cycle K - 1 brings them back to the first pair.
         const int K = 32;
         if (!c->gexec || c->g_sweeps != sweeps_per_swap || c->g_icm != (int)icm || c->g_record != rec ||
-            c->g_trace != trace || c->g_trace_cap != cap) {
+            c->g_trace != trace || c->g_trace_cap != cap || c->g_pairs != icm_pairs) {
             if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
             c->gexec = nullptr;
             hipGraph_t g = nullptr;
@@ -1146,6 +1187,7 @@ sg_status sg_run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, doubl
             c->g_record = rec;
             c->g_trace = trace;
             c->g_trace_cap = cap;
+            c->g_pairs = icm_pairs;
         }
         int64_t done = 0;
         for (; done + K <= n_cycles; done += K) {
@@ -1166,6 +1208,31 @@ sg_status sg_run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, doubl
             hip_check(hipStreamSynchronize(c->stream), "trace");
             std::memcpy(best_trace, t.data(), t.size() * sizeof(int64_t));
         }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+sg_status sg_run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, double icm_cutoff,
+                     int32_t record_every, int64_t *best_trace)
+{
+    return guarded(c, [&] {
+        require(c, SG_APT);
+        run_apt(c, n_cycles, sweeps_per_swap, cutoffs_of(c, icm_cutoff, nullptr), 2, record_every,
+                best_trace);
+    });
+}
+
+sg_status sg_run_apt_ex(sg_ctx *c, int64_t n_cycles, const sg_apt_options *opt, int64_t *best_trace)
+{
+    return guarded(c, [&] {
+        require(c, SG_APT);
+        if (!opt) fail(SG_EINVAL, "options are NULL");
+        run_apt(c, n_cycles, opt->sweeps_per_swap,
+                cutoffs_of(c, opt->icm_cutoff, opt->icm_cutoff_per_inst), opt->icm_pairs,
+                opt->record_every, best_trace);
     });
 }
 

@@ -127,6 +127,7 @@ struct AptArgs {
     int32_t do_energy;         // 0: leave E, 1: E += change in this launch, 2: recompute E
     int32_t mom_from;          // accumulate moments after sweep index >= mom_from (-1: never)
     int32_t reps;              // ICM labels per temperature
+    int32_t icm_pairs;         // 4 labels: pairs moved per temperature per ICM call (2 or 1)
     int32_t imax;              // LUT covers fields -imax..imax
     int32_t ni;                // 2 * imax + 1
     int32_t n_blocks;

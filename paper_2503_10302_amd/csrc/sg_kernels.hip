@@ -1080,10 +1080,9 @@ void apt_quad_kernel(AptArgs A)
             } else if (A.reps == 4) {
                 const int b = q;
                 if (b < n_beta && A.icm_on[D.inst * n_beta + b]) {
-                    const uint32_t wp = philox10((uint32_t)b, a, 0u,
-                                                 ((uint32_t)D.inst << 4) | TAG_ICM_PAIR, A.key0,
-                                                 A.key1).x;
-                    const uint32_t pairing = (uint32_t)(((uint64_t)wp * 3u) >> 32);
+                    const uint4 wp = philox10((uint32_t)b, a, 0u,
+                                              ((uint32_t)D.inst << 4) | TAG_ICM_PAIR, A.key0, A.key1);
+                    const uint32_t pairing = (uint32_t)(((uint64_t)wp.x * 3u) >> 32);
                     // matchings {01,23}, {02,13}, {03,12}: partner of label 0, then the other two
                     const uint32_t p1 = pairing + 1u;
                     pa = 0u | ((p1 == 1u ? 2u : 1u) << 8);
@@ -1091,6 +1090,17 @@ void apt_quad_kernel(AptArgs A)
                     pidx0 = b * npair;
                     pidx1 = b * npair + 1;
                     np = 2;
+                    if (A.icm_pairs == 1) {
+                        // one move per call: the pair named by the top bit of the block's word 1
+                        if (wp.y >> 31) {
+                            pa >>= 8;
+                            pb >>= 8;
+                            pidx0 = pidx1;
+                        }
+                        pa &= 0xFFu;
+                        pb &= 0xFFu;
+                        np = 1;
+                    }
                 }
             }
             if (np > 0) {

@@ -41,6 +41,11 @@ class _Config(C.Structure):
                 ("seed", C.c_uint64), ("hip_stream", C.c_void_p)]
 
 
+class _AptOptions(C.Structure):
+    _fields_ = [("sweeps_per_swap", C.c_int32), ("icm_pairs", C.c_int32), ("icm_cutoff", C.c_double),
+                ("icm_cutoff_per_inst", C.c_void_p), ("record_every", C.c_int32)]
+
+
 class _Adaptive(C.Structure):
     _fields_ = [("beta0", C.c_double), ("alpha", C.c_double), ("tol", C.c_double),
                 ("n_chains", C.c_int32), ("sweeps", C.c_int32), ("tail", C.c_int32),
@@ -49,7 +54,7 @@ class _Adaptive(C.Structure):
 
 EXPORTS = [
     "sg_create", "sg_destroy", "sg_last_error", "sg_sweep", "sg_icm", "sg_energy", "sg_swap",
-    "sg_run_apt", "sg_best", "sg_swap_counts", "sg_sqa_anneal", "sg_get_launch_config",
+    "sg_run_apt", "sg_run_apt_ex", "sg_icm_ex", "sg_best", "sg_swap_counts", "sg_sqa_anneal", "sg_get_launch_config",
     "sg_set_launch_config", "sg_get_spins", "sg_get_spins_range", "sg_set_spins",
     "sg_get_counters", "sg_get_state", "sg_set_state", "sg_timer_start", "sg_timer_stop",
     "sg_synchronize", "sg_kernel_timing", "sg_kernel_time", "sg_adaptive_ladder", "sg_mlp_create", "sg_mlp_destroy",
@@ -78,6 +83,8 @@ def load():
         "sg_energy": (i32, [P, P]),
         "sg_swap": (i32, [P, P]),
         "sg_run_apt": (i32, [P, i64, i32, dbl, i32, P]),
+        "sg_run_apt_ex": (i32, [P, i64, C.POINTER(_AptOptions), P]),
+        "sg_icm_ex": (i32, [P, C.POINTER(_AptOptions), P]),
         "sg_best": (i32, [P, P]),
         "sg_swap_counts": (i32, [P, P]),
         "sg_sqa_anneal": (i32, [P, P, i32, P, P]),
@@ -210,6 +217,36 @@ class Context:
         self._check(self.lib.sg_run_apt(self.h, int(n_cycles), int(sweeps_per_swap),
                                         float(icm_cutoff), int(record_every), _p(tr)))
         return tr
+
+    def _options(self, sweeps_per_swap, icm_pairs, icm_cutoff, record_every):
+        cut = np.asarray(icm_cutoff, dtype=np.float64)
+        per = None
+        if cut.ndim == 1:
+            if cut.size != self.n_inst:
+                raise ValueError("one ICM cutoff per instance expected")
+            per = np.ascontiguousarray(cut)
+        opt = _AptOptions(int(sweeps_per_swap), int(icm_pairs),
+                          float(cut) if per is None else float("inf"),
+                          None if per is None else per.ctypes.data, int(record_every))
+        return opt, per
+
+    def run_apt_ex(self, n_cycles, sweeps_per_swap=1, icm_cutoff=float("inf"), icm_pairs=2,
+                   record_every=0):
+        """sg_run_apt_ex: icm_cutoff is one value or one per instance; icm_pairs 2 or 1."""
+        opt, keep = self._options(sweeps_per_swap, icm_pairs, icm_cutoff, record_every)
+        tr = None
+        if record_every > 0:
+            tr = np.zeros((self.n_inst, n_cycles // record_every), np.int64)
+        self._check(self.lib.sg_run_apt_ex(self.h, int(n_cycles), C.byref(opt), _p(tr)))
+        return tr
+
+    def icm_ex(self, icm_cutoff, icm_pairs=2, want_info=False):
+        opt, keep = self._options(1, icm_pairs, icm_cutoff, 0)
+        info = None
+        if want_info:
+            info = np.zeros((self.n_inst, self.n_beta, max(1, self.reps // 2), 4), np.int32)
+        self._check(self.lib.sg_icm_ex(self.h, C.byref(opt), _p(info)))
+        return info
 
     def best(self):
         b = np.zeros(self.n_inst, np.int64)

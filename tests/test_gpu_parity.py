@@ -115,6 +115,56 @@ def test_apt_cycles_match_oracle(reps, S, cutoff):
     assert ctx.counters().tolist() == [n_cyc * S, n_cyc, n_cyc]
 
 
+@pytest.mark.parametrize("reps,pairs,S", [(4, 1, 1), (4, 2, 10), (2, 1, 1)])
+def test_apt_options_match_oracle(reps, pairs, S):
+    """sg_run_apt_ex: one or two Houdayer moves per temperature per cycle (four labels), a
+    sweep-to-swap ratio of 10, and a different ICM cutoff per instance, against the oracle
+    (each instance run with its own cutoff): spins, best-energy traces, swap counts, over two
+    replays of the 32-cycle graph and a ragged tail."""
+    insts = [_inst(*m) for m in MIXED[:6]]
+    beta = geometric_ladder(10, 0.2, 3.0)
+    cut = np.array([0.2, 1.0, 0.6, float("inf"), 1.5, 0.9])
+    ctx = sg.apt(insts, beta, SEED + 7 * reps + pairs, reps_per_beta=reps)
+    n_cyc = 70
+    trace = ctx.run_apt_ex(n_cyc, S, cut, pairs, record_every=7)
+    g = ctx.spins()
+    cnt = ctx.swap_counts()
+    for i, inst in enumerate(insts):
+        l = _olat(inst)
+        sp = oracle.apt_init(l, i, beta.size * reps, SEED + 7 * reps + pairs)
+        ctr = np.zeros(3, np.uint32)
+        E = np.zeros(beta.size * reps, np.int64)
+        b = np.array([np.iinfo(np.int64).max], np.int64)
+        rc, otr, oacc = oracle.apt_run(l, i, beta, reps, SEED + 7 * reps + pairs, n_cyc, S, cut[i], 7,
+                                       ctr, sp, E, b, icm_pairs=pairs)
+        assert rc == 0
+        assert np.array_equal(g[i, :, :l.n], sp), f"instance {i}"
+        assert np.array_equal(trace[i], otr), f"trace, instance {i}"
+        assert np.array_equal(cnt[i], oacc)
+
+
+def test_icm_one_pair_records_match_oracle():
+    """sg_icm_ex with one move per temperature: the (m, seed, |C|, branch) record of the moved
+    pair and the not-applied record of the other, per temperature, equal the oracle's."""
+    insts = [_inst(*m) for m in MIXED]
+    beta = geometric_ladder(8, 0.2, 3.0)
+    ctx = sg.apt(insts, beta, SEED + 99, reps_per_beta=4)
+    lats = [_olat(x) for x in insts]
+    osp = [oracle.apt_init(l, i, beta.size * 4, SEED + 99) for i, l in enumerate(lats)]
+    cut = np.array([0.5, 1.0, 0.2, 2.0, 0.7, 0.3, 1.1, 0.9])
+    for call in range(1, 4):
+        ctx.sweep(1)
+        for i, l in enumerate(lats):
+            oracle.apt_sweep(l, i, np.repeat(beta, 4), SEED + 99, call - 1, osp[i])
+        info = ctx.icm_ex(cut, icm_pairs=1, want_info=True)
+        g = ctx.spins()
+        for i, l in enumerate(lats):
+            rc, oinfo = oracle.apt_icm(l, i, beta, 4, cut[i], SEED + 99, call, osp[i], pairs_per_call=1)
+            assert rc == 0
+            assert np.array_equal(info[i], oinfo), f"call {call}, instance {i}"
+            assert np.array_equal(g[i, :, :l.n], osp[i]), f"call {call}, instance {i}"
+
+
 def test_apt_with_fields_and_open_axes():
     insts = [_inst((5, 4, 3), 0, 11, hmax=3), _inst((6, 6, 6), 7, 12, hmax=31), _inst((3, 3, 3), 2, 13, hmax=1)]
     beta = geometric_ladder(6, 0.3, 2.0)

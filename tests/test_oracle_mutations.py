@@ -48,6 +48,9 @@ MUTANTS = [
     ("sqa_init_biased_threshold", "spins[((int64_t)r * M + k) * n + j] = (w < 0x80000000u) ? 1 : -1;",
      "spins[((int64_t)r * M + k) * n + j] = (w < 0x40000000u) ? 1 : -1;"),
     ("sqa_init_one_word_per_block", "SGO_TAG_SQA_INIT, (k >> 1) & 3);", "SGO_TAG_SQA_INIT, 0);"),
+    ("icm_one_pair_always_first",
+     "only = (int32_t)(sgo_word(seed, (uint32_t)b, a, 0u, inst, SGO_TAG_ICM_PAIR, 1) >> 31);",
+     "only = 0;"),
 ]
 
 

@@ -223,6 +223,61 @@ def test_icm_invariants(shape, periodic, R_lab, p_abs):
     assert 0 in branches and (1 in branches or 2 in branches)
 
 
+def test_icm_one_pair_per_call():
+    """Four labels, one ICM per sweep (Supplementary comparison of one and two ICMs): at every
+    temperature at or above the cutoff exactly one pair of the drawn matching is moved, each of
+    the two with probability 1/2 (binomial, 5 sigma over 1200 temperature-calls), the other
+    pair keeps its spins and gets the not-applied record, and the moved pair undergoes the
+    same move as in the two-pair call (same record, same spins)."""
+    J, _ = ej_couplings((5, 4, 4), 7, seed=19)
+    lat = oracle.Lattice(J, 7)
+    beta = np.array([0.4, 1.0, 1.3, 2.0, 2.5])
+    rng = np.random.default_rng(6)
+    first = 0
+    total = 0
+    for a in range(1, 301):
+        spins = np.where(rng.random((beta.size * 4, lat.n)) < 0.5, 1, -1).astype(np.int8)
+        both = spins.copy()
+        rc, info = oracle.apt_icm(lat, 2, beta, 4, 1.0, SEED, a, spins, pairs_per_call=1)
+        rc2, info2 = oracle.apt_icm(lat, 2, beta, 4, 1.0, SEED, a, both, pairs_per_call=2)
+        assert rc == 0 and rc2 == 0 and np.all(info[0] == -1)
+        for b in range(1, beta.size):
+            applied = [pi for pi in range(2) if info[b, pi, 0] >= 0]
+            assert len(applied) == 1, (a, b, info[b])
+            pi = applied[0]
+            first += pi == 0
+            total += 1
+            assert np.all(info[b, 1 - pi] == -1)
+            assert np.array_equal(info[b, pi], info2[b, pi])
+            w = oracle.word(SEED, b, a, 0, 2, oracle.TAG_ICM_PAIR, 0)
+            pairing = (w * 3) >> 32
+            plist = [[(0, 1), (2, 3)], [(0, 2), (1, 3)], [(0, 3), (1, 2)]][pairing]
+            for lab in plist[pi]:
+                assert np.array_equal(spins[b * 4 + lab], both[b * 4 + lab])
+    assert abs(first - total / 2) <= 5 * 0.5 * np.sqrt(total), (first, total)
+
+
+def test_icm_one_pair_leaves_the_other_pair_alone():
+    J, _ = ej_couplings((4, 4, 4), 7, seed=20)
+    lat = oracle.Lattice(J, 7)
+    beta = np.array([1.2, 1.5, 2.0])
+    rng = np.random.default_rng(7)
+    for a in range(1, 60):
+        spins = np.where(rng.random((beta.size * 4, lat.n)) < 0.5, 1, -1).astype(np.int8)
+        before = spins.copy()
+        _, info = oracle.apt_icm(lat, 0, beta, 4, 1.0, SEED, a, spins, pairs_per_call=1)
+        for b in range(beta.size):
+            pi = 0 if info[b, 0, 0] >= 0 else 1
+            w = oracle.word(SEED, b, a, 0, 0, oracle.TAG_ICM_PAIR, 0)
+            plist = [[(0, 1), (2, 3)], [(0, 2), (1, 3)], [(0, 3), (1, 2)]][(w * 3) >> 32]
+            for lab in plist[1 - pi]:
+                assert np.array_equal(spins[b * 4 + lab], before[b * 4 + lab])
+            la, lb = plist[pi]
+            E0 = oracle.energy(lat, before[b * 4 + la]) + oracle.energy(lat, before[b * 4 + lb])
+            E1 = oracle.energy(lat, spins[b * 4 + la]) + oracle.energy(lat, spins[b * 4 + lb])
+            assert E0 == E1
+
+
 def test_icm_rejects_fields():
     J, h = ej_couplings((4, 4, 4), 7, seed=16, h_max=1)
     lat = oracle.Lattice(J, 7, h)
