@@ -525,6 +525,7 @@ def main():
         c3.run_apt(args.apt_cycles, 1, 1.0)
         ms3 = c3.timer_stop()
         k3, _ = c3.kernel_time()
+        code = c3.launch_config()
         c3.timer_start()
         c3.sweep(32)
         ms3s = c3.timer_stop()
@@ -544,7 +545,9 @@ def main():
                "ms_per_cycle": round(ms3 / args.apt_cycles, 5),
                "flips_per_ns": round(flips_cycle * args.apt_cycles / (ms3 * 1e6), 3),
                "sweep_only_flips_per_ns": round(flips_cycle * 32 / (ms3s * 1e6), 3),
-               "graph_kernel_ms": round(k3, 3)}
+               "graph_kernel_ms": round(k3, 3),
+               "launch_config": {"code": code, "order": (code - 1) % 6,
+                                 "waves_per_simd": 8 if code > 6 else 7, "chosen_by": "autotuner"}}
         apt["icm_swap_energy_share"] = round(1.0 - (ms3s / 32) / (ms3 / args.apt_cycles), 4)
         out["apt_batched"] = apt
         out["apt_plain"] = {"workload": "one L=8 periodic instance, 32 betas x 2 labels, ICM at beta >= 1",

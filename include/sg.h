@@ -159,14 +159,23 @@ sg_status sg_swap_counts(sg_ctx *ctx, int64_t *counts_host);
 sg_status sg_sqa_anneal(sg_ctx *ctx, const double *gamma, int32_t n_steps, int64_t *best_E,
                         int8_t *best_state);
 
-/* DT-SQA work-group size (an implementation choice; results do not depend on it):
- * a multiple of 64 in 128..1024.  The first sg_sqa_anneal of a context whose size
- * is unset (0) times 256, 512, 768 and 1024 for a few steps on a scratch copy of the
- * replicas and keeps the fastest (cached per workload shape for the process).
- * get: 0 while unset.  set: 0 re-enables the autotuner; any other value outside the
- * allowed set gives SG_EINVAL. */
-sg_status sg_get_launch_config(sg_ctx *ctx, int32_t *threads);
-sg_status sg_set_launch_config(sg_ctx *ctx, int32_t threads);
+/* Launch configuration (an implementation choice; results do not depend on it).
+ * DT-SQA contexts: the work-group size, a multiple of 64 in 128..1024.  The first
+ * sg_sqa_anneal of a context whose size is unset (0) times 256, 512, 768 and 1024 for a few
+ * steps on a scratch copy of the replicas and keeps the fastest.
+ * APT contexts: a code 1..12 = 1 + order + 6 * (8 waves per SIMD ? 1 : 0), order 0..5 the
+ * dispatch order of the replica kernel's work-groups (0-3: instances spread over the eight
+ * XCDs, quads sorted by estimated cost with cluster-move weight 3, 1, 2, 4; 4: one global cost
+ * sort; 5: instance-major), and at least 7 or 8 waves per SIMD (the kernel's register
+ * budget).  The first sg_run_apt / sg_run_apt_ex of a context whose code is unset (0) times
+ * all twelve on its own shape (sweeps per swap, cluster moves) and keeps the fastest, leaving
+ * the context's state as it was; other calls use code 1 until then.
+ * Both tuners cache their pick per workload shape for the process and in the file named by
+ * the environment variable SG_TUNE_CACHE (default ~/.cache/libsg_tune.txt; best effort).
+ * get: 0 while unset.  set: 0 re-enables the autotuner; any other value outside the allowed
+ * set gives SG_EINVAL. */
+sg_status sg_get_launch_config(sg_ctx *ctx, int32_t *config);
+sg_status sg_set_launch_config(sg_ctx *ctx, int32_t config);
 
 /* Spins in logical order, +1/-1.  APT [n_inst][n_beta*reps][n_max];
  * DT-SQA [n_inst][R][M][n_max]; n_max = largest n, unused tail zero. */

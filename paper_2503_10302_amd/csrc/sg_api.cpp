@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <map>
@@ -303,6 +304,9 @@ struct sg_ctx {
     DevBuf<uint4> d_rowA, d_rowB, d_rowC;
     int n_blocks = 0;
     size_t quad_lds = 0;
+    int apt_config = 0;        // launch configuration asked for: 0 = the autotuner's on the next run
+    int apt_config_used = 1;   // configuration of d_desc / apt_waves (1: order 0, 7 waves)
+    int apt_waves = 7;
     std::vector<double> icm_cutoff_loaded;   // per instance, as last uploaded into d_icm_on
     // graph cache for APT cycles
     hipGraphExec_t gexec = nullptr;
@@ -475,37 +479,46 @@ void apt_rows(const Lat &L, std::vector<uint4> &rowA, std::vector<uint4> &rowB,
     }
 }
 
-// Work-group tasks, grouped so that all quads of an instance run on one
-// XCD (blocks are dispatched round-robin over the 8 XCDs; each XCD has its own
-// L2 holding that instance's records and tables).  Largest instances first.
-// Work-group order of the APT replica kernel.  Instances are spread over the eight XCDs by
-// size (an instance's quads share one XCD's L2 for its site records); within an XCD, quads
-// are ordered by estimated cost, largest first: sites, tripled for quads holding a
-// temperature >= 1 (where the cluster moves usually run; the weight measured best among
-// 1.5, 2, 3 and 4 on a batch of mixed sizes).
+// Work-group order of the APT replica kernel (a launch-configuration choice: every order
+// gives the same results).  Orders 0-3: instances spread over the eight XCDs by size (an
+// instance's quads share one XCD's L2 for its site records); within an XCD, quads sorted by
+// estimated cost, largest first: sites, times w = 3, 1, 2 or 4 for quads holding a
+// temperature >= 1 (where the cluster moves usually run).  Order 4: one global cost sort
+// (w = 3), handed to the XCDs in turn.  Order 5: instance-major, quads ascending.
+constexpr int kAptOrders = 6;
+constexpr int kAptConfigs = 2 * kAptOrders;   // x {7, 8} waves per SIMD
+
 std::vector<QuadDesc> make_quad_descs(const std::vector<Lat> &lat, int n_quads,
-                                      const std::vector<double> &beta, int n_beta, int reps)
+                                      const std::vector<double> &beta, int n_beta, int reps,
+                                      int order)
 {
     const int ni = (int)lat.size();
-    std::vector<int> order(ni);
-    for (int i = 0; i < ni; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lat[a].n > lat[b].n; });
+    std::vector<QuadDesc> out;
+    if (order == 5) {
+        for (int i = 0; i < ni; ++i)
+            for (int q = 0; q < n_quads; ++q) out.push_back({i, q});
+        return out;
+    }
+    static const int kWeight[5] = {3, 1, 2, 4, 3};
+    const int w = kWeight[order];
+    std::vector<int> idx(ni);
+    for (int i = 0; i < ni; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return lat[a].n > lat[b].n; });
     auto cost = [&](const QuadDesc &d) {
         bool icm = false;
         for (int k = 0; k < 4 && reps >= 2; ++k) {
             const int b = std::min(4 * d.quad + k, n_beta * reps - 1) / reps;
             icm |= beta[(size_t)d.inst * n_beta + b] >= 1.0;
         }
-        return (int64_t)lat[d.inst].n * (icm ? 3 : 1);
+        return (int64_t)lat[d.inst].n * (icm ? w : 1);
     };
     auto by_cost = [&](std::vector<QuadDesc> &v) {
         std::stable_sort(v.begin(), v.end(),
                          [&](const QuadDesc &a, const QuadDesc &b) { return cost(a) > cost(b); });
     };
-    std::vector<QuadDesc> out;
     // within an instance the last quads hold the largest betas: start them first
-    if (ni < 8) {
-        for (int i : order)
+    if (ni < 8 || order == 4) {
+        for (int i : idx)
             for (int q = n_quads - 1; q >= 0; --q) out.push_back({i, q});
         by_cost(out);
         return out;
@@ -513,7 +526,7 @@ std::vector<QuadDesc> make_quad_descs(const std::vector<Lat> &lat, int n_quads,
     const int X = 8;
     std::vector<std::vector<QuadDesc>> qs(X);
     std::vector<int64_t> load(X, 0);
-    for (int i : order) {
+    for (int i : idx) {
         const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         load[x] += (int64_t)lat[i].n;
         for (int q = n_quads - 1; q >= 0; --q) qs[x].push_back({i, q});
@@ -631,7 +644,7 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
     c->d_icm_info.alloc((size_t)c->n_inst * c->n_beta * std::max(1, c->reps / 2) * 4, "icm info");
     c->d_icm_on.alloc((size_t)c->n_inst * c->n_beta, "icm flags");
     c->d_ctr.alloc(8, "counters");
-    std::vector<QuadDesc> desc = make_quad_descs(c->lat, c->n_quads, c->beta, c->n_beta, c->reps);
+    std::vector<QuadDesc> desc = make_quad_descs(c->lat, c->n_quads, c->beta, c->n_beta, c->reps, 0);
     c->n_blocks = (int)desc.size();
     c->d_desc.upload(desc, s, "tasks");
     c->quad_lds = 0;
@@ -707,6 +720,7 @@ AptArgs apt_args(sg_ctx *c, int n_sweeps, int do_icm)
     a.n_blocks = c->n_blocks;
     a.nb4 = 4 * c->n_quads;
     a.fused_swap = 0;
+    a.waves = c->apt_waves;
     return a;
 }
 
@@ -846,6 +860,63 @@ SqaArgs sqa_args(sg_ctx *c)
     return a;
 }
 
+// ---- on-disk autotuner cache: one "key value" line per workload shape, the key a hash of
+// the device, the library build and the shape; file $SG_TUNE_CACHE or ~/.cache/libsg_tune.txt
+// (best effort: an unreadable or unwritable file only disables the cache)
+std::string tune_cache_path()
+{
+    if (const char *e = std::getenv("SG_TUNE_CACHE")) return e;
+    if (const char *h = std::getenv("HOME")) return std::string(h) + "/.cache/libsg_tune.txt";
+    return "";
+}
+
+std::string tune_disk_key(const std::string &shape)
+{
+    int dev = 0;
+    hipDeviceProp_t p{};
+    std::string arch = "?";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+        arch = p.gcnArchName;
+    const std::string all = arch + "|" __DATE__ " " __TIME__ "|" + shape;
+    uint64_t h = 1469598103934665603ull;   // FNV-1a
+    for (unsigned char ch : all) {
+        h ^= ch;
+        h *= 1099511628211ull;
+    }
+    char buf[24];
+    std::snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
+    return buf;
+}
+
+bool tune_disk_lookup(const std::string &shape, int *value)
+{
+    const std::string path = tune_cache_path();
+    if (path.empty()) return false;
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return false;
+    const std::string key = tune_disk_key(shape);
+    char k[64];
+    int v = 0;
+    bool found = false;
+    while (std::fscanf(f, "%63s %d", k, &v) == 2)
+        if (key == k) {
+            *value = v;
+            found = true;
+        }
+    std::fclose(f);
+    return found;
+}
+
+void tune_disk_store(const std::string &shape, int value)
+{
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    FILE *f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d\n", tune_disk_key(shape).c_str(), value);
+    std::fclose(f);
+}
+
 // ---- DT-SQA launch-configuration autotuner
 // Candidates: work-groups of 4, 8, 12 and 16 waves (a whole number of waves per
 // SIMD; other sizes leave the four SIMDs of a CU unevenly loaded and measured 10-25 %
@@ -860,7 +931,7 @@ std::map<std::string, int> g_tune_cache;
 
 std::string sqa_tune_key(const sg_ctx *c)
 {
-    std::string k = std::to_string(c->n_inst) + "/" + std::to_string(c->R) + "/" +
+    std::string k = "sqa/" + std::to_string(c->n_inst) + "/" + std::to_string(c->R) + "/" +
                     std::to_string(c->M) + "/" + std::to_string(c->nl);
     for (const InstDev &I : c->idev)
         k += ":" + std::to_string(I.npad) + "," + std::to_string(I.col_cnt[0]) + "," +
@@ -878,6 +949,13 @@ void sqa_autotune(sg_ctx *c, const SqaArgs &base, int ns)
             c->sqa_threads = it->second;
             return;
         }
+    }
+    int cached = 0;
+    if (tune_disk_lookup(key, &cached) && sqa_config_valid(cached)) {
+        c->sqa_threads = cached;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = cached;
+        return;
     }
     constexpr int kCand = 4;   // 256, 512, 768, 1024 threads
     DevBuf<uint32_t> scratch;
@@ -916,11 +994,133 @@ void sqa_autotune(sg_ctx *c, const SqaArgs &base, int ns)
     for (int q = 1; q < kCand; ++q)
         if (best_ms[q] < best_ms[pick]) pick = q;
     c->sqa_threads = 256 * (pick + 1);
+    tune_disk_store(key, c->sqa_threads);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = c->sqa_threads;
 }
 
 int sqa_threads_or_default(const sg_ctx *c) { return c->sqa_threads ? c->sqa_threads : 512; }
+
+// ---- APT launch configuration: code 1 + order + kAptOrders * (8 waves ? 1 : 0), order as in
+// make_quad_descs.  Every configuration computes the same bits (counter-based random numbers,
+// each work-group's work fixed by its quad).
+void apply_apt_config(sg_ctx *c, int code)
+{
+    if (code == c->apt_config_used) return;
+    const int order = (code - 1) % kAptOrders;
+    std::vector<QuadDesc> d = make_quad_descs(c->lat, c->n_quads, c->beta, c->n_beta, c->reps, order);
+    // launches in flight still read the old task list
+    hip_check(hipStreamSynchronize(c->stream), "launch config");
+    c->d_desc.upload(d, c->stream, "tasks");
+    c->n_blocks = (int)d.size();
+    c->apt_waves = (code - 1) / kAptOrders ? 8 : 7;
+    c->apt_config_used = code;
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+}
+
+std::string apt_tune_key(const sg_ctx *c, int S, bool icm, int pairs)
+{
+    std::string k = "apt/" + std::to_string(c->n_inst) + "/" + std::to_string(c->n_beta) + "/" +
+                    std::to_string(c->reps) + "/" + std::to_string(c->imax) + "/" + std::to_string(S) +
+                    "/" + std::to_string((int)icm) + "/" + std::to_string(pairs);
+    for (const InstDev &I : c->idev)
+        k += ":" + std::to_string(I.n) + "," + std::to_string(I.n_colours) + "," +
+             std::to_string(I.row_off >= 0) + std::to_string(I.planes);
+    k += "/";   // temperatures with cluster moves (their share of the cost)
+    for (const double &cut : c->icm_cutoff_loaded) k += std::to_string(cut) + ",";
+    return k;
+}
+
+std::map<std::string, int> g_apt_tune_cache;   // guarded by g_tune_mu
+
+// Candidates: the six work-group orders x {7, 8} waves per SIMD, each timed over eight
+// replica-kernel launches of the run's shape (sweeps, cluster moves) twice; the state is
+// saved before and restored after, so the context is unchanged.  The pick is cached per
+// workload shape for the process and on disk.
+void apt_autotune(sg_ctx *c, int S, bool icm, int pairs)
+{
+    const std::string key = apt_tune_key(c, S, icm, pairs);
+    int pick = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_apt_tune_cache.find(key);
+        if (it != g_apt_tune_cache.end()) pick = it->second;
+    }
+    if (pick == 0 && tune_disk_lookup(key, &pick) && (pick < 1 || pick > kAptConfigs)) pick = 0;
+    if (pick == 0) {
+        hipStream_t st = c->stream;
+        DevBuf<uint8_t> s_spins;
+        DevBuf<int32_t> s_perm, s_E, s_info;
+        DevBuf<int64_t> s_best, s_acc, s_mom;
+        DevBuf<uint32_t> s_ctr;
+        auto save = [&](auto &dst, auto &src) {
+            dst.alloc(src.n, "autotune snapshot");
+            hip_check(hipMemcpyAsync(dst.p, src.p, src.n * sizeof(*src.p), hipMemcpyDeviceToDevice, st),
+                      "autotune snapshot");
+        };
+        auto restore = [&](auto &dst, auto &src) {
+            hip_check(hipMemcpyAsync(dst.p, src.p, src.n * sizeof(*src.p), hipMemcpyDeviceToDevice, st),
+                      "autotune restore");
+        };
+        save(s_spins, c->d_spins);
+        save(s_perm, c->d_perm);
+        save(s_E, c->d_E);
+        save(s_info, c->d_icm_info);
+        save(s_best, c->d_best);
+        save(s_acc, c->d_acc_count);
+        save(s_mom, c->d_mom);
+        save(s_ctr, c->d_ctr);
+        hipEvent_t e0, e1;
+        hip_check(hipEventCreate(&e0), "autotune");
+        hip_check(hipEventCreate(&e1), "autotune");
+        std::vector<float> best_ms(kAptConfigs + 1, std::numeric_limits<float>::infinity());
+        hipError_t err = hipSuccess;
+        try {
+            for (int rep = 0; rep < 2 && err == hipSuccess; ++rep)
+                for (int code = 1; code <= kAptConfigs && err == hipSuccess; ++code) {
+                    apply_apt_config(c, code);
+                    AptArgs a = apt_args(c, S, icm ? 1 : 0);
+                    a.icm_pairs = pairs;
+                    err = hipEventRecord(e0, st);
+                    for (int k = 0; k < 8 && err == hipSuccess; ++k) err = launch_apt_quad(a, c->quad_lds, st);
+                    if (err == hipSuccess) err = hipEventRecord(e1, st);
+                    if (err == hipSuccess) err = hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+                    if (err == hipSuccess) best_ms[code] = std::min(best_ms[code], ms);
+                }
+        } catch (...) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            throw;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        hip_check(err, "autotune");
+        restore(c->d_spins, s_spins);
+        restore(c->d_perm, s_perm);
+        restore(c->d_E, s_E);
+        restore(c->d_icm_info, s_info);
+        restore(c->d_best, s_best);
+        restore(c->d_acc_count, s_acc);
+        restore(c->d_mom, s_mom);
+        restore(c->d_ctr, s_ctr);
+        hip_check(hipStreamSynchronize(st), "autotune restore");
+        pick = 1;
+        for (int code = 2; code <= kAptConfigs; ++code)
+            if (best_ms[code] < best_ms[pick]) pick = code;
+        tune_disk_store(key, pick);
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_apt_tune_cache[key] = pick;
+    }
+    c->apt_config = pick;
+    apply_apt_config(c, pick);
+}
 
 // Event pair bracketing one main-kernel launch when kernel timing is on.
 hipEvent_t kernel_event(sg_ctx *c, bool start)
@@ -1126,6 +1326,8 @@ void run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, const std::ve
         if (n_cycles == 0) return;
         upload_icm_flags(c, icm ? cut : std::vector<double>((size_t)c->n_inst,
                                                               std::numeric_limits<double>::infinity()));
+        if (c->apt_config == 0) apt_autotune(c, sweeps_per_swap, icm, icm_pairs);
+        else apply_apt_config(c, c->apt_config);
         const int cap = best_trace ? (int)(n_cycles / record_every) : 0;
         if (best_trace) {
             if ((size_t)c->n_inst * cap > c->d_trace.n) c->d_trace.alloc((size_t)c->n_inst * cap, "trace");
@@ -1257,22 +1459,29 @@ sg_status sg_swap_counts(sg_ctx *c, int64_t *counts)
     });
 }
 
-sg_status sg_get_launch_config(sg_ctx *c, int32_t *threads)
+sg_status sg_get_launch_config(sg_ctx *c, int32_t *config)
 {
     return guarded(c, [&] {
-        require(c, SG_SQA);
-        if (!threads) fail(SG_EINVAL, "threads is NULL");
-        *threads = c->sqa_threads;
+        if (!c) fail(SG_EINVAL, "context is NULL");
+        if (!config) fail(SG_EINVAL, "config is NULL");
+        *config = c->mode == SG_SQA ? c->sqa_threads : c->apt_config;
     });
 }
 
-sg_status sg_set_launch_config(sg_ctx *c, int32_t threads)
+sg_status sg_set_launch_config(sg_ctx *c, int32_t config)
 {
     return guarded(c, [&] {
-        require(c, SG_SQA);
-        if (threads != 0 && !sqa_config_valid(threads))
-            fail(SG_EINVAL, "work-group size must be a multiple of 64 in 128..1024");
-        c->sqa_threads = threads;
+        if (!c) fail(SG_EINVAL, "context is NULL");
+        if (c->mode == SG_SQA) {
+            if (config != 0 && !sqa_config_valid(config))
+                fail(SG_EINVAL, "work-group size must be a multiple of 64 in 128..1024");
+            c->sqa_threads = config;
+        } else {
+            if (config < 0 || config > kAptConfigs)
+                fail(SG_EINVAL, "APT launch configuration must be 0..%d", kAptConfigs);
+            c->apt_config = config;
+            if (config) apply_apt_config(c, config);
+        }
     });
 }
 

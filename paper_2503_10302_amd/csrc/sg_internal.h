@@ -135,6 +135,7 @@ struct AptArgs {
     int32_t cyc_k;             // cycle offset of this launch inside a captured graph: the
                                // kernel uses sweep counter ctr[0] + cyc_k * n_sweeps and ICM
                                // call ctr[1] + cyc_k + 1; counters advance only between graphs
+    int32_t waves;             // kernel variant: at least 8 or 7 (also for 0) waves per SIMD
     int32_t fused_swap;        // 1: first perform the replica exchange described by sw (the
                                //    previous cycle's attempt) for this work-group's slots,
                                //    reading sw.perm_in / sw.E_in and writing sw.perm and E

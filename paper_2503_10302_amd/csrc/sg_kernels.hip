@@ -884,8 +884,10 @@ __global__ __launch_bounds__(kQuadThreads) void apt_init_kernel(const InstDev *i
 // defined with the DT-SQA kernel
 __device__ __forceinline__ uint4 sqa_group_words(uint32_t t, uint32_t x2, uint32_t k0, uint32_t k1);
 
-template <bool SCALED>
-__global__ __launch_bounds__(kQuadThreads) __attribute__((amdgpu_waves_per_eu(7, 8)))
+// W: at least W waves per SIMD (the register budget: 64 VGPRs for W = 8, 72 for W = 7), a
+// launch-configuration choice of the autotuner; results do not depend on it.
+template <bool SCALED, int W>
+__global__ __launch_bounds__(kQuadThreads) __attribute__((amdgpu_waves_per_eu(W, 8)))
 void apt_quad_kernel(AptArgs A)
 {
     // SCALED (at most 16 threshold entries per slot): the four tables sit in static LDS at
@@ -1919,20 +1921,27 @@ static hipError_t allow_lds(const void *fn, size_t bytes)
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <bool SCALED>
+template <bool SCALED, int W>
 hipError_t launch_apt_quad_t(const AptArgs &a, size_t lds_bytes, hipStream_t s)
 {
-    hipError_t e = allow_lds((const void *)apt_quad_kernel<SCALED>, lds_bytes);
+    hipError_t e = allow_lds((const void *)apt_quad_kernel<SCALED, W>, lds_bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(apt_quad_kernel<SCALED>, dim3(a.n_blocks), dim3(kQuadThreads), lds_bytes, s,
-                       a);
+    hipLaunchKernelGGL((apt_quad_kernel<SCALED, W>), dim3(a.n_blocks), dim3(kQuadThreads), lds_bytes,
+                       s, a);
     return hipGetLastError();
+}
+
+template <bool SCALED>
+hipError_t launch_apt_quad_w(const AptArgs &a, size_t lds_bytes, hipStream_t s)
+{
+    if (a.waves == 8) return launch_apt_quad_t<SCALED, 8>(a, lds_bytes, s);
+    return launch_apt_quad_t<SCALED, 7>(a, lds_bytes, s);
 }
 
 hipError_t launch_apt_quad(const AptArgs &a, size_t lds_bytes, hipStream_t s)
 {
-    return a.ni <= 16 ? launch_apt_quad_t<true>(a, lds_bytes, s)
-                      : launch_apt_quad_t<false>(a, lds_bytes, s);
+    return a.ni <= 16 ? launch_apt_quad_w<true>(a, lds_bytes, s)
+                      : launch_apt_quad_w<false>(a, lds_bytes, s);
 }
 
 hipError_t launch_apt_swap(const SwapArgs &a, hipStream_t s)

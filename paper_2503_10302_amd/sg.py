@@ -267,7 +267,8 @@ class Context:
         return bE, bs
 
     def launch_config(self):
-        """DT-SQA work-group size; 0 until the autotuner has run."""
+        """DT-SQA work-group size, or APT configuration code (1..12); 0 until the autotuner
+        has run."""
         t = C.c_int32(0)
         self._check(self.lib.sg_get_launch_config(self.h, C.byref(t)))
         return t.value

@@ -143,6 +143,73 @@ def test_apt_options_match_oracle(reps, pairs, S):
         assert np.array_equal(cnt[i], oacc)
 
 
+def test_apt_every_launch_config_matches_oracle():
+    """Every APT launch configuration (six work-group orders x 7 or 8 waves per SIMD) gives the
+    oracle's spins, traces and swap counts, over a 32-cycle graph replay and a tail."""
+    insts = [_inst(*m) for m in MIXED]
+    beta = geometric_ladder(8, 0.2, 3.0)
+    ref = []
+    for i, inst in enumerate(insts):
+        l = _olat(inst)
+        sp = oracle.apt_init(l, i, beta.size * 2, SEED + 5)
+        ctr = np.zeros(3, np.uint32)
+        E = np.zeros(beta.size * 2, np.int64)
+        b = np.array([np.iinfo(np.int64).max], np.int64)
+        rc, otr, oacc = oracle.apt_run(l, i, beta, 2, SEED + 5, 37, 1, 1.0, 1, ctr, sp, E, b)
+        assert rc == 0
+        ref.append((l.n, sp, otr, oacc))
+    for code in range(1, 13):
+        ctx = sg.apt(insts, beta, SEED + 5, reps_per_beta=2)
+        ctx.set_launch_config(code)
+        assert ctx.launch_config() == code
+        tr = ctx.run_apt(37, 1, 1.0, record_every=1)
+        g = ctx.spins()
+        cnt = ctx.swap_counts()
+        for i, (n, sp, otr, oacc) in enumerate(ref):
+            assert np.array_equal(g[i, :, :n], sp), f"config {code}, instance {i}"
+            assert np.array_equal(tr[i], otr) and np.array_equal(cnt[i], oacc), f"config {code}"
+        ctx.close()
+    ctx = sg.apt(insts, beta, SEED + 5, reps_per_beta=2)
+    for bad in (-1, 13, 1000):
+        with pytest.raises(sg.SGError) as e:
+            ctx.set_launch_config(bad)
+        assert e.value.code == sg.SG_EINVAL
+
+
+def test_apt_autotuner_keeps_state_and_caches(tmp_path, monkeypatch):
+    """The first run of a context with no configuration times the twelve candidates on a saved
+    copy of the state and restores it: the run still matches the oracle; the pick is kept by
+    the context, in the process cache and in the on-disk cache file."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("SG_TUNE_CACHE", str(cache))
+    insts = [_inst(*m) for m in MIXED[:5]] + [_inst((11, 10, 9), 7, 44)]
+    beta = geometric_ladder(12, 0.2, 3.0)
+    ctx = sg.apt(insts, beta, SEED + 6, reps_per_beta=4)
+    assert ctx.launch_config() == 0
+    ctx.sweep(3)
+    tr = ctx.run_apt_ex(45, 1, 0.9, 1, record_every=3)
+    code = ctx.launch_config()
+    assert 1 <= code <= 12
+    g = ctx.spins()
+    for i, inst in enumerate(insts):
+        l = _olat(inst)
+        sp = oracle.apt_init(l, i, beta.size * 4, SEED + 6)
+        for t in range(3):
+            oracle.apt_sweep(l, i, np.repeat(beta, 4), SEED + 6, t, sp)
+        ctr = np.array([3, 0, 0], np.uint32)
+        E = np.array([oracle.energy(l, x) for x in sp], np.int64)
+        b = np.array([np.iinfo(np.int64).max], np.int64)
+        rc, otr, _ = oracle.apt_run(l, i, beta, 4, SEED + 6, 45, 1, 0.9, 3, ctr, sp, E, b, icm_pairs=1)
+        assert rc == 0
+        assert np.array_equal(g[i, :, :l.n], sp), f"instance {i}"
+        assert np.array_equal(tr[i], otr)
+    lines = cache.read_text().split("\n")
+    assert any(l.endswith(f" {code}") for l in lines if l)
+    again = sg.apt(insts, beta, SEED + 7, reps_per_beta=4)
+    again.run_apt_ex(2, 1, 0.9, 1)
+    assert again.launch_config() == code
+
+
 def test_icm_one_pair_records_match_oracle():
     """sg_icm_ex with one move per temperature: the (m, seed, |C|, branch) record of the moved
     pair and the not-applied record of the other, per temperature, equal the oracle's."""
