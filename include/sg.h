@@ -91,6 +91,19 @@ typedef struct {
  * allocate device memory and draw the random initial spins (Algorithm S1 and
  * S2: "initialize all replicas to random states").  *out is NULL on error. */
 sg_status sg_create(const sg_config *cfg, sg_ctx **out);
+/* sg_create with a colour map per instance (Methods, "Graph Coloring": the p-bits of one
+ * colour share no bond and are updated in parallel).  colour (nullable) [n_inst], colour[i]
+ * (nullable: the closed-form colouring) [n] int8 in 0..3, copied.  APT sweeps colour classes
+ * 0, 1, ... in turn; DT-SQA colours site j of slice k with (colour[j] + k mod 2) mod C,
+ * C = max(colours, 2).  SG_EINVAL when two sites joined by a bond with J != 0 share a colour
+ * or a value is outside 0..3.  Any proper map gives a valid sampler; the oracle takes the
+ * same map.  sg_create(cfg, out) = sg_create_ex(cfg, NULL, out). */
+sg_status sg_create_ex(const sg_config *cfg, const int8_t *const *colour, sg_ctx **out);
+/* DSATUR colouring (Brelaz) of one instance's interaction graph (sites joined by bonds with
+ * J != 0): colour_out [n] in 0..*n_colours - 1.  It uses two colours on every bipartite
+ * graph (all lattices without an odd periodic axis, diluted or not), three or more where an
+ * odd cycle remains.  SG_EUNSUPPORTED if more than four colours would be needed. */
+sg_status sg_dsatur_colouring(const sg_lattice *inst, int8_t *colour_out, int32_t *n_colours);
 void sg_destroy(sg_ctx *ctx);
 const char *sg_last_error(const sg_ctx *ctx);
 

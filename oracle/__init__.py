@@ -43,7 +43,8 @@ def build(force: bool = False) -> str:
 
 class _Lattice(C.Structure):
     _fields_ = [("Lx", C.c_int32), ("Ly", C.c_int32), ("Lz", C.c_int32),
-                ("periodic", C.c_uint32), ("J", C.c_void_p), ("h", C.c_void_p)]
+                ("periodic", C.c_uint32), ("J", C.c_void_p), ("h", C.c_void_p),
+                ("colour", C.c_void_p), ("n_map_colours", C.c_int32)]
 
 
 class _AdaptiveParams(C.Structure):
@@ -104,15 +105,19 @@ def _ptr(a):
 class Lattice:
     """An instance: couplings J[Lz, Ly, Lx, 3] (int8, bond to +x,+y,+z), fields h."""
 
-    def __init__(self, J, periodic=7, h=None):
+    def __init__(self, J, periodic=7, h=None, colour=None):
+        """colour: optional colour map [n] (a proper colouring of the coupled sites)."""
         self.J = np.ascontiguousarray(J, dtype=np.int8)
         assert self.J.ndim == 4 and self.J.shape[3] == 3
         self.Lz, self.Ly, self.Lx = self.J.shape[:3]
         self.periodic = int(periodic)
         self.h = None if h is None else np.ascontiguousarray(h, dtype=np.int8).reshape(-1)
         self.n = self.Lx * self.Ly * self.Lz
+        self.colour = None if colour is None else np.ascontiguousarray(colour, dtype=np.int8).reshape(-1)
+        ncol = 0 if self.colour is None else int(self.colour.max()) + 1
         self._c = _Lattice(self.Lx, self.Ly, self.Lz, self.periodic,
-                           self.J.ctypes.data, None if self.h is None else self.h.ctypes.data)
+                           self.J.ctypes.data, None if self.h is None else self.h.ctypes.data,
+                           None if self.colour is None else self.colour.ctypes.data, ncol)
 
     @property
     def c(self):

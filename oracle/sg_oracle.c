@@ -110,8 +110,23 @@ static int odd_ring(const sgo_lattice *lat, int32_t a)
     return ((lat->periodic >> a) & 1u) && L >= 3 && (L & 1);
 }
 
+/* With a given colour map c(j) (a proper colouring of the coupled sites, e.g. DSATUR's for an
+ * irregular graph, Methods "Graph Coloring") the Trotter label t(k) is added modulo
+ * C = max(map colours, 2 for an even ring, 3 for an odd one): spatial neighbours share t
+ * and differ in c; Trotter neighbours share c and differ in t by 1 or 2. */
+static int32_t trotter_label(int32_t M, int32_t k)
+{
+    if (M <= 0) return 0;
+    return ((M & 1) && k == M - 1) ? 2 : (k & 1);
+}
+
 int32_t sgo_n_colours(const sgo_lattice *lat, int32_t M)
 {
+    if (lat->colour) {
+        int32_t C = lat->n_map_colours;
+        if (M > 0 && C < ((M & 1) ? 3 : 2)) C = (M & 1) ? 3 : 2;
+        return C;
+    }
     int three = odd_ring(lat, 0) || odd_ring(lat, 1) || odd_ring(lat, 2);
     if (M > 0 && (M & 1)) three = 1;
     return three ? 3 : 2;
@@ -120,6 +135,7 @@ int32_t sgo_n_colours(const sgo_lattice *lat, int32_t M)
 int32_t sgo_colour(const sgo_lattice *lat, int32_t M, int32_t j, int32_t k)
 {
     int32_t C = sgo_n_colours(lat, M);
+    if (lat->colour) return (lat->colour[j] + trotter_label(M, k)) % C;
     int32_t sum = 0;
     for (int32_t a = 0; a < 3; ++a) {
         int32_t c = axis_coord(lat, j, a);

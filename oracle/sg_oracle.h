@@ -45,6 +45,9 @@ typedef struct {
     uint32_t periodic;   /* bit0 = x, bit1 = y, bit2 = z */
     const int8_t *J;     /* [Lz][Ly][Lx][3]: bond from site j to its +x,+y,+z neighbour */
     const int8_t *h;     /* [n] or NULL (all zero) */
+    const int8_t *colour;   /* [n] colour of every site (a proper colouring of the bonds with
+                               J != 0, values 0 .. n_map_colours - 1), or NULL: closed form */
+    int32_t n_map_colours;
 } sgo_lattice;
 
 /* ---- random numbers: Philox4x32-10 (Salmon et al., SC'11) ---- */

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -17,7 +18,9 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <set>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "sg.h"
@@ -94,8 +97,10 @@ struct Lat {
     int Lx, Ly, Lz;
     uint32_t periodic;
     int n;
-    std::vector<int8_t> J;   // [n][3]
-    std::vector<int8_t> h;   // [n]
+    std::vector<int8_t> J;        // [n][3]
+    std::vector<int8_t> h;        // [n]
+    std::vector<int8_t> cmap;     // [n] given colour map, or empty: the closed form
+    int cmap_colours = 0;
     int len(int a) const { return a == 0 ? Lx : (a == 1 ? Ly : Lz); }
     int coord(int j, int a) const
     {
@@ -140,6 +145,19 @@ struct Lat {
         return s;
     }
     bool any_odd_ring() const { return odd_ring(0) || odd_ring(1) || odd_ring(2); }
+    // Spatial colouring (Methods, "Graph Coloring"): the given map, else the closed form
+    // (label sum mod 2, or mod 3 with an odd periodic axis).
+    int n_colours() const
+    {
+        if (!cmap.empty()) return std::max(cmap_colours, 1);
+        return any_odd_ring() ? 3 : 2;
+    }
+    int colour(int j) const
+    {
+        if (!cmap.empty()) return cmap[j];
+        const bool three = any_odd_ring();
+        return label_sum(j, three) % (three ? 3 : 2);
+    }
     int hmax() const
     {
         int m = 0;
@@ -376,18 +394,17 @@ size_t apt_lds_bytes(int npad, int n_rows, int ni, bool queue)
 // Colour classes of the spatial lattice (Methods, "Graph Coloring").
 void apt_records(const Lat &L, std::vector<uint4> &rec, std::vector<uint4> &recj, InstDev &I)
 {
-    const bool three = L.any_odd_ring();
-    const int C = three ? 3 : 2;
+    const int C = L.n_colours();
     I.n_colours = C;
     I.rec_off = (int64_t)rec.size();
     I.recj_off = (int64_t)recj.size();
     int off = 0;
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < kMaxColours; ++c) {
         I.col_off[c] = off;
         I.col_cnt[c] = 0;
         if (c >= C) continue;
         for (int j = 0; j < L.n; ++j)
-            if (L.label_sum(j, three) % C == c) {
+            if (L.colour(j) == c) {
                 rec.push_back(make_record(L, j, 0u));
                 ++I.col_cnt[c];
             }
@@ -397,18 +414,17 @@ void apt_records(const Lat &L, std::vector<uint4> &rec, std::vector<uint4> &recj
 }
 
 // Phases of the (d+1)-dimensional lattice with an even periodic Trotter ring:
-// colour(j, k) = (spatial label sum + k) mod C, so in phase c site j updates
-// the slices of parity p = (c - label sum) mod C when p is 0 or 1.
+// colour(j, k) = (spatial colour + k) mod C, C = max(spatial colours, 2), so in phase c
+// site j updates the slices of parity p = (c - spatial colour) mod C when p is 0 or 1.
 void sqa_records(const Lat &L, std::vector<uint4> &rec, std::vector<uint4> &recj, InstDev &I)
 {
     if (2 * L.n + 1 > 0xFFFF) fail(SG_EUNSUPPORTED, "DT-SQA lattice of %d sites is too large", L.n);
-    const bool three = L.any_odd_ring();
-    const int C = three ? 3 : 2;
+    const int C = std::max(L.n_colours(), 2);
     I.n_colours = C;
     I.rec_off = (int64_t)rec.size();
     I.recj_off = (int64_t)recj.size();
     int off = 0;
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < kMaxColours; ++c) {
         I.col_off[c] = off;
         I.col_cnt[c] = 0;
         I.col_p1[c] = 0;
@@ -418,7 +434,7 @@ void sqa_records(const Lat &L, std::vector<uint4> &rec, std::vector<uint4> &recj
         for (int pp = 0; pp < 2; ++pp) {
             if (pp == 1) I.col_p1[c] = I.col_cnt[c];
             for (int j = 0; j < L.n; ++j) {
-                const int p = ((c - L.label_sum(j, three)) % C + C) % C;
+                const int p = ((c - L.colour(j)) % C + C) % C;
                 if (p != pp) continue;
                 uint4 rr = make_record(L, j, (uint32_t)p);
                 // neighbour fields -> word offsets 2 nb + p into the replica's spin words
@@ -540,11 +556,35 @@ std::vector<QuadDesc> make_quad_descs(const std::vector<Lat> &lat, int n_quads,
     return out;
 }
 
-void build_common(sg_ctx *c, const sg_config *cfg)
+// A given colour map: values 0..kMaxColours-1, and no two sites joined by a bond (J != 0)
+// share a colour, so that every colour class can be updated in parallel.
+void set_colour_map(Lat &L, const int8_t *map, int idx)
+{
+    int C = 1;
+    for (int j = 0; j < L.n; ++j) {
+        if (map[j] < 0 || map[j] >= kMaxColours)
+            fail(SG_EINVAL, "instance %d: colour of site %d must be in 0..%d", idx, j, kMaxColours - 1);
+        C = std::max(C, (int)map[j] + 1);
+    }
+    for (int j = 0; j < L.n; ++j)
+        for (int a = 0; a < 3; ++a) {
+            const int nb = L.nbr(j, a, +1);
+            if (nb >= 0 && nb != j && L.coupling(j, a, +1) != 0 && map[nb] == map[j])
+                fail(SG_EINVAL, "instance %d: bonded sites %d and %d share colour %d", idx, j, nb,
+                     (int)map[j]);
+        }
+    L.cmap.assign(map, map + L.n);
+    L.cmap_colours = C;
+}
+
+void build_common(sg_ctx *c, const sg_config *cfg, const int8_t *const *colour = nullptr)
 {
     if (cfg->n_inst < 1) fail(SG_EINVAL, "n_inst must be >= 1");
     if (!cfg->inst) fail(SG_EINVAL, "inst is NULL");
-    for (int i = 0; i < cfg->n_inst; ++i) c->lat.push_back(copy_lattice(cfg->inst[i], i));
+    for (int i = 0; i < cfg->n_inst; ++i) {
+        c->lat.push_back(copy_lattice(cfg->inst[i], i));
+        if (colour && colour[i]) set_colour_map(c->lat.back(), colour[i], i);
+    }
     c->n_inst = cfg->n_inst;
     for (auto &L : c->lat) {
         c->n_max = std::max(c->n_max, L.n);
@@ -554,7 +594,7 @@ void build_common(sg_ctx *c, const sg_config *cfg)
 }
 
 // --------------------------------------------------------------------- APT
-void create_apt(sg_ctx *c, const sg_config *cfg)
+void create_apt(sg_ctx *c, const sg_config *cfg, const int8_t *const *colour = nullptr)
 {
     if (cfg->n_beta < 2) fail(SG_EINVAL, "n_beta must be >= 2");
     if (!cfg->beta) fail(SG_EINVAL, "beta is NULL");
@@ -574,7 +614,7 @@ void create_apt(sg_ctx *c, const sg_config *cfg)
             if (b > 0 && !(v > c->beta[(size_t)i * c->n_beta + b - 1]))
                 fail(SG_EINVAL, "beta must be strictly ascending");
         }
-    build_common(c, cfg);
+    build_common(c, cfg, colour);
     init_stream(c, cfg->hip_stream);
     hipStream_t s = c->stream;
     const int nb4 = 4 * c->n_quads;   // physical buffers per instance (slots padded to a quad)
@@ -784,14 +824,14 @@ bool any_field(const sg_ctx *c)
 }
 
 // --------------------------------------------------------------------- DT-SQA
-void create_sqa(sg_ctx *c, const sg_config *cfg)
+void create_sqa(sg_ctx *c, const sg_config *cfg, const int8_t *const *colour = nullptr)
 {
     if (cfg->M < 2 || cfg->M > 64) fail(SG_EINVAL, "M must be in 2..64");
     if (cfg->M & 1) fail(SG_EUNSUPPORTED, "odd M (Trotter ring with three colours) is not implemented");
     if (cfg->R < 1 || cfg->R > 65535) fail(SG_EINVAL, "R must be in 1..65535");
     if (!(cfg->sqa_beta > 0.0) || !std::isfinite(cfg->sqa_beta)) fail(SG_EINVAL, "sqa_beta must be > 0");
     if ((int64_t)cfg->n_inst * cfg->R > (1 << 28)) fail(SG_ENOMEM, "too many replicas");
-    build_common(c, cfg);
+    build_common(c, cfg, colour);
     init_stream(c, cfg->hip_stream);
     c->M = cfg->M;
     c->R = cfg->R;
@@ -1167,7 +1207,9 @@ void sg::set_global_error(const char *msg) { g_create_error = msg ? msg : ""; }
 // ====================================================================== C ABI
 extern "C" {
 
-sg_status sg_create(const sg_config *cfg, sg_ctx **out)
+sg_status sg_create(const sg_config *cfg, sg_ctx **out) { return sg_create_ex(cfg, nullptr, out); }
+
+sg_status sg_create_ex(const sg_config *cfg, const int8_t *const *colour, sg_ctx **out)
 {
     if (!out) return SG_EINVAL;
     *out = nullptr;
@@ -1176,8 +1218,8 @@ sg_status sg_create(const sg_config *cfg, sg_ctx **out)
         if (!cfg) fail(SG_EINVAL, "config is NULL");
         c = new sg_ctx();
         c->mode = cfg->mode;
-        if (cfg->mode == SG_APT) create_apt(c, cfg);
-        else if (cfg->mode == SG_SQA) create_sqa(c, cfg);
+        if (cfg->mode == SG_APT) create_apt(c, cfg, colour);
+        else if (cfg->mode == SG_SQA) create_sqa(c, cfg, colour);
         else fail(SG_EINVAL, "mode must be SG_APT or SG_SQA");
         hip_check(hipStreamSynchronize(c->stream), "create");
     } catch (const Failure &e) {
@@ -1191,6 +1233,63 @@ sg_status sg_create(const sg_config *cfg, sg_ctx **out)
     }
     g_create_error.clear();
     *out = c;
+    return SG_OK;
+}
+
+sg_status sg_dsatur_colouring(const sg_lattice *inst, int8_t *colour_out, int32_t *n_colours)
+{
+    try {
+        if (!inst || !colour_out || !n_colours) fail(SG_EINVAL, "NULL argument");
+        const Lat L = copy_lattice(*inst, 0);
+        // interaction graph: sites joined by a bond with J != 0
+        std::vector<std::array<int, 6>> adj((size_t)L.n);
+        std::vector<int> deg((size_t)L.n, 0);
+        for (int j = 0; j < L.n; ++j)
+            for (int a = 0; a < 3; ++a)
+                for (int dir = -1; dir <= 1; dir += 2) {
+                    const int nb = L.nbr(j, a, dir);
+                    if (nb < 0 || nb == j || L.coupling(j, a, dir) == 0) continue;
+                    bool seen = false;   // an axis of length 2 reaches one neighbour twice
+                    for (int k = 0; k < deg[j]; ++k) seen |= adj[j][k] == nb;
+                    if (!seen) adj[j][deg[j]++] = nb;
+                }
+        // Brelaz's DSATUR: repeatedly colour the uncoloured site with the most distinct
+        // neighbour colours (ties: most uncoloured neighbours, then lowest index) with the
+        // smallest colour none of its neighbours has.
+        std::vector<int> col((size_t)L.n, -1), udeg(deg), sat((size_t)L.n, 0);
+        std::vector<uint32_t> seen((size_t)L.n, 0u);   // bit c: a neighbour has colour c
+        std::set<std::tuple<int, int, int>> open;       // (-sat, -udeg, site)
+        for (int j = 0; j < L.n; ++j) open.insert({0, -udeg[j], j});
+        int C = 1;
+        while (!open.empty()) {
+            const int v = std::get<2>(*open.begin());
+            open.erase(open.begin());
+            int cv = 0;
+            while ((seen[v] >> cv) & 1u) ++cv;
+            col[v] = cv;
+            C = std::max(C, cv + 1);
+            for (int k = 0; k < deg[v]; ++k) {
+                const int u = adj[v][k];
+                if (col[u] >= 0) continue;
+                open.erase({-sat[u], -udeg[u], u});
+                --udeg[u];
+                if (!((seen[u] >> cv) & 1u)) {
+                    seen[u] |= 1u << cv;
+                    ++sat[u];
+                }
+                open.insert({-sat[u], -udeg[u], u});
+            }
+        }
+        if (C > kMaxColours) fail(SG_EUNSUPPORTED, "the colouring needs %d > %d colours", C, kMaxColours);
+        for (int j = 0; j < L.n; ++j) colour_out[j] = (int8_t)col[j];
+        *n_colours = C;
+    } catch (const Failure &e) {
+        g_create_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_create_error = "host allocation failed";
+        return SG_ENOMEM;
+    }
     return SG_OK;
 }
 

@@ -21,6 +21,7 @@ enum : uint32_t {
     TAG_ADAPT_SWEEP = 9,
 };
 
+constexpr int kMaxColours = 4;   // colour classes of a given colour map
 constexpr int kMaxH = 31;      // |h| bound, so that h + 32 fits 6 bits of a site record
 constexpr int kMaxN = 32767;   // sites per instance (16-bit site and neighbour indices)
 constexpr int kQuadThreads = 256;
@@ -45,11 +46,11 @@ constexpr size_t kMaxLds = 160 * 1024;   // LDS per CU on gfx950
 struct InstDev {
     int32_t n;           // sites
     int32_t npad;        // sites rounded up to a multiple of 16
-    int32_t n_colours;   // colour classes (APT) or phases (DT-SQA)
+    int32_t n_colours;   // colour classes (APT) or phases (DT-SQA), at most kMaxColours
     int32_t n_slots;     // APT: n_beta * reps; DT-SQA: M
-    int32_t col_off[3];  // first record of each colour class / phase (relative)
-    int32_t col_cnt[3];  // records in each class / phase
-    int32_t col_p1[3];   // DT-SQA: records of parity 0 at the start of each phase (the rest
+    int32_t col_off[4];  // first record of each colour class / phase (relative)
+    int32_t col_cnt[4];  // records in each class / phase
+    int32_t col_p1[4];   // DT-SQA: records of parity 0 at the start of each phase (the rest
                          // have parity 1)
     int64_t rec_off;     // colour-sorted (or phase) records
     int64_t recj_off;    // site-ordered records

@@ -60,3 +60,20 @@ def linear_gamma(n_steps, start=3.0, end=0.01):
 def mixed_sizes(n_inst, sizes=(6, 8, 10, 12, 15)):
     """Round-robin lattice sizes for a batch of instances."""
     return [sizes[i % len(sizes)] for i in range(n_inst)]
+
+
+def missing_spin_couplings(shape, periodic=7, seed=0, n_missing=1):
+    """+-1 couplings with `n_missing` randomly chosen sites removed: every bond of a missing
+    site is 0, so it is isolated (the paper's L = 10 instances have 999 of 1000 spins)."""
+    J, _ = ej_couplings(shape, periodic, seed)
+    if np.isscalar(shape):
+        shape = (int(shape),) * 3
+    Lx, Ly, Lz = (int(v) for v in shape)
+    rng = np.random.default_rng(np.random.SeedSequence([0x5717, int(seed)]))
+    for j in rng.choice(Lx * Ly * Lz, size=n_missing, replace=False):
+        x, y, z = j % Lx, (j // Lx) % Ly, j // (Lx * Ly)
+        J[z, y, x, :] = 0
+        J[z, y, (x - 1) % Lx, 0] = 0
+        J[z, (y - 1) % Ly, x, 1] = 0
+        J[(z - 1) % Lz, y, x, 2] = 0
+    return J

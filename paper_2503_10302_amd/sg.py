@@ -53,7 +53,7 @@ class _Adaptive(C.Structure):
 
 
 EXPORTS = [
-    "sg_create", "sg_destroy", "sg_last_error", "sg_sweep", "sg_icm", "sg_energy", "sg_swap",
+    "sg_create", "sg_create_ex", "sg_dsatur_colouring", "sg_destroy", "sg_last_error", "sg_sweep", "sg_icm", "sg_energy", "sg_swap",
     "sg_run_apt", "sg_run_apt_ex", "sg_icm_ex", "sg_best", "sg_swap_counts", "sg_sqa_anneal", "sg_get_launch_config",
     "sg_set_launch_config", "sg_get_spins", "sg_get_spins_range", "sg_set_spins",
     "sg_get_counters", "sg_get_state", "sg_set_state", "sg_timer_start", "sg_timer_stop",
@@ -76,6 +76,8 @@ def load():
     P, i32, i64, u64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
     sig = {
         "sg_create": (i32, [C.POINTER(_Config), C.POINTER(P)]),
+        "sg_create_ex": (i32, [C.POINTER(_Config), P, C.POINTER(P)]),
+        "sg_dsatur_colouring": (i32, [C.POINTER(_Lattice), P, C.POINTER(i32)]),
         "sg_destroy": (None, [P]),
         "sg_last_error": (C.c_char_p, [P]),
         "sg_sweep": (i32, [P, i32]),
@@ -142,7 +144,9 @@ def _lattices(instances):
 class Context:
     """One libsg context (APT or DT-SQA) over a batch of instances."""
 
-    def __init__(self, instances, mode, seed, beta=None, reps_per_beta=2, M=0, R=0, sqa_beta=0.0):
+    def __init__(self, instances, mode, seed, beta=None, reps_per_beta=2, M=0, R=0, sqa_beta=0.0,
+                 colours=None):
+        """colours: optional list of per-instance colour maps ([n] int8 or None)."""
         self.lib = load()
         self._arr, self._keep = _lattices(instances)
         self.n_inst = len(instances)
@@ -165,7 +169,16 @@ class Context:
                       M, R, float(sqa_beta), int(seed) & (2 ** 64 - 1), None)
         self._cfg_keep = bt
         h = C.c_void_p()
-        rc = self.lib.sg_create(C.byref(cfg), C.byref(h))
+        if colours is None:
+            rc = self.lib.sg_create(C.byref(cfg), C.byref(h))
+        else:
+            maps = [None if m is None else np.ascontiguousarray(m, dtype=np.int8).reshape(-1)
+                    for m in colours]
+            if len(maps) != self.n_inst:
+                raise ValueError("one colour map (or None) per instance expected")
+            ptrs = (C.c_void_p * self.n_inst)(*[None if m is None else m.ctypes.data for m in maps])
+            self._maps = (maps, ptrs)
+            rc = self.lib.sg_create_ex(C.byref(cfg), ptrs, C.byref(h))
         if rc != SG_OK:
             raise SGError(rc, self.lib.sg_last_error(None).decode())
         self.h = h
@@ -334,12 +347,25 @@ class Context:
         return ms.value, n.value
 
 
-def apt(instances, beta, seed, reps_per_beta=2):
-    return Context(instances, SG_APT, seed, beta=beta, reps_per_beta=reps_per_beta)
+def apt(instances, beta, seed, reps_per_beta=2, colours=None):
+    return Context(instances, SG_APT, seed, beta=beta, reps_per_beta=reps_per_beta, colours=colours)
 
 
-def sqa(instances, M, R, beta, seed):
-    return Context(instances, SG_SQA, seed, M=M, R=R, sqa_beta=beta)
+def sqa(instances, M, R, beta, seed, colours=None):
+    return Context(instances, SG_SQA, seed, M=M, R=R, sqa_beta=beta, colours=colours)
+
+
+def dsatur(instance):
+    """DSATUR colouring of one instance (J, periodic, h): (colour map [n] int8, colours)."""
+    lib = load()
+    arr, keep = _lattices([instance])
+    n = arr[0].Lx * arr[0].Ly * arr[0].Lz
+    col = np.zeros(n, np.int8)
+    nc = C.c_int32(0)
+    rc = lib.sg_dsatur_colouring(arr, _p(col), C.byref(nc))
+    if rc != SG_OK:
+        raise SGError(rc, lib.sg_last_error(None).decode())
+    return col, nc.value
 
 
 def adaptive_ladder(instances, seed, beta0=0.5, alpha=1.25, tol=0.5, n_chains=100, sweeps=10000,

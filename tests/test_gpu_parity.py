@@ -14,7 +14,7 @@ import pytest
 import oracle
 from paper_2503_10302_amd import sg
 from paper_2503_10302_amd.inputs import (diluted_couplings, ej_couplings, geometric_ladder,
-                                         linear_gamma, mixed_sizes)
+                                         linear_gamma, missing_spin_couplings, mixed_sizes)
 
 pytestmark = pytest.mark.gpu
 SEED = 0x5EED_1234_ABCD
@@ -230,6 +230,62 @@ def test_icm_one_pair_records_match_oracle():
             assert rc == 0
             assert np.array_equal(info[i], oinfo), f"call {call}, instance {i}"
             assert np.array_equal(g[i, :, :l.n], osp[i]), f"call {call}, instance {i}"
+
+
+def _coloured_instances():
+    """Irregular instances with given colour maps: DSATUR maps of a heavily diluted odd
+    periodic lattice, a lattice with a missing spin (open x, y) and an odd periodic cube, and a
+    four-colour map (checkerboard classes split at random) of an even periodic cube."""
+    insts = [(diluted_couplings((7, 6, 5), 7, 31, 0.75), 7, None),
+             (missing_spin_couplings((10, 10, 10), 4, 32, 1), 4, None),
+             (ej_couplings((5, 5, 5), 7, 33)[0], 7, None),
+             (ej_couplings((6, 6, 4), 7, 34)[0], 7, None)]
+    maps = [sg.dsatur(x)[0] for x in insts[:3]]
+    base = (np.indices((4, 6, 6)).sum(axis=0) % 2).reshape(-1)
+    maps.append((base + 2 * (np.random.default_rng(35).random(base.size) < 0.5)).astype(np.int8))
+    return insts, maps
+
+
+def test_colour_maps_apt_match_oracle():
+    """APT+ICM with given colour maps against the oracle with the same maps: spins, traces and
+    swap counts.  The maps include two colours on an odd lattice (dilution removed its odd
+    cycles; the closed form would use three) and four colours."""
+    insts, maps = _coloured_instances()
+    ncol = [int(m.max()) + 1 for m in maps]
+    assert 4 in ncol and ncol[0] == 2
+    beta = geometric_ladder(8, 0.2, 3.0)
+    ctx = sg.apt(insts, beta, SEED + 11, reps_per_beta=2, colours=maps)
+    tr = ctx.run_apt(40, 1, 1.0, record_every=4)
+    g = ctx.spins()
+    for i, ((J, per, h), m) in enumerate(zip(insts, maps)):
+        l = oracle.Lattice(J, per, h, m)
+        sp = oracle.apt_init(l, i, beta.size * 2, SEED + 11)
+        ctr = np.zeros(3, np.uint32)
+        E = np.zeros(beta.size * 2, np.int64)
+        b = np.array([np.iinfo(np.int64).max], np.int64)
+        rc, otr, _ = oracle.apt_run(l, i, beta, 2, SEED + 11, 40, 1, 1.0, 4, ctr, sp, E, b)
+        assert rc == 0
+        assert np.array_equal(g[i, :, :l.n], sp), f"instance {i}"
+        assert np.array_equal(tr[i], otr), f"instance {i}"
+
+
+def test_colour_maps_sqa_match_oracle():
+    """DT-SQA with the same maps (slice k of site j coloured (map[j] + k mod 2) mod C): spins,
+    slice energies and the minimum, against the oracle."""
+    insts, maps = _coloured_instances()
+    M, R, beta = 8, 3, 2.0
+    ctx = sg.sqa(insts, M, R, beta, SEED + 12, colours=maps)
+    gam = linear_gamma(9)
+    bE, bs = ctx.sqa_anneal(gam)
+    g = ctx.spins()
+    E = ctx.energy()
+    for i, ((J, per, h), m) in enumerate(zip(insts, maps)):
+        l = oracle.Lattice(J, per, h, m)
+        sp = oracle.sqa_init(l, i, M, R, SEED + 12)
+        obE, obs, osE = oracle.sqa_anneal(l, i, M, R, beta, gam, SEED + 12, 0, sp)
+        assert np.array_equal(g[i, :, :, :l.n], sp), f"instance {i}"
+        assert np.array_equal(E[i], osE) and bE[i] == obE
+        assert np.array_equal(bs[i, :l.n], obs)
 
 
 def test_apt_with_fields_and_open_axes():

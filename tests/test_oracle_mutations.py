@@ -1,6 +1,7 @@
 """Planted mistakes: each test builds a copy of the oracle with one plausible mistake (a
 wrong sign, a dropped term, a wrong factor or index) and checks that the oracle's pin suite
-(tests/test_oracle_basic.py, tests/test_oracle_sampling.py) fails against it.  The mutated
+(tests/test_oracle_basic.py, tests/test_oracle_sampling.py, tests/test_colouring_cpu.py) fails
+against it.  The mutated
 copies live in a temporary directory; the oracle itself is untouched."""
 import os
 import subprocess
@@ -48,6 +49,8 @@ MUTANTS = [
     ("sqa_init_biased_threshold", "spins[((int64_t)r * M + k) * n + j] = (w < 0x80000000u) ? 1 : -1;",
      "spins[((int64_t)r * M + k) * n + j] = (w < 0x40000000u) ? 1 : -1;"),
     ("sqa_init_one_word_per_block", "SGO_TAG_SQA_INIT, (k >> 1) & 3);", "SGO_TAG_SQA_INIT, 0);"),
+    ("colour_map_drops_trotter_label", "if (lat->colour) return (lat->colour[j] + trotter_label(M, k)) % C;",
+     "if (lat->colour) return lat->colour[j] % C;"),
     ("icm_one_pair_always_first",
      "only = (int32_t)(sgo_word(seed, (uint32_t)b, a, 0u, inst, SGO_TAG_ICM_PAIR, 1) >> 31);",
      "only = 0;"),
@@ -68,7 +71,8 @@ def _run_mutant(tmp, name, old, new):
                            "-shared", "-o", so, os.path.join(d, "sg_oracle.c"), "-lm"])
     env = dict(os.environ, SG_ORACLE_SO=so, PYTHONDONTWRITEBYTECODE="1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        "tests/test_oracle_basic.py", "tests/test_oracle_sampling.py"],
+                        "tests/test_oracle_basic.py", "tests/test_oracle_sampling.py",
+                        "tests/test_colouring_cpu.py"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
     failed = [l for l in r.stdout.splitlines() if l.startswith("FAILED")]
     return name, r.returncode, failed[:1]
