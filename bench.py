@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -380,6 +381,126 @@ def apt_ablation(n_inst=128, L=8, budget=100000,
             "rho": table}
 
 
+def _e0_apt(insts, cycles, seeds=(101, 202)):
+    """Lowest energy per instance over long batched APT+ICM runs (32 geometric betas in
+    [0.2, 3.0], 2 labels, ICM at beta >= 1): the reference E0 for Eq. (2) when the instances'
+    ground energies are not known."""
+    from paper_2503_10302_amd import sg
+    from paper_2503_10302_amd.inputs import geometric_ladder
+    E0 = np.full(len(insts), np.iinfo(np.int64).max)
+    for sd in seeds:
+        c = sg.apt(insts, geometric_ladder(32, 0.2, 3.0), seed=sd, reps_per_beta=2)
+        c.run_apt(cycles, 1, 1.0)
+        E0 = np.minimum(E0, c.best())
+        c.close()
+    return E0
+
+
+def evt_study(n_inst=32, L=15, M=32, R=1024, lengths=(50, 100, 200, 500, 1000, 2000), e0_cycles=30000):
+    """DT-SQA extreme-value study (Supplementary EVT section, Figs. S4-S8) on the extreme-value
+    workload's instances (periodic L = 15 +-J, seeds 20000+), M = 32 Trotter slices (the paper's
+    32 replicas), beta = M / 2, R independent replicas (the paper's P runs), Gamma linear
+    3.0 -> 0.01 over t_a steps.  Per t_a:
+      * conventional EVT: the best slice of every independent replica; the measured residual of
+        the best of P replicas (disjoint groups) against the prediction a + sqrt(2) b
+        erfc^-1(2^((P-1)/P)) from the per-instance mean and spread of single-replica residuals;
+      * modified EVT: the self-consistent block size along the Trotter ring;
+      * C_k, the correlation with slice 0 (mean over instances and replicas), and the first k
+        where it falls below 1/e;
+    and kappa_f (Eq. 3) of the best of P = 1, 32 and R replicas against t_a."""
+    from paper_2503_10302_amd import analysis as A
+    from paper_2503_10302_amd import sg
+    from paper_2503_10302_amd.inputs import linear_gamma
+    insts, _, _, _ = sqa_workload(64, n_inst=n_inst, L=L)
+    n = L ** 3
+    beta = M / 2.0
+    E0 = _e0_apt(insts, e0_cycles)
+    print("evt-study: E0 reference runs done", file=sys.stderr, flush=True)
+    runs = {}
+    for T in lengths:
+        ctx = sg.sqa(insts, M, R, beta, seed=8000 + T)
+        ctx.sqa_anneal(linear_gamma(T))
+        sE = ctx.energy()
+        agree = ctx.trotter_agreement()
+        ctx.close()
+        E0 = np.minimum(E0, sE.reshape(n_inst, -1).min(axis=1))
+        runs[T] = (sE, agree)
+        print(f"evt-study: t_a = {T} done", file=sys.stderr, flush=True)
+    Ps = [P for P in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024) if P <= R]
+    out = {}
+    rho_best = {P: [] for P in (1, 32, R)}
+    for T, (sE, agree) in runs.items():
+        best = sE.min(axis=2)
+        conv = {}
+        for P in Ps:
+            pred, meas, a, b = A.evt_prediction(best, E0, n, P)
+            conv[str(P)] = {"predicted": round(pred, 6), "measured": round(meas, 6)}
+        for P in rho_best:
+            rho_best[P].append(A.evt_prediction(best, E0, n, P)[1])
+        mod = A.block_size_fit(sE, E0, n)
+        Ck = A.trotter_correlation(agree, n)
+        below = np.flatnonzero(Ck[:M // 2 + 1] < math.exp(-1.0))
+        out[str(T)] = {
+            "conventional_evt": conv,
+            "single_replica_a_b": [round(A.evt_prediction(best, E0, n, 1)[2], 6),
+                                   round(A.evt_prediction(best, E0, n, 1)[3], 6)],
+            "modified_evt": {"block_size": mod["block_size"], "closest": mod["closest"],
+                             "measured": round(mod["measured"], 6),
+                             "predicted_by_block": {str(B): round(v["predicted"], 6)
+                                                    for B, v in mod["table"].items()}},
+            "C_k": [round(float(c), 4) for c in Ck[:M // 2 + 1]],
+            "corr_length_1_over_e": int(below[0]) if below.size else None}
+    kap = {}
+    for P, rho in rho_best.items():
+        f = A.power_law_fit(np.array(lengths, float), np.array(rho))
+        kap[str(P)] = {"kappa": round(f["kappa"], 4), "ci95": [round(v, 4) for v in f["ci"]],
+                       "rho": [round(r, 6) for r in rho]}
+    return {"metric": f"DT-SQA extreme-value study ({n_inst} periodic L={L} instances, M={M} slices, "
+                      f"beta={beta}, R={R} independent replicas)",
+            "e0": f"min over two {e0_cycles}-cycle batched APT+ICM runs and every slice here",
+            "t_a": list(lengths), "by_t_a": out, "kappa_best_of_P": kap}
+
+
+def sqa_plateaus(Ls=(8, 10, 12, 15), Ms=(16, 32, 64), lengths=(100, 300, 1000, 3000, 10000),
+                 R=64, n_inst=32, e0_cycles=30000):
+    """DT-SQA residual energy against annealing time for lattice sizes L and Trotter slice counts
+    M (Supplementary Fig. S3): periodic +-J instances (seeds 20000+), beta = M / 2, Gamma linear
+    3.0 -> 0.01, R independent replicas per instance; rho(t_a) = mean over instances and replicas
+    of (best slice - E0) / n with a 95 % bootstrap interval across instances, and the slope
+    kappa_f (Eq. 3) over the first three annealing times."""
+    from paper_2503_10302_amd import analysis as A
+    from paper_2503_10302_amd import sg
+    from paper_2503_10302_amd.inputs import linear_gamma
+    out = {}
+    for L in Ls:
+        insts, _, _, _ = sqa_workload(64, n_inst=n_inst, L=L)
+        n = L ** 3
+        E0 = _e0_apt(insts, e0_cycles)
+        res = {}
+        for M in Ms:
+            for T in lengths:
+                ctx = sg.sqa(insts, M, R, M / 2.0, seed=9000 + M + T)
+                ctx.sqa_anneal(linear_gamma(T))
+                sE = ctx.energy()
+                ctx.close()
+                best = sE.min(axis=2)
+                E0 = np.minimum(E0, best.min(axis=1))
+                res[(M, T)] = best
+        for M in Ms:
+            per_inst = [A.residual(res[(M, T)], E0[:, None], n).mean(axis=1) for T in lengths]
+            rho = [float(x.mean()) for x in per_inst]
+            ci = [A.bootstrap_ci(x) for x in per_inst]
+            f = A.power_law_fit(np.array(lengths[:3], float), np.array(rho[:3]))
+            out[f"L{L}_M{M}"] = {"rho": [round(r, 6) for r in rho],
+                                 "ci95": [[round(a, 6), round(b, 6)] for a, b in ci],
+                                 "kappa_first3": round(f["kappa"], 4)}
+        print(f"sqa-plateaus: L = {L} done", file=sys.stderr, flush=True)
+    return {"metric": f"DT-SQA rho(t_a) by L and M ({n_inst} periodic instances per L, R={R} "
+                      "independent replicas, beta = M/2)", "t_a": list(lengths),
+            "e0": f"min over two {e0_cycles}-cycle batched APT+ICM runs and every run here",
+            "curves": out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -409,6 +530,10 @@ def main():
     ap.add_argument("--ablation", action="store_true",
                     help="APT+ICM ablations: ICM on/off, labels, ICMs per sweep, sweep-to-swap ratio")
     ap.add_argument("--ablation-L", type=int, default=8)
+    ap.add_argument("--evt-study", action="store_true",
+                    help="DT-SQA extreme-value study: conventional and modified EVT, C_k, kappa_f")
+    ap.add_argument("--sqa-plateaus", action="store_true",
+                    help="DT-SQA rho(t_a) by lattice size L and Trotter slices M")
     ap.add_argument("--valu-rates", action="store_true",
                     help="compile and run bench_valu.hip: issue rate of single VALU instruction "
                          "forms (the evidence for the ALU peak)")
@@ -435,6 +560,12 @@ def main():
 
     if args.ttt:
         print(json.dumps(time_to_target(e0_cycles=args.ttt_cycles)), flush=True)
+        return
+    if args.evt_study:
+        print(json.dumps(evt_study()), flush=True)
+        return
+    if args.sqa_plateaus:
+        print(json.dumps(sqa_plateaus()), flush=True)
         return
     if args.ablation:
         print(json.dumps(apt_ablation(L=args.ablation_L)), flush=True)

@@ -172,6 +172,12 @@ sg_status sg_swap_counts(sg_ctx *ctx, int64_t *counts_host);
 sg_status sg_sqa_anneal(sg_ctx *ctx, const double *gamma, int32_t n_steps, int64_t *best_E,
                         int8_t *best_state);
 
+/* DT-SQA: correlation along the Trotter direction of the current state (Supplementary
+ * correlation-length figure, C_k = (1/n) sum_i s_{i,0} s_{i,k} measured from slice 0),
+ * exactly: agree_host [n_inst][R][M] = number of sites where slice k of replica r agrees with
+ * its slice 0 (C_k = (2 agree - n) / n). */
+sg_status sg_sqa_trotter_agreement(sg_ctx *ctx, int32_t *agree_host);
+
 /* Launch configuration (an implementation choice; results do not depend on it).
  * DT-SQA contexts: the work-group size, a multiple of 64 in 128..1024.  The first
  * sg_sqa_anneal of a context whose size is unset (0) times 256, 512, 768 and 1024 for a few

@@ -86,6 +86,7 @@ def lib():
             "sgo_sqa_init": (None, [LP, u32, i32, i32, i32, u64, P]),
             "sgo_sqa_step": (None, [LP, u32, i32, i32, i32, dbl, dbl, u64, u32, P]),
             "sgo_sqa_anneal": (None, [LP, u32, i32, i32, i32, dbl, P, i32, u64, u32, P, P, P, P]),
+            "sgo_trotter_agreement": (None, [LP, i32, i32, P, P]),
             "sgo_adaptive_ladder": (i32, [LP, u32, C.POINTER(_AdaptiveParams), u64, P, P, P]),
             "sgo_sigma_from_moments": (dbl, [i64, i64, i64]),
             "sgo_instance_features": (None, [LP, P]),
@@ -241,6 +242,16 @@ def sqa_anneal(lat, inst, M, R, beta, gammas, seed, t0, spins, r0=0):
     lib().sgo_sqa_anneal(lat.c, inst, M, r0, R, float(beta), _ptr(g), g.size, seed, t0,
                          _ptr(spins), _ptr(sE), _ptr(bE), _ptr(bs))
     return int(bE[0]), bs, sE
+
+
+def trotter_agreement(lat, spins):
+    """spins [R, M, n] -> agree [R, M]: sites where slice k agrees with slice 0."""
+    s = np.ascontiguousarray(spins, dtype=np.int8)
+    R, M, n = s.shape
+    assert n == lat.n
+    out = np.zeros((R, M), np.int32)
+    lib().sgo_trotter_agreement(lat.c, M, R, _ptr(s), _ptr(out))
+    return out
 
 
 def adaptive_ladder(lat, inst, seed, beta0=0.5, alpha=1.25, tol=0.5, n_chains=100, sweeps=10000,

@@ -491,6 +491,24 @@ void sgo_sqa_anneal(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t r0
     if (best_state) memcpy(best_state, spins + arg * n, (size_t)n);
 }
 
+/* Correlation along the Trotter direction (Supplementary, correlation-length
+ * figure): C_r = (1/n) sum_i s_{i,0} s_{i,r}.  Returned exactly as the number of
+ * sites where slice r agrees with slice 0, agree[r][k] for replica r, slice k
+ * (C_k = (2 agree - n) / n). */
+void sgo_trotter_agreement(const sgo_lattice *lat, int32_t M, int32_t R, const int8_t *spins,
+                           int32_t *agree)
+{
+    int32_t n = sgo_n_sites(lat);
+    for (int32_t r = 0; r < R; ++r)
+        for (int32_t k = 0; k < M; ++k) {
+            const int8_t *s0 = spins + ((int64_t)r * M) * n;
+            const int8_t *sk = spins + ((int64_t)r * M + k) * n;
+            int32_t a = 0;
+            for (int32_t i = 0; i < n; ++i) a += (s0[i] * sk[i] > 0);
+            agree[r * M + k] = a;
+        }
+}
+
 /* ------------------------------------------------------------------------- */
 /* Adaptive inverse-temperature ladder (Algorithm S2 preprocessing; Methods  */
 /* "APT details"): chains run at beta_t, each chain's energy spread over the */

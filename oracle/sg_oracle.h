@@ -96,6 +96,10 @@ void sgo_sqa_anneal(const sgo_lattice *lat, uint32_t inst, int32_t M, int32_t r0
                     double beta, const double *gamma, int32_t n_steps, uint64_t seed, uint32_t t0,
                     int8_t *spins, int64_t *slice_E, int64_t *best_E, int8_t *best_state);
 
+/* Trotter-direction correlation: agree[r][k] = #{i : s_{i,0} = s_{i,k}} in replica r. */
+void sgo_trotter_agreement(const sgo_lattice *lat, int32_t M, int32_t R, const int8_t *spins,
+                           int32_t *agree);
+
 /* ---- adaptive beta ladder (Algorithm S2, preprocessing loop) ---- */
 typedef struct {
     double beta0, alpha, tol;

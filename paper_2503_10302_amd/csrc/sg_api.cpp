@@ -1656,6 +1656,20 @@ sg_status sg_sqa_anneal(sg_ctx *c, const double *gamma, int32_t n_steps, int64_t
     });
 }
 
+sg_status sg_sqa_trotter_agreement(sg_ctx *c, int32_t *agree_host)
+{
+    return guarded(c, [&] {
+        require(c, SG_SQA);
+        if (!agree_host) fail(SG_EINVAL, "agree_host is NULL");
+        DevBuf<int32_t> d;
+        d.alloc((size_t)c->n_inst * c->R * c->M, "correlation");
+        SqaArgs a = sqa_args(c);
+        hip_check(launch_sqa_corr(a, c->n_inst, d.p, c->stream), "correlation");
+        d.download(agree_host, d.n, c->stream, "correlation");
+        hip_check(hipStreamSynchronize(c->stream), "correlation");
+    });
+}
+
 sg_status sg_get_spins(sg_ctx *c, int8_t *out)
 {
     return guarded(c, [&] {

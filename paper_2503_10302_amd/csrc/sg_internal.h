@@ -202,6 +202,8 @@ hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, int thread
 // The slice chosen by best_key[i] of every instance as +1/-1 bytes, out[i][n_max].
 hipError_t launch_sqa_best_state(const SqaArgs &a, int n_inst, int n_max, int8_t *out,
                                  hipStream_t s);
+// agree[inst][r][k]: sites where slice k of replica r agrees with its slice 0.
+hipError_t launch_sqa_corr(const SqaArgs &a, int n_inst, int32_t *agree, hipStream_t s);
 hipError_t launch_adapt_init(const AdaptArgs &a, int n_inst, hipStream_t s);
 hipError_t launch_adapt(const AdaptArgs &a, int n_inst, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);

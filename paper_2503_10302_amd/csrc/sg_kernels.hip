@@ -1395,11 +1395,44 @@ __device__ __forceinline__ void sqa_site(const SqaArgs &A, const uint4 rr, uint3
     sp[2 * j + P] = res & mask;
 }
 
+// v += c for P-bit vertical counters (plane q = bit q of every bit position's count).
+template <int P>
+__device__ __forceinline__ void vadd(uint32_t v[P], uint32_t c)
+{
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const uint32_t d = v[q] & c;
+        v[q] ^= c;
+        c = d;
+    }
+}
+
+// Per-slice totals over a wave of the vertical counters v0 (slices 2h, bit h) and v1 (slices
+// 2h + 1): plane q of slice bit h across the 64 lanes is one ballot.  Returns, in lane
+// k = 2h + p, the wave's count for slice k (0 in lanes >= 2H).
+template <int P>
+__device__ __forceinline__ int32_t ballot_slice_counts(const uint32_t v0[P], const uint32_t v1[P], int H)
+{
+    const int lane = threadIdx.x & 63;
+    int32_t mine = 0;
+#pragma unroll
+    for (int h = 0; h < 32; ++h) {
+        if (h >= H) break;
+        int32_t u0 = 0, u1 = 0;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            u0 += (int32_t)__popcll(__ballot((v0[q] >> h) & 1u)) << q;
+            u1 += (int32_t)__popcll(__ballot((v1[q] >> h) & 1u)) << q;
+        }
+        mine = lane == 2 * h ? u0 : mine;
+        mine = lane == 2 * h + 1 ? u1 : mine;
+    }
+    return mine;
+}
+
 // Unsatisfied bonds of every slice of one replica (no fields): the calling thread folds the
 // forward bonds of its sites (j = tid, tid + threads, ...), 32 slices per parity word, into
-// P-bit vertical counters (plane q = bit q of every slice's count); the wave then reads plane
-// q of slice bit h across its 64 lanes with one ballot.  Returns, in lane k = 2h + p of each
-// wave, that wave's count for slice k (0 in lanes >= 2H).
+// P-bit vertical counters; ballot_slice_counts turns them into the wave's per-slice counts.
 template <int P>
 __device__ __forceinline__ int32_t sqa_unsat_counts(const uint4 *recj, const uint32_t *sp, int n,
                                                     int threads, uint32_t mask, int H)
@@ -1416,33 +1449,28 @@ __device__ __forceinline__ int32_t sqa_unsat_counts(const uint4 *recj, const uin
             // no bond (dummy neighbour): nothing to count
             const uint32_t live = nb == (uint32_t)n ? 0u : mask;
             const uint32_t neg = 0u - ((jn >> (2 * a)) & 1u);
-            uint32_t c0 = (w0 ^ sp[2 * nb] ^ neg) & live;
-            uint32_t c1 = (w1 ^ sp[2 * nb + 1] ^ neg) & live;
-#pragma unroll
-            for (int q = 0; q < P; ++q) {
-                const uint32_t d0 = v0[q] & c0, d1 = v1[q] & c1;
-                v0[q] ^= c0;
-                v1[q] ^= c1;
-                c0 = d0;
-                c1 = d1;
-            }
+            vadd<P>(v0, (w0 ^ sp[2 * nb] ^ neg) & live);
+            vadd<P>(v1, (w1 ^ sp[2 * nb + 1] ^ neg) & live);
         }
     }
-    const int lane = threadIdx.x & 63;
-    int32_t mine = 0;
+    return ballot_slice_counts<P>(v0, v1, H);
+}
+
+// Sites where slice k disagrees with slice 0 (word 0, bit 0), for every slice of one replica
+// held in global memory (pairs of words per site, as in SqaArgs::spins).
+template <int P>
+__device__ __forceinline__ int32_t sqa_disagree_counts(const uint32_t *g, int n, uint32_t mask, int H)
+{
+    uint32_t v0[P], v1[P];
 #pragma unroll
-    for (int h = 0; h < 32; ++h) {
-        if (h >= H) break;
-        int32_t u0 = 0, u1 = 0;
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-            u0 += (int32_t)__popcll(__ballot((v0[q] >> h) & 1u)) << q;
-            u1 += (int32_t)__popcll(__ballot((v1[q] >> h) & 1u)) << q;
-        }
-        mine = lane == 2 * h ? u0 : mine;
-        mine = lane == 2 * h + 1 ? u1 : mine;
+    for (int q = 0; q < P; ++q) v0[q] = v1[q] = 0u;
+    for (int j = threadIdx.x; j < n; j += 256) {
+        const uint2 w = *(const uint2 *)(g + 2 * j);
+        const uint32_t b = 0u - (w.x & 1u);
+        vadd<P>(v0, (w.x ^ b) & mask);
+        vadd<P>(v1, (w.y ^ b) & mask);
     }
-    return mine;
+    return ballot_slice_counts<P>(v0, v1, H);
 }
 
 // The work-group size is a launch-time choice (a multiple of 64, at most 1024);
@@ -1606,6 +1634,28 @@ void sqa_kernel(SqaArgs A)
             if (tid == 0) atomicMin((unsigned long long *)&A.best_key[inst], (unsigned long long)key);
         }
     }
+}
+
+// Correlation along the Trotter direction (C_k = (1/n) sum_i s_{i,0} s_{i,k}), exactly: the
+// number of sites where slice k agrees with slice 0, agree[inst][r][k], one work-group of 256
+// threads per replica.
+__global__ __launch_bounds__(256) void sqa_corr_kernel(SqaArgs A, int32_t *agree)
+{
+    __shared__ int32_t red[64];
+    const int inst = blockIdx.x / A.R, r = blockIdx.x - inst * A.R;
+    const InstDev I = A.inst[inst];
+    const uint32_t *g = A.spins + I.spin_off + (int64_t)r * I.npad * 2;
+    const int H = A.H, n = I.n, M = A.M;
+    const uint32_t mask = (H >= 32) ? 0xFFFFFFFFu : ((1u << H) - 1u);
+    if (threadIdx.x < 64) red[threadIdx.x] = 0;
+    const int per = (n + 255) / 256;
+    const int32_t mine = per < 32 ? sqa_disagree_counts<5>(g, n, mask, H)
+                                  : sqa_disagree_counts<kSqaPlanes>(g, n, mask, H);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    if (lane < M) atomicAdd(&red[lane], mine);
+    __syncthreads();
+    if (threadIdx.x < M) agree[((int64_t)inst * A.R + r) * M + threadIdx.x] = n - red[threadIdx.x];
 }
 
 // Spins of the slice that best_key[i] names (replica r, slice k = 2h + p: bit h of word p),
@@ -1987,6 +2037,12 @@ hipError_t launch_sqa_best_state(const SqaArgs &a, int n_inst, int n_max, int8_t
                                  hipStream_t s)
 {
     hipLaunchKernelGGL(sqa_best_state_kernel, dim3(n_inst), dim3(256), 0, s, a, n_max, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sqa_corr(const SqaArgs &a, int n_inst, int32_t *agree, hipStream_t s)
+{
+    hipLaunchKernelGGL(sqa_corr_kernel, dim3(n_inst * a.R), dim3(256), 0, s, a, agree);
     return hipGetLastError();
 }
 

@@ -54,7 +54,7 @@ class _Adaptive(C.Structure):
 
 EXPORTS = [
     "sg_create", "sg_create_ex", "sg_dsatur_colouring", "sg_destroy", "sg_last_error", "sg_sweep", "sg_icm", "sg_energy", "sg_swap",
-    "sg_run_apt", "sg_run_apt_ex", "sg_icm_ex", "sg_best", "sg_swap_counts", "sg_sqa_anneal", "sg_get_launch_config",
+    "sg_run_apt", "sg_run_apt_ex", "sg_icm_ex", "sg_best", "sg_swap_counts", "sg_sqa_anneal", "sg_sqa_trotter_agreement", "sg_get_launch_config",
     "sg_set_launch_config", "sg_get_spins", "sg_get_spins_range", "sg_set_spins",
     "sg_get_counters", "sg_get_state", "sg_set_state", "sg_timer_start", "sg_timer_stop",
     "sg_synchronize", "sg_kernel_timing", "sg_kernel_time", "sg_adaptive_ladder", "sg_mlp_create", "sg_mlp_destroy",
@@ -90,6 +90,7 @@ def load():
         "sg_best": (i32, [P, P]),
         "sg_swap_counts": (i32, [P, P]),
         "sg_sqa_anneal": (i32, [P, P, i32, P, P]),
+        "sg_sqa_trotter_agreement": (i32, [P, P]),
         "sg_get_launch_config": (i32, [P, P]),
         "sg_set_launch_config": (i32, [P, i32]),
         "sg_get_spins": (i32, [P, P]),
@@ -278,6 +279,12 @@ class Context:
         bs = np.zeros((self.n_inst, self.n_max), np.int8)
         self._check(self.lib.sg_sqa_anneal(self.h, _p(g), g.size, _p(bE), _p(bs)))
         return bE, bs
+
+    def trotter_agreement(self):
+        """DT-SQA: [n_inst, R, M] sites where slice k agrees with slice 0 of its replica."""
+        a = np.zeros((self.n_inst, self.R, self.M), np.int32)
+        self._check(self.lib.sg_sqa_trotter_agreement(self.h, _p(a)))
+        return a
 
     def launch_config(self):
         """DT-SQA work-group size, or APT configuration code (1..12); 0 until the autotuner

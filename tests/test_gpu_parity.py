@@ -288,6 +288,23 @@ def test_colour_maps_sqa_match_oracle():
         assert np.array_equal(bs[i, :l.n], obs)
 
 
+@pytest.mark.parametrize("M", [8, 16, 64])
+def test_trotter_agreement_matches_oracle(M):
+    """Correlation along the Trotter direction (agreement of every slice with slice 0) after an
+    anneal, against the oracle: ragged site counts, three-colour lattices, R > 1."""
+    insts = [_inst((5, 5, 5), 7, 41), _inst((7, 6, 3), 5, 42), _inst((9, 9, 9), 7, 43, 0, 0.2)]
+    R = 3
+    ctx = sg.sqa(insts, M, R, 3.0, SEED + 13)
+    gam = linear_gamma(12)
+    ctx.sqa_anneal(gam)
+    got = ctx.trotter_agreement()
+    for i, inst in enumerate(insts):
+        l = _olat(inst)
+        sp = oracle.sqa_init(l, i, M, R, SEED + 13)
+        oracle.sqa_anneal(l, i, M, R, 3.0, gam, SEED + 13, 0, sp)
+        assert np.array_equal(got[i], oracle.trotter_agreement(l, sp)), f"instance {i}"
+
+
 def test_apt_with_fields_and_open_axes():
     insts = [_inst((5, 4, 3), 0, 11, hmax=3), _inst((6, 6, 6), 7, 12, hmax=31), _inst((3, 3, 3), 2, 13, hmax=1)]
     beta = geometric_ladder(6, 0.3, 2.0)

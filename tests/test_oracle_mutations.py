@@ -51,6 +51,8 @@ MUTANTS = [
     ("sqa_init_one_word_per_block", "SGO_TAG_SQA_INIT, (k >> 1) & 3);", "SGO_TAG_SQA_INIT, 0);"),
     ("colour_map_drops_trotter_label", "if (lat->colour) return (lat->colour[j] + trotter_label(M, k)) % C;",
      "if (lat->colour) return lat->colour[j] % C;"),
+    ("trotter_agreement_with_previous_slice", "const int8_t *s0 = spins + ((int64_t)r * M) * n;",
+     "const int8_t *s0 = spins + ((int64_t)r * M + (k > 0 ? k - 1 : 0)) * n;"),
     ("icm_one_pair_always_first",
      "only = (int32_t)(sgo_word(seed, (uint32_t)b, a, 0u, inst, SGO_TAG_ICM_PAIR, 1) >> 31);",
      "only = 0;"),

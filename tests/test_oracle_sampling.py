@@ -398,6 +398,25 @@ def test_sqa_small_gamma_locks_slices():
     assert np.all(spins == spins[:, :1, :])
 
 
+def test_trotter_agreement_pins():
+    """C_k from agreement counts: 1 at k = 0, -1 for a reversed slice, 0 within 5 sigma for the
+    independent random slices of the initial state; after an anneal at vanishing transverse
+    field (J_perp large) from a locked state every slice agrees with slice 0."""
+    J, _ = ej_couplings((6, 5, 4), 7, seed=21)
+    lat = oracle.Lattice(J, 7)
+    M, R = 8, 6
+    s = oracle.sqa_init(lat, 0, M, R, SEED)
+    a = oracle.trotter_agreement(lat, s)
+    assert np.all(a[:, 0] == lat.n)
+    assert np.all(np.abs(a[:, 1:] - lat.n / 2) <= 5 * 0.5 * np.sqrt(lat.n))
+    s2 = s.copy()
+    s2[:, 3] = -s2[:, 0]
+    assert np.all(oracle.trotter_agreement(lat, s2)[:, 3] == 0)
+    locked = np.repeat(s[:, :1], M, axis=1).copy()
+    oracle.sqa_anneal(lat, 0, M, R, 2.0, np.full(20, 1e-6), SEED, 0, locked)
+    assert np.all(oracle.trotter_agreement(lat, locked) == lat.n)
+
+
 def test_sqa_anneal_reports_minimum_slice():
     J, _ = ej_couplings((4, 4, 4), 7, seed=22)
     lat = oracle.Lattice(J, 7)
