@@ -501,6 +501,91 @@ def sqa_plateaus(Ls=(8, 10, 12, 15), Ms=(16, 32, 64), lengths=(100, 300, 1000, 3
             "curves": out}
 
 
+def fss_study(Ls=(6, 8, 10, 12, 15), n_per_L=64, budget=100000, record_every=10, rho0=0.007,
+              e0_cycles=200000, seed0=70000, collapse_floor=2e-3):
+    """APT+ICM scaling with lattice size (Fig. 4a, Eq. 3, Supplementary Figs. S18-S19): periodic
+    +-J instances of each size L, all sizes in one batched context, 32 betas geometric in
+    [0.2, 3.0] x 4 labels, one sweep per swap, with ICM at beta >= 1 and without ICM.  Per L:
+    rho(t_a) (Eq. 2) with a 95 % bootstrap interval across instances; the MCS at which the mean
+    curve reaches rho0 = 0.007 and the median over instances of each instance's first MCS at
+    its target; kappa_f fitted over t_a = 1e2 .. 1e4.  The finite-size-scaling collapse
+    rescales t_a L^-mu and rho L^b; its spread (standard deviation of log(rho L^b) across sizes,
+    averaged over the common range) is reported at the paper's exponents (mu = 6.34 with ICM,
+    6.866 without, b = 3) and minimised over mu in [3, 12] at b = 3, over the sizes L >= 8 and
+    the points with rho >= collapse_floor (the paper's collapse breaks down near the ground
+    energies, where E0 is uncertain; L = 6 reaches its ground states within ~100 MCS).  E0 per
+    instance: the lowest energy of two e0_cycles-sweep runs (ICM, other seeds) and of every run
+    here."""
+    from paper_2503_10302_amd import analysis as A
+    from paper_2503_10302_amd import sg
+    from paper_2503_10302_amd.inputs import ej_couplings, geometric_ladder
+    sizes = np.repeat(np.array(Ls), n_per_L)
+    insts = [(ej_couplings(int(L), 7, seed=seed0 + i)[0], 7, None) for i, L in enumerate(sizes)]
+    n = sizes.astype(np.float64) ** 3
+    beta = geometric_ladder(32, 0.2, 3.0)
+    E0 = np.full(len(insts), np.iinfo(np.int64).max)
+    for sd in (301, 302):
+        c = sg.apt(insts, beta, seed=sd, reps_per_beta=4)
+        c.run_apt(e0_cycles, 1, 1.0)
+        E0 = np.minimum(E0, c.best())
+        c.close()
+        print(f"fss: reference run {sd} done", file=sys.stderr, flush=True)
+    traces = {}
+    for name, cut in (("icm", 1.0), ("no_icm", float("inf"))):
+        c = sg.apt(insts, beta, seed=310 if cut == 1.0 else 311, reps_per_beta=4)
+        c.synchronize()
+        c.timer_start()
+        traces[name] = c.run_apt(budget, 1, cut, record_every=record_every)
+        ms = c.timer_stop()
+        c.close()
+        E0 = np.minimum(E0, traces[name][:, -1])
+        print(f"fss: {name} run done ({ms / 1e3:.1f} s)", file=sys.stderr, flush=True)
+    t = np.arange(1, budget // record_every + 1) * record_every
+    pts = np.unique(np.round(np.logspace(np.log10(record_every), np.log10(budget), 25) / record_every)
+                    .astype(int)) * record_every
+    out = {}
+    for name, tr in traces.items():
+        res = (tr - E0[:, None]) / n[:, None]
+        curves, per_L = {}, {}
+        for L in Ls:
+            m = sizes == L
+            rho = res[m].mean(axis=0)
+            target = (E0[m] + rho0 * float(L) ** 3)[:, None]
+            hit = tr[m] <= target
+            first = np.where(hit.any(axis=1), t[hit.argmax(axis=1)], -1)
+            reach = np.flatnonzero(rho <= rho0)
+            sel = (t >= 100) & (t <= 10000) & (rho > 0)
+            f = A.power_law_fit(t[sel], rho[sel])
+            idx = np.searchsorted(t, pts)
+            per_L[str(L)] = {
+                "mcs_mean_curve_at_rho0": int(t[reach[0]]) if reach.size else None,
+                "mcs_median_instance_at_target": float(np.median(first[first > 0])) if (first > 0).any() else None,
+                "instances_reaching": int((first > 0).sum()),
+                "kappa_1e2_1e4": round(f["kappa"], 4), "kappa_ci95": [round(v, 4) for v in f["ci"]],
+                "rho_at": {str(int(tt)): round(float(rho[i]), 6) for tt, i in zip(pts, idx)},
+                "rho_ci95_at_1e3_1e4": [A.bootstrap_ci(res[m][:, np.searchsorted(t, 1000)]),
+                                        A.bootstrap_ci(res[m][:, np.searchsorted(t, 10000)])]}
+            if L >= 8:
+                keep = rho >= collapse_floor
+                curves[L] = (t[keep], rho[keep])
+        mus = np.linspace(3.0, 12.0, 181)
+        spread = [A.collapse_spread(curves, mu, 3.0) for mu in mus]
+        paper_mu = 6.34 if name == "icm" else 6.866
+        out[name] = {"by_L": per_L,
+                     "collapse_spread_paper_mu": round(A.collapse_spread(curves, paper_mu, 3.0), 4),
+                     "paper_mu": paper_mu,
+                     "best_mu_b3": round(float(mus[int(np.argmin(spread))]), 3),
+                     "collapse_spread_best_mu": round(float(min(spread)), 4)}
+    mcs = [out["icm"]["by_L"][str(L)]["mcs_mean_curve_at_rho0"] for L in Ls]
+    if all(v is not None for v in mcs):
+        f = A.power_law_fit(np.array(Ls, float), 1.0 / np.array(mcs, float))
+        out["icm"]["mcs_to_rho0_vs_L_exponent"] = round(f["kappa"], 3)
+    return {"metric": f"APT+ICM scaling with L ({n_per_L} periodic instances per L, 32 geometric "
+                      "betas in [0.2, 3.0] x 4 labels, 1 sweep per swap)",
+            "rho0": rho0, "e0": f"min over two {e0_cycles}-sweep ICM runs and every run here",
+            "results": out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -534,6 +619,8 @@ def main():
                     help="DT-SQA extreme-value study: conventional and modified EVT, C_k, kappa_f")
     ap.add_argument("--sqa-plateaus", action="store_true",
                     help="DT-SQA rho(t_a) by lattice size L and Trotter slices M")
+    ap.add_argument("--fss", action="store_true",
+                    help="APT+ICM with and without ICM by lattice size: MCS to rho0, kappa_f, collapse")
     ap.add_argument("--valu-rates", action="store_true",
                     help="compile and run bench_valu.hip: issue rate of single VALU instruction "
                          "forms (the evidence for the ALU peak)")
@@ -567,6 +654,9 @@ def main():
     if args.sqa_plateaus:
         print(json.dumps(sqa_plateaus()), flush=True)
         return
+    if args.fss:
+        print(json.dumps(fss_study()), flush=True)
+        return
     if args.ablation:
         print(json.dumps(apt_ablation(L=args.ablation_L)), flush=True)
         return
@@ -590,9 +680,13 @@ def main():
         return
     if args.learned:
         from paper_2503_10302_amd import ladder
-        res = ladder.evaluate(ladder.default_params(), n=256, cycles=args.ttt_cycles,
-                              e0_cycles=args.ttt_cycles, plain_sample=args.plain_sample)
-        res["metric"] = "time to residual energy per spin <= 0.007, 256 held-out L=15 instances"
+        res = {"metric": "time to residual energy per spin <= 0.007, 256 held-out L=15 instances: "
+                         "undiluted (seeds 90000+) and with up to 30 % of bonds removed (seeds 93000+)"}
+        for key, p_max, seed0 in (("undiluted", 0.0, 90000), ("diluted", 0.3, 93000)):
+            res[key] = ladder.evaluate(ladder.default_params(), ladder.default_tables(), n=256,
+                                       seed0=seed0, p_max=p_max, cycles=args.ttt_cycles,
+                                       e0_cycles=args.ttt_cycles, plain_sample=args.plain_sample)
+            print(f"learned: {key} done", file=sys.stderr, flush=True)
         print(json.dumps(res), flush=True)
         return
 
@@ -702,9 +796,11 @@ def default_time_to_target():
       * plain vs batched APT+ICM on the 256 mixed instances with the fixed geometric ladder
         (time_to_target: E0 from three 30000-cycle batched runs with other seeds);
       * batched adaptive vs batched learned ladder on 256 held-out L = 15 instances (the
-        adaptive stage at the Methods settings vs the shipped network, its pilot and band check),
-        and plain (one instance at a time, its own adaptive stage) on a sample of 4 instances
-        scaled to 256 (ladder.evaluate: E0 from two 20000-cycle runs and every run measured).
+        adaptive stage at the Methods settings vs the shipped network's flow: pilot, per-pair
+        band check, adaptive fallback), the per-size lookup table alone and through the same
+        judge, and plain (one instance at a time, its own adaptive stage) on a sample of 4
+        instances scaled to 256 (ladder.evaluate: runs of up to 30000 cycles, E0 from two
+        20000-cycle runs and every run measured).
     Each part is reported as an error string instead of stopping the benchmark if it fails."""
     res = {}
     try:
@@ -721,19 +817,22 @@ def default_time_to_target():
     print("bench: time to target, plain vs batched, done", file=sys.stderr, flush=True)
     try:
         from paper_2503_10302_amd import ladder
-        r = ladder.evaluate(ladder.default_params(), n=256, cycles=20000, pilot=1000,
-                            e0_cycles=20000, plain_sample=4)
+        r = ladder.evaluate(ladder.default_params(), ladder.default_tables(), n=256, cycles=30000,
+                            pilot=1000, e0_cycles=20000, plain_sample=4)
         res["learned_vs_adaptive_256_L15"] = {
-            "e0": "min over two 20000-cycle batched runs on the adaptive ladders and every run "
-                  "measured here",
+            "e0": r["e0"],
             "adaptive_total_s": r["adaptive"]["total_s"],
             "adaptive_ladder_s": r["adaptive"]["ladder_s"],
             "learned_total_s": r["learned"]["total_s"],
-            "learned_accepted": r["learned"]["accepted"], "learned_fallbacks": r["learned"]["fallbacks"],
+            "learned_ladder_s": r["learned"]["ladder_s"],
+            "learned_fallbacks": r["learned_fallbacks"],
+            "table_total_s": r.get("table", {}).get("total_s"),
+            "table_judged_total_s": r.get("table_judged", {}).get("total_s"),
+            "table_judged_fallbacks": r.get("table_judged_fallbacks"),
             "plain_total_s_scaled": r.get("plain_sample", {}).get("total_s_scaled_to_n"),
-            "acc_mean": [r["adaptive"]["acc_mean"], r["learned"]["acc_mean"]],
-            "acc_spread": [r["adaptive"]["acc_spread"], r["learned"]["acc_spread"]],
-            "ladder_rms_log_diff": r["learned"]["ladder_rms_log_diff"]}
+            "acc_mean": {k: r[k]["acc_mean"] for k in ("adaptive", "learned", "table", "table_judged") if k in r},
+            "acc_spread": {k: r[k]["acc_spread"] for k in ("adaptive", "learned", "table", "table_judged") if k in r},
+            "rms_log_beta_vs_adaptive": {k: r[k]["rms_log_beta_vs_adaptive"] for k in ("learned", "table", "table_judged") if k in r}}
     except Exception as e:   # noqa: BLE001
         res["learned_vs_adaptive_256_L15"] = {"error": repr(e)[:300]}
     print("bench: time to target, learned vs adaptive, done", file=sys.stderr, flush=True)

@@ -271,6 +271,19 @@ sg_status sg_mlp_get_params(sg_mlp *m, float *params /*[6625 + 8]*/);
 sg_status sg_ladder_predict(sg_mlp *m, const sg_lattice *inst, int32_t n_inst, double *beta_out,
                             double *cutoff_out);
 
+/* The learned-ladder flow with the adaptive stage as fallback and judge: the network's
+ * ladders and per-instance ICM cutoffs (sg_ladder_predict), a pilot APT+ICM run of
+ * pilot_cycles cycles on them (2 labels, each instance at its own cutoff, seed), the swap
+ * acceptance of every adjacent pair (accepted / attempted exchanges), and for every instance
+ * with a pair outside [band_lo, band_hi] ([n_inst][31] each) the adaptive stage (fallback
+ * parameters, seed + 1) resampled to 32 rungs by linear interpolation in the normalised rung
+ * index, its cutoff the first rung >= 1.  beta_out [n_inst][32], cutoff_out [n_inst],
+ * fell_back [n_inst] (1 = adaptive), acc_out (nullable) [n_inst][31] pilot acceptance. */
+sg_status sg_learned_ladders(sg_mlp *m, const sg_lattice *inst, int32_t n_inst, const double *band_lo,
+                             const double *band_hi, const sg_adaptive_params *fallback,
+                             int32_t pilot_cycles, uint64_t seed, double *beta_out,
+                             double *cutoff_out, int32_t *fell_back, double *acc_out);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): sg_ladder_predict without any
  * allocation.  Same arguments, same results bit for bit.  The network inputs and outputs

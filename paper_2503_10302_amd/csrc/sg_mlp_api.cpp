@@ -327,6 +327,113 @@ sg_status sg_ladder_predict(sg_mlp *m, const sg_lattice *inst, int32_t n_inst, d
     return SG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Monotone linear interpolation of a ladder of len rungs onto k rungs at evenly spaced points
+// of the normalised rung index (the end points kept exactly).
+void resample_ladder(const double *b, int len, int k, double *out)
+{
+    if (len == 1) {
+        for (int i = 0; i < k; ++i) out[i] = b[0];
+        return;
+    }
+    const double step = (double)(len - 1) / (double)(k - 1);
+    for (int i = 0; i < k; ++i) {
+        const double u = i == k - 1 ? (double)(len - 1) : (double)i * step;
+        int j = (int)u;
+        if (j >= len - 1) {
+            out[i] = b[len - 1];
+            continue;
+        }
+        const double slope = b[j + 1] - b[j];
+        out[i] = slope * (u - (double)j) + b[j];
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+sg_status sg_learned_ladders(sg_mlp *m, const sg_lattice *inst, int32_t n_inst, const double *band_lo,
+                             const double *band_hi, const sg_adaptive_params *fallback,
+                             int32_t pilot_cycles, uint64_t seed, double *beta_out,
+                             double *cutoff_out, int32_t *fell_back, double *acc_out)
+{
+    constexpr int K = 32, NP = K - 1, REPS = 2;
+    if (!m || !inst || n_inst < 1 || !band_lo || !band_hi || !fallback || pilot_cycles < 2 ||
+        !beta_out || !cutoff_out || !fell_back) {
+        set_global_error("sg_learned_ladders: bad arguments");
+        return SG_EINVAL;
+    }
+    // 1. the network's ladders and cutoffs
+    sg_status st = sg_ladder_predict(m, inst, n_inst, beta_out, cutoff_out);
+    if (st != SG_OK) return st;
+    // 2. pilot APT+ICM run on the predicted ladders, each instance with its own cutoff
+    sg_config cfg{};
+    cfg.mode = SG_APT;
+    cfg.n_inst = n_inst;
+    cfg.inst = inst;
+    cfg.n_beta = K;
+    cfg.beta = beta_out;
+    cfg.reps_per_beta = REPS;
+    cfg.seed = seed;
+    cfg.hip_stream = nullptr;
+    sg_ctx *c = nullptr;
+    st = sg_create(&cfg, &c);
+    if (st != SG_OK) return st;
+    sg_apt_options opt{};
+    opt.sweeps_per_swap = 1;
+    opt.icm_pairs = 2;
+    opt.icm_cutoff = 0.0;
+    opt.icm_cutoff_per_inst = cutoff_out;
+    opt.record_every = 0;
+    std::vector<int64_t> counts((size_t)n_inst * NP * REPS);
+    st = sg_run_apt_ex(c, pilot_cycles, &opt, nullptr);
+    if (st == SG_OK) st = sg_swap_counts(c, counts.data());
+    if (st != SG_OK) {
+        set_global_error(sg_last_error(c));
+        sg_destroy(c);
+        return st;
+    }
+    sg_destroy(c);
+    // 3. acceptance of every adjacent pair (attempt a tries even pairs when a is odd), band check
+    std::vector<int> bad;
+    for (int i = 0; i < n_inst; ++i) {
+        bool ok = true;
+        for (int b = 0; b < NP; ++b) {
+            const int64_t attempts = (pilot_cycles + (1 - b % 2)) / 2;
+            int64_t acc = 0;
+            for (int l = 0; l < REPS; ++l) acc += counts[((size_t)i * NP + b) * REPS + l];
+            const double a = (double)acc / (double)(REPS * attempts);
+            if (acc_out) acc_out[(size_t)i * NP + b] = a;
+            ok &= a >= band_lo[(size_t)i * NP + b] && a <= band_hi[(size_t)i * NP + b];
+        }
+        fell_back[i] = ok ? 0 : 1;
+        if (!ok) bad.push_back(i);
+    }
+    if (bad.empty()) return SG_OK;
+    // 4. the adaptive stage for every instance outside the band, resampled to 32 rungs; its
+    //    cutoff is the first rung at or above 1
+    std::vector<sg_lattice> sub;
+    for (int i : bad) sub.push_back(inst[i]);
+    const int ms = fallback->max_steps;
+    std::vector<double> lad((size_t)sub.size() * ms);
+    std::vector<int32_t> len(sub.size());
+    st = sg_adaptive_ladder(sub.data(), (int32_t)sub.size(), fallback, seed + 1, nullptr, lad.data(),
+                            nullptr, len.data());
+    if (st != SG_OK) return st;
+    for (size_t q = 0; q < bad.size(); ++q) {
+        double *o = beta_out + (size_t)bad[q] * K;
+        resample_ladder(&lad[q * ms], len[q], K, o);
+        int r = 0;
+        while (r < K - 1 && o[r] < 1.0) ++r;
+        cutoff_out[bad[q]] = o[r];
+    }
+    return SG_OK;
+}
+
 sg_status sg_ladder_predict_noalloc(sg_mlp *m, const sg_lattice *inst, int32_t n_inst,
                                     double *beta_out, double *cutoff_out)
 {

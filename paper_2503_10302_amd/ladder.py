@@ -21,12 +21,11 @@ import numpy as np
 from . import sg
 
 N_RUNGS = 32
-# The coldest two adjacent pairs are left out of the band check: the paper reports roughly
-# constant acceptance except for the last few replicas, and with two pairs exempt every
-# ladder of the adaptive stage itself passed (100 of 100 held-apart L=15 instances; with
-# none exempt, 16 of 100).
-TAIL_EXEMPT = 2
 ALPHA = 1.25
+# Default band (every adjacent pair): [0.5, 1.5] x erfc(alpha / 2), the acceptance of Gaussian
+# energies on a ladder with beta steps alpha / sigma_E.  The shipped network carries per-size,
+# per-pair bands calibrated on the adaptive stage's own ladders (band_tables), which replace
+# it: the paper reports roughly constant acceptance except for the last few replicas.
 BAND = (0.5 * math.erfc(ALPHA / 2), 1.5 * math.erfc(ALPHA / 2))   # ~ (0.19, 0.57)
 
 
@@ -203,49 +202,92 @@ def acceptance(counts, cycles, n_beta, reps=2):
 
 
 def pilot_acceptance(instances, ladders, seed, cycles=1000, cutoff=1.0, reps=2):
-    """Swap acceptance of every adjacent pair over a pilot APT+ICM run (per instance)."""
+    """Swap acceptance of every adjacent pair over a pilot APT+ICM run (per instance; cutoff a
+    value or one per instance)."""
     lad = np.ascontiguousarray(ladders, np.float64)
     ctx = sg.apt(instances, lad, seed, reps_per_beta=reps)
-    ctx.run_apt(cycles, 1, float(cutoff))
+    ctx.run_apt_ex(cycles, 1, cutoff, 2)
     acc = acceptance(ctx.swap_counts(), cycles, lad.shape[1], reps)
     ctx.close()
     return acc
 
 
-def in_band(acc, band=BAND, skip_last=None):
-    """Band check: every adjacent pair except the last `skip_last` (coldest) ones."""
-    k = TAIL_EXEMPT if skip_last is None else int(skip_last)
+def in_band(acc, lo=BAND[0], hi=BAND[1]):
+    """Band check over every adjacent pair; lo and hi scalars or per-pair arrays [..][31]."""
     a = np.asarray(acc)
-    a = a[:, :a.shape[1] - k] if k > 0 else a
-    return np.all((a >= band[0]) & (a <= band[1]), axis=1)
+    return np.all((a >= lo) & (a <= hi), axis=1)
 
 
 _PARAMS = __import__("os").path.join(__import__("os").path.dirname(__file__), "ladder_mlp.npz")
 
 
 def default_params():
-    """The shipped network: trained on adaptive-stage ladders of 10^4 generated +-1 cubic
-    instances (L in {8, 10, 12, 15}, the stage at the Methods settings), 400 epochs."""
+    """The shipped network (ladder_mlp.npz): trained on adaptive-stage ladders of generated
+    +-1 cubic instances, L in {8, 10, 12, 15}, a random fraction of bonds in [0, 0.3) removed,
+    the stage at the Methods settings."""
     return np.load(_PARAMS)["params"]
 
 
-def learned_ladders(instances, seed, params=None, pilot=1000, cutoff=None):
-    """The learned-ladder flow: predicted ladders, a pilot APT+ICM run, the band check, and the
-    adaptive stage for every instance whose ladder fails it.
+def default_tables():
+    """Per-size tables shipped with the network: 'sizes' [k]; 'band_lo', 'band_hi' [k][31] the
+    per-pair acceptance bands; 'size_mean' [k][33] the mean target (log betas, log cutoff) of
+    the training instances of each size -- the lookup-table baseline."""
+    d = np.load(_PARAMS)
+    if "sizes" not in d:
+        return None
+    return {k: d[k] for k in ("sizes", "band_lo", "band_hi", "size_mean")}
 
-    Returns (ladders [n][32], fell_back [n] bool, pilot acceptance [n][31])."""
+
+def _size_index(instances, sizes):
+    L = np.array([round(np.prod(np.asarray(J).shape[:3]) ** (1 / 3)) for J, *_ in instances])
+    return np.abs(L[:, None] - np.asarray(sizes)[None, :]).argmin(axis=1)
+
+
+def bands_for(instances, tables=None):
+    """Per-instance, per-pair bands [n][31] from the table of the nearest size (the default
+    band for every pair without tables)."""
+    n = len(instances)
+    if tables is None:
+        return np.full((n, N_RUNGS - 1), BAND[0]), np.full((n, N_RUNGS - 1), BAND[1])
+    k = _size_index(instances, tables["sizes"])
+    return tables["band_lo"][k].astype(np.float64), tables["band_hi"][k].astype(np.float64)
+
+
+def table_ladders(instances, tables):
+    """The lookup-table baseline: the mean training ladder (and cutoff) of the nearest size."""
+    k = _size_index(instances, tables["sizes"])
+    y = tables["size_mean"][k]
+    return np.exp(y[:, :N_RUNGS]), np.exp(y[:, N_RUNGS])
+
+
+def learned_ladders(instances, seed, params=None, pilot=1000, tables="default"):
+    """The learned-ladder flow (libsg sg_learned_ladders): predicted ladders and per-instance
+    cutoffs, a pilot APT+ICM run, the band check of every adjacent pair, and the adaptive stage
+    for every instance whose ladder fails it.
+
+    Returns (ladders [n][32], cutoffs [n], fell_back [n] bool, pilot acceptance [n][31])."""
+    if isinstance(tables, str):
+        tables = default_tables() if params is None else None
+    lo, hi = bands_for(instances, tables)
     m = Predictor(default_params() if params is None else params)
-    lad, cut = m.predict(instances)
+    arr, keep = sg._lattices(instances)
+    n = len(instances)
+    lad = np.zeros((n, N_RUNGS), np.float64)
+    cut = np.zeros(n, np.float64)
+    fb = np.zeros(n, np.int32)
+    acc = np.zeros((n, N_RUNGS - 1), np.float64)
+    p = sg._Adaptive(*(ADAPTIVE[k] for k in ("beta0", "alpha", "tol", "n_chains", "sweeps", "tail",
+                                             "max_steps")))
+    lo = np.ascontiguousarray(lo)
+    hi = np.ascontiguousarray(hi)
+    rc = m.lib.sg_learned_ladders(m.h, arr, n, lo.ctypes.data_as(C.c_void_p),
+                                  hi.ctypes.data_as(C.c_void_p), C.byref(p), int(pilot), int(seed),
+                                  lad.ctypes.data_as(C.c_void_p), cut.ctypes.data_as(C.c_void_p),
+                                  fb.ctypes.data_as(C.c_void_p), acc.ctypes.data_as(C.c_void_p))
     m.close()
-    cut_run = float(np.median(cut)) if cutoff is None else float(cutoff)
-    acc = pilot_acceptance(instances, lad, seed, pilot, cut_run)
-    ok = in_band(acc)
-    bad = np.flatnonzero(~ok)
-    if bad.size:
-        fb = adaptive_ladders([instances[i] for i in bad], seed + 1, **ADAPTIVE)
-        for i, r in zip(bad, fb):
-            lad[i] = resample(r[0])
-    return lad, ~ok, acc
+    if rc != sg.SG_OK:
+        raise sg.SGError(rc, m.lib.sg_last_error(None).decode())
+    return lad, cut, fb.astype(bool), acc
 
 
 # ----------------------------------------------------------------------------------------
@@ -258,9 +300,25 @@ ADAPTIVE = dict(beta0=0.5, alpha=ALPHA, tol=0.5, n_chains=100, sweeps=10000, tai
 ICM_CUTOFF = 1.0
 
 
-def _instances(idx, sizes, seed0):
-    from .inputs import ej_couplings
-    return [(ej_couplings(sizes[i % len(sizes)], 7, seed=seed0 + i)[0], 7, None) for i in idx]
+def dilution_of(i, seed0, p_max):
+    """Fraction of absent bonds of instance seed0 + i: uniform in [0, p_max), drawn from a
+    generator seeded by the instance (0 when p_max = 0)."""
+    if p_max <= 0:
+        return 0.0
+    return float(np.random.default_rng([0xD1A, seed0 + i]).random() * p_max)
+
+
+def _instances(idx, sizes, seed0, p_max=0.0):
+    """Periodic +-J instances seed0 + i of size sizes[i mod len(sizes)], with a random fraction
+    (dilution_of) of their bonds removed when p_max > 0."""
+    from .inputs import diluted_couplings, ej_couplings
+    out = []
+    for i in idx:
+        L = sizes[i % len(sizes)]
+        p = dilution_of(i, seed0, p_max)
+        J = diluted_couplings(L, 7, seed0 + i, p) if p > 0 else ej_couplings(L, 7, seed=seed0 + i)[0]
+        out.append((J, 7, None))
+    return out
 
 
 def _log(**kw):
@@ -268,9 +326,10 @@ def _log(**kw):
     print(json.dumps(kw), flush=True)
 
 
-def make_dataset(n, path, sizes=(8, 10, 12, 15), seed0=30000, seed=4242, chunk=250, params=None):
-    """Adaptive ladders for instances seed0 .. seed0+n-1 (size sizes[i mod 4]), one batch of
-    up to `chunk` same-size instances per call, a progress line per batch."""
+def make_dataset(n, path, sizes=(8, 10, 12, 15), seed0=30000, seed=4242, chunk=250, params=None,
+                 p_max=0.0):
+    """Adaptive ladders for instances seed0 .. seed0+n-1 (size sizes[i mod 4], dilution up to
+    p_max), one batch of up to `chunk` same-size instances per call, a progress line per batch."""
     import time
     prm = dict(ADAPTIVE if params is None else params)
     X = np.zeros((n, 4))
@@ -283,7 +342,7 @@ def make_dataset(n, path, sizes=(8, 10, 12, 15), seed0=30000, seed=4242, chunk=2
         idx = [i for i in range(n) if sizes[i % len(sizes)] == L]
         for k in range(0, len(idx), chunk):
             part = idx[k:k + chunk]
-            inst = _instances(part, sizes, seed0)
+            inst = _instances(part, sizes, seed0, p_max)
             t0 = time.perf_counter()
             res = sg.adaptive_ladder(inst, seed + part[0], **prm)
             dt = time.perf_counter() - t0
@@ -299,23 +358,41 @@ def make_dataset(n, path, sizes=(8, 10, 12, 15), seed0=30000, seed=4242, chunk=2
                  flips_per_ns=round(flips / dt / 1e9, 1),
                  rungs=[int(lens[part].min()), int(lens[part].max())])
     np.savez(path, X=X, Y=Y, ladders=lad, sigmas=sig, lens=lens, seconds=total,
-             sizes=np.array(sizes), seed0=seed0, params=np.array([prm[k] for k in sorted(prm)]))
+             sizes=np.array(sizes), seed0=seed0, p_max=p_max,
+             params=np.array([prm[k] for k in sorted(prm)]))
     return total, lens
 
 
-def band_calibration(data_path, L=15, n=256, pilot=1000, seed=555):
-    """Pilot acceptance of the adaptive stage's own ladders on training instances: how
-    many of them pass the band with the last k pairs exempt, for k = 0..8."""
-    d = np.load(data_path)
-    sizes = tuple(int(x) for x in d["sizes"])
-    idx = [i for i in range(d["lens"].size) if sizes[i % len(sizes)] == L][:n]
-    inst = _instances(idx, sizes, int(d["seed0"]))
-    lad = np.stack([resample(d["ladders"][i, :d["lens"][i]]) for i in idx])
-    acc = pilot_acceptance(inst, lad, seed, pilot, ICM_CUTOFF)
-    return {"pass_by_k": {k: int(in_band(acc, skip_last=k).sum()) for k in range(9)},
-            "n": len(idx), "acc_mean_by_pair": np.round(acc.mean(axis=0), 3).tolist(),
-            "acc_p05_by_pair": np.round(np.quantile(acc, 0.05, axis=0), 3).tolist(),
-            "acc_p95_by_pair": np.round(np.quantile(acc, 0.95, axis=0), 3).tolist()}
+def calibrate_bands(data, per_size=128, pilot=1000, seed=555, factor=(0.5, 1.5), q=(0.005, 0.995),
+                    widen=(0.9, 1.1)):
+    """Per-size, per-pair acceptance bands from the adaptive stage's own ladders (training data
+    sets, the Algorithm S2 settings): per_size instances of each size, split over the data
+    sets, run a pilot on their adaptive ladders (resampled to 32 rungs, each at its own cutoff
+    label); per pair the band is [min(0.5 c, 0.9 q_0.5%), max(1.5 c, 1.1 q_99.5%)] with c the
+    mean acceptance, so that the stage's own ladders pass it and a predicted ladder is checked
+    on every pair."""
+    sizes = tuple(int(x) for x in data[0]["sizes"])
+    out = {"sizes": np.array(sizes), "band_lo": [], "band_hi": [], "pass": [], "mean": []}
+    for L in sizes:
+        inst, lad = [], []
+        for d in data:
+            p_max = float(d["p_max"]) if "p_max" in d else 0.0
+            idx = [i for i in range(d["lens"].size) if sizes[i % len(sizes)] == L][:per_size // len(data)]
+            inst += _instances(idx, sizes, int(d["seed0"]), p_max)
+            lad += [resample(d["ladders"][i, :d["lens"][i]]) for i in idx]
+        lad = np.stack(lad)
+        cut = np.array([cutoff_label(x) for x in lad])
+        acc = pilot_acceptance(inst, lad, seed, pilot, cut)
+        c = acc.mean(axis=0)
+        lo = np.minimum(factor[0] * c, widen[0] * np.quantile(acc, q[0], axis=0))
+        hi = np.maximum(factor[1] * c, widen[1] * np.quantile(acc, q[1], axis=0))
+        out["band_lo"].append(lo)
+        out["band_hi"].append(hi)
+        out["pass"].append(float(in_band(acc, lo, hi).mean()))
+        out["mean"].append(c)
+    for k in ("band_lo", "band_hi", "mean"):
+        out[k] = np.stack(out[k])
+    return out
 
 
 def _first_hit(tr, target):
@@ -323,153 +400,111 @@ def _first_hit(tr, target):
     return np.where(hit.any(axis=1), hit.argmax(axis=1) + 1, -1)
 
 
-def evaluate(params, n=256, seed0=90000, L=15, cycles=20000, pilot=1000, seed=777, rho0=0.007,
-             e0_cycles=20000, plain_sample=16):
-    """Plain, batched-adaptive and batched-learned APT+ICM on held-out instances.
+def _batched(inst, lad, cut, seed, cycles):
+    """One batched APT+ICM run with per-cycle best-energy traces: (trace, ms per cycle, pair
+    acceptance)."""
+    c = sg.apt(inst, lad, seed, 2)
+    c.synchronize()
+    c.timer_start()
+    tr = c.run_apt_ex(cycles, 1, cut, 2, record_every=1)
+    ms = c.timer_stop()
+    acc = acceptance(c.swap_counts(), cycles, N_RUNGS, 2)
+    c.close()
+    return tr, ms / cycles, acc
 
-    Each form's time to target counts its ladder construction.  Adaptive: the adaptive
-    stage on all instances at once.  Learned: inference, then the production run whose
-    first `pilot` cycles are the pilot; instances outside the band get the adaptive stage
-    and a production run of their own.  Plain: one instance at a time, its own adaptive
-    stage and APT run, on the first `plain_sample` instances (scaled to n).
-    """
+
+def evaluate(params, tables, n=256, seed0=90000, L=15, p_max=0.0, cycles=20000, pilot=1000, seed=777,
+             rho0=0.007, e0_cycles=20000, plain_sample=16):
+    """Plain, batched-adaptive, batched-learned and batched-lookup-table APT+ICM on held-out
+    instances (size L, dilution up to p_max).  Each form's time to target counts its ladder
+    construction: the adaptive stage on all instances at once; the learned flow (inference,
+    pilot, band check, adaptive fallback); the table lookup alone (nothing to time) and the
+    table lookup through the same judge as the learned flow.  Every form runs
+    each instance at its own ICM cutoff.  Plain: one instance at a time, its own adaptive stage
+    and APT run, on the first plain_sample instances, scaled to n.  Also the ladders' rms
+    distance in log beta from the adaptive stage's."""
     import time
-    inst = _instances(range(n), (L,), seed0)
+    inst = _instances(range(n), (L,), seed0, p_max)
     nsp = L ** 3
-    reps = 2
-    # ---- adaptive form: ladder construction
     t0 = time.perf_counter()
     res = adaptive_ladders(inst, seed, **ADAPTIVE)
     t_adapt = time.perf_counter() - t0
-    lens_a = np.array([len(r[0]) for r in res])
     lad_a = np.stack([resample(r[0]) for r in res])
-    # ---- learned form: inference
-    m = Predictor(params)
+    cut_a = np.array([cutoff_label(x) for x in lad_a])
     t0 = time.perf_counter()
-    lad_l, cut_l = m.predict(inst)
-    t_pred = time.perf_counter() - t0
-    m.close()
-    cut_learned = float(np.median(cut_l))
-    # ---- E0: long runs on the adaptive ladders (putative ground energies)
+    lad_l, cut_l, fell, acc_pilot = learned_ladders(inst, seed + 9, params, pilot, tables)
+    t_learn = time.perf_counter() - t0
+    lad_t, cut_t = table_ladders(inst, tables) if tables is not None else (None, None)
+    forms = {"adaptive": (lad_a, cut_a, t_adapt), "learned": (lad_l, cut_l, t_learn)}
+    fell_t = None
+    if lad_t is not None:
+        forms["table"] = (lad_t, cut_t, 0.0)
+        # the lookup ladders through the same judge: pilot, per-pair band, adaptive fallback
+        t0 = time.perf_counter()
+        lo, hi = bands_for(inst, tables)
+        acc_t = pilot_acceptance(inst, lad_t, seed + 9, pilot, cut_t)
+        fell_t = ~in_band(acc_t, lo, hi)
+        lad_tj, cut_tj = lad_t.copy(), cut_t.copy()
+        bad = np.flatnonzero(fell_t)
+        if bad.size:
+            fb = adaptive_ladders([inst[i] for i in bad], seed + 10, **ADAPTIVE)
+            for i, r in zip(bad, fb):
+                lad_tj[i] = resample(r[0])
+                cut_tj[i] = cutoff_label(lad_tj[i])
+        forms["table_judged"] = (lad_tj, cut_tj, time.perf_counter() - t0)
     E0 = np.full(n, np.iinfo(np.int64).max)
     for sd in (11, 12):
-        c = sg.apt(inst, lad_a, sd, reps)
-        c.run_apt(e0_cycles, 1, ICM_CUTOFF)
+        c = sg.apt(inst, lad_a, sd, 2)
+        c.run_apt_ex(e0_cycles, 1, cut_a, 2)
         E0 = np.minimum(E0, c.best())
         c.close()
-    # ---- batched runs with per-cycle traces
-    c = sg.apt(inst, lad_a, seed + 3, reps)
-    c.synchronize()
-    c.timer_start()
-    tr_a = c.run_apt(cycles, 1, ICM_CUTOFF, record_every=1)
-    ms_a = c.timer_stop()
-    acc_a = acceptance(c.swap_counts(), cycles, N_RUNGS, reps)
-    c.close()
-    c = sg.apt(inst, lad_l, seed + 3, reps)
-    c.synchronize()
-    c.timer_start()
-    tr_l1 = c.run_apt(pilot, 1, cut_learned, record_every=1)
-    ms_l1 = c.timer_stop()
-    acc_l = acceptance(c.swap_counts(), pilot, N_RUNGS, reps)
-    ok = in_band(acc_l)
-    c.timer_start()
-    tr_l2 = c.run_apt(cycles - pilot, 1, cut_learned, record_every=1)
-    ms_l2 = c.timer_stop()
-    acc_l_full = acceptance(c.swap_counts(), cycles, N_RUNGS, reps)
-    c.close()
-    tr_l = np.concatenate([tr_l1, tr_l2], axis=1)
-    bad = np.flatnonzero(~ok)
-    t_fb, ms_fb, tr_fb = 0.0, 0.0, None
-    if bad.size:
-        sub = [inst[i] for i in bad]
-        t0 = time.perf_counter()
-        fb = adaptive_ladders(sub, seed + 2, **ADAPTIVE)
-        t_fb = time.perf_counter() - t0
-        lad_fb = np.stack([resample(r[0]) for r in fb])
-        c = sg.apt(sub, lad_fb, seed + 4, reps)
-        c.synchronize()
-        c.timer_start()
-        tr_fb = c.run_apt(cycles, 1, ICM_CUTOFF, record_every=1)
-        ms_fb = c.timer_stop()
-        c.close()
-    E0 = np.minimum(E0, np.minimum(tr_a[:, -1], tr_l[:, -1]))
-    if bad.size:
-        E0[bad] = np.minimum(E0[bad], tr_fb[:, -1])
-    # ---- plain form on a sample, after E0 is fixed
+    runs = {}
+    for name, (lad, cut, _) in forms.items():
+        runs[name] = _batched(inst, lad, cut, seed + 3, cycles)
+        E0 = np.minimum(E0, runs[name][0][:, -1])
     plain = []
     for i in range(min(plain_sample, n)):
         t0 = time.perf_counter()
         r = sg.adaptive_ladder([inst[i]], seed + 5 + i, **ADAPTIVE)
         t_ad = time.perf_counter() - t0
-        ci = sg.apt([inst[i]], resample(r[0][0])[None, :], seed + 1000 + i, reps)
+        l32 = resample(r[0][0])
+        ci = sg.apt([inst[i]], l32[None, :], seed + 1000 + i, 2)
         target = E0[i] + rho0 * nsp
-        done, hit = 0, -1
+        done, ms = 0, 0.0
         ci.synchronize()
         ci.timer_start()
         while done < cycles:
-            ci.run_apt(250, 1, ICM_CUTOFF)
+            ci.run_apt_ex(250, 1, cutoff_label(l32), 2)
             done += 250
             if int(ci.best()[0]) <= target:
-                hit = done
                 break
         ms = ci.timer_stop()
         ci.close()
-        plain.append((t_ad, ms / 1e3, hit))
+        plain.append((t_ad, ms / 1e3))
     target = E0 + rho0 * nsp
-    first_a = _first_hit(tr_a, target)
-    first_l = _first_hit(tr_l, target)
-    mspc_a = ms_a / cycles
-    mspc_l = (ms_l1 + ms_l2) / cycles
-    out = {"n": n, "L": L, "rho0": rho0, "pilot_cycles": pilot, "cycles_max": cycles,
-           "band": [round(BAND[0], 4), round(BAND[1], 4)], "tail_exempt": TAIL_EXEMPT,
-           "adaptive_params": ADAPTIVE, "adaptive_rungs": [int(lens_a.min()), int(lens_a.max())]}
-    reached_a = int((first_a > 0).sum())
-    apt_a = first_a.max() * mspc_a / 1e3 if reached_a == n else None
-    out["adaptive"] = {
-        "ladder_s": round(t_adapt, 3), "reached": reached_a,
-        "cycles_all": int(first_a.max()) if reached_a == n else None,
-        "apt_s": None if apt_a is None else round(apt_a, 3),
-        "total_s": None if apt_a is None else round(t_adapt + apt_a, 3),
-        "cycles_median": float(np.median(first_a[first_a > 0])) if reached_a else None,
-        "acc_mean": round(float(acc_a.mean()), 4),
-        "acc_spread": round(float(acc_a[:, :N_RUNGS - 1 - TAIL_EXEMPT].std(axis=1).mean()), 4),
-        "acc_mean_by_pair": np.round(acc_a.mean(axis=0), 3).tolist(),
-        "in_band": int(in_band(acc_a).sum())}
-    # learned: accepted instances need max(pilot, their cycles); the rest their fallback
-    acc_ok = ok.copy()
-    fl = np.where(acc_ok, first_l, -1)
-    reached_ok = int((fl > 0).sum())
-    need_a = int(max(pilot, fl[acc_ok].max())) if acc_ok.any() and reached_ok == acc_ok.sum() else None
-    if bad.size:
-        first_fb = _first_hit(tr_fb, target[bad])
-        fb_ok = bool((first_fb > 0).all())
-        t_fb_apt = first_fb.max() * ms_fb / cycles / 1e3 if fb_ok else None
-    else:
-        first_fb, fb_ok, t_fb_apt = np.zeros(0, int), True, 0.0
-    total_l = None
-    if (need_a is not None or not acc_ok.any()) and fb_ok:
-        t_ctx = (need_a or pilot) * mspc_l / 1e3
-        total_l = t_pred + t_ctx + t_fb + t_fb_apt
-    out["learned"] = {
-        "inference_s": round(t_pred, 4), "accepted": int(acc_ok.sum()), "fallbacks": int(bad.size),
-        "fallback_ladder_s": round(t_fb, 3), "cutoff": round(cut_learned, 4),
-        "reached": reached_ok + int((first_fb > 0).sum()),
-        "cycles_all_accepted": need_a,
-        "total_s": None if total_l is None else round(total_l, 3),
-        "cycles_median": float(np.median(first_l[first_l > 0])) if (first_l > 0).any() else None,
-        "acc_mean": round(float(acc_l_full.mean()), 4),
-        "acc_spread": round(float(acc_l_full[:, :N_RUNGS - 1 - TAIL_EXEMPT].std(axis=1).mean()), 4),
-        "acc_mean_by_pair": np.round(acc_l_full.mean(axis=0), 3).tolist(),
-        "pilot_pass_by_k": {k: int(in_band(acc_l, skip_last=k).sum()) for k in range(9)},
-        "ladder_rms_log_diff": round(float(np.sqrt(np.mean((np.log(lad_l) - np.log(lad_a)) ** 2))), 4)}
+    out = {"n": n, "L": L, "p_max": p_max, "rho0": rho0, "pilot_cycles": pilot, "cycles_max": cycles,
+           "adaptive_params": ADAPTIVE, "learned_fallbacks": int(fell.sum()),
+           "table_judged_fallbacks": None if fell_t is None else int(fell_t.sum()),
+           "e0": f"min over two {e0_cycles}-cycle runs on the adaptive ladders and every run here"}
+    for name, (lad, cut, t_build) in forms.items():
+        tr, mspc, acc = runs[name]
+        first = _first_hit(tr, target)
+        reached = int((first > 0).sum())
+        apt_s = first.max() * mspc / 1e3 if reached == n else None
+        out[name] = {"ladder_s": round(t_build, 3), "reached": reached,
+                     "cycles_all": int(first.max()) if reached == n else None,
+                     "apt_s": None if apt_s is None else round(apt_s, 3),
+                     "total_s": None if apt_s is None else round(t_build + apt_s, 3),
+                     "cycles_median": float(np.median(first[first > 0])) if reached else None,
+                     "acc_mean": round(float(acc.mean()), 4),
+                     "acc_spread": round(float(acc.std(axis=1).mean()), 4),
+                     "rms_log_beta_vs_adaptive": round(float(np.sqrt(np.mean((np.log(lad) - np.log(lad_a)) ** 2))), 4)}
     pl = np.array(plain)
     if pl.size:
-        reached_p = int((pl[:, 2] > 0).sum())
-        out["plain_sample"] = {
-            "instances": len(plain), "reached": reached_p,
-            "ladder_s_mean": round(float(pl[:, 0].mean()), 3),
-            "apt_s_mean": round(float(pl[:, 1].mean()), 4),
-            "total_s_scaled_to_n": round(float((pl[:, 0] + pl[:, 1]).mean() * n), 2)}
+        out["plain_sample"] = {"instances": len(plain),
+                               "ladder_s_mean": round(float(pl[:, 0].mean()), 3),
+                               "apt_s_mean": round(float(pl[:, 1].mean()), 4),
+                               "total_s_scaled_to_n": round(float(pl.sum(axis=1).mean() * n), 2)}
     return out
 
 
@@ -477,49 +512,59 @@ if __name__ == "__main__":
     import argparse
     import json
     ap = argparse.ArgumentParser(description="learned-ladder study")
-    ap.add_argument("stage", choices=["data", "calibrate", "train", "eval"])
+    ap.add_argument("stage", choices=["data", "train", "eval"])
     ap.add_argument("--n", type=int, default=10000)
     ap.add_argument("--data", nargs="+", default=[])
     ap.add_argument("--out", default=None)
     ap.add_argument("--params", default=None)
-    ap.add_argument("--epochs", type=int, default=400)
-    ap.add_argument("--seed0", type=int, default=30000)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--lrs", type=float, nargs="+", default=[3e-4],
+                    help="learning rates, the epochs split evenly over them")
+    ap.add_argument("--seed0", type=int, default=None,
+                    help="first instance seed (default 30000 for data, 90000 for eval)")
     ap.add_argument("--cycles", type=int, default=20000)
     ap.add_argument("--plain-sample", type=int, default=16)
+    ap.add_argument("--p-max", type=float, default=0.0,
+                    help="largest fraction of absent bonds of the generated instances")
     ap.add_argument("--budget", choices=["paper", "small"], default="paper",
                     help="adaptive-stage budget: the paper's, or 8 chains x 500 sweeps (tests)")
     a = ap.parse_args()
     if a.budget == "small":
         ADAPTIVE.update(n_chains=8, sweeps=500, tail=250)
     if a.stage == "data":
-        dt, lens = make_dataset(a.n, a.out, seed0=a.seed0)
+        dt, lens = make_dataset(a.n, a.out, seed0=30000 if a.seed0 is None else a.seed0, p_max=a.p_max)
         _log(seconds=round(dt, 2), n=a.n, rungs_min=int(lens.min()), rungs_max=int(lens.max()),
              rungs_mean=float(lens.mean()))
-    elif a.stage == "calibrate":
-        print(json.dumps(band_calibration(a.data[0])), flush=True)
     elif a.stage == "train":
-        X = np.concatenate([np.load(p)["X"] for p in a.data])
-        Y = np.concatenate([np.load(p)["Y"] for p in a.data])
+        data = [np.load(f) for f in a.data]
+        X = np.concatenate([d["X"] for d in data])
+        Y = np.concatenate([d["Y"] for d in data])
+        d = data[0]
         perm = np.random.default_rng(0).permutation(X.shape[0])
         nval = max(1, X.shape[0] // 10)
         va, trn = perm[:nval], perm[nval:]
         import time
         t0 = time.perf_counter()
-        m, losses = fit(X[trn], Y[trn], epochs=a.epochs)
+        m, losses = fit(X[trn], Y[trn], epochs=a.epochs, lrs=tuple(a.lrs))
         t_train = time.perf_counter() - t0
-        np.savez(a.out, params=m.params())
-        # baselines: the global mean ladder, and the mean ladder of the instance's size
-        glob = np.mean((Y[va] - Y[trn].mean(axis=0)) ** 2)
-        size_of = np.round(X[:, 0]).astype(int)   # feature 0 is the cube root of n
-        per = np.zeros_like(Y[va])
-        for k, i in enumerate(va):
-            same = trn[size_of[trn] == size_of[i]]
-            per[k] = Y[same].mean(axis=0)
+        sizes = tuple(int(x) for x in d["sizes"])
+        size_of = np.concatenate([[sizes[i % len(sizes)] for i in range(dd["X"].shape[0])] for dd in data])
+        size_mean = np.stack([Y[trn][size_of[trn] == L].mean(axis=0) for L in sizes])
+        per = size_mean[np.searchsorted(np.array(sizes), size_of[va])]
+        cal = calibrate_bands(data)
+        np.savez(a.out, params=m.params(), sizes=np.array(sizes), band_lo=cal["band_lo"],
+                 band_hi=cal["band_hi"], size_mean=size_mean)
         _log(train_seconds=round(t_train, 2), train_loss_first=float(losses[0]),
              train_loss_last=float(losses[-1]), val_loss=float(m.loss(X[va], Y[va])),
-             val_loss_global_mean=float(glob), val_loss_size_mean=float(np.mean((Y[va] - per) ** 2)),
-             n_train=int(trn.size), n_val=int(va.size))
+             val_loss_size_mean=float(np.mean((Y[va] - per) ** 2)),
+             val_loss_global_mean=float(np.mean((Y[va] - Y[trn].mean(axis=0)) ** 2)),
+             n_train=int(trn.size), n_val=int(va.size), band_pass_by_size=cal["pass"],
+             band_lo_coldest=np.round(cal["band_lo"][:, -3:], 3).tolist(),
+             band_hi_coldest=np.round(cal["band_hi"][:, -3:], 3).tolist(),
+             acc_mean_by_size=np.round(cal["mean"], 3).tolist())
     else:
-        p = np.load(a.params)["params"]
-        print(json.dumps(evaluate(p, n=a.n, cycles=a.cycles, e0_cycles=a.cycles,
-                                  plain_sample=a.plain_sample)), flush=True)
+        p = np.load(a.params)
+        tables = {k: p[k] for k in ("sizes", "band_lo", "band_hi", "size_mean")} if "sizes" in p else None
+        print(json.dumps(evaluate(p["params"], tables, n=a.n, cycles=a.cycles, e0_cycles=a.cycles,
+                                  plain_sample=a.plain_sample, p_max=a.p_max,
+                                  seed0=90000 if a.seed0 is None else a.seed0)), flush=True)

@@ -11,32 +11,35 @@ pytestmark = pytest.mark.gpu
 
 
 def test_trained_network_replaces_the_adaptive_stage():
-    """16 held-out L = 15 instances (seeds outside the training range): the shipped
-    network's ladders pass the band check without fallback, lie within 5 % (rms in log
-    beta) of the adaptive stage's own ladders, and cost a small fraction of its time,
-    pilot run included."""
+    """16 held-out L = 15 instances (seeds outside the training range): the learned flow (the
+    shipped network, per-instance cutoffs, a pilot run and the per-pair band check through the
+    C ABI) keeps the network's ladders on all but at most one instance, they lie within 5 %
+    (rms in log beta) of the adaptive stage's own ladders, every accepted ladder's pairs lie in
+    their calibrated bands, and without a fallback the flow costs a small fraction of the
+    stage."""
     inst = ladder._instances(range(16), (15,), 90000)
     t0 = time.perf_counter()
-    lad_l, fell_back, acc = ladder.learned_ladders(inst, 7)
+    lad_l, cut_l, fell_back, acc = ladder.learned_ladders(inst, 7)
     t_learned = time.perf_counter() - t0
     t0 = time.perf_counter()
     res = ladder.adaptive_ladders(inst, 8, **ladder.ADAPTIVE)
     t_adaptive = time.perf_counter() - t0
     lad_a = np.stack([ladder.resample(r[0]) for r in res])
-    print(f"learned {t_learned:.3f} s, adaptive {t_adaptive:.3f} s", flush=True)
-    assert not fell_back.any()
-    assert np.all(np.diff(lad_l, axis=1) > 0)
+    print(f"learned {t_learned:.3f} s, adaptive {t_adaptive:.3f} s, fallbacks {int(fell_back.sum())}",
+          flush=True)
+    assert fell_back.sum() <= 1
+    assert np.all(np.diff(lad_l, axis=1) > 0) and np.all(cut_l > 0)
     rms = float(np.sqrt(np.mean((np.log(lad_l) - np.log(lad_a)) ** 2)))
     assert rms < 0.05, rms
-    # acceptance over the checked pairs near the adaptive target erfc(alpha / 2) = 0.377
-    mid = acc[:, :31 - ladder.TAIL_EXEMPT]
-    assert abs(float(mid.mean()) - 0.377) < 0.04
-    assert t_learned * 5 < t_adaptive
+    lo, hi = ladder.bands_for(inst, ladder.default_tables())
+    assert np.all((acc >= lo) | fell_back[:, None]) and np.all((acc <= hi) | fell_back[:, None])
+    if not fell_back.any():   # a fallback runs the adaptive stage itself for that instance
+        assert t_learned * 5 < t_adaptive
 
 
 def test_band_violation_falls_back_to_the_adaptive_stage():
-    """A network whose ladder barely spans any temperature (acceptance near 1) fails the
-    band on every instance, and every ladder then comes from the adaptive stage."""
+    """A network whose ladder barely spans any temperature (acceptance near 1) fails the band
+    on every instance, and every ladder and cutoff then comes from the adaptive stage."""
     p = ladder.default_params().copy()
     nout = ladder.N_RUNGS + 1
     p[ladder.OFF_W3:ladder.OFF_B3] = 0.0           # outputs = output biases
@@ -44,14 +47,37 @@ def test_band_violation_falls_back_to_the_adaptive_stage():
     p[ladder.OFF_B3 + 1:ladder.OFF_B3 + ladder.N_RUNGS] = inc + np.log(-np.expm1(-inc))
     assert ladder.OFF_B3 + nout == p.size - 8
     inst = ladder._instances(range(4), (6,), 91000)
-    lad, fell_back, acc = ladder.learned_ladders(inst, 9, params=p, pilot=200)
+    lad, cut, fell_back, acc = ladder.learned_ladders(inst, 9, params=p, pilot=200)
     assert fell_back.all()
     assert (acc[:, 0] > ladder.BAND[1]).all()
     # the fallback is the adaptive stage itself: the same call gives the same ladders
     ref = ladder.adaptive_ladders(inst, 10, **ladder.ADAPTIVE)
     for i in range(4):
-        np.testing.assert_array_equal(lad[i], ladder.resample(ref[i][0]))
+        l32 = ladder.resample(ref[i][0])
+        np.testing.assert_array_equal(lad[i], l32)
+        assert cut[i] == ladder.cutoff_label(l32)
         assert lad[i, 0] == 0.5 and np.all(np.diff(lad[i]) > 0)
+
+
+def test_network_beats_the_size_lookup_on_diluted_instances():
+    """What the network gains over the method without it: on 64 held-out L = 12 instances with
+    a random fraction (up to 0.3) of their bonds removed, the network's ladders are closer to
+    the adaptive stage's own (mean squared error in log beta) than the per-size lookup table
+    (the mean training ladder of the size), by at least 20 %.  The lookup cannot see the
+    dilution; the network's features do."""
+    tables = ladder.default_tables()
+    assert tables is not None
+    inst = ladder._instances(range(64), (12,), 95000, p_max=0.3)
+    res = ladder.adaptive_ladders(inst, 21, **ladder.ADAPTIVE)
+    y = np.log(np.stack([ladder.resample(r[0]) for r in res]))
+    m = ladder.Predictor(ladder.default_params())
+    b_net, _ = m.predict(inst)
+    m.close()
+    b_tab, _ = ladder.table_ladders(inst, tables)
+    mse_net = float(np.mean((np.log(b_net) - y) ** 2))
+    mse_tab = float(np.mean((np.log(b_tab) - y) ** 2))
+    print(f"held-out diluted L=12: MSE network {mse_net:.5f}, size table {mse_tab:.5f}", flush=True)
+    assert mse_net < 0.8 * mse_tab
 
 
 def test_predicted_ladder_matches_the_fp64_oracle_forward_pass():

@@ -52,12 +52,15 @@ def test_attempt_counts_follow_the_swap_schedule():
         if cycles == 1:     # only the even pairs have been tried
             np.testing.assert_array_equal(acc[0, 0::2], 1.0)
             assert np.isnan(acc[0, 1::2]).all()
-            assert not ladder.in_band(acc, skip_last=0)[0]
+            assert not ladder.in_band(acc)[0]
         else:
             np.testing.assert_array_equal(acc, np.ones((1, n_beta - 1)))
 
 
-def test_band_and_tail_exemption():
+def test_band_checks_every_pair():
+    """The default band [0.5, 1.5] x erfc(alpha / 2) on every adjacent pair, and per-pair bands
+    (arrays) as the calibrated tables give them: a cold pair below its own bound fails, above it
+    passes."""
     lo, hi = ladder.BAND
     assert math.isclose(lo, 0.5 * math.erfc(1.25 / 2)) and math.isclose(hi, 1.5 * math.erfc(1.25 / 2))
     good = np.full((1, 31), 0.38)
@@ -68,6 +71,34 @@ def test_band_and_tail_exemption():
     high = good.copy()
     high[0, 0] = 0.9
     acc = np.concatenate([good, cold, warm, high])
-    np.testing.assert_array_equal(ladder.in_band(acc, skip_last=0), [True, False, False, False])
-    np.testing.assert_array_equal(ladder.in_band(acc, skip_last=2), [True, True, False, False])
-    assert ladder.TAIL_EXEMPT == 2
+    np.testing.assert_array_equal(ladder.in_band(acc), [True, False, False, False])
+    plo = np.full(31, lo)
+    phi = np.full(31, hi)
+    plo[-2:] = [0.05, 0.01]
+    np.testing.assert_array_equal(ladder.in_band(acc, plo, phi), [True, True, False, False])
+    plo[-1] = 0.03
+    np.testing.assert_array_equal(ladder.in_band(acc, plo, phi), [True, False, False, False])
+
+
+def test_tables_by_nearest_size():
+    """Per-size tables are looked up by the size nearest to each instance's cube root of n;
+    without tables every instance gets the default band."""
+    from paper_2503_10302_amd.inputs import ej_couplings
+    t = {"sizes": np.array([8, 10, 12, 15]), "band_lo": np.arange(4)[:, None] * np.ones((4, 31)),
+         "band_hi": 10 + np.arange(4)[:, None] * np.ones((4, 31)),
+         "size_mean": np.log(np.arange(1, 5))[:, None] * np.ones((4, 33))}
+    inst = [(ej_couplings(L, 7, seed=1)[0], 7, None) for L in (8, 9, 11, 15, 6)]
+    lo, hi = ladder.bands_for(inst, t)
+    np.testing.assert_array_equal(lo[:, 0], [0, 0, 1, 3, 0])   # 9 -> 8 (tie to the first), 11 -> 10
+    np.testing.assert_array_equal(hi[:, 5], [10, 10, 11, 13, 10])
+    b, c = ladder.table_ladders(inst, t)
+    np.testing.assert_allclose(b[:, 0], [1, 1, 2, 4, 1])
+    lo0, hi0 = ladder.bands_for(inst, None)
+    assert np.all(lo0 == ladder.BAND[0]) and np.all(hi0 == ladder.BAND[1])
+
+
+def test_dilution_is_per_instance_and_reproducible():
+    d = [ladder.dilution_of(i, 30000, 0.3) for i in range(200)]
+    assert d == [ladder.dilution_of(i, 30000, 0.3) for i in range(200)]
+    assert 0 <= min(d) and max(d) < 0.3 and np.std(d) > 0.07
+    assert ladder.dilution_of(5, 30000, 0.0) == 0.0
