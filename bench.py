@@ -54,10 +54,10 @@ def alg_ops_per_flip(groups):
 # copy (fetch x 2.0, write x 1.0), for the launch lengths measured (20 steps: the default
 # benchmark command; 200 steps).  Reported only while the DT-SQA kernel source is the one
 # measured.
-SQA_TRAFFIC = {"kernel_src_sha256_16": "5f80516834aee567", "R": 1024, "fetch_scale": 2.0,
+SQA_TRAFFIC = {"kernel_src_sha256_16": "e40b87e980aad511", "R": 1024, "fetch_scale": 2.0,
                "write_scale": 1.0,
-               "by_steps": {20: {"fetch_kib": 452607.125, "write_kib": 873472.0},
-                            200: {"fetch_kib": 452747.25, "write_kib": 873472.0}}}
+               "by_steps": {20: {"fetch_kib": 452604.75, "write_kib": 873472.0},
+                            200: {"fetch_kib": 452713.625, "write_kib": 873472.0}}}
 
 
 def sqa_kernel_source_hash():
@@ -596,6 +596,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["all", "sqa", "apt"], default="all")
+    ap.add_argument("--sqa-launch-config", type=int, default=0,
+                    help="DT-SQA work-group size (0: the autotuner's pick)")
     ap.add_argument("--ttt", action="store_true", help="time-to-target run (plain vs batched APT+ICM)")
     ap.add_argument("--ttt-cycles", type=int, default=30000,
                     help="length of each reference run that fixes E0 (--ttt), of each run (--learned)")
@@ -701,6 +703,7 @@ def main():
     gam = linear_gamma(max(1000, args.warmup + args.steps))
     if args.only in ("all", "sqa"):
         ctx = sg.sqa(insts, M, R, beta, seed=4004)
+        ctx.set_launch_config(args.sqa_launch_config)
         if args.warmup:
             ctx.sqa_anneal(gam[:args.warmup])
         ctx.synchronize()
@@ -730,7 +733,8 @@ def main():
                          "alg_ops_per_flip": round(ops_flip, 3),
                          "kernel_ms": round(kms, 3), "launches": nlaunch,
                          "launch_config": {"threads": ctx.launch_config(),
-                                           "chosen_by": "autotuner"},
+                                           "chosen_by": "autotuner" if not args.sqa_launch_config
+                                           else "--sqa-launch-config"},
                          "kernel_flips_per_ns": round(flips_per_step * args.steps / (kms * 1e6), 3)},
             "wall_s_timed": round(wall, 3),
             "sqa_best_residual_proxy": {"min_E_per_spin": round(float(bE.min()) / n, 5)},
