@@ -271,18 +271,45 @@ sg_status sg_mlp_get_params(sg_mlp *m, float *params /*[6625 + 8]*/);
 sg_status sg_ladder_predict(sg_mlp *m, const sg_lattice *inst, int32_t n_inst, double *beta_out,
                             double *cutoff_out);
 
-/* The learned-ladder flow with the adaptive stage as fallback and judge: the network's
- * ladders and per-instance ICM cutoffs (sg_ladder_predict), a pilot APT+ICM run of
- * pilot_cycles cycles on them (2 labels, each instance at its own cutoff, seed), the swap
- * acceptance of every adjacent pair (accepted / attempted exchanges), and for every instance
- * with a pair outside [band_lo, band_hi] ([n_inst][31] each) the adaptive stage (fallback
- * parameters, seed + 1) resampled to 32 rungs by linear interpolation in the normalised rung
- * index, its cutoff the first rung >= 1.  beta_out [n_inst][32], cutoff_out [n_inst],
- * fell_back [n_inst] (1 = adaptive), acc_out (nullable) [n_inst][31] pilot acceptance. */
+/* One repair step of a 32-rung (any n_beta >= 2) ladder from a pilot's swap acceptance, for
+ * a ladder that failed its band.  With the acceptance of a pair at inverse temperatures
+ * spaced dbeta read as erfc(dbeta sigma / 2) (Gaussian energies of spread sigma; the adaptive
+ * stage's rule beta + alpha / sigma_E gives erfc(alpha / 2), Methods "APT details"), each pair
+ * has a length 2 erfc^-1(a): measured from acc, wanted from the band's midpoint.  Rung k moves
+ * to where the measured length, interpolated linearly in log beta between the old rungs,
+ * reaches the share of the total that the wanted lengths give it; the end rungs stay.  With
+ * damping d in (0, 1] the result is exp((1 - d) log beta + d log beta_new) rung by rung.
+ * Acceptances are clamped to [1e-3, 1 - 1e-3].  beta [n_beta] strictly ascending, positive;
+ * acc, band_lo, band_hi [n_beta - 1]; beta_out [n_beta] (may alias beta), strictly ascending.
+ * Host arithmetic only.  SG_EINVAL (message in sg_last_error(NULL)) for invalid arguments. */
+sg_status sg_ladder_repair(const double *beta, const double *acc, const double *band_lo,
+                           const double *band_hi, int32_t n_beta, double damping, double *beta_out);
+
+/* The judge of candidate 32-rung ladders, with the adaptive stage as fallback:
+ *   1. a pilot APT+ICM run of pilot_cycles cycles on the candidates (2 labels, one sweep per
+ *      attempt, each instance at its own ICM cutoff, seed) and the swap acceptance of every
+ *      adjacent pair (accepted / attempted exchanges) against [band_lo, band_hi];
+ *   2. up to repair_rounds rounds on the instances outside the band: sg_ladder_repair from the
+ *      last pilot's acceptance (damping 1 in the first round, 0.5 after), a pilot of the
+ *      repaired ladders of those instances alone (seed + 2 + round), the band check;
+ *   3. for every instance still outside, the adaptive stage (fallback parameters, seed + 1)
+ *      resampled to 32 rungs by linear interpolation in the normalised rung index, its cutoff
+ *      the first rung >= 1.
+ * beta_io [n_inst][32] and cutoff_io [n_inst]: the candidates in, the judged ladders out.
+ * band_lo, band_hi [n_inst][31].  status [n_inst]: 0 the candidate passed, 2 a repaired
+ * ladder passed, 1 the adaptive stage's ladder.  acc_out (nullable) [n_inst][31]: the
+ * acceptance of the last pilot run on the instance (status 1: of its last rejected ladder). */
+sg_status sg_judge_ladders(const sg_lattice *inst, int32_t n_inst, const double *band_lo,
+                           const double *band_hi, const sg_adaptive_params *fallback,
+                           int32_t pilot_cycles, int32_t repair_rounds, uint64_t seed,
+                           double *beta_io, double *cutoff_io, int32_t *status, double *acc_out);
+
+/* The learned-ladder flow: the network's ladders and per-instance ICM cutoffs
+ * (sg_ladder_predict) put through sg_judge_ladders with the same arguments. */
 sg_status sg_learned_ladders(sg_mlp *m, const sg_lattice *inst, int32_t n_inst, const double *band_lo,
                              const double *band_hi, const sg_adaptive_params *fallback,
-                             int32_t pilot_cycles, uint64_t seed, double *beta_out,
-                             double *cutoff_out, int32_t *fell_back, double *acc_out);
+                             int32_t pilot_cycles, int32_t repair_rounds, uint64_t seed,
+                             double *beta_out, double *cutoff_out, int32_t *status, double *acc_out);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): sg_ladder_predict without any

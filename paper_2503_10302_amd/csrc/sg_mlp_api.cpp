@@ -352,45 +352,58 @@ void resample_ladder(const double *b, int len, int k, double *out)
     }
 }
 
-}  // namespace
-
-extern "C" {
-
-sg_status sg_learned_ladders(sg_mlp *m, const sg_lattice *inst, int32_t n_inst, const double *band_lo,
-                             const double *band_hi, const sg_adaptive_params *fallback,
-                             int32_t pilot_cycles, uint64_t seed, double *beta_out,
-                             double *cutoff_out, int32_t *fell_back, double *acc_out)
+// Inverse of the complementary error function on (0, 1]: Newton's method on erfc(x) = y,
+// kept inside a bracket [lo, hi] of the root (erfc falls from 1 at 0 to below 1e-300 at 27)
+// and bisecting whenever a step would leave it.
+double erfc_inv(double y)
 {
-    constexpr int K = 32, NP = K - 1, REPS = 2;
-    if (!m || !inst || n_inst < 1 || !band_lo || !band_hi || !fallback || pilot_cycles < 2 ||
-        !beta_out || !cutoff_out || !fell_back) {
-        set_global_error("sg_learned_ladders: bad arguments");
-        return SG_EINVAL;
+    constexpr double kPi = 3.14159265358979323846;
+    double lo = 0.0, hi = 27.0, x = 1.0;
+    for (int it = 0; it < 200; ++it) {
+        const double f = std::erfc(x) - y;   // decreasing in x
+        if (f > 0.0)
+            lo = x;
+        else
+            hi = x;
+        const double d = -2.0 / std::sqrt(kPi) * std::exp(-x * x);
+        double xn = d != 0.0 ? x - f / d : 0.5 * (lo + hi);
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        if (std::fabs(xn - x) <= 1e-15 * std::max(1.0, x)) return xn;
+        x = xn;
     }
-    // 1. the network's ladders and cutoffs
-    sg_status st = sg_ladder_predict(m, inst, n_inst, beta_out, cutoff_out);
-    if (st != SG_OK) return st;
-    // 2. pilot APT+ICM run on the predicted ladders, each instance with its own cutoff
+    return x;
+}
+
+constexpr int kRungs = 32, kPairs = kRungs - 1, kPilotReps = 2;
+// Pilot acceptances are clamped to [kAccEps, 1 - kAccEps] before they are turned into lengths.
+constexpr double kAccEps = 1e-3;
+
+// Swap acceptance of every adjacent pair of each instance over a pilot APT+ICM run: two labels,
+// one sweep per attempt, each instance at its own ICM cutoff.  Pair b is attempted on every other
+// attempt (odd attempts try the even pairs), once per label.
+sg_status pilot_acceptance(const sg_lattice *inst, int n, const double *beta, const double *cutoff,
+                           int cycles, uint64_t seed, double *acc)
+{
     sg_config cfg{};
     cfg.mode = SG_APT;
-    cfg.n_inst = n_inst;
+    cfg.n_inst = n;
     cfg.inst = inst;
-    cfg.n_beta = K;
-    cfg.beta = beta_out;
-    cfg.reps_per_beta = REPS;
+    cfg.n_beta = kRungs;
+    cfg.beta = beta;
+    cfg.reps_per_beta = kPilotReps;
     cfg.seed = seed;
     cfg.hip_stream = nullptr;
     sg_ctx *c = nullptr;
-    st = sg_create(&cfg, &c);
+    sg_status st = sg_create(&cfg, &c);
     if (st != SG_OK) return st;
     sg_apt_options opt{};
     opt.sweeps_per_swap = 1;
     opt.icm_pairs = 2;
     opt.icm_cutoff = 0.0;
-    opt.icm_cutoff_per_inst = cutoff_out;
+    opt.icm_cutoff_per_inst = cutoff;
     opt.record_every = 0;
-    std::vector<int64_t> counts((size_t)n_inst * NP * REPS);
-    st = sg_run_apt_ex(c, pilot_cycles, &opt, nullptr);
+    std::vector<int64_t> counts((size_t)n * kPairs * kPilotReps);
+    st = sg_run_apt_ex(c, cycles, &opt, nullptr);
     if (st == SG_OK) st = sg_swap_counts(c, counts.data());
     if (st != SG_OK) {
         set_global_error(sg_last_error(c));
@@ -398,24 +411,132 @@ sg_status sg_learned_ladders(sg_mlp *m, const sg_lattice *inst, int32_t n_inst, 
         return st;
     }
     sg_destroy(c);
-    // 3. acceptance of every adjacent pair (attempt a tries even pairs when a is odd), band check
-    std::vector<int> bad;
-    for (int i = 0; i < n_inst; ++i) {
-        bool ok = true;
-        for (int b = 0; b < NP; ++b) {
-            const int64_t attempts = (pilot_cycles + (1 - b % 2)) / 2;
-            int64_t acc = 0;
-            for (int l = 0; l < REPS; ++l) acc += counts[((size_t)i * NP + b) * REPS + l];
-            const double a = (double)acc / (double)(REPS * attempts);
-            if (acc_out) acc_out[(size_t)i * NP + b] = a;
-            ok &= a >= band_lo[(size_t)i * NP + b] && a <= band_hi[(size_t)i * NP + b];
+    for (int i = 0; i < n; ++i)
+        for (int b = 0; b < kPairs; ++b) {
+            const int64_t attempts = (cycles + (1 - b % 2)) / 2;
+            int64_t a = 0;
+            for (int l = 0; l < kPilotReps; ++l) a += counts[((size_t)i * kPairs + b) * kPilotReps + l];
+            acc[(size_t)i * kPairs + b] = (double)a / (double)(kPilotReps * attempts);
         }
-        fell_back[i] = ok ? 0 : 1;
-        if (!ok) bad.push_back(i);
+    return SG_OK;
+}
+
+bool in_band(const double *acc, const double *lo, const double *hi)
+{
+    for (int b = 0; b < kPairs; ++b)
+        if (!(acc[b] >= lo[b] && acc[b] <= hi[b])) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+sg_status sg_ladder_repair(const double *beta, const double *acc, const double *band_lo,
+                           const double *band_hi, int32_t n_beta, double damping, double *beta_out)
+{
+    if (!beta || !acc || !band_lo || !band_hi || !beta_out || n_beta < 2 ||
+        !(damping > 0.0 && damping <= 1.0)) {
+        set_global_error("sg_ladder_repair: NULL argument, n_beta < 2 or damping outside (0, 1]");
+        return SG_EINVAL;
     }
+    const int NP = n_beta - 1;
+    for (int k = 0; k < n_beta; ++k)
+        if (!(beta[k] > 0.0) || !std::isfinite(beta[k]) || (k > 0 && !(beta[k] > beta[k - 1]))) {
+            set_global_error("sg_ladder_repair: betas must be finite, positive and strictly ascending");
+            return SG_EINVAL;
+        }
+    for (int b = 0; b < NP; ++b)
+        if (!(acc[b] >= 0.0 && acc[b] <= 1.0) || !(band_lo[b] <= band_hi[b]) ||
+            !std::isfinite(band_lo[b]) || !std::isfinite(band_hi[b])) {
+            set_global_error("sg_ladder_repair: acceptance outside [0, 1] or an empty band");
+            return SG_EINVAL;
+        }
+    // Length of each pair under the Gaussian-energy acceptance erfc(dbeta sigma / 2): measured
+    // (S, from the pilot) and wanted (T, from the band's midpoint), accumulated over the rungs.
+    auto length = [](double a) { return 2.0 * erfc_inv(std::min(std::max(a, kAccEps), 1.0 - kAccEps)); };
+    std::vector<double> S(n_beta, 0.0), T(n_beta, 0.0), out(n_beta);
+    for (int b = 0; b < NP; ++b) {
+        S[b + 1] = S[b] + length(acc[b]);
+        T[b + 1] = T[b] + length(0.5 * (band_lo[b] + band_hi[b]));
+    }
+    // Rung k moves to where the instance's measured length reaches the share T[k] / T[NP] of
+    // its total, interpolated linearly in log beta between the old rungs; the end rungs stay.
+    int j = 0;
+    for (int k = 0; k < n_beta; ++k) {
+        double lb;
+        if (k == 0) {
+            lb = std::log(beta[0]);
+        } else if (k == NP) {
+            lb = std::log(beta[NP]);
+        } else {
+            const double P = S[NP] * T[k] / T[NP];
+            while (j < NP - 1 && S[j + 1] < P) ++j;
+            const double u = (P - S[j]) / (S[j + 1] - S[j]);
+            lb = std::log(beta[j]) + u * (std::log(beta[j + 1]) - std::log(beta[j]));
+        }
+        out[k] = std::exp((1.0 - damping) * std::log(beta[k]) + damping * lb);
+    }
+    out[0] = beta[0];
+    out[NP] = beta[NP];
+    std::copy(out.begin(), out.end(), beta_out);
+    return SG_OK;
+}
+
+sg_status sg_judge_ladders(const sg_lattice *inst, int32_t n_inst, const double *band_lo,
+                           const double *band_hi, const sg_adaptive_params *fallback,
+                           int32_t pilot_cycles, int32_t repair_rounds, uint64_t seed,
+                           double *beta_io, double *cutoff_io, int32_t *status, double *acc_out)
+{
+    if (!inst || n_inst < 1 || !band_lo || !band_hi || !fallback || pilot_cycles < 2 ||
+        repair_rounds < 0 || !beta_io || !cutoff_io || !status) {
+        set_global_error("sg_judge_ladders: bad arguments");
+        return SG_EINVAL;
+    }
+    const size_t n = (size_t)n_inst;
+    std::vector<double> acc(n * kPairs);
+    // 1. pilot on the candidate ladders, band check of every pair
+    sg_status st = pilot_acceptance(inst, n_inst, beta_io, cutoff_io, pilot_cycles, seed, acc.data());
+    if (st != SG_OK) return st;
+    std::vector<int> bad;
+    for (size_t i = 0; i < n; ++i) {
+        const bool ok = in_band(&acc[i * kPairs], &band_lo[i * kPairs], &band_hi[i * kPairs]);
+        status[i] = ok ? 0 : 1;
+        if (!ok) bad.push_back((int)i);
+    }
+    // 2. repair rounds on the failing instances: re-space the rungs from the last pilot's
+    //    acceptance (the full step first, half steps after), pilot again, keep what passes
+    for (int r = 0; r < repair_rounds && !bad.empty(); ++r) {
+        const size_t m = bad.size();
+        std::vector<sg_lattice> sub(m);
+        std::vector<double> lad(m * kRungs), cut(m), acc2(m * kPairs);
+        for (size_t q = 0; q < m; ++q) {
+            const size_t i = (size_t)bad[q];
+            sub[q] = inst[i];
+            cut[q] = cutoff_io[i];
+            st = sg_ladder_repair(&beta_io[i * kRungs], &acc[i * kPairs], &band_lo[i * kPairs],
+                                  &band_hi[i * kPairs], kRungs, r == 0 ? 1.0 : 0.5, &lad[q * kRungs]);
+            if (st != SG_OK) return st;
+        }
+        st = pilot_acceptance(sub.data(), (int)m, lad.data(), cut.data(), pilot_cycles, seed + 2 + r,
+                              acc2.data());
+        if (st != SG_OK) return st;
+        std::vector<int> still;
+        for (size_t q = 0; q < m; ++q) {
+            const size_t i = (size_t)bad[q];
+            std::copy(&lad[q * kRungs], &lad[q * kRungs] + kRungs, &beta_io[i * kRungs]);
+            std::copy(&acc2[q * kPairs], &acc2[q * kPairs] + kPairs, &acc[i * kPairs]);
+            if (in_band(&acc[i * kPairs], &band_lo[i * kPairs], &band_hi[i * kPairs]))
+                status[i] = 2;
+            else
+                still.push_back((int)i);
+        }
+        bad.swap(still);
+    }
+    if (acc_out) std::copy(acc.begin(), acc.end(), acc_out);
     if (bad.empty()) return SG_OK;
-    // 4. the adaptive stage for every instance outside the band, resampled to 32 rungs; its
-    //    cutoff is the first rung at or above 1
+    // 3. the adaptive stage for every instance still outside the band, resampled to 32 rungs;
+    //    its cutoff is the first rung at or above 1
     std::vector<sg_lattice> sub;
     for (int i : bad) sub.push_back(inst[i]);
     const int ms = fallback->max_steps;
@@ -425,13 +546,31 @@ sg_status sg_learned_ladders(sg_mlp *m, const sg_lattice *inst, int32_t n_inst, 
                             nullptr, len.data());
     if (st != SG_OK) return st;
     for (size_t q = 0; q < bad.size(); ++q) {
-        double *o = beta_out + (size_t)bad[q] * K;
-        resample_ladder(&lad[q * ms], len[q], K, o);
+        double *o = beta_io + (size_t)bad[q] * kRungs;
+        resample_ladder(&lad[q * ms], len[q], kRungs, o);
         int r = 0;
-        while (r < K - 1 && o[r] < 1.0) ++r;
-        cutoff_out[bad[q]] = o[r];
+        while (r < kRungs - 1 && o[r] < 1.0) ++r;
+        cutoff_io[bad[q]] = o[r];
+        status[bad[q]] = 1;
     }
     return SG_OK;
+}
+
+sg_status sg_learned_ladders(sg_mlp *m, const sg_lattice *inst, int32_t n_inst, const double *band_lo,
+                             const double *band_hi, const sg_adaptive_params *fallback,
+                             int32_t pilot_cycles, int32_t repair_rounds, uint64_t seed,
+                             double *beta_out, double *cutoff_out, int32_t *status, double *acc_out)
+{
+    if (!m || !inst || n_inst < 1 || !band_lo || !band_hi || !fallback || pilot_cycles < 2 ||
+        repair_rounds < 0 || !beta_out || !cutoff_out || !status) {
+        set_global_error("sg_learned_ladders: bad arguments");
+        return SG_EINVAL;
+    }
+    // the network's ladders and cutoffs, then the judge
+    const sg_status st = sg_ladder_predict(m, inst, n_inst, beta_out, cutoff_out);
+    if (st != SG_OK) return st;
+    return sg_judge_ladders(inst, n_inst, band_lo, band_hi, fallback, pilot_cycles, repair_rounds,
+                            seed, beta_out, cutoff_out, status, acc_out);
 }
 
 sg_status sg_ladder_predict_noalloc(sg_mlp *m, const sg_lattice *inst, int32_t n_inst,

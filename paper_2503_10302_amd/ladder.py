@@ -260,34 +260,87 @@ def table_ladders(instances, tables):
     return np.exp(y[:, :N_RUNGS]), np.exp(y[:, N_RUNGS])
 
 
-def learned_ladders(instances, seed, params=None, pilot=1000, tables="default"):
-    """The learned-ladder flow (libsg sg_learned_ladders): predicted ladders and per-instance
-    cutoffs, a pilot APT+ICM run, the band check of every adjacent pair, and the adaptive stage
-    for every instance whose ladder fails it.
+# Repair rounds of the judge before the adaptive fallback (sg_judge_ladders).
+REPAIR_ROUNDS = 3
+# Status codes of a judged ladder.
+KEPT, ADAPTIVE_FALLBACK, REPAIRED = 0, 1, 2
 
-    Returns (ladders [n][32], cutoffs [n], fell_back [n] bool, pilot acceptance [n][31])."""
+
+def repair(beta, acc, lo, hi, damping=1.0):
+    """sg_ladder_repair: one re-spacing of a ladder from a pilot's per-pair acceptance towards
+    the middle of the band (end rungs fixed).  Host arithmetic, no GPU."""
+    lib = sg.load()
+    b = np.ascontiguousarray(beta, np.float64)
+    a = np.ascontiguousarray(acc, np.float64)
+    lo = np.ascontiguousarray(np.broadcast_to(lo, a.shape), np.float64)
+    hi = np.ascontiguousarray(np.broadcast_to(hi, a.shape), np.float64)
+    out = np.zeros_like(b)
+    rc = lib.sg_ladder_repair(b.ctypes.data_as(C.c_void_p), a.ctypes.data_as(C.c_void_p),
+                              lo.ctypes.data_as(C.c_void_p), hi.ctypes.data_as(C.c_void_p), b.size,
+                              float(damping), out.ctypes.data_as(C.c_void_p))
+    if rc != sg.SG_OK:
+        raise sg.SGError(rc, lib.sg_last_error(None).decode())
+    return out
+
+
+def _judge_args(instances, tables):
+    lo, hi = bands_for(instances, tables)
+    p = sg._Adaptive(*(ADAPTIVE[k] for k in ("beta0", "alpha", "tol", "n_chains", "sweeps", "tail",
+                                             "max_steps")))
+    return np.ascontiguousarray(lo), np.ascontiguousarray(hi), p
+
+
+def judge_ladders(instances, ladders, cutoffs, seed, pilot=1000, tables="default",
+                  repair_rounds=REPAIR_ROUNDS):
+    """sg_judge_ladders on given candidate ladders (e.g. the lookup table's): pilot, per-pair
+    band check, repair rounds, adaptive fallback.  Returns (ladders [n][32], cutoffs [n],
+    status [n] (KEPT, REPAIRED or ADAPTIVE_FALLBACK), acceptance of the last pilot [n][31])."""
+    if isinstance(tables, str):
+        tables = default_tables()
+    lo, hi, p = _judge_args(instances, tables)
+    arr, keep = sg._lattices(instances)
+    n = len(instances)
+    lad = np.ascontiguousarray(ladders, np.float64).copy()
+    cut = np.ascontiguousarray(np.broadcast_to(cutoffs, (n,)), np.float64).copy()
+    st = np.zeros(n, np.int32)
+    acc = np.zeros((n, N_RUNGS - 1), np.float64)
+    lib = sg.load()
+    rc = lib.sg_judge_ladders(arr, n, lo.ctypes.data_as(C.c_void_p), hi.ctypes.data_as(C.c_void_p),
+                              C.byref(p), int(pilot), int(repair_rounds), int(seed),
+                              lad.ctypes.data_as(C.c_void_p), cut.ctypes.data_as(C.c_void_p),
+                              st.ctypes.data_as(C.c_void_p), acc.ctypes.data_as(C.c_void_p))
+    if rc != sg.SG_OK:
+        raise sg.SGError(rc, lib.sg_last_error(None).decode())
+    return lad, cut, st, acc
+
+
+def learned_ladders(instances, seed, params=None, pilot=1000, tables="default",
+                    repair_rounds=REPAIR_ROUNDS):
+    """The learned-ladder flow (libsg sg_learned_ladders): predicted ladders and per-instance
+    cutoffs put through the judge (pilot APT+ICM run, band check of every adjacent pair, repair
+    rounds, the adaptive stage for every instance still outside the band).
+
+    Returns (ladders [n][32], cutoffs [n], status [n] (KEPT, REPAIRED or ADAPTIVE_FALLBACK),
+    acceptance of the last pilot [n][31])."""
     if isinstance(tables, str):
         tables = default_tables() if params is None else None
-    lo, hi = bands_for(instances, tables)
+    lo, hi, p = _judge_args(instances, tables)
     m = Predictor(default_params() if params is None else params)
     arr, keep = sg._lattices(instances)
     n = len(instances)
     lad = np.zeros((n, N_RUNGS), np.float64)
     cut = np.zeros(n, np.float64)
-    fb = np.zeros(n, np.int32)
+    st = np.zeros(n, np.int32)
     acc = np.zeros((n, N_RUNGS - 1), np.float64)
-    p = sg._Adaptive(*(ADAPTIVE[k] for k in ("beta0", "alpha", "tol", "n_chains", "sweeps", "tail",
-                                             "max_steps")))
-    lo = np.ascontiguousarray(lo)
-    hi = np.ascontiguousarray(hi)
     rc = m.lib.sg_learned_ladders(m.h, arr, n, lo.ctypes.data_as(C.c_void_p),
-                                  hi.ctypes.data_as(C.c_void_p), C.byref(p), int(pilot), int(seed),
-                                  lad.ctypes.data_as(C.c_void_p), cut.ctypes.data_as(C.c_void_p),
-                                  fb.ctypes.data_as(C.c_void_p), acc.ctypes.data_as(C.c_void_p))
+                                  hi.ctypes.data_as(C.c_void_p), C.byref(p), int(pilot),
+                                  int(repair_rounds), int(seed), lad.ctypes.data_as(C.c_void_p),
+                                  cut.ctypes.data_as(C.c_void_p), st.ctypes.data_as(C.c_void_p),
+                                  acc.ctypes.data_as(C.c_void_p))
     m.close()
     if rc != sg.SG_OK:
         raise sg.SGError(rc, m.lib.sg_last_error(None).decode())
-    return lad, cut, fb.astype(bool), acc
+    return lad, cut, st, acc
 
 
 # ----------------------------------------------------------------------------------------
@@ -400,6 +453,16 @@ def _first_hit(tr, target):
     return np.where(hit.any(axis=1), hit.argmax(axis=1) + 1, -1)
 
 
+def mean_rho_cycles(tr, E0, nspins, rho0):
+    """First cycle (1-based) at which the residual energy per spin averaged over the instances
+    (Eq. 2: the mean over instances of (E_best(t) - E0) / n) is at most rho0, or -1.  tr is the
+    per-cycle running best energy [n_inst][cycles]."""
+    rho = ((np.asarray(tr, np.float64) - np.asarray(E0, np.float64)[:, None])
+           / np.asarray(nspins, np.float64).reshape(-1, 1)).mean(axis=0)
+    hit = np.flatnonzero(rho <= rho0)
+    return int(hit[0]) + 1 if hit.size else -1
+
+
 def _batched(inst, lad, cut, seed, cycles):
     """One batched APT+ICM run with per-cycle best-energy traces: (trace, ms per cycle, pair
     acceptance)."""
@@ -414,15 +477,17 @@ def _batched(inst, lad, cut, seed, cycles):
 
 
 def evaluate(params, tables, n=256, seed0=90000, L=15, p_max=0.0, cycles=20000, pilot=1000, seed=777,
-             rho0=0.007, e0_cycles=20000, plain_sample=16):
+             rho0=0.007, e0_cycles=20000, plain_sample=16, repair_rounds=REPAIR_ROUNDS):
     """Plain, batched-adaptive, batched-learned and batched-lookup-table APT+ICM on held-out
     instances (size L, dilution up to p_max).  Each form's time to target counts its ladder
     construction: the adaptive stage on all instances at once; the learned flow (inference,
-    pilot, band check, adaptive fallback); the table lookup alone (nothing to time) and the
-    table lookup through the same judge as the learned flow.  Every form runs
+    pilot, band check, repair rounds, adaptive fallback); the table lookup alone (nothing to
+    time) and the table lookup through the same judge as the learned flow.  Every form runs
     each instance at its own ICM cutoff.  Plain: one instance at a time, its own adaptive stage
     and APT run, on the first plain_sample instances, scaled to n.  Also the ladders' rms
-    distance in log beta from the adaptive stage's."""
+    distance in log beta from the adaptive stage's.  Two targets: the residual energy per spin
+    averaged over the instances reaching rho0 (Eq. 2, the paper's criterion: cycles_mean_rho,
+    total_s_mean_rho), and every instance within rho0 n of its E0 (cycles_all, total_s)."""
     import time
     inst = _instances(range(n), (L,), seed0, p_max)
     nsp = L ** 3
@@ -432,25 +497,17 @@ def evaluate(params, tables, n=256, seed0=90000, L=15, p_max=0.0, cycles=20000, 
     lad_a = np.stack([resample(r[0]) for r in res])
     cut_a = np.array([cutoff_label(x) for x in lad_a])
     t0 = time.perf_counter()
-    lad_l, cut_l, fell, acc_pilot = learned_ladders(inst, seed + 9, params, pilot, tables)
+    lad_l, cut_l, st_l, acc_pilot = learned_ladders(inst, seed + 9, params, pilot, tables, repair_rounds)
     t_learn = time.perf_counter() - t0
     lad_t, cut_t = table_ladders(inst, tables) if tables is not None else (None, None)
     forms = {"adaptive": (lad_a, cut_a, t_adapt), "learned": (lad_l, cut_l, t_learn)}
-    fell_t = None
+    st_t = None
     if lad_t is not None:
         forms["table"] = (lad_t, cut_t, 0.0)
-        # the lookup ladders through the same judge: pilot, per-pair band, adaptive fallback
+        # the lookup ladders through the same judge: pilot, per-pair band, repair, fallback
         t0 = time.perf_counter()
-        lo, hi = bands_for(inst, tables)
-        acc_t = pilot_acceptance(inst, lad_t, seed + 9, pilot, cut_t)
-        fell_t = ~in_band(acc_t, lo, hi)
-        lad_tj, cut_tj = lad_t.copy(), cut_t.copy()
-        bad = np.flatnonzero(fell_t)
-        if bad.size:
-            fb = adaptive_ladders([inst[i] for i in bad], seed + 10, **ADAPTIVE)
-            for i, r in zip(bad, fb):
-                lad_tj[i] = resample(r[0])
-                cut_tj[i] = cutoff_label(lad_tj[i])
+        lad_tj, cut_tj, st_t, _ = judge_ladders(inst, lad_t, cut_t, seed + 9, pilot, tables,
+                                                repair_rounds)
         forms["table_judged"] = (lad_tj, cut_tj, time.perf_counter() - t0)
     E0 = np.full(n, np.iinfo(np.int64).max)
     for sd in (11, 12):
@@ -480,18 +537,25 @@ def evaluate(params, tables, n=256, seed0=90000, L=15, p_max=0.0, cycles=20000, 
                 break
         ms = ci.timer_stop()
         ci.close()
-        plain.append((t_ad, ms / 1e3))
+        plain.append((t_ad, ms / 1e3, ms / 1e3 / done))
     target = E0 + rho0 * nsp
     out = {"n": n, "L": L, "p_max": p_max, "rho0": rho0, "pilot_cycles": pilot, "cycles_max": cycles,
-           "adaptive_params": ADAPTIVE, "learned_fallbacks": int(fell.sum()),
-           "table_judged_fallbacks": None if fell_t is None else int(fell_t.sum()),
+           "adaptive_params": ADAPTIVE, "repair_rounds": repair_rounds,
+           "learned_fallbacks": int((st_l == ADAPTIVE_FALLBACK).sum()),
+           "learned_repaired": int((st_l == REPAIRED).sum()),
+           "table_judged_fallbacks": None if st_t is None else int((st_t == ADAPTIVE_FALLBACK).sum()),
+           "table_judged_repaired": None if st_t is None else int((st_t == REPAIRED).sum()),
            "e0": f"min over two {e0_cycles}-cycle runs on the adaptive ladders and every run here"}
     for name, (lad, cut, t_build) in forms.items():
         tr, mspc, acc = runs[name]
         first = _first_hit(tr, target)
         reached = int((first > 0).sum())
         apt_s = first.max() * mspc / 1e3 if reached == n else None
-        out[name] = {"ladder_s": round(t_build, 3), "reached": reached,
+        cm = mean_rho_cycles(tr, E0, nsp, rho0)
+        out[name] = {"ladder_s": round(t_build, 3),
+                     "cycles_mean_rho": cm if cm > 0 else None,
+                     "total_s_mean_rho": round(t_build + cm * mspc / 1e3, 3) if cm > 0 else None,
+                     "reached": reached,
                      "cycles_all": int(first.max()) if reached == n else None,
                      "apt_s": None if apt_s is None else round(apt_s, 3),
                      "total_s": None if apt_s is None else round(t_build + apt_s, 3),
@@ -504,7 +568,12 @@ def evaluate(params, tables, n=256, seed0=90000, L=15, p_max=0.0, cycles=20000, 
         out["plain_sample"] = {"instances": len(plain),
                                "ladder_s_mean": round(float(pl[:, 0].mean()), 3),
                                "apt_s_mean": round(float(pl[:, 1].mean()), 4),
-                               "total_s_scaled_to_n": round(float(pl.sum(axis=1).mean() * n), 2)}
+                               "total_s_scaled_to_n": round(float(pl[:, :2].sum(axis=1).mean() * n), 2)}
+        cm = out["adaptive"]["cycles_mean_rho"]
+        if cm is not None:
+            # every instance alone for as many cycles as the batched adaptive form needed
+            out["plain_sample"]["total_s_mean_rho_scaled_to_n"] = round(
+                float((pl[:, 0] + cm * pl[:, 2]).mean() * n), 2)
     return out
 
 

@@ -60,6 +60,7 @@ EXPORTS = [
     "sg_synchronize", "sg_kernel_timing", "sg_kernel_time", "sg_adaptive_ladder", "sg_mlp_create", "sg_mlp_destroy",
     "sg_instance_features", "sg_mlp_set_standardisation", "sg_mlp_loss_grad", "sg_mlp_train",
     "sg_mlp_get_params", "sg_ladder_predict", "sg_learned_ladders", "sg_ladder_predict_noalloc",
+    "sg_ladder_repair", "sg_judge_ladders",
 ]
 
 _lib = None
@@ -114,8 +115,11 @@ def load():
         "sg_mlp_get_params": (i32, [P, P]),
         "sg_ladder_predict": (i32, [P, C.POINTER(_Lattice), i32, P, P]),
         "sg_ladder_predict_noalloc": (i32, [P, C.POINTER(_Lattice), i32, P, P]),
-        "sg_learned_ladders": (i32, [P, C.POINTER(_Lattice), i32, P, P, C.POINTER(_Adaptive), i32, u64,
-                                     P, P, P, P]),
+        "sg_learned_ladders": (i32, [P, C.POINTER(_Lattice), i32, P, P, C.POINTER(_Adaptive), i32, i32,
+                                     u64, P, P, P, P]),
+        "sg_judge_ladders": (i32, [C.POINTER(_Lattice), i32, P, P, C.POINTER(_Adaptive), i32, i32, u64,
+                                   P, P, P, P]),
+        "sg_ladder_repair": (i32, [P, P, P, P, i32, C.c_double, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

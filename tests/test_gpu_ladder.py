@@ -12,14 +12,15 @@ pytestmark = pytest.mark.gpu
 
 def test_trained_network_replaces_the_adaptive_stage():
     """16 held-out L = 15 instances (seeds outside the training range): the learned flow (the
-    shipped network, per-instance cutoffs, a pilot run and the per-pair band check through the
-    C ABI) keeps the network's ladders on all but at most one instance, they lie within 5 %
-    (rms in log beta) of the adaptive stage's own ladders, every accepted ladder's pairs lie in
-    their calibrated bands, and without a fallback the flow costs a small fraction of the
-    stage."""
+    shipped network, per-instance cutoffs, a pilot run, the per-pair band check and repair
+    rounds through the C ABI) keeps the network's ladders, as predicted or repaired, on all but
+    at most one instance; they lie within 5 % (rms in log beta) of the adaptive stage's own
+    ladders, every kept ladder's pairs lie in their calibrated bands in its last pilot, and
+    without a fallback the flow costs a small fraction of the stage."""
     inst = ladder._instances(range(16), (15,), 90000)
     t0 = time.perf_counter()
-    lad_l, cut_l, fell_back, acc = ladder.learned_ladders(inst, 7)
+    lad_l, cut_l, status, acc = ladder.learned_ladders(inst, 7)
+    fell_back = status == ladder.ADAPTIVE_FALLBACK
     t_learned = time.perf_counter() - t0
     t0 = time.perf_counter()
     res = ladder.adaptive_ladders(inst, 8, **ladder.ADAPTIVE)
@@ -39,7 +40,8 @@ def test_trained_network_replaces_the_adaptive_stage():
 
 def test_band_violation_falls_back_to_the_adaptive_stage():
     """A network whose ladder barely spans any temperature (acceptance near 1) fails the band
-    on every instance, and every ladder and cutoff then comes from the adaptive stage."""
+    on every instance, the repair (which keeps the end rungs) cannot mend it, and every ladder
+    and cutoff then comes from the adaptive stage."""
     p = ladder.default_params().copy()
     nout = ladder.N_RUNGS + 1
     p[ladder.OFF_W3:ladder.OFF_B3] = 0.0           # outputs = output biases
@@ -47,8 +49,8 @@ def test_band_violation_falls_back_to_the_adaptive_stage():
     p[ladder.OFF_B3 + 1:ladder.OFF_B3 + ladder.N_RUNGS] = inc + np.log(-np.expm1(-inc))
     assert ladder.OFF_B3 + nout == p.size - 8
     inst = ladder._instances(range(4), (6,), 91000)
-    lad, cut, fell_back, acc = ladder.learned_ladders(inst, 9, params=p, pilot=200)
-    assert fell_back.all()
+    lad, cut, status, acc = ladder.learned_ladders(inst, 9, params=p, pilot=200)
+    assert (status == ladder.ADAPTIVE_FALLBACK).all()
     assert (acc[:, 0] > ladder.BAND[1]).all()
     # the fallback is the adaptive stage itself: the same call gives the same ladders
     ref = ladder.adaptive_ladders(inst, 10, **ladder.ADAPTIVE)
@@ -57,6 +59,48 @@ def test_band_violation_falls_back_to_the_adaptive_stage():
         np.testing.assert_array_equal(lad[i], l32)
         assert cut[i] == ladder.cutoff_label(l32)
         assert lad[i, 0] == 0.5 and np.all(np.diff(lad[i]) > 0)
+
+
+def test_repair_round_is_the_host_step_on_the_first_pilot():
+    """The judge on the per-size lookup ladders of 48 held-out L = 15 instances, with bands
+    narrowed to 60 % of their width around the middle so that many ladders fail: with no
+    repair round the call reports the first pilot's acceptance; with one round, every
+    instance it reports as repaired holds exactly sg_ladder_repair of its candidate under
+    that acceptance (same seed, so the same first pilot), and its repaired ladder's own pilot
+    lies inside the narrowed band; the others are kept (and identical) or come from the
+    adaptive stage; with three rounds no more instances fall back than with one."""
+    tables = ladder.default_tables()
+    inst = ladder._instances(range(48), (15,), 90300)
+    lad_t, cut_t = ladder.table_ladders(inst, tables)
+    lo, hi = ladder.bands_for(inst, tables)
+    mid = 0.5 * (lo + hi)
+    nt = dict(tables)
+    k = ladder._size_index(inst[:1], tables["sizes"])[0]
+    nt["band_lo"] = tables["band_lo"].copy()
+    nt["band_hi"] = tables["band_hi"].copy()
+    nt["band_lo"][k] = mid[0] - 0.6 * (mid[0] - lo[0])
+    nt["band_hi"][k] = mid[0] + 0.6 * (hi[0] - mid[0])
+    nlo, nhi = ladder.bands_for(inst, nt)
+    _, _, st0, acc0 = ladder.judge_ladders(inst, lad_t, cut_t, 31, 1000, nt, repair_rounds=0)
+    lad1, cut1, st1, acc1 = ladder.judge_ladders(inst, lad_t, cut_t, 31, 1000, nt, repair_rounds=1)
+    print(f"narrowed band: {int((st0 == 1).sum())} of 48 fail the first pilot; after one "
+          f"round {int((st1 == 2).sum())} repaired, {int((st1 == 1).sum())} fall back", flush=True)
+    assert (st0 == ladder.ADAPTIVE_FALLBACK).sum() >= 8
+    assert (st1 == ladder.REPAIRED).sum() >= 1
+    for i in range(48):
+        if st0[i] == ladder.KEPT:
+            assert st1[i] == ladder.KEPT
+            np.testing.assert_array_equal(lad1[i], lad_t[i])
+            assert np.all((acc1[i] >= nlo[i]) & (acc1[i] <= nhi[i]))
+        elif st1[i] == ladder.REPAIRED:
+            ref = ladder.repair(lad_t[i], acc0[i], nlo[i], nhi[i], 1.0)
+            np.testing.assert_array_equal(lad1[i], ref)
+            assert cut1[i] == cut_t[i]
+            assert np.all((acc1[i] >= nlo[i]) & (acc1[i] <= nhi[i]))
+        else:
+            assert st1[i] == ladder.ADAPTIVE_FALLBACK and lad1[i, 0] == 0.5
+    _, _, st3, _ = ladder.judge_ladders(inst, lad_t, cut_t, 31, 1000, nt, repair_rounds=3)
+    assert (st3 == ladder.ADAPTIVE_FALLBACK).sum() <= (st1 == ladder.ADAPTIVE_FALLBACK).sum()
 
 
 def test_network_beats_the_size_lookup_on_diluted_instances():

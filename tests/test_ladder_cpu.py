@@ -102,3 +102,96 @@ def test_dilution_is_per_instance_and_reproducible():
     assert d == [ladder.dilution_of(i, 30000, 0.3) for i in range(200)]
     assert 0 <= min(d) and max(d) < 0.3 and np.std(d) > 0.07
     assert ladder.dilution_of(5, 30000, 0.0) == 0.0
+
+
+def _geom(n=32, lo=0.4, hi=3.2):
+    return lo * (hi / lo) ** (np.arange(n) / (n - 1))
+
+
+def test_repair_keeps_a_ladder_whose_pairs_sit_at_the_band_middle():
+    """Acceptances exactly at the middle of every pair's band: the measured and wanted lengths
+    coincide and the repair returns the ladder itself (to rounding)."""
+    rng = np.random.default_rng(5)
+    b = _geom()
+    mid = rng.uniform(0.1, 0.5, 31)
+    lo, hi = mid - 0.05, mid + 0.05
+    out = ladder.repair(b, 0.5 * (lo + hi), lo, hi)
+    np.testing.assert_allclose(out, b, rtol=1e-12)
+    assert out[0] == b[0] and out[-1] == b[-1]
+
+
+def test_repair_gives_every_pair_its_wanted_length_under_the_gaussian_model():
+    """Model check: an instance whose pair lengths (dbeta sigma) are x_b has pilot acceptance
+    erfc(x_b / 2); with the length taken as linear in log beta between the old rungs, the
+    repaired rungs must cut the instance's total length in the proportions of the band
+    midpoints' lengths 2 erfc^-1(m_b).  When the totals agree, each repaired pair has exactly
+    its wanted length, i.e. acceptance m_b under the model.  The lengths of the repaired
+    pairs are measured here with numpy interpolation, independently of the library."""
+    from scipy import special
+    rng = np.random.default_rng(11)
+    b = _geom()
+    x = rng.uniform(0.4, 3.5, 31)              # measured pair lengths, some far off
+    acc = special.erfc(x / 2)
+    y = rng.uniform(0.8, 2.2, 31)
+    y *= x.sum() / y.sum()                     # wanted lengths with the same total
+    mid = special.erfc(y / 2)
+    lo, hi = mid - 0.02, mid + 0.02
+    out = ladder.repair(b, acc, lo, hi)
+    S = np.concatenate([[0.0], np.cumsum(x)])
+    s_new = np.interp(np.log(out), np.log(b), S)
+    np.testing.assert_allclose(np.diff(s_new), y, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(special.erfc(np.diff(s_new) / 2), mid, atol=1e-9)
+    # totals that disagree: lengths scale by one common factor, ends fixed
+    out2 = ladder.repair(b, special.erfc(1.3 * x / 2), lo, hi)
+    s2 = np.interp(np.log(out2), np.log(b), 1.3 * S)
+    np.testing.assert_allclose(np.diff(s2), 1.3 * y, atol=1e-9)
+
+
+def test_repair_damping_is_a_geometric_mix():
+    """Damping d gives exp((1 - d) log beta + d log beta_full) rung by rung."""
+    rng = np.random.default_rng(2)
+    b = _geom()
+    acc = rng.uniform(0.05, 0.7, 31)
+    lo, hi = np.full(31, 0.2), np.full(31, 0.5)
+    full = ladder.repair(b, acc, lo, hi, 1.0)
+    half = ladder.repair(b, acc, lo, hi, 0.5)
+    np.testing.assert_allclose(half, np.sqrt(b * full), rtol=1e-12)
+    q = ladder.repair(b, acc, lo, hi, 0.25)
+    np.testing.assert_allclose(q, np.exp(0.75 * np.log(b) + 0.25 * np.log(full)), rtol=1e-12)
+
+
+def test_repair_extremes_and_errors():
+    """Acceptances of 0 and 1 (clamped) still give a strictly ascending ladder with the same
+    ends; invalid arguments are refused."""
+    from paper_2503_10302_amd import sg
+    b = _geom()
+    acc = np.tile([0.0, 1.0, 0.3], 11)[:31]
+    out = ladder.repair(b, acc, np.full(31, 0.2), np.full(31, 0.5))
+    assert out[0] == b[0] and out[-1] == b[-1] and np.all(np.diff(out) > 0)
+    lo, hi = np.full(31, 0.2), np.full(31, 0.5)
+    bad = [(b[::-1], np.full(31, 0.3), lo, hi, 1.0),          # descending
+           (b, np.full(31, 1.5), lo, hi, 1.0),                # acceptance > 1
+           (b, np.full(31, 0.3), hi, lo, 1.0),                # empty band
+           (b, np.full(31, 0.3), lo, hi, 0.0),                # damping 0
+           (b, np.full(31, 0.3), lo, hi, 1.5)]                # damping > 1
+    for args in bad:
+        try:
+            ladder.repair(*args[:4], damping=args[4])
+        except sg.SGError as e:
+            assert e.code == sg.SG_EINVAL
+        else:
+            raise AssertionError("accepted invalid arguments")
+
+
+def test_mean_rho_crossing_averages_over_instances():
+    """Eq. (2): the residual energy per spin is averaged over the instances before the target
+    is applied, so one slow instance delays the crossing only by its share of the mean."""
+    E0 = np.array([-100, -200])
+    n = np.array([10, 20])
+    # instance 0 reaches E0 at cycle 3; instance 1 stays 2 above E0 (rho 0.1) throughout
+    tr = np.array([[-90, -95, -100, -100, -100],
+                   [-198, -198, -198, -198, -198]])
+    # mean rho per cycle: (1.0 + 0.1)/2, (0.5 + 0.1)/2, (0 + 0.1)/2, ...
+    assert ladder.mean_rho_cycles(tr, E0, n, 0.05) == 3
+    assert ladder.mean_rho_cycles(tr, E0, n, 0.3) == 2
+    assert ladder.mean_rho_cycles(tr, E0, n, 0.01) == -1
