@@ -527,17 +527,20 @@ def evaluate(params, tables, n=256, seed0=90000, L=15, p_max=0.0, cycles=20000, 
         l32 = resample(r[0][0])
         ci = sg.apt([inst[i]], l32[None, :], seed + 1000 + i, 2)
         target = E0[i] + rho0 * nsp
-        done, ms = 0, 0.0
+        done, hit = 0, -1
         ci.synchronize()
         ci.timer_start()
         while done < cycles:
-            ci.run_apt_ex(250, 1, cutoff_label(l32), 2)
+            tr_i = ci.run_apt_ex(250, 1, cutoff_label(l32), 2, record_every=1)[0]
             done += 250
-            if int(ci.best()[0]) <= target:
+            if tr_i[-1] <= target:
+                hit = done - 250 + int(np.argmax(tr_i <= target)) + 1
                 break
         ms = ci.timer_stop()
         ci.close()
-        plain.append((t_ad, ms / 1e3, ms / 1e3 / done))
+        # charged for the cycles up to the target at the measured cost per cycle
+        per = ms / 1e3 / done
+        plain.append((t_ad, per * (hit if hit > 0 else done), per))
     target = E0 + rho0 * nsp
     out = {"n": n, "L": L, "p_max": p_max, "rho0": rho0, "pilot_cycles": pilot, "cycles_max": cycles,
            "adaptive_params": ADAPTIVE, "repair_rounds": repair_rounds,
