@@ -615,8 +615,6 @@ void create_apt(sg_ctx *c, const sg_config *cfg, const int8_t *const *colour = n
                 fail(SG_EINVAL, "beta must be strictly ascending");
         }
     build_common(c, cfg, colour);
-    init_stream(c, cfg->hip_stream);
-    hipStream_t s = c->stream;
     const int nb4 = 4 * c->n_quads;   // physical buffers per instance (slots padded to a quad)
 
     std::vector<uint4> rec, recj, rowA, rowB, rowC;
@@ -661,6 +659,9 @@ void create_apt(sg_ctx *c, const sg_config *cfg, const int8_t *const *colour = n
         }
         c->idev.push_back(I);
     }
+    // every host-side table is built before the first device call
+    init_stream(c, cfg->hip_stream);
+    hipStream_t s = c->stream;
     c->d_inst.upload(c->idev, s, "instances");
     c->d_rec.upload(rec, s, "records");
     c->d_recj.upload(recj, s, "records");
@@ -832,14 +833,12 @@ void create_sqa(sg_ctx *c, const sg_config *cfg, const int8_t *const *colour = n
     if (!(cfg->sqa_beta > 0.0) || !std::isfinite(cfg->sqa_beta)) fail(SG_EINVAL, "sqa_beta must be > 0");
     if ((int64_t)cfg->n_inst * cfg->R > (1 << 28)) fail(SG_ENOMEM, "too many replicas");
     build_common(c, cfg, colour);
-    init_stream(c, cfg->hip_stream);
     c->M = cfg->M;
     c->R = cfg->R;
     c->H = cfg->M / 2;
     c->sqa_beta = cfg->sqa_beta;
     c->smax = 6 + c->hmax;
     c->nl = (2 * c->smax + 1) * 3;
-    hipStream_t s = c->stream;
     std::vector<uint4> rec, recj;
     int64_t words = 0;
     int npad_max = 0;
@@ -856,6 +855,9 @@ void create_sqa(sg_ctx *c, const sg_config *cfg, const int8_t *const *colour = n
         npad_max = std::max(npad_max, I.npad);
         c->idev.push_back(I);
     }
+    // every host-side table is built before the first device call
+    init_stream(c, cfg->hip_stream);
+    hipStream_t s = c->stream;
     c->d_inst.upload(c->idev, s, "instances");
     c->d_rec.upload(rec, s, "records");
     c->d_recj.upload(recj, s, "records");
