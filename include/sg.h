@@ -80,7 +80,7 @@ typedef struct {
     const double *beta;        /* [n_inst][n_beta], strictly ascending, >= 0 */
     int32_t reps_per_beta;     /* ICM labels per temperature: 1, 2 or 4 */
     /* DT-SQA (Algorithm S1): */
-    int32_t M;                 /* Trotter slices, even, 2..64 */
+    int32_t M;                 /* Trotter slices, 2..64 (an odd ring takes a third colour) */
     int32_t R;                 /* independent replicas per instance, 1..65535 */
     double sqa_beta;           /* inverse temperature beta > 0 */
     uint64_t seed;
@@ -94,8 +94,8 @@ sg_status sg_create(const sg_config *cfg, sg_ctx **out);
 /* sg_create with a colour map per instance (Methods, "Graph Coloring": the p-bits of one
  * colour share no bond and are updated in parallel).  colour (nullable) [n_inst], colour[i]
  * (nullable: the closed-form colouring) [n] int8 in 0..3, copied.  APT sweeps colour classes
- * 0, 1, ... in turn; DT-SQA colours site j of slice k with (colour[j] + k mod 2) mod C,
- * C = max(colours, 2).  SG_EINVAL when two sites joined by a bond with J != 0 share a colour
+ * 0, 1, ... in turn; DT-SQA colours site j of slice k with (colour[j] + t(k)) mod C, where
+ * t(k) = k mod 2 except t(M - 1) = 2 when M is odd, and C = max(colours, 2, 3 if M is odd).  SG_EINVAL when two sites joined by a bond with J != 0 share a colour
  * or a value is outside 0..3.  Any proper map gives a valid sampler; the oracle takes the
  * same map.  sg_create(cfg, out) = sg_create_ex(cfg, NULL, out). */
 sg_status sg_create_ex(const sg_config *cfg, const int8_t *const *colour, sg_ctx **out);

@@ -416,30 +416,50 @@ void apt_records(const Lat &L, std::vector<uint4> &rec, std::vector<uint4> &recj
 // Phases of the (d+1)-dimensional lattice with an even periodic Trotter ring:
 // colour(j, k) = (spatial colour + k) mod C, C = max(spatial colours, 2), so in phase c
 // site j updates the slices of parity p = (c - spatial colour) mod C when p is 0 or 1.
-void sqa_records(const Lat &L, std::vector<uint4> &rec, std::vector<uint4> &recj, InstDev &I)
+// DT-SQA phases (Methods, "Graph Coloring", with the Trotter direction as a fourth axis):
+// slice k of site j takes colour (c(j) + t(k)) mod C with t(k) = k mod 2, except t(M - 1) = 2
+// when M is odd (an odd Trotter ring); c is the given map, else the closed form, which takes
+// three colours when any ring, spatial or Trotter, is odd.  C = max(spatial colours, 2, and 3
+// for odd M).  A site is listed in each phase with the part of its slices that phase updates:
+// part 0, word 0 (even slices; with odd M all but the last), part 1, word 1 (odd slices), and
+// with odd M part 2, the last slice M - 1 alone.
+void sqa_records(const Lat &L, int M, std::vector<uint4> &rec, std::vector<uint4> &recj, InstDev &I)
 {
     if (2 * L.n + 1 > 0xFFFF) fail(SG_EUNSUPPORTED, "DT-SQA lattice of %d sites is too large", L.n);
-    const int C = std::max(L.n_colours(), 2);
+    const bool odd_m = (M & 1) != 0;
+    int C;
+    std::vector<int> cs(L.n);
+    if (!L.cmap.empty()) {
+        C = std::max(L.n_colours(), odd_m ? 3 : 2);
+        for (int j = 0; j < L.n; ++j) cs[j] = L.cmap[j];
+    } else {
+        const bool three = L.any_odd_ring() || odd_m;
+        C = three ? 3 : 2;
+        for (int j = 0; j < L.n; ++j) cs[j] = L.label_sum(j, three) % C;
+    }
+    if (C > kMaxColours) fail(SG_EUNSUPPORTED, "more than %d DT-SQA phases", kMaxColours);
     I.n_colours = C;
     I.rec_off = (int64_t)rec.size();
     I.recj_off = (int64_t)recj.size();
+    const int parts = odd_m ? 3 : 2;
     int off = 0;
     for (int c = 0; c < kMaxColours; ++c) {
         I.col_off[c] = off;
         I.col_cnt[c] = 0;
         I.col_p1[c] = 0;
+        I.col_p2[c] = 0;
         if (c >= C) continue;
-        // the phase's sites of parity 0 first (col_p1[c] of them), then those of parity 1,
-        // so that the kernel sweeps each part with the parity fixed
-        for (int pp = 0; pp < 2; ++pp) {
-            if (pp == 1) I.col_p1[c] = I.col_cnt[c];
+        // the phase's records by part, so that the kernel sweeps each part with the word fixed
+        for (int q = 0; q < parts; ++q) {
+            if (q == 1) I.col_p1[c] = I.col_cnt[c];
+            if (q == 2) I.col_p2[c] = I.col_cnt[c];
+            const uint32_t p = q == 1 ? 1u : 0u;
             for (int j = 0; j < L.n; ++j) {
-                const int p = ((c - L.colour(j)) % C + C) % C;
-                if (p != pp) continue;
-                uint4 rr = make_record(L, j, (uint32_t)p);
+                if ((cs[j] + q) % C != c) continue;
+                uint4 rr = make_record(L, j, p);
                 // neighbour fields -> word offsets 2 nb + p into the replica's spin words
                 auto wo = [p](uint32_t f) {
-                    return (2u * (f & 0xFFFFu) + (uint32_t)p) | ((2u * (f >> 16) + (uint32_t)p) << 16);
+                    return (2u * (f & 0xFFFFu) + p) | ((2u * (f >> 16) + p) << 16);
                 };
                 rr.y = wo(rr.y);
                 rr.z = wo(rr.z);
@@ -448,6 +468,7 @@ void sqa_records(const Lat &L, std::vector<uint4> &rec, std::vector<uint4> &recj
                 ++I.col_cnt[c];
             }
         }
+        if (!odd_m) I.col_p2[c] = I.col_cnt[c];
         off += I.col_cnt[c];
     }
     for (int j = 0; j < L.n; ++j) recj.push_back(make_record(L, j, 0u));
@@ -828,14 +849,13 @@ bool any_field(const sg_ctx *c)
 void create_sqa(sg_ctx *c, const sg_config *cfg, const int8_t *const *colour = nullptr)
 {
     if (cfg->M < 2 || cfg->M > 64) fail(SG_EINVAL, "M must be in 2..64");
-    if (cfg->M & 1) fail(SG_EUNSUPPORTED, "odd M (Trotter ring with three colours) is not implemented");
     if (cfg->R < 1 || cfg->R > 65535) fail(SG_EINVAL, "R must be in 1..65535");
     if (!(cfg->sqa_beta > 0.0) || !std::isfinite(cfg->sqa_beta)) fail(SG_EINVAL, "sqa_beta must be > 0");
     if ((int64_t)cfg->n_inst * cfg->R > (1 << 28)) fail(SG_ENOMEM, "too many replicas");
     build_common(c, cfg, colour);
     c->M = cfg->M;
     c->R = cfg->R;
-    c->H = cfg->M / 2;
+    c->H = (cfg->M + 1) / 2;   // slices per word 0 (word 1 holds M / 2)
     c->sqa_beta = cfg->sqa_beta;
     c->smax = 6 + c->hmax;
     c->nl = (2 * c->smax + 1) * 3;
@@ -848,7 +868,7 @@ void create_sqa(sg_ctx *c, const sg_config *cfg, const int8_t *const *colour = n
         I.n = L.n;
         I.npad = round_up(L.n, 16);
         I.n_slots = c->M;
-        sqa_records(L, rec, recj, I);
+        sqa_records(L, c->M, rec, recj, I);
         I.n_bonds = L.bonds();
         I.spin_off = words;
         words += (int64_t)c->R * I.npad * 2;

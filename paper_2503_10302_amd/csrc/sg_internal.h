@@ -50,8 +50,10 @@ struct InstDev {
     int32_t n_slots;     // APT: n_beta * reps; DT-SQA: M
     int32_t col_off[4];  // first record of each colour class / phase (relative)
     int32_t col_cnt[4];  // records in each class / phase
-    int32_t col_p1[4];   // DT-SQA: records of parity 0 at the start of each phase (the rest
-                         // have parity 1)
+    int32_t col_p1[4];   // DT-SQA: records of parity 0 at the start of each phase, then
+                         // those of parity 1 up to col_p2
+    int32_t col_p2[4];   // DT-SQA, odd M: start of the records that update the last slice
+                         // M - 1 alone (bit H - 1 of word 0); col_cnt when M is even
     int64_t rec_off;     // colour-sorted (or phase) records
     int64_t recj_off;    // site-ordered records
     int64_t spin_off;    // APT: byte offset of replica buffer 0; DT-SQA: word offset

@@ -1213,7 +1213,8 @@ __global__ __launch_bounds__(kSqaThreads) void sqa_init_kernel(SqaArgs A)
                     const uint32_t us[4] = {u.x, u.y, u.z, u.w};
                     for (int i = 0; i < 4; ++i) {
                         const int h = 4 * gq + i;
-                        if (h < A.H && us[i] < 0x80000000u) wd[p] |= 1u << h;
+                        // word 0 holds slices 0, 2, ..., word 1 slices 1, 3, ... (M / 2 of them)
+                        if (h < (p == 0 ? A.H : A.M / 2) && us[i] < 0x80000000u) wd[p] |= 1u << h;
                     }
                 }
         }
@@ -1342,13 +1343,16 @@ __device__ __forceinline__ uint4 sqa_group_words(uint32_t t, uint32_t x2, uint32
 // Heat-bath update of the slices of parity P (slice 2 h + P at bit h) at the site of record
 // rr (Supplementary Eq. S.3): the aligned-neighbour count of every slice, bit-sliced over the
 // six spatial neighbours, the number of up Trotter neighbours from the other parity's word,
-// then sqa_slices.
-template <int NG, bool SCALED, int P>
+// then sqa_slices.  ODD (an odd number M of slices, H = (M + 1) / 2): word 0 holds H slices and
+// word 1 H - 1; the ring closes between slice M - 1 (bit H - 1 of word 0) and slice 0 (bit 0),
+// so word 0's Trotter neighbours come partly from word 0 itself, and only the bits in umask
+// are written (the rest keep their values: they belong to other phases).
+template <int NG, bool SCALED, int P, bool ODD = false>
 __device__ __forceinline__ void sqa_site(const SqaArgs &A, const uint4 rr, uint32_t *sp,
                                          const uint32_t *lrow, const uint32_t *tab01,
                                          const uint32_t *tab2t, const uint32_t *tab1,
                                          uint32_t mask, int H, const uint4 *ug, uint32_t c3,
-                                         int ngrp)
+                                         int ngrp, uint32_t umask = 0u)
 {
     const uint32_t j = rr.x & 0xFFFFu;
     const uint32_t jn = rr.x >> 19;
@@ -1369,7 +1373,18 @@ __device__ __forceinline__ void sqa_site(const SqaArgs &A, const uint4 rr, uint3
     const uint32_t c2 = ((k1 & k2) | (cy & (k1 ^ k2))) & mask;
     // Trotter neighbours 2h + P - 1 and 2h + P + 1 from the other parity's word
     uint32_t up, dn;
-    if (P) {
+    if constexpr (ODD) {
+        const uint32_t mask1 = mask >> 1;   // word 1's H - 1 slices
+        const uint32_t ev = sp[2 * j];
+        if (P) {
+            up = ev & mask1;                 // slice 2h
+            dn = (ev >> 1) & mask1;          // slice 2h + 2 (bit H - 1: slice M - 1)
+        } else {
+            const uint32_t od = sp[2 * j + 1] & mask1;
+            up = od | ((ev & 1u) << (H - 1));                    // 2h + 1; for M - 1: slice 0
+            dn = ((od << 1) & mask) | ((ev >> (H - 1)) & 1u);    // 2h - 1; for 0: slice M - 1
+        }
+    } else if (P) {
         const uint32_t ev = sp[2 * j];
         up = ev;
         dn = rotr_h(ev, H, mask);
@@ -1392,7 +1407,10 @@ __device__ __forceinline__ void sqa_site(const SqaArgs &A, const uint4 rr, uint3
     const uint32_t res = sqa_slices<NG, SCALED>(lsite, tab01, tab2t, tab1, e01, o01, e2t, o2t,
                                                 t1b, (uint32_t)(pb >> 32), (uint32_t)pj,
                                                 (uint32_t)pb, ug, A.key0, A.key1, ngrp);
-    sp[2 * j + P] = res & mask;
+    if constexpr (ODD)
+        sp[2 * j + P] = (sp[2 * j + P] & ~umask) | (res & umask);
+    else
+        sp[2 * j + P] = res & mask;
 }
 
 // v += c for P-bit vertical counters (plane q = bit q of every bit position's count).
@@ -1554,6 +1572,24 @@ void sqa_kernel(SqaArgs A)
             // the boundary, so only the wave that straddles it runs both bodies)
             const int n0 = A.inst[inst].col_p1[c];
             int i = tid;
+            if constexpr (NG == 0) {
+                if (A.M & 1) {
+                    // odd M: word 0 but its last slice, word 1, then the last slice alone
+                    const int n2 = A.inst[inst].col_p2[c];
+                    const uint32_t last = 1u << (H - 1);
+                    for (; i < n0; i += THREADS)
+                        sqa_site<0, SCALED, 0, true>(A, rc[i], sp, lrow, tab01, tab2t, tab1, mask,
+                                                     H, ug, c3, ngrp, mask & ~last);
+                    for (; i < n2; i += THREADS)
+                        sqa_site<0, SCALED, 1, true>(A, rc[i], sp, lrow, tab01, tab2t, tab1, mask,
+                                                     H, ug, c3, ngrp, mask >> 1);
+                    for (; i < cnt; i += THREADS)
+                        sqa_site<0, SCALED, 0, true>(A, rc[i], sp, lrow, tab01, tab2t, tab1, mask,
+                                                     H, ug, c3, ngrp, last);
+                    __syncthreads();
+                    continue;
+                }
+            }
             for (; i < n0; i += THREADS)
                 sqa_site<NG, SCALED, 0>(A, rc[i], sp, lrow, tab01, tab2t, tab1, mask, H, ug, c3,
                                         ngrp);
@@ -2023,6 +2059,9 @@ hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, int thread
     if (!sqa_config_valid(threads)) return hipErrorInvalidValue;
     const bool scaled = a.nl <= 64;
     const int ngrp = (a.H + 3) >> 2;
+    if (a.M & 1)   // odd M: the general kernel, which holds the three-part phases
+        return scaled ? launch_sqa_t<0, true>(a, n_inst, lds_bytes, threads, s)
+                      : launch_sqa_t<0, false>(a, n_inst, lds_bytes, threads, s);
     if (ngrp == 8)
         return scaled ? launch_sqa_t<8, true>(a, n_inst, lds_bytes, threads, s)
                       : launch_sqa_t<8, false>(a, n_inst, lds_bytes, threads, s);

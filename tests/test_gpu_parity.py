@@ -269,11 +269,12 @@ def test_colour_maps_apt_match_oracle():
         assert np.array_equal(tr[i], otr), f"instance {i}"
 
 
-def test_colour_maps_sqa_match_oracle():
-    """DT-SQA with the same maps (slice k of site j coloured (map[j] + k mod 2) mod C): spins,
-    slice energies and the minimum, against the oracle."""
+@pytest.mark.parametrize("M", [8, 7])
+def test_colour_maps_sqa_match_oracle(M):
+    """DT-SQA with the same maps (slice k of site j coloured (map[j] + t(k)) mod C, t(k) = k mod 2
+    but t(M - 1) = 2 for odd M): spins, slice energies and the minimum, against the oracle."""
     insts, maps = _coloured_instances()
-    M, R, beta = 8, 3, 2.0
+    R, beta = 3, 2.0
     ctx = sg.sqa(insts, M, R, beta, SEED + 12, colours=maps)
     gam = linear_gamma(9)
     bE, bs = ctx.sqa_anneal(gam)
@@ -288,7 +289,7 @@ def test_colour_maps_sqa_match_oracle():
         assert np.array_equal(bs[i, :l.n], obs)
 
 
-@pytest.mark.parametrize("M", [8, 16, 64])
+@pytest.mark.parametrize("M", [8, 16, 64, 9])
 def test_trotter_agreement_matches_oracle(M):
     """Correlation along the Trotter direction (agreement of every slice with slice 0) after an
     anneal, against the oracle: ragged site counts, three-colour lattices, R > 1."""
@@ -456,8 +457,11 @@ def test_checkpoint_resume_is_exact():
     assert c2.counters().tolist() == [40, 40, 40]
 
 
-@pytest.mark.parametrize("M", [8, 6, 2, 16, 32, 64])
+@pytest.mark.parametrize("M", [8, 6, 2, 16, 32, 64, 3, 5, 7, 33, 63])
 def test_sqa_matches_oracle(M):
+    """DT-SQA against the oracle: initial state, spins after two anneal calls, slice energies
+    and the minimum.  Odd M closes the Trotter ring between slices M - 1 and 0, both in word 0:
+    three phases, the last slice updated on its own."""
     insts = [_inst((4, 4, 4), 7, 21), _inst((5, 5, 5), 7, 22), _inst((3, 4, 6), 3, 23),
              _inst((6, 6, 6), 7, 24, hmax=2), _inst((5, 3, 2), 0, 25, p_absent=0.2)]
     R, beta = 3, 2.0
@@ -524,7 +528,8 @@ def test_sqa_energy_without_schedule():
 SQA_THREADS = [192, 256, 320, 448, 512, 576, 768, 1024]
 
 
-@pytest.mark.parametrize("hmax,M", [(0, 64), (6, 64), (20, 64), (0, 6), (20, 6), (0, 60)])
+@pytest.mark.parametrize("hmax,M", [(0, 64), (6, 64), (20, 64), (0, 6), (20, 6), (0, 60), (0, 63),
+                                    (20, 5)])
 def test_sqa_every_launch_config_matches_oracle(hmax, M):
     """DT-SQA at several work-group sizes against the oracle, with threshold tables small
     enough to be pre-scaled (hmax 0), larger (6) and too large for double buffering (20);

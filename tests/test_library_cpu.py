@@ -49,7 +49,7 @@ def test_invalid_arguments_are_rejected_before_any_device_work():
     Jbig = np.ones((40, 40, 40, 3), np.int8)
     _expect(sg.SG_EINVAL, lambda: sg.apt([(Jbig, 7, None)], beta, 1, 2))                 # n too large
     _expect(sg.SG_EINVAL, lambda: sg.sqa([(J, 7, None)], 65, 2, 1.0, 1))                 # M > 64
-    _expect(sg.SG_EUNSUPPORTED, lambda: sg.sqa([(J, 7, None)], 7, 2, 1.0, 1))            # odd M
+    _expect(sg.SG_EINVAL, lambda: sg.sqa([(J, 7, None)], 1, 2, 1.0, 1))                  # M < 2
     _expect(sg.SG_EINVAL, lambda: sg.sqa([(J, 7, None)], 8, 0, 1.0, 1))                  # R = 0
     _expect(sg.SG_EINVAL, lambda: sg.sqa([(J, 7, None)], 8, 2, -1.0, 1))                 # beta <= 0
 
