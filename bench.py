@@ -644,6 +644,9 @@ def main():
                     help="DT-SQA rho(t_a) by lattice size L and Trotter slices M")
     ap.add_argument("--fss", action="store_true",
                     help="APT+ICM with and without ICM by lattice size: MCS to rho0, kappa_f, collapse")
+    ap.add_argument("--apt-parts", action="store_true",
+                    help="batched APT: time of a cycle with and without cluster moves, of a "
+                         "one-sweep launch and of a cluster-move launch (split of the cycle)")
     ap.add_argument("--valu-rates", action="store_true",
                     help="compile and run bench_valu.hip: issue rate of single VALU instruction "
                          "forms (the evidence for the ALU peak)")
@@ -654,6 +657,9 @@ def main():
               "part of it.", file=sys.stderr)
         sys.exit(2)
 
+    if args.apt_parts:
+        print(json.dumps(apt_parts()), flush=True)
+        return
     if args.valu_rates:
         import subprocess
         import tempfile
@@ -813,6 +819,41 @@ def main():
     if not args.no_cpu_baseline and args.only in ("all", "sqa"):
         out["cpu_baseline"] = cpu_baseline(insts, M, beta, gam, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def apt_parts(reps=8):
+    """Split of the batched APT+ICM cycle (256 mixed instances, the benchmark's workload): the
+    mean time of a cycle with cluster moves, of one without (cutoff +inf), of a launch that only
+    sweeps once, of one that only makes the cluster moves, and of one sweep inside a 32-sweep
+    launch, each over a graph of 32 cycles or `reps` launches after a 64-cycle warm-up: wall
+    time per cycle or launch (library timers around the calls, host work included) and, for the
+    cycles, the graph's kernel time per cycle (HIP events around each graph launch)."""
+    from paper_2503_10302_amd import sg
+    insts, ladder, _ = apt_batched_workload()
+    c = sg.apt(insts, ladder, seed=777, reps_per_beta=2)
+    c.run_apt(64, 1, 1.0)
+    out = {"workload": "256 instances, L round-robin {6,8,10,12,15}, 32 betas x 2 labels, ICM at "
+                       "beta >= 1", "launch_config": c.launch_config()}
+
+    c.kernel_timing(True)
+
+    def timed(name, fn, count, graph=False):
+        c.synchronize()
+        c.kernel_time()
+        c.timer_start()
+        fn()
+        out[name + "_us"] = round(c.timer_stop() * 1e3 / count, 2)
+        kms, _ = c.kernel_time()
+        if graph:   # the graph's kernel time, per cycle
+            out[name + "_graph_kernel_us"] = round(kms * 1e3 / count, 2)
+
+    timed("cycle_with_icm", lambda: c.run_apt(32, 1, 1.0), 32, True)
+    timed("cycle_without_icm", lambda: c.run_apt(32, 1, float("inf")), 32, True)
+    timed("one_sweep_launch", lambda: [c.sweep(1) for _ in range(reps)], reps)
+    timed("icm_launch", lambda: [c.icm(1.0) for _ in range(reps)], reps)
+    timed("sweep_in_32_sweep_launch", lambda: c.sweep(32), 32)
+    c.close()
+    return out
 
 
 def default_time_to_target():
