@@ -178,6 +178,24 @@ sg_status sg_sqa_anneal(sg_ctx *ctx, const double *gamma, int32_t n_steps, int64
  * its slice 0 (C_k = (2 agree - n) / n). */
 sg_status sg_sqa_trotter_agreement(sg_ctx *ctx, int32_t *agree_host);
 
+/* ---- device outputs ----
+ * The same results as sg_energy, sg_get_spins, sg_best and sg_sqa_anneal, written to memory
+ * the caller allocated on the context's device with the HIP runtime the library uses, in the same
+ * layouts (E_dev int64 [n_inst][n_beta * reps] or [n_inst][R][M]; spins_dev int8 +1/-1
+ * [n_inst][slots][n_max] or [n_inst][R][M][n_max], 0 past an instance's n; best_dev int64
+ * [n_inst]; best_E_dev int64 [n_inst], best_state_dev int8 [n_inst][n_max]).  The work is
+ * queued on the context's stream and nothing is copied to the host: the results are there once
+ * that stream reaches them (create the context on the consumer's stream, or call
+ * sg_synchronize).  sg_sqa_anneal_dev still waits for the stream between 256-step chunks of a
+ * longer schedule, whose threshold tables it rebuilds on the host.  The caller provides buffers
+ * of the sizes above; a pointer that is not device memory of the context's device gives
+ * SG_EINVAL before any work is queued. */
+sg_status sg_energy_dev(sg_ctx *ctx, int64_t *E_dev);
+sg_status sg_get_spins_dev(sg_ctx *ctx, int8_t *spins_dev);
+sg_status sg_best_dev(sg_ctx *ctx, int64_t *best_dev);
+sg_status sg_sqa_anneal_dev(sg_ctx *ctx, const double *gamma, int32_t n_steps, int64_t *best_E_dev,
+                            int8_t *best_state_dev);
+
 /* Launch configuration (an implementation choice; results do not depend on it).
  * DT-SQA contexts: the work-group size, a multiple of 64 in 128..1024.  The first
  * sg_sqa_anneal of a context whose size is unset (0) times 256, 512, 768 and 1024 for a few

@@ -332,6 +332,8 @@ struct sg_ctx {
     int64_t *g_trace = nullptr;
     int g_trace_cap = 0;
 
+    int device = 0;   // the HIP device the context's memory lives on
+
     // DT-SQA
     int M = 0, R = 0, H = 0, smax = 0, nl = 0;
     double sqa_beta = 0.0;
@@ -369,6 +371,7 @@ void init_stream(sg_ctx *c, void *s)
 {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(SG_EHIP, "no HIP device");
+    hip_check(hipGetDevice(&c->device), "hipGetDevice");
     if (s) {
         c->stream = (hipStream_t)s;
     } else {
@@ -1606,57 +1609,87 @@ sg_status sg_set_launch_config(sg_ctx *c, int32_t config)
     });
 }
 
+}  // extern "C"
+
+namespace {
+
+// Algorithm S1 over the schedule gamma[0 .. n_steps) and the energy pass, leaving the lowest
+// slice of every instance in d_best_key (also for n_steps = 0: the energies of the present
+// state).
+void run_sqa_anneal(sg_ctx *c, const double *gamma, int32_t n_steps)
+{
+    if (n_steps < 0 || (n_steps > 0 && !gamma)) fail(SG_EINVAL, "bad schedule");
+    for (int t = 0; t < n_steps; ++t)
+        if (!(gamma[t] > 0.0) || !std::isfinite(gamma[t])) fail(SG_EINVAL, "gamma must be > 0");
+    // thresholds for every step, FP64 -> uint32 (Supplementary Eq. S.3)
+    const int chunk = 256;
+    int done = 0;
+    std::vector<uint32_t> lut;
+    while (done < n_steps) {
+        const int ns = std::min(chunk, n_steps - done);
+        lut.assign((size_t)ns * c->nl, 0u);
+        for (int t = 0; t < ns; ++t) {
+            const double K = trotter_K(c->sqa_beta, c->M, gamma[done + t]);
+            for (int s = -c->smax; s <= c->smax; ++s)
+                for (int tt = 0; tt < 3; ++tt)
+                    lut[(size_t)t * c->nl + (s + c->smax) * 3 + tt] =
+                        trotter_threshold(c->sqa_beta, c->M, K, s, 2 * tt - 2);
+        }
+        // the previous chunk's kernel may still read the table: wait before replacing it
+        hip_check(hipStreamSynchronize(c->stream), "anneal");
+        c->d_sqa_lut.upload(lut.data(), lut.size(), c->stream, "sqa thresholds");
+        SqaArgs a = sqa_args(c);
+        a.t0 = (int32_t)c->sqa_steps;
+        a.n_steps = ns;
+        a.lut_step0 = 0;
+        a.do_energy = (done + ns == n_steps) ? 1 : 0;
+        if (c->sqa_threads == 0) sqa_autotune(c, a, ns);
+        if (a.do_energy) {
+            hip_check(launch_fill_i64(c->d_best_key.p, -1, c->n_inst, c->stream), "anneal");
+            a.best_key = (uint64_t *)c->d_best_key.p;
+        }
+        kernel_event(c, true);
+        hip_check(launch_sqa(a, c->n_inst, c->sqa_lds, c->sqa_threads, c->stream),
+                  "anneal");
+        kernel_event(c, false);
+        c->sqa_steps += (uint32_t)ns;
+        done += ns;
+    }
+    if (n_steps == 0) {
+        hip_check(launch_fill_i64(c->d_best_key.p, -1, c->n_inst, c->stream), "anneal");
+        SqaArgs a = sqa_args(c);
+        a.n_steps = 0;
+        a.do_energy = 1;
+        a.best_key = (uint64_t *)c->d_best_key.p;
+        hip_check(launch_sqa(a, c->n_inst, c->sqa_lds, sqa_threads_or_default(c), c->stream),
+                  "anneal");
+    }
+}
+
+// A device pointer for a device-output call: memory of the context's device (SG_EINVAL
+// otherwise, so that a host pointer is refused instead of being written by a kernel).
+void check_device_ptr(const sg_ctx *c, const void *p, const char *what)
+{
+    if (!p) fail(SG_EINVAL, "%s is NULL", what);
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(SG_EINVAL, "%s is not device memory", what);
+    }
+    if ((at.type != hipMemoryTypeDevice && !at.isManaged) || at.device != c->device)
+        fail(SG_EINVAL, "%s is not device memory of the context's device %d", what, c->device);
+}
+
+}  // namespace
+
+extern "C" {
+
 sg_status sg_sqa_anneal(sg_ctx *c, const double *gamma, int32_t n_steps, int64_t *best_E,
                         int8_t *best_state)
 {
     return guarded(c, [&] {
         require(c, SG_SQA);
-        if (n_steps < 0 || (n_steps > 0 && !gamma)) fail(SG_EINVAL, "bad schedule");
-        for (int t = 0; t < n_steps; ++t)
-            if (!(gamma[t] > 0.0) || !std::isfinite(gamma[t])) fail(SG_EINVAL, "gamma must be > 0");
-        // thresholds for every step, FP64 -> uint32 (Supplementary Eq. S.3)
-        const int chunk = 256;
-        int done = 0;
-        std::vector<uint32_t> lut;
-        while (done < n_steps) {
-            const int ns = std::min(chunk, n_steps - done);
-            lut.assign((size_t)ns * c->nl, 0u);
-            for (int t = 0; t < ns; ++t) {
-                const double K = trotter_K(c->sqa_beta, c->M, gamma[done + t]);
-                for (int s = -c->smax; s <= c->smax; ++s)
-                    for (int tt = 0; tt < 3; ++tt)
-                        lut[(size_t)t * c->nl + (s + c->smax) * 3 + tt] =
-                            trotter_threshold(c->sqa_beta, c->M, K, s, 2 * tt - 2);
-            }
-            // the previous chunk's kernel may still read the table: wait before replacing it
-            hip_check(hipStreamSynchronize(c->stream), "anneal");
-            c->d_sqa_lut.upload(lut.data(), lut.size(), c->stream, "sqa thresholds");
-            SqaArgs a = sqa_args(c);
-            a.t0 = (int32_t)c->sqa_steps;
-            a.n_steps = ns;
-            a.lut_step0 = 0;
-            a.do_energy = (done + ns == n_steps) ? 1 : 0;
-            if (c->sqa_threads == 0) sqa_autotune(c, a, ns);
-            if (a.do_energy) {
-                hip_check(launch_fill_i64(c->d_best_key.p, -1, c->n_inst, c->stream), "anneal");
-                a.best_key = (uint64_t *)c->d_best_key.p;
-            }
-            kernel_event(c, true);
-            hip_check(launch_sqa(a, c->n_inst, c->sqa_lds, c->sqa_threads, c->stream),
-                      "anneal");
-            kernel_event(c, false);
-            c->sqa_steps += (uint32_t)ns;
-            done += ns;
-        }
-        if (n_steps == 0) {
-            hip_check(launch_fill_i64(c->d_best_key.p, -1, c->n_inst, c->stream), "anneal");
-            SqaArgs a = sqa_args(c);
-            a.n_steps = 0;
-            a.do_energy = 1;
-            a.best_key = (uint64_t *)c->d_best_key.p;
-            hip_check(launch_sqa(a, c->n_inst, c->sqa_lds, sqa_threads_or_default(c), c->stream),
-                      "anneal");
-        }
+        run_sqa_anneal(c, gamma, n_steps);
         // Alg. S1, last lines: the lowest slice energy of every instance and its state, both
         // reduced on the device (the energy pass keeps an atomic minimum per instance)
         if (best_E || best_state) {
@@ -1675,6 +1708,77 @@ sg_status sg_sqa_anneal(sg_ctx *c, const double *gamma, int32_t n_steps, int64_t
                 for (int i = 0; i < c->n_inst; ++i)
                     best_E[i] = (int64_t)(uint32_t)((uint64_t)key[i] >> 32) - 0x40000000;
         }
+    });
+}
+
+sg_status sg_sqa_anneal_dev(sg_ctx *c, const double *gamma, int32_t n_steps, int64_t *best_E_dev,
+                            int8_t *best_state_dev)
+{
+    return guarded(c, [&] {
+        require(c, SG_SQA);
+        if (best_E_dev) check_device_ptr(c, best_E_dev, "best_E_dev");
+        if (best_state_dev) check_device_ptr(c, best_state_dev, "best_state_dev");
+        run_sqa_anneal(c, gamma, n_steps);
+        if (best_state_dev) {
+            SqaArgs a = sqa_args(c);
+            a.best_key = (uint64_t *)c->d_best_key.p;
+            hip_check(launch_sqa_best_state(a, c->n_inst, c->n_max, best_state_dev, c->stream),
+                      "best state");
+        }
+        if (best_E_dev)
+            hip_check(launch_best_key_energy((const uint64_t *)c->d_best_key.p, c->n_inst, best_E_dev,
+                                             c->stream),
+                      "best energy");
+    });
+}
+
+sg_status sg_energy_dev(sg_ctx *c, int64_t *E_dev)
+{
+    return guarded(c, [&] {
+        if (!c) fail(SG_EINVAL, "context is NULL");
+        check_device_ptr(c, E_dev, "E_dev");
+        if (c->mode == SG_APT) {
+            hip_check(launch_widen_rows(c->d_E.p, 4 * c->n_quads, E_dev, c->n_inst, c->n_slots,
+                                        c->stream),
+                      "energy");
+        } else {
+            SqaArgs a = sqa_args(c);
+            a.n_steps = 0;
+            a.do_energy = 1;
+            a.lut = nullptr;
+            hip_check(launch_sqa(a, c->n_inst, c->sqa_lds, sqa_threads_or_default(c), c->stream),
+                      "energy");
+            hip_check(launch_widen_rows(c->d_slice_E.p, c->R * c->M, E_dev, c->n_inst, c->R * c->M,
+                                        c->stream),
+                      "energy");
+        }
+    });
+}
+
+sg_status sg_best_dev(sg_ctx *c, int64_t *best_dev)
+{
+    return guarded(c, [&] {
+        require(c, SG_APT);
+        check_device_ptr(c, best_dev, "best_dev");
+        hip_check(hipMemcpyAsync(best_dev, c->d_best.p, sizeof(int64_t) * (size_t)c->n_inst,
+                                 hipMemcpyDeviceToDevice, c->stream),
+                  "best");
+    });
+}
+
+sg_status sg_get_spins_dev(sg_ctx *c, int8_t *spins_dev)
+{
+    return guarded(c, [&] {
+        if (!c) fail(SG_EINVAL, "context is NULL");
+        check_device_ptr(c, spins_dev, "spins_dev");
+        if (c->mode == SG_APT)
+            hip_check(launch_apt_spins_out(c->d_spins.p, c->d_perm.p, c->d_inst.p, c->n_inst,
+                                           4 * c->n_quads, c->n_slots, c->n_max, spins_dev, c->stream),
+                      "spins");
+        else
+            hip_check(launch_sqa_spins_out(c->d_sqa.p, c->d_inst.p, c->n_inst, c->R, c->M, c->n_max,
+                                           spins_dev, c->stream),
+                      "spins");
     });
 }
 

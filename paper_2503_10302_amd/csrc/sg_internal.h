@@ -205,6 +205,13 @@ hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, int thread
 hipError_t launch_sqa_best_state(const SqaArgs &a, int n_inst, int n_max, int8_t *out,
                                  hipStream_t s);
 // agree[inst][r][k]: sites where slice k of replica r agrees with its slice 0.
+hipError_t launch_widen_rows(const int32_t *src, int src_stride, int64_t *dst, int rows, int cols,
+                             hipStream_t s);
+hipError_t launch_apt_spins_out(const uint8_t *spins, const int32_t *perm, const InstDev *inst,
+                                int n_inst, int nb4, int n_slots, int n_max, int8_t *out, hipStream_t s);
+hipError_t launch_sqa_spins_out(const uint32_t *words, const InstDev *inst, int n_inst, int R, int M,
+                                int n_max, int8_t *out, hipStream_t s);
+hipError_t launch_best_key_energy(const uint64_t *key, int n, int64_t *out, hipStream_t s);
 hipError_t launch_sqa_corr(const SqaArgs &a, int n_inst, int32_t *agree, hipStream_t s);
 hipError_t launch_adapt_init(const AdaptArgs &a, int n_inst, hipStream_t s);
 hipError_t launch_adapt(const AdaptArgs &a, int n_inst, size_t lds_bytes, hipStream_t s);

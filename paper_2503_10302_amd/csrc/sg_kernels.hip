@@ -12,6 +12,7 @@
 // lattice of Supplementary Eq. S.3.  Up to 64 Trotter slices are bit-packed
 // per site, even and odd slices in separate words; the six spatial
 // neighbours are summed bit-sliced over all slices of a parity at once.
+#include <algorithm>
 #include "sg_internal.h"
 
 namespace sg {
@@ -1708,6 +1709,55 @@ __global__ __launch_bounds__(256) void sqa_best_state_kernel(SqaArgs A, int n_ma
         o[j] = j < I.n ? (((g[2 * j + (k & 1)] >> (k >> 1)) & 1u) ? 1 : -1) : 0;
 }
 
+// ---------------------------------------------------------------------------
+// Results written to the caller's device memory (the device-output calls).
+// ---------------------------------------------------------------------------
+// The first `cols` entries of every row of src (row stride src_stride), widened to int64, rows
+// packed one after another.
+__global__ void widen_rows_kernel(const int32_t *src, int src_stride, int64_t *dst, int rows, int cols)
+{
+    const int64_t total = (int64_t)rows * cols;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / cols;
+        dst[i] = src[r * src_stride + (i - r * cols)];
+    }
+}
+
+// APT spins as +1/-1, [n_inst][n_slots][n_max] (0 past an instance's n): logical slot s of
+// instance i is physical buffer perm[i][s].  Grid (n_slots, n_inst).
+__global__ void apt_spins_out_kernel(const uint8_t *spins, const int32_t *perm, const InstDev *inst,
+                                     int nb4, int n_slots, int n_max, int8_t *out)
+{
+    const int s = blockIdx.x, i = blockIdx.y;
+    const InstDev I = inst[i];
+    const uint8_t *src = spins + I.spin_off + (int64_t)perm[(int64_t)i * nb4 + s] * I.npad;
+    int8_t *dst = out + ((int64_t)i * n_slots + s) * n_max;
+    for (int j = threadIdx.x; j < n_max; j += blockDim.x)
+        dst[j] = j < I.n ? (src[j] ? 1 : -1) : 0;
+}
+
+// DT-SQA spins as +1/-1, [n_inst][R][M][n_max]: slice k = 2 h + p is bit h of word p.
+// Grid (R * M, n_inst).
+__global__ void sqa_spins_out_kernel(const uint32_t *words, const InstDev *inst, int R, int M,
+                                     int n_max, int8_t *out)
+{
+    const int rk = blockIdx.x, i = blockIdx.y;
+    const int r = rk / M, k = rk - r * M;
+    const InstDev I = inst[i];
+    const uint32_t *w = words + I.spin_off + (int64_t)r * I.npad * 2;
+    int8_t *dst = out + (((int64_t)i * R + r) * M + k) * n_max;
+    for (int j = threadIdx.x; j < n_max; j += blockDim.x)
+        dst[j] = j < I.n ? (((w[2 * j + (k & 1)] >> (k >> 1)) & 1u) ? 1 : -1) : 0;
+}
+
+// The lowest slice energy of every instance from its key ((E + 2^30) << 32 | (r M + k)).
+__global__ void best_key_energy_kernel(const uint64_t *key, int n, int64_t *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (int64_t)(uint32_t)(key[i] >> 32) - 0x40000000;
+}
+
 __global__ void advance_kernel(uint32_t *ctr, uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -2070,6 +2120,38 @@ hipError_t launch_sqa(const SqaArgs &a, int n_inst, size_t lds_bytes, int thread
     if (ngrp == 2 && scaled) return launch_sqa_t<2, true>(a, n_inst, lds_bytes, threads, s);
     return scaled ? launch_sqa_t<0, true>(a, n_inst, lds_bytes, threads, s)
                   : launch_sqa_t<0, false>(a, n_inst, lds_bytes, threads, s);
+}
+
+hipError_t launch_widen_rows(const int32_t *src, int src_stride, int64_t *dst, int rows, int cols,
+                             hipStream_t s)
+{
+    const int64_t total = (int64_t)rows * cols;
+    const int blocks = (int)std::min<int64_t>(4096, (total + 255) / 256);
+    hipLaunchKernelGGL(widen_rows_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, s, src, src_stride,
+                       dst, rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_apt_spins_out(const uint8_t *spins, const int32_t *perm, const InstDev *inst,
+                                int n_inst, int nb4, int n_slots, int n_max, int8_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(apt_spins_out_kernel, dim3(n_slots, n_inst), dim3(256), 0, s, spins, perm, inst,
+                       nb4, n_slots, n_max, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sqa_spins_out(const uint32_t *words, const InstDev *inst, int n_inst, int R, int M,
+                                int n_max, int8_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(sqa_spins_out_kernel, dim3(R * M, n_inst), dim3(256), 0, s, words, inst, R, M,
+                       n_max, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_best_key_energy(const uint64_t *key, int n, int64_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(best_key_energy_kernel, dim3((n + 255) / 256), dim3(256), 0, s, key, n, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_sqa_best_state(const SqaArgs &a, int n_inst, int n_max, int8_t *out,

@@ -60,7 +60,8 @@ EXPORTS = [
     "sg_synchronize", "sg_kernel_timing", "sg_kernel_time", "sg_adaptive_ladder", "sg_mlp_create", "sg_mlp_destroy",
     "sg_instance_features", "sg_mlp_set_standardisation", "sg_mlp_loss_grad", "sg_mlp_train",
     "sg_mlp_get_params", "sg_ladder_predict", "sg_learned_ladders", "sg_ladder_predict_noalloc",
-    "sg_ladder_repair", "sg_judge_ladders",
+    "sg_ladder_repair", "sg_judge_ladders", "sg_energy_dev", "sg_get_spins_dev", "sg_best_dev",
+    "sg_sqa_anneal_dev",
 ]
 
 _lib = None
@@ -120,6 +121,10 @@ def load():
         "sg_judge_ladders": (i32, [C.POINTER(_Lattice), i32, P, P, C.POINTER(_Adaptive), i32, i32, u64,
                                    P, P, P, P]),
         "sg_ladder_repair": (i32, [P, P, P, P, i32, C.c_double, P]),
+        "sg_energy_dev": (i32, [P, P]),
+        "sg_get_spins_dev": (i32, [P, P]),
+        "sg_best_dev": (i32, [P, P]),
+        "sg_sqa_anneal_dev": (i32, [P, P, i32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -131,6 +136,14 @@ def load():
 
 def _p(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _dev(x):
+    """A device address for the device-output calls: None, an int, or an object with
+    data_ptr() (a framework tensor); the library checks that it is device memory."""
+    if x is None:
+        return None
+    return C.c_void_p(int(x.data_ptr()) if hasattr(x, "data_ptr") else int(x))
 
 
 def _lattices(instances):
@@ -285,6 +298,21 @@ class Context:
         bs = np.zeros((self.n_inst, self.n_max), np.int8)
         self._check(self.lib.sg_sqa_anneal(self.h, _p(g), g.size, _p(bE), _p(bs)))
         return bE, bs
+
+    # -- device outputs: `out` is a device address (int) or an object with data_ptr() on the
+    #    context's device; the work is queued on the context's stream
+    def energy_dev(self, out):
+        self._check(self.lib.sg_energy_dev(self.h, _dev(out)))
+
+    def spins_dev(self, out):
+        self._check(self.lib.sg_get_spins_dev(self.h, _dev(out)))
+
+    def best_dev(self, out):
+        self._check(self.lib.sg_best_dev(self.h, _dev(out)))
+
+    def sqa_anneal_dev(self, gammas, best_E=None, best_state=None):
+        g = np.ascontiguousarray(gammas, dtype=np.float64)
+        self._check(self.lib.sg_sqa_anneal_dev(self.h, _p(g), g.size, _dev(best_E), _dev(best_state)))
 
     def trotter_agreement(self):
         """DT-SQA: [n_inst, R, M] sites where slice k agrees with slice 0 of its replica."""

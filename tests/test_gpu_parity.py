@@ -756,3 +756,86 @@ def test_degenerate_lattices():
         s5 = oracle.sqa_init(l, i, 8, 2, SEED)
         obE, _, _ = oracle.sqa_anneal(l, i, 8, 2, 2.0, gam, SEED, 0, s5)
         assert np.array_equal(q.spins()[i, :, :, :l.n], s5) and bE[i] == obE, f"instance {i}"
+
+
+class _DevBuf:
+    """Device memory from the HIP runtime that libsg itself uses (found among the process's
+    loaded libraries), for the device-output calls; filled with 7 so that unwritten entries
+    show."""
+
+    _hip = None
+
+    def __init__(self, shape, dtype):
+        import ctypes
+        if _DevBuf._hip is None:
+            sg.load()
+            path = next(line.split()[-1] for line in open("/proc/self/maps")
+                        if "libamdhip64" in line)
+            _DevBuf._hip = ctypes.CDLL(path)
+        self.shape, self.dtype = tuple(shape), np.dtype(dtype)
+        self.nbytes = int(np.prod(self.shape)) * self.dtype.itemsize
+        self.ptr = ctypes.c_void_p()
+        assert _DevBuf._hip.hipMalloc(ctypes.byref(self.ptr), ctypes.c_size_t(self.nbytes)) == 0
+        fill = np.full(self.shape, 7, self.dtype)
+        assert _DevBuf._hip.hipMemcpy(self.ptr, fill.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.c_size_t(self.nbytes), 1) == 0   # host to device
+
+    def data_ptr(self):
+        return self.ptr.value
+
+    def numpy(self):
+        import ctypes
+        out = np.empty(self.shape, self.dtype)
+        assert _DevBuf._hip.hipMemcpy(out.ctypes.data_as(ctypes.c_void_p), self.ptr,
+                                      ctypes.c_size_t(self.nbytes), 2) == 0   # device to host
+        return out
+
+    def free(self):
+        if self.ptr:
+            _DevBuf._hip.hipFree(self.ptr)
+            self.ptr = None
+
+
+def test_device_outputs_equal_the_host_calls():
+    """The device-output calls write the host calls' results, bit for bit, into device memory:
+    APT energies, spins (through the slot mapping after exchanges) and running minima after
+    cycles; DT-SQA (even and odd M) the anneal's minimum and state from a twin context with the
+    same seed, then slice energies and spins.  Host addresses are refused before any work."""
+    insts = [_inst((5, 5, 5), 7, 71), _inst((4, 6, 3), 5, 72), _inst((6, 6, 6), 7, 73, p_absent=0.1)]
+    ctx = sg.apt(insts, geometric_ladder(8, 0.3, 2.0), SEED, reps_per_beta=2)
+    ctx.run_apt(20, 1, 1.0)
+    E, S, B = ctx.energy(), ctx.spins(), ctx.best()
+    bufs = [_DevBuf(E.shape, np.int64), _DevBuf(S.shape, np.int8), _DevBuf(B.shape, np.int64)]
+    ctx.energy_dev(bufs[0])
+    ctx.spins_dev(bufs[1])
+    ctx.best_dev(bufs[2])
+    ctx.synchronize()
+    assert np.array_equal(bufs[0].numpy(), E)
+    assert np.array_equal(bufs[1].numpy(), S)
+    assert np.array_equal(bufs[2].numpy(), B)
+    host = np.zeros(S.size, np.int64)
+    for call in (ctx.energy_dev, ctx.best_dev, ctx.spins_dev):
+        with pytest.raises(sg.SGError) as e:
+            call(host.ctypes.data)
+        assert e.value.code == sg.SG_EINVAL
+    assert np.array_equal(ctx.energy(), E)                      # the refusals changed nothing
+    ctx.close()
+    for b in bufs:
+        b.free()
+    for M in (8, 7):
+        gam = linear_gamma(9)
+        ca = sg.sqa(insts, M, 3, 2.0, SEED + 21)
+        cb = sg.sqa(insts, M, 3, 2.0, SEED + 21)
+        bE, bs = ca.sqa_anneal(gam)
+        sE, sS = ca.energy(), ca.spins()
+        bufs = [_DevBuf(bE.shape, np.int64), _DevBuf(bs.shape, np.int8), _DevBuf(sE.shape, np.int64),
+                _DevBuf(sS.shape, np.int8)]
+        cb.sqa_anneal_dev(gam, bufs[0], bufs[1])
+        cb.energy_dev(bufs[2])
+        cb.spins_dev(bufs[3])
+        cb.synchronize()
+        for got, want in zip(bufs, (bE, bs, sE, sS)):
+            assert np.array_equal(got.numpy(), want), M
+            got.free()
+        ca.close()
+        cb.close()
