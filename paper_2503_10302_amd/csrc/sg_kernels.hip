@@ -1709,6 +1709,30 @@ __global__ __launch_bounds__(256) void sqa_best_state_kernel(SqaArgs A, int n_ma
         o[j] = j < I.n ? (((g[2 * j + (k & 1)] >> (k >> 1)) & 1u) ? 1 : -1) : 0;
 }
 
+__global__ void advance_kernel(uint32_t *ctr, uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctr[0] += d0;
+        ctr[1] += d1;
+        ctr[2] += d2;
+        ctr[3] += d3;
+    }
+}
+
+__global__ void fill_i64_kernel(int64_t *p, int64_t v, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 // ---------------------------------------------------------------------------
 // Results written to the caller's device memory (the device-output calls).
 // ---------------------------------------------------------------------------
@@ -1756,30 +1780,6 @@ __global__ void best_key_energy_kernel(const uint64_t *key, int n, int64_t *out)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = (int64_t)(uint32_t)(key[i] >> 32) - 0x40000000;
-}
-
-__global__ void advance_kernel(uint32_t *ctr, uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        ctr[0] += d0;
-        ctr[1] += d1;
-        ctr[2] += d2;
-        ctr[3] += d3;
-    }
-}
-
-__global__ void fill_i64_kernel(int64_t *p, int64_t v, int64_t n)
-{
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
-}
-
-__global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n)
-{
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
