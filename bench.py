@@ -110,7 +110,8 @@ def cpu_baseline(insts, M, beta, gam, seconds):
     share of the host on the GPU machines).  Alongside, on one core: the same DT-SQA step, the
     plain APT+ICM cycle (one L = 8 instance, 32 betas x 2 labels, ICM at beta >= 1) and the
     L = 10, M = 32 DT-SQA step, each timed over a short sample and extrapolated to its full
-    workload.  The oracle evaluates tanh (and exp for swaps) per decision in FP64: it is the
+    workload; on all the threads: the plain APT+ICM cycle on one L = 8 instance per thread
+    (seeds 1..8) and the L = 10, M = 32 DT-SQA step with its 64 replicas split over the threads.  The oracle evaluates tanh (and exp for swaps) per decision in FP64: it is the
     slow, literal reference, not a tuned CPU code."""
     import ctypes  # noqa: F401  (ctypes calls release the GIL: threads run in parallel)
     from concurrent.futures import ThreadPoolExecutor
@@ -181,6 +182,44 @@ def cpu_baseline(insts, M, beta, gam, seconds):
     out["sqa_L10_M32_single_core"] = {"flips_per_ns": round(k10 * 32000 / (d10 * 1e9), 5),
                                       "steps_timed": k10,
                                       "full_64_replicas_2000_steps_s": round(d10 / k10 * 2000 * 64, 1)}
+    # all cores: plain APT+ICM on L = 8 instances (seeds 1..8), one instance per thread; DT-SQA
+    # L = 10, M = 32 with the 64 replicas split over the threads
+    l8s = [oracle.Lattice(ej_couplings(8, 7, seed=1 + i)[0], 7) for i in range(8)]
+
+    def apt_task(w):
+        lw = l8s[w % 8]
+        sw = oracle.apt_init(lw, 0, 64, 1000 + w)
+        cw = np.zeros(3, np.uint32)
+        Ew = np.array([oracle.energy(lw, x) for x in sw], np.int64)
+        bw = np.array([np.iinfo(np.int64).max], np.int64)
+        oracle.apt_run(lw, 0, bt, 2, 1000 + w, cyc, 1, 1.0, 0, cw, sw, Ew, bw)
+        return cyc * 64 * 512
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        fa = sum(ex.map(apt_task, range(cores)))
+    da = time.perf_counter() - t0
+    out["apt_L8_all_cores"] = {"flips_per_ns": round(fa / (da * 1e9), 5), "threads": cores,
+                               "cycles_per_thread": cyc}
+    per = [64 // cores + (1 if w < 64 % cores else 0) for w in range(cores)]
+    k10a = max(1, k10 * cores // 64)   # about the single-core sample's work per thread
+
+    def sqa_task(w):
+        if per[w] == 0:
+            return 0
+        r0 = sum(per[:w])
+        sw = oracle.sqa_init(l10, 0, 32, per[w], 77, r0=r0)
+        for t in range(k10a):
+            oracle.sqa_step(l10, 0, 32, per[w], 4.0, g10[t], 77, t, sw, r0=r0)
+        return k10a * 32000 * per[w]
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        fs = sum(ex.map(sqa_task, range(cores)))
+    ds = time.perf_counter() - t0
+    out["sqa_L10_M32_all_cores"] = {"flips_per_ns": round(fs / (ds * 1e9), 5), "threads": cores,
+                                    "steps": k10a, "replicas": 64,
+                                    "full_2000_steps_s": round(ds / k10a * 2000, 1)}
     return out
 
 
@@ -323,10 +362,17 @@ def sqa_study(Rs=(64, 256, 1024), lengths=(1000, 3000, 10000), e0_cycles=30000,
         gam = linear_gamma(T)
         for R in Rs:
             ctx = sg.sqa(insts, M, R, beta, seed=5000 + R + T)
-            ctx.synchronize()
-            ctx.timer_start()
-            bE, _ = ctx.sqa_anneal(gam)
-            ms = ctx.timer_stop()
+            ms = 0.0
+            # in pieces of at most 10^4 steps (the step counter carries on, so the anneal is the
+            # same as one call), with a line after each long piece
+            for t0 in range(0, T, 10000):
+                ctx.synchronize()
+                ctx.timer_start()
+                bE, _ = ctx.sqa_anneal(gam[t0:t0 + 10000])
+                ms += ctx.timer_stop()
+                if T > 10000:
+                    print(f"sqa-study: R={R} steps={T}: {min(t0 + 10000, T)} done", file=sys.stderr,
+                          flush=True)
             ctx.close()
             runs.append((R, T, bE, ms))
             E0 = np.minimum(E0, bE)
@@ -635,6 +681,8 @@ def main():
     ap.add_argument("--sqa-study", action="store_true",
                     help="DT-SQA residual energy per spin against R (64, 256, 1024) and annealing "
                          "steps (1e3, 3e3, 1e4) on the L=15 extreme-value workload")
+    ap.add_argument("--sqa-lengths", type=int, nargs="+", default=[1000, 3000, 10000],
+                    help="annealing lengths of --sqa-study")
     ap.add_argument("--ablation", action="store_true",
                     help="APT+ICM ablations: ICM on/off, labels, ICMs per sweep, sweep-to-swap ratio")
     ap.add_argument("--ablation-L", type=int, default=8)
@@ -690,7 +738,8 @@ def main():
         print(json.dumps(apt_ablation(L=args.ablation_L)), flush=True)
         return
     if args.sqa_study:
-        print(json.dumps(sqa_study(e0_cycles=args.ttt_cycles)), flush=True)
+        print(json.dumps(sqa_study(lengths=tuple(args.sqa_lengths), e0_cycles=args.ttt_cycles)),
+              flush=True)
         return
     if args.adaptive:
         from paper_2503_10302_amd.inputs import ej_couplings
