@@ -910,7 +910,10 @@ void apt_quad_kernel(AptArgs A)
         uint16_t *queue = (uint16_t *)(vis + ((npad + 31) >> 5) + 1);   // npad
         const int q = D.quad;
         const int slot_off = D.inst * A.nb4;   // == I.slot_off, without waiting for I
-        for (int e = tid; e < 4 * ni; e += kQuadThreads) {
+        // The threshold rows are loaded by waves 1..3 while wave 0 makes the exchange, so that
+        // the two chains of dependent loads overlap (the exchange ends with a barrier; without
+        // it the gather's barrier orders the rows before the sweep).
+        for (int e = tid - 64; e >= 0 && e < 4 * ni; e += kQuadThreads - 64) {
             const int i = e / ni;
             lut[e] = A.lut[(int64_t)A.slot_lut[slot_off + 4 * q + i] * ni + (e - i * ni)];
         }
@@ -926,17 +929,31 @@ void apt_quad_kernel(AptArgs A)
         const int64_t b0 = (int64_t)pq[0] * npad, b1 = (int64_t)pq[1] * npad;
         const int64_t b2 = (int64_t)pq[2] * npad, b3 = (int64_t)pq[3] * npad;
         const uint8_t *gs = A.spins + I.spin_off;
-        // gather + transpose: word j holds byte i = spin of slot 4q+i at site j
-        for (int g = tid; g < (npad >> 2); g += kQuadThreads) {
-            const uint32_t v0 = *(const uint32_t *)(gs + b0 + 4 * g);
-            const uint32_t v1 = *(const uint32_t *)(gs + b1 + 4 * g);
-            const uint32_t v2 = *(const uint32_t *)(gs + b2 + 4 * g);
-            const uint32_t v3 = *(const uint32_t *)(gs + b3 + 4 * g);
+        // gather + transpose: word j holds byte i = spin of slot 4q+i at site j; two groups of
+        // four sites per thread and pass, all eight loads issued before either is transposed
+        const int ng4 = npad >> 2;
+        for (int g0 = tid; g0 < ng4; g0 += 2 * kQuadThreads) {
+            const int g1 = g0 + kQuadThreads;
+            const bool two = g1 < ng4;
+            uint32_t v[2][4];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int sh = 8 * m;
-                sp[4 * g + m] = ((v0 >> sh) & 0xFFu) | (((v1 >> sh) & 0xFFu) << 8) |
-                                (((v2 >> sh) & 0xFFu) << 16) | (((v3 >> sh) & 0xFFu) << 24);
+            for (int h = 0; h < 2; ++h) {
+                const int g = h ? (two ? g1 : g0) : g0;
+                v[h][0] = *(const uint32_t *)(gs + b0 + 4 * g);
+                v[h][1] = *(const uint32_t *)(gs + b1 + 4 * g);
+                v[h][2] = *(const uint32_t *)(gs + b2 + 4 * g);
+                v[h][3] = *(const uint32_t *)(gs + b3 + 4 * g);
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (h && !two) break;
+                const int g = h ? g1 : g0;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int sh = 8 * m;
+                    sp[4 * g + m] = ((v[h][0] >> sh) & 0xFFu) | (((v[h][1] >> sh) & 0xFFu) << 8) |
+                                    (((v[h][2] >> sh) & 0xFFu) << 16) | (((v[h][3] >> sh) & 0xFFu) << 24);
+                }
             }
         }
         if (tid < 4) sp[npad + tid] = 0u;
