@@ -49,6 +49,9 @@ struct Failure {
 void hip_check(hipError_t e, const char *what)
 {
     if (e == hipSuccess) return;
+    // The failed call also left the thread's last error set; clear it, or the next kernel
+    // launch, checked with hipGetLastError, would report this failure again.
+    (void)hipGetLastError();
     if (e == hipErrorOutOfMemory) fail(SG_ENOMEM, "%s: out of device memory", what);
     fail(SG_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
@@ -370,7 +373,10 @@ void set_key(sg_ctx *c, uint64_t seed)
 void init_stream(sg_ctx *c, void *s)
 {
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(SG_EHIP, "no HIP device");
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        fail(SG_EHIP, "no HIP device");
+    }
     hip_check(hipGetDevice(&c->device), "hipGetDevice");
     if (s) {
         c->stream = (hipStream_t)s;
@@ -942,6 +948,8 @@ std::string tune_disk_key(const std::string &shape)
     std::string arch = "?";
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
         arch = p.gcnArchName;
+    else
+        (void)hipGetLastError();
     const std::string all = arch + "|" __DATE__ " " __TIME__ "|" + shape;
     uint64_t h = 1469598103934665603ull;   // FNV-1a
     for (unsigned char ch : all) {

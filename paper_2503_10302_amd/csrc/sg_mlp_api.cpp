@@ -29,8 +29,10 @@ struct Err {
 
 void chk(hipError_t e)
 {
+    if (e == hipSuccess) return;
+    (void)hipGetLastError();   // clear the thread's last error (see hip_check in sg_api.cpp)
     if (e == hipErrorOutOfMemory) throw Err{SG_ENOMEM};
-    if (e != hipSuccess) throw Err{SG_EHIP};
+    throw Err{SG_EHIP};
 }
 
 template <class T>

@@ -839,3 +839,25 @@ def test_device_outputs_equal_the_host_calls():
             got.free()
         ca.close()
         cb.close()
+
+
+def test_device_allocation_failure_is_reported():
+    """A DT-SQA context whose replicas need more than the device's memory (256 L = 15 instances
+    x 65535 replicas x 27 KB = 453 GB, inside the replica-count limit) fails at its allocation
+    with SG_ENOMEM and a message, before any kernel runs; the device then serves a small
+    context exactly as before."""
+    from paper_2503_10302_amd.inputs import ej_couplings
+    J, _ = ej_couplings(15, 7, seed=5)
+    with pytest.raises(sg.SGError) as e:
+        sg.sqa([(J, 7, None)] * 256, 64, 65535, 32.0, SEED)
+    assert e.value.code == sg.SG_ENOMEM
+    assert "out of device memory" in str(e.value)
+    inst = _inst((4, 4, 4), 7, 81)
+    ctx = sg.sqa([inst], 8, 2, 2.0, SEED)
+    gam = linear_gamma(5)
+    bE, _ = ctx.sqa_anneal(gam)
+    l = _olat(inst)
+    sp = oracle.sqa_init(l, 0, 8, 2, SEED)
+    obE, _, _ = oracle.sqa_anneal(l, 0, 8, 2, 2.0, gam, SEED, 0, sp)
+    assert np.array_equal(ctx.spins()[0, :, :, :l.n], sp) and bE[0] == obE
+    ctx.close()
