@@ -861,3 +861,63 @@ def test_device_allocation_failure_is_reported():
     obE, _, _ = oracle.sqa_anneal(l, 0, 8, 2, 2.0, gam, SEED, 0, sp)
     assert np.array_equal(ctx.spins()[0, :, :, :l.n], sp) and bE[0] == obE
     ctx.close()
+
+
+def test_invalid_calls_leave_the_context_unchanged():
+    """SG_EINVAL leaves a context as it was: invalid calls on an APT and a DT-SQA context are
+    each refused and change neither spins, energies, counters, running minima nor swap counts,
+    and both contexts then continue exactly like twins that never saw the calls."""
+    insts = [_inst((5, 5, 5), 7, 91), _inst((4, 4, 6), 5, 92)]
+    beta = geometric_ladder(8, 0.3, 2.0)
+    a, ta = sg.apt(insts, beta, SEED, 2), sg.apt(insts, beta, SEED, 2)
+    a.run_apt(10, 1, 1.0)
+    ta.run_apt(10, 1, 1.0)
+
+    def snap(c):
+        return (c.spins(), c.energy(), c.counters(), c.best(), c.swap_counts())
+
+    before = snap(a)
+    bad = [lambda: a.sweep(-1), lambda: a.run_apt(5, 0, 1.0), lambda: a.run_apt(-1, 1, 1.0),
+           lambda: a.run_apt_ex(5, 1, 1.0, icm_pairs=3), lambda: a.run_apt_ex(5, 1, float("nan")),
+           lambda: a.icm_ex(1.0, icm_pairs=0), lambda: a.set_spins(np.zeros_like(before[0])),
+           lambda: a.set_state(np.zeros(7, np.uint8)), lambda: a.set_launch_config(99)]
+    for k, f in enumerate(bad):
+        with pytest.raises(sg.SGError) as e:
+            f()
+        assert e.value.code == sg.SG_EINVAL, k
+    for x, y in zip(before, snap(a)):
+        assert np.array_equal(x, y)
+    a.run_apt(10, 1, 1.0)
+    ta.run_apt(10, 1, 1.0)
+    for x, y in zip(snap(a), snap(ta)):
+        assert np.array_equal(x, y)
+    a.close()
+    ta.close()
+
+    s, ts = sg.sqa(insts, 8, 2, 2.0, SEED), sg.sqa(insts, 8, 2, 2.0, SEED)
+    g = linear_gamma(6)
+    s.sqa_anneal(g[:3])
+    ts.sqa_anneal(g[:3])
+
+    def snap2(c):
+        return (c.spins(), c.energy(), c.counters())
+
+    before = snap2(s)
+    zero = g[3:].copy()
+    zero[1] = 0.0
+    bad = [lambda: s.sqa_anneal(zero), lambda: s.sqa_anneal(np.array([np.nan])),
+           lambda: s.set_spins(np.zeros_like(before[0])), lambda: s.set_launch_config(100),
+           lambda: s.set_state(np.zeros(3, np.uint8))]
+    for k, f in enumerate(bad):
+        with pytest.raises(sg.SGError) as e:
+            f()
+        assert e.value.code == sg.SG_EINVAL, k
+    for x, y in zip(before, snap2(s)):
+        assert np.array_equal(x, y)
+    bE, bs = s.sqa_anneal(g[3:])
+    tE, tsb = ts.sqa_anneal(g[3:])
+    assert np.array_equal(bE, tE) and np.array_equal(bs, tsb)
+    for x, y in zip(snap2(s), snap2(ts)):
+        assert np.array_equal(x, y)
+    s.close()
+    ts.close()
