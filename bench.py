@@ -45,6 +45,12 @@ VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 # site and parity 3 + 2 more, shared by its groups; plus the threshold compare.  Index
 # arithmetic, LDS traffic and the neighbour sums are implementation overhead and are
 # not counted.
+def flips_per_ns(flips, ms):
+    """Throughput as the paper counts it: spin-update attempts per nanosecond (a sweep of n
+    spins in t ns is n / t flips/ns), from a count of attempts and a time in milliseconds."""
+    return flips / (ms * 1e6)
+
+
 def alg_ops_per_flip(groups):
     return 65 / 4 + 5 / (4 * groups) + 1
 
@@ -141,7 +147,7 @@ def cpu_baseline(insts, M, beta, gam, seconds):
     with ThreadPoolExecutor(max_workers=cores) as ex:
         flips = sum(ex.map(task, range(cores)))
     wall = time.perf_counter() - t0
-    out = {"value": flips / (wall * 1e9), "unit": "flips/ns", "cores": cores, "kind": "oracle",
+    out = {"value": flips_per_ns(flips, wall * 1e3), "unit": "flips/ns", "cores": cores, "kind": "oracle",
            "sample": f"{cores} replicas x {steps} DT-SQA steps of the L=15, M=64 workload, one per "
                      f"thread ({flips:.3g} spin updates, {wall:.1f} s wall)",
            "cpu_model": cpu_model(), "host_cpus_visible": visible}
@@ -152,7 +158,7 @@ def cpu_baseline(insts, M, beta, gam, seconds):
     for t in range(k1):
         oracle.sqa_step(lat[0], 0, M, 1, beta, gam[t], 1234, t, sp, r0=0)
     d1 = time.perf_counter() - t0
-    out["single_core_flips_per_ns"] = round(k1 * M * n / (d1 * 1e9), 5)
+    out["single_core_flips_per_ns"] = round(flips_per_ns(k1 * M * n, d1 * 1e3), 5)
     # one core: plain APT+ICM, one L = 8 instance (32 betas x 2 labels, ICM at beta >= 1)
     J8, _ = ej_couplings(8, 7, seed=1)
     l8 = oracle.Lattice(J8, 7)
@@ -166,7 +172,7 @@ def cpu_baseline(insts, M, beta, gam, seconds):
     oracle.apt_run(l8, 0, bt, 2, 1001, cyc, 1, 1.0, 0, ctr, s8, E, best)
     d8 = time.perf_counter() - t0
     out["apt_L8_single_core"] = {"ms_per_cycle": round(d8 * 1e3 / cyc, 4),
-                                 "flips_per_ns": round(cyc * 64 * 512 / (d8 * 1e9), 5),
+                                 "flips_per_ns": round(flips_per_ns(cyc * 64 * 512, d8 * 1e3), 5),
                                  "cycles_timed": cyc,
                                  "full_1e4_cycles_s": round(d8 / cyc * 1e4, 1)}
     # one core: DT-SQA L = 10, M = 32, beta = 4 (Gamma 3.0 -> 0.01 over 2000 steps)
@@ -179,7 +185,7 @@ def cpu_baseline(insts, M, beta, gam, seconds):
     for t in range(k10):
         oracle.sqa_step(l10, 0, 32, 1, 4.0, g10[t], 77, t, s10)
     d10 = time.perf_counter() - t0
-    out["sqa_L10_M32_single_core"] = {"flips_per_ns": round(k10 * 32000 / (d10 * 1e9), 5),
+    out["sqa_L10_M32_single_core"] = {"flips_per_ns": round(flips_per_ns(k10 * 32000, d10 * 1e3), 5),
                                       "steps_timed": k10,
                                       "full_64_replicas_2000_steps_s": round(d10 / k10 * 2000 * 64, 1)}
     # all cores: plain APT+ICM on L = 8 instances (seeds 1..8), one instance per thread; DT-SQA
@@ -199,7 +205,7 @@ def cpu_baseline(insts, M, beta, gam, seconds):
     with ThreadPoolExecutor(max_workers=cores) as ex:
         fa = sum(ex.map(apt_task, range(cores)))
     da = time.perf_counter() - t0
-    out["apt_L8_all_cores"] = {"flips_per_ns": round(fa / (da * 1e9), 5), "threads": cores,
+    out["apt_L8_all_cores"] = {"flips_per_ns": round(flips_per_ns(fa, da * 1e3), 5), "threads": cores,
                                "cycles_per_thread": cyc}
     per = [64 // cores + (1 if w < 64 % cores else 0) for w in range(cores)]
     k10a = max(1, k10 * cores // 64)   # about the single-core sample's work per thread
@@ -217,7 +223,7 @@ def cpu_baseline(insts, M, beta, gam, seconds):
     with ThreadPoolExecutor(max_workers=cores) as ex:
         fs = sum(ex.map(sqa_task, range(cores)))
     ds = time.perf_counter() - t0
-    out["sqa_L10_M32_all_cores"] = {"flips_per_ns": round(fs / (ds * 1e9), 5), "threads": cores,
+    out["sqa_L10_M32_all_cores"] = {"flips_per_ns": round(flips_per_ns(fs, ds * 1e3), 5), "threads": cores,
                                     "steps": k10a, "replicas": 64,
                                     "full_2000_steps_s": round(ds / k10a * 2000, 1)}
     return out
@@ -383,7 +389,7 @@ def sqa_study(Rs=(64, 256, 1024), lengths=(1000, 3000, 10000), e0_cycles=30000,
         table[f"R{R}_steps{T}"] = {"rho_mean": round(float(rho.mean()), 6),
                                    "rho_median": round(float(np.median(rho)), 6),
                                    "at_E0": int((bE == E0).sum()), "wall_s": round(ms / 1e3, 3),
-                                   "flips_per_ns": round(len(insts) * R * M * n * T / (ms * 1e6), 1)}
+                                   "flips_per_ns": round(flips_per_ns(len(insts) * R * M * n * T, ms), 1)}
     return {"metric": "DT-SQA residual energy per spin vs replicas R and annealing steps "
                       "(32 periodic L=15 instances, M=64, beta=32)",
             "e0": f"min over every run here and {len(e0_seeds)} x {e0_cycles}-cycle batched APT+ICM runs",
@@ -791,7 +797,7 @@ def main():
         ms = ctx.timer_stop()
         wall = time.perf_counter() - t0
         kms, nlaunch = ctx.kernel_time()
-        value = flips_per_step * args.steps / (ms * 1e6)
+        value = flips_per_ns(flips_per_step * args.steps, ms)
         ops_flip = alg_ops_per_flip((M // 2 + 3) // 4)
         achieved = ops_flip * flips_per_step * args.steps / (kms * 1e-3) / 1e12
         out.update({
@@ -811,7 +817,7 @@ def main():
                          "launch_config": {"threads": ctx.launch_config(),
                                            "chosen_by": "autotuner" if not args.sqa_launch_config
                                            else "--sqa-launch-config"},
-                         "kernel_flips_per_ns": round(flips_per_step * args.steps / (kms * 1e6), 3)},
+                         "kernel_flips_per_ns": round(flips_per_ns(flips_per_step * args.steps, kms), 3)},
             "wall_s_timed": round(wall, 3),
             "sqa_best_residual_proxy": {"min_E_per_spin": round(float(bE.min()) / n, 5)},
         })
@@ -848,8 +854,8 @@ def main():
                            "geometric in [0.2, 3.0] x 2 labels, ICM at beta >= 1, 1 sweep per swap",
                "flips_per_cycle": flips_cycle, "cycles": args.apt_cycles,
                "ms_per_cycle": round(ms3 / args.apt_cycles, 5),
-               "flips_per_ns": round(flips_cycle * args.apt_cycles / (ms3 * 1e6), 3),
-               "sweep_only_flips_per_ns": round(flips_cycle * 32 / (ms3s * 1e6), 3),
+               "flips_per_ns": round(flips_per_ns(flips_cycle * args.apt_cycles, ms3), 3),
+               "sweep_only_flips_per_ns": round(flips_per_ns(flips_cycle * 32, ms3s), 3),
                "graph_kernel_ms": round(k3, 3),
                "launch_config": {"code": code, "order": (code - 1) % 6,
                                  "waves_per_simd": 8 if code > 6 else 7, "chosen_by": "autotuner"}}
@@ -857,7 +863,7 @@ def main():
         out["apt_batched"] = apt
         out["apt_plain"] = {"workload": "one L=8 periodic instance, 32 betas x 2 labels, ICM at beta >= 1",
                             "ms_per_cycle": round(ms1 / args.apt_cycles, 5),
-                            "flips_per_ns": round(512 * 64 * args.apt_cycles / (ms1 * 1e6), 3)}
+                            "flips_per_ns": round(flips_per_ns(512 * 64 * args.apt_cycles, ms1), 3)}
         if args.only == "apt":
             out.update({"value": apt["flips_per_ns"], "ms_per_step": apt["ms_per_cycle"],
                         "config": {"workload": "batched APT+ICM, 256 mixed instances (L = 6..15)"}})

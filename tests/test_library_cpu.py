@@ -129,3 +129,14 @@ def test_instance_features_equal_the_oracle():
     for i, (J, per, h) in enumerate(cases):
         want = oracle.instance_features(oracle.Lattice(J, per, h))
         assert got[i].tolist() == want.tolist(), (i, got[i], want)
+
+
+def test_flips_per_ns_is_the_papers_count():
+    """The benchmark's throughput is the paper's: one flip is one update attempt of one spin,
+    so a sweep of n p-bits in t ns gives n / t flips/ns.  The paper's FPGA figures: 2687 and
+    4096 p-bits per 22.22 ns sweep are 120.9 and 184.3 flips/ns."""
+    import bench
+    assert abs(bench.flips_per_ns(2687, 22.22e-6) - 120.9) < 0.05
+    assert abs(bench.flips_per_ns(4096, 22.22e-6) - 184.3) < 0.05
+    # one DT-SQA step of the headline workload: 32 instances x R replicas x M slices x 15^3
+    assert bench.flips_per_ns(32 * 1024 * 64 * 3375, 2.64) == 32 * 1024 * 64 * 3375 / 2.64e6
