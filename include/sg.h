@@ -178,6 +178,20 @@ sg_status sg_sqa_anneal(sg_ctx *ctx, const double *gamma, int32_t n_steps, int64
  * its slice 0 (C_k = (2 agree - n) / n). */
 sg_status sg_sqa_trotter_agreement(sg_ctx *ctx, int32_t *agree_host);
 
+/* ---- acceptance thresholds ----
+ * The FP64-built thresholds the kernels compare their uniform 32-bit words with, computed by
+ * the same host code that fills the contexts' tables, so that the builders can be checked
+ * against an independent implementation.  Heat bath (Eq. 6): T = floor(2^32 (1 + tanh(beta
+ * I)) / 2), saturated at 2^32 - 1, s = +1 iff u < T.  DT-SQA (Supplementary Eq. S.3): the same
+ * with the argument (beta / M) s + K tau, K = -ln tanh(beta gamma / M) / 2, s the spatial
+ * field and tau the sum of the two Trotter neighbours.  Swap (Eq. 4): an exchange of
+ * inverse temperatures beta_lo < beta_hi whose energy change is unfavourable by d >= 1
+ * (Delta beta Delta E = -(beta_hi - beta_lo) d) is accepted iff u < T = floor(exp(-(beta_hi -
+ * beta_lo) d) 2^32).  SG_EINVAL (message in sg_last_error(NULL)) for invalid arguments. */
+sg_status sg_threshold_heat_bath(double beta, int32_t I, uint32_t *T);
+sg_status sg_threshold_sqa(double beta, int32_t M, double gamma, int32_t s, int32_t tau, uint32_t *T);
+sg_status sg_threshold_swap(double beta_lo, double beta_hi, int64_t d, uint32_t *T);
+
 /* ---- device outputs ----
  * The same results as sg_energy, sg_get_spins, sg_best and sg_sqa_anneal, written to memory
  * the caller allocated on the context's device with the HIP runtime the library uses, in the same

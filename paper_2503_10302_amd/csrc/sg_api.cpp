@@ -1570,6 +1570,37 @@ sg_status sg_run_apt_ex(sg_ctx *c, int64_t n_cycles, const sg_apt_options *opt, 
     });
 }
 
+sg_status sg_threshold_heat_bath(double beta, int32_t I, uint32_t *T)
+{
+    if (!T || !std::isfinite(beta)) {
+        sg::set_global_error("sg_threshold_heat_bath: NULL output or non-finite beta");
+        return SG_EINVAL;
+    }
+    *T = heat_bath_threshold(beta, I);
+    return SG_OK;
+}
+
+sg_status sg_threshold_sqa(double beta, int32_t M, double gamma, int32_t s, int32_t tau, uint32_t *T)
+{
+    if (!T || !(beta > 0.0) || !std::isfinite(beta) || M < 1 || !(gamma > 0.0) ||
+        !std::isfinite(gamma)) {
+        sg::set_global_error("sg_threshold_sqa: NULL output, beta or gamma not > 0, or M < 1");
+        return SG_EINVAL;
+    }
+    *T = trotter_threshold(beta, M, trotter_K(beta, M, gamma), s, tau);
+    return SG_OK;
+}
+
+sg_status sg_threshold_swap(double beta_lo, double beta_hi, int64_t d, uint32_t *T)
+{
+    if (!T || d < 1 || !std::isfinite(beta_lo) || !std::isfinite(beta_hi)) {
+        sg::set_global_error("sg_threshold_swap: NULL output, d < 1 or non-finite beta");
+        return SG_EINVAL;
+    }
+    *T = swap_threshold(beta_lo, beta_hi, d);
+    return SG_OK;
+}
+
 sg_status sg_best(sg_ctx *c, int64_t *best_host)
 {
     return guarded(c, [&] {

@@ -61,7 +61,7 @@ EXPORTS = [
     "sg_instance_features", "sg_mlp_set_standardisation", "sg_mlp_loss_grad", "sg_mlp_train",
     "sg_mlp_get_params", "sg_ladder_predict", "sg_learned_ladders", "sg_ladder_predict_noalloc",
     "sg_ladder_repair", "sg_judge_ladders", "sg_energy_dev", "sg_get_spins_dev", "sg_best_dev",
-    "sg_sqa_anneal_dev",
+    "sg_sqa_anneal_dev", "sg_threshold_heat_bath", "sg_threshold_sqa", "sg_threshold_swap",
 ]
 
 _lib = None
@@ -125,6 +125,9 @@ def load():
         "sg_get_spins_dev": (i32, [P, P]),
         "sg_best_dev": (i32, [P, P]),
         "sg_sqa_anneal_dev": (i32, [P, P, i32, P, P]),
+        "sg_threshold_heat_bath": (i32, [C.c_double, i32, P]),
+        "sg_threshold_sqa": (i32, [C.c_double, i32, C.c_double, i32, i32, P]),
+        "sg_threshold_swap": (i32, [C.c_double, C.c_double, C.c_int64, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -386,6 +389,30 @@ class Context:
         ms, n = C.c_float(0), C.c_int32(0)
         self._check(self.lib.sg_kernel_time(self.h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+
+def _threshold(fn, *args):
+    lib = load()
+    t = C.c_uint32(0)
+    rc = getattr(lib, fn)(*args, C.byref(t))
+    if rc != SG_OK:
+        raise SGError(rc, lib.sg_last_error(None).decode())
+    return t.value
+
+
+def threshold_heat_bath(beta, I):
+    """The library's heat-bath threshold (Eq. 6) for local field I at inverse temperature beta."""
+    return _threshold("sg_threshold_heat_bath", float(beta), int(I))
+
+
+def threshold_sqa(beta, M, gamma, s, tau):
+    """The library's DT-SQA threshold (Supplementary Eq. S.3)."""
+    return _threshold("sg_threshold_sqa", float(beta), int(M), float(gamma), int(s), int(tau))
+
+
+def threshold_swap(beta_lo, beta_hi, d):
+    """The library's swap threshold (Eq. 4) for an unfavourable energy change d >= 1."""
+    return _threshold("sg_threshold_swap", float(beta_lo), float(beta_hi), int(d))
 
 
 def apt(instances, beta, seed, reps_per_beta=2, colours=None):

@@ -140,3 +140,38 @@ def test_flips_per_ns_is_the_papers_count():
     assert abs(bench.flips_per_ns(4096, 22.22e-6) - 184.3) < 0.05
     # one DT-SQA step of the headline workload: 32 instances x R replicas x M slices x 15^3
     assert bench.flips_per_ns(32 * 1024 * 64 * 3375, 2.64) == 32 * 1024 * 64 * 3375 / 2.64e6
+
+
+def test_threshold_builders_equal_the_oracle():
+    """The library's FP64 threshold builders (the code that fills every context's tables) give
+    the oracle's thresholds exactly, over the inverse temperatures and fields of the workloads
+    and beyond: the heat bath for the geometric ladders, adaptive-like ladders and fields up to
+    31; DT-SQA for M = 2..64 (odd included), beta = M / 2 and 4, every Gamma of 2000-step
+    linear schedules, fields up to 6 + 31 and every Trotter sum; the swap rule for random
+    ladder pairs, unfavourable energy changes and uniform words (the oracle decides the
+    exchange, the library's threshold must decide it the same way)."""
+    import oracle
+    from paper_2503_10302_amd import sg
+    from paper_2503_10302_amd.inputs import geometric_ladder, linear_gamma
+    oracle.build()
+    rng = np.random.default_rng(17)
+    betas = np.concatenate([geometric_ladder(32, 0.2, 3.0), geometric_ladder(8, 0.3, 2.0),
+                            np.cumsum(rng.uniform(0.01, 0.3, 40)) + 0.5, [0.0, 1e-9, 30.0]])
+    for b in betas:
+        for I in range(-37, 38):
+            assert sg.threshold_heat_bath(b, I) == oracle.heat_threshold(b, I), (b, I)
+    for M in (2, 3, 7, 16, 32, 33, 63, 64):
+        for beta in (M / 2.0, 4.0):
+            gam = linear_gamma(2000)[rng.choice(2000, 60, replace=False)]
+            for g in np.concatenate([gam, [3.0, 0.01]]):
+                for s_ in (-37, -6, -2, 0, 1, 2, 6, 37):
+                    for tau in (-2, 0, 2):
+                        assert (sg.threshold_sqa(beta, M, g, s_, tau) ==
+                                oracle.sqa_threshold(beta, M, g, s_, tau)), (M, beta, g, s_, tau)
+    lad = geometric_ladder(32, 0.2, 3.0)
+    for _ in range(3000):
+        k = int(rng.integers(0, 31))
+        d = int(rng.integers(1, 400))
+        u = int(rng.integers(0, 2 ** 32))
+        T = sg.threshold_swap(lad[k], lad[k + 1], d)
+        assert (u < T) == bool(oracle.swap_accept(lad[k], lad[k + 1], 0, -d, u)), (k, d, u)
