@@ -304,6 +304,7 @@ struct sg_ctx {
     int hmax = 0;
     DevBuf<InstDev> d_inst;
     DevBuf<uint4> d_rec, d_recj;
+    DevBuf<uint4> d_recb;      // APT: d_rec with byte offsets (empty when a lattice is too large)
     DevBuf<uint32_t> d_ctr;      // {sweeps/steps, icm calls, swap attempts, cycles, done}
     Timer timer;
     // events around every main kernel launch (DT-SQA kernel, APT cycle graph)
@@ -694,6 +695,24 @@ void create_apt(sg_ctx *c, const sg_config *cfg, const int8_t *const *colour = n
     hipStream_t s = c->stream;
     c->d_inst.upload(c->idev, s, "instances");
     c->d_rec.upload(rec, s, "records");
+    // The sweep's copy of the colour-sorted records: neighbour fields as byte offsets into the
+    // tile (4 x site index, at most 4 x 16383 in 16 bits), and x = j | jneg << 16 | base << 24
+    // with base = h - d + imax, the table index of a site with no aligned bond (0..2 imax, at
+    // most 74).  Kept until the stream is synchronised.
+    std::vector<uint4> recb;
+    if (c->n_max <= kMaxByteOffsetSites) {
+        recb = rec;
+        for (uint4 &r : recb) {
+            const uint32_t j = r.x & 0xFFFFu, d = (r.x >> 16) & 7u, jneg = (r.x >> 19) & 63u;
+            const int h = (int)((r.x >> 25) & 63u) - 32;
+            const uint32_t base = (uint32_t)(h - (int)d + c->imax);
+            r.x = j | (jneg << 16) | (base << 24);
+            r.y <<= 2;
+            r.z <<= 2;
+            r.w <<= 2;
+        }
+        c->d_recb.upload(recb, s, "records");
+    }
     c->d_recj.upload(recj, s, "records");
     c->d_rowA.upload(rowA, s, "row tables");
     c->d_rowB.upload(rowB, s, "row tables");
@@ -762,7 +781,8 @@ AptArgs apt_args(sg_ctx *c, int n_sweeps, int do_icm)
     AptArgs a{};
     a.desc = c->d_desc.p;
     a.inst = c->d_inst.p;
-    a.rec_col = c->d_rec.p;
+    a.boff = c->d_recb.p != nullptr;
+    a.rec_col = a.boff ? c->d_recb.p : c->d_rec.p;
     a.rec_j = c->d_recj.p;
     a.spins = c->d_spins.p;
     a.perm = c->d_perm.p;

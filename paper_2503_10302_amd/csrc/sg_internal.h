@@ -24,6 +24,7 @@ enum : uint32_t {
 constexpr int kMaxColours = 4;   // colour classes of a given colour map
 constexpr int kMaxH = 31;      // |h| bound, so that h + 32 fits 6 bits of a site record
 constexpr int kMaxN = 32767;   // sites per instance (16-bit site and neighbour indices)
+constexpr int kMaxByteOffsetSites = 16383;   // neighbour byte offsets (4 x index) fit 16 bits
 constexpr int kQuadThreads = 256;
 constexpr int kSqaThreads = 512;
 constexpr int kSqaTabWords = 976;        // static LDS of the DT-SQA kernel (tables)
@@ -139,6 +140,7 @@ struct AptArgs {
                                // kernel uses sweep counter ctr[0] + cyc_k * n_sweeps and ICM
                                // call ctr[1] + cyc_k + 1; counters advance only between graphs
     int32_t waves;             // kernel variant: at least 8 or 7 (also for 0) waves per SIMD
+    int32_t boff;              // 1: rec_col holds neighbour byte offsets (kernel variant)
     int32_t fused_swap;        // 1: first perform the replica exchange described by sw (the
                                //    previous cycle's attempt) for this work-group's slots,
                                //    reading sw.perm_in / sw.E_in and writing sw.perm and E

@@ -885,9 +885,103 @@ __global__ __launch_bounds__(kQuadThreads) void apt_init_kernel(const InstDev *i
 // defined with the DT-SQA kernel
 __device__ __forceinline__ uint4 sqa_group_words(uint32_t t, uint32_t x2, uint32_t k0, uint32_t k1);
 
+// One site of a colour class in all four slots of the tile (Eq. 5, Eq. 6): the aligned-bond
+// count per slot byte, one Philox4x32-10 block (site j, sweep, quad, instance) for the four
+// uniform words, the heat-bath compare against each slot's threshold row, and the packed
+// energy-change sums (Eq. 8).  Record r: x = j | d << 16 | jneg << 19 | (h + 32) << 25 and y, z, w
+// the six neighbours in 16-bit fields as site indices; or with BOFF x = j | jneg << 16 |
+// (h - d + imax) << 24 and the neighbours as byte offsets into the tile (4 x index), which
+// saves the scaling of each neighbour address and the assembly of the table index base.
+template <bool SCALED, bool BOFF>
+__device__ __forceinline__ void apt_site(const AptArgs &A, uint32_t *sp, const uint32_t *lut,
+                                         const uint4 r, const uint4 uq, const uint32_t c3,
+                                         const uint32_t soff4, const uint32_t rev4, uint32_t &V02,
+                                         uint32_t &V13, uint32_t &C4)
+{
+    const int ni = A.ni;
+    const uint32_t j = r.x & 0xFFFFu;
+    // The first half of the site's Philox block covers the latency of the neighbour reads,
+    // the second half that of the threshold reads.
+    const uint32_t jn = BOFF ? r.x >> 16 : r.x >> 19;
+    uint32_t nb0, nb1, nb2, nb3, nb4, nb5;
+    if (BOFF) {
+        nb0 = lds_word(sp, r.y & 0xFFFFu);
+        nb1 = lds_word(sp, r.y >> 16);
+        nb2 = lds_word(sp, r.z & 0xFFFFu);
+        nb3 = lds_word(sp, r.z >> 16);
+        nb4 = lds_word(sp, r.w & 0xFFFFu);
+        nb5 = lds_word(sp, r.w >> 16);
+    } else {
+        nb0 = sp[r.y & 0xFFFFu];
+        nb1 = sp[r.y >> 16];
+        nb2 = sp[r.z & 0xFFFFu];
+        nb3 = sp[r.z >> 16];
+        nb4 = sp[r.w & 0xFFFFu];
+        nb5 = sp[r.w >> 16];
+    }
+    const uint32_t old = sp[j];
+    __builtin_amdgcn_sched_barrier(0);
+    // Philox block (j, t, q, instance): rounds 0-1 split into the site's part and the
+    // work-group's per-sweep words (uq, as in sqa_slices), then round 2 and rounds 3-4
+    const uint64_t pj = (uint64_t)0xD2511F53u * j;
+    const uint32_t B = (uint32_t)(pj >> 32) ^ c3 ^ A.key1;
+    const uint64_t pb = (uint64_t)0xCD9E8D57u * B;
+    const uint32_t x0r = (uint32_t)(pb >> 32) ^ uq.x, x2r = (uint32_t)pj ^ uq.y;
+    const uint64_t p0r = (uint64_t)0xD2511F53u * x0r;
+    const uint64_t p1r = (uint64_t)0xCD9E8D57u * x2r;
+    uint32_t x[4] = {xor3_vvs((uint32_t)(p1r >> 32), (uint32_t)pb, A.key0 + 2u * 0x9E3779B9u),
+                     (uint32_t)p1r, (uint32_t)(p0r >> 32) ^ uq.z, (uint32_t)p0r};
+    uint32_t key[2] = {A.key0 + 3u * 0x9E3779B9u, A.key1 + 3u * 0xBB67AE85u};
+    philox_rounds<3, 5>(x, key);
+    __builtin_amdgcn_sched_barrier(0);
+    // per byte (slot): number of present bonds whose J * s_neighbour = +1
+    const uint32_t k4 = (nb0 ^ bytemask(jn & 1u)) + (nb1 ^ bytemask((jn >> 1) & 1u)) +
+                        (nb2 ^ bytemask((jn >> 2) & 1u)) + (nb3 ^ bytemask((jn >> 3) & 1u)) +
+                        (nb4 ^ bytemask((jn >> 4) & 1u)) + (nb5 ^ bytemask((jn >> 5) & 1u));
+    // table index per slot byte: 2 k + h - d + imax (>= 0, <= 2 imax)
+    const uint32_t base =
+        BOFF ? r.x >> 24 : ((r.x >> 25) & 63u) + (uint32_t)(A.imax - 32) - ((r.x >> 16) & 7u);
+    const uint32_t idx4 = (k4 << 1) + __builtin_amdgcn_perm(0u, base, 0u);   // base in every byte
+    uint32_t o0, o1, o2, o3;
+    if (SCALED) {
+        const uint32_t off4 = (idx4 + soff4) << 2;
+        o0 = off4 & 0xFFu;
+        o1 = (off4 >> 8) & 0xFFu;
+        o2 = (off4 >> 16) & 0xFFu;
+        o3 = off4 >> 24;
+    } else {
+        o0 = (idx4 & 0xFFu) << 2;
+        o1 = (((idx4 >> 8) & 0xFFu) + (uint32_t)ni) << 2;
+        o2 = (((idx4 >> 16) & 0xFFu) + 2u * (uint32_t)ni) << 2;
+        o3 = ((idx4 >> 24) + 3u * (uint32_t)ni) << 2;
+    }
+    const uint32_t T3 = lds_word(lut, o3), T2 = lds_word(lut, o2);
+    const uint32_t T1 = lds_word(lut, o1), T0 = lds_word(lut, o0);
+    __builtin_amdgcn_sched_barrier(0);
+    philox_rounds<5, 10>(x, key);
+    uint32_t acc = 0u;   // bit b: new state of slot b (Eq. 6)
+    acc = shift_in_lt(acc, x[3], T3);
+    acc = shift_in_lt(acc, x[2], T2);
+    acc = shift_in_lt(acc, x[1], T1);
+    acc = shift_in_lt(acc, x[0], T0);
+    const uint32_t nw = __umul24(acc, 0x00204081u) & 0x01010101u;   // bit b -> byte b
+    // Eq. (8): the update changes E by -(s_new - s_old) I_j = 2 (o - n) I_j, with o, n the
+    // old and new states (0/1) and I_j = index - imax
+    const uint32_t fl = old ^ nw;                    // flipped slots, bytes 0/1
+    // byte 1 -> 0xFF, 0 -> 0x00 (two full-rate operations, no carries)
+    const uint32_t mo = (old + 0x7F7F7F7Fu) ^ 0x7F7F7F7Fu;   // where o = 1
+    const uint32_t mf = (fl + 0x7F7F7F7Fu) ^ 0x7F7F7F7Fu;    // where flipped
+    const uint32_t v4 = (((idx4 ^ (rev4 - idx4)) & mo) ^ (rev4 - idx4)) & mf;
+    V02 += v4 & 0x00FF00FFu;
+    V13 += (v4 >> 8) & 0x00FF00FFu;
+    C4 += fl;
+    sp[j] = nw;
+}
+
 // W: at least W waves per SIMD (the register budget: 64 VGPRs for W = 8, 72 for W = 7), a
-// launch-configuration choice of the autotuner; results do not depend on it.
-template <bool SCALED, int W>
+// launch-configuration choice of the autotuner; results do not depend on it.  BOFF: the
+// colour-sorted records carry byte offsets (every instance of at most 16383 sites).
+template <bool SCALED, int W, bool BOFF>
 __global__ __launch_bounds__(kQuadThreads) __attribute__((amdgpu_waves_per_eu(W, 8)))
 void apt_quad_kernel(AptArgs A)
 {
@@ -983,79 +1077,17 @@ void apt_quad_kernel(AptArgs A)
             for (int c = 0; c < I.n_colours; ++c) {
                 const uint4 *rc = A.rec_col + I.rec_off + A.inst[D.inst].col_off[c];
                 const int cnt = A.inst[D.inst].col_cnt[c];
-                uint4 rnext = (tid < cnt) ? rc[tid] : make_uint4(0u, 0u, 0u, 0u);
-                for (int i = tid; i < cnt; i += kQuadThreads) {
-                    const uint4 r = rnext;
-                    if (i + kQuadThreads < cnt) rnext = rc[i + kQuadThreads];   // prefetch
-                    const uint32_t j = r.x & 0xFFFFu;
-                    // The first half of the site's Philox block covers the latency of the
-                    // neighbour reads, the second half that of the threshold reads.
-                    const uint32_t jn = r.x >> 19;
-                    const uint32_t nb0 = sp[r.y & 0xFFFFu], nb1 = sp[r.y >> 16];
-                    const uint32_t nb2 = sp[r.z & 0xFFFFu], nb3 = sp[r.z >> 16];
-                    const uint32_t nb4 = sp[r.w & 0xFFFFu], nb5 = sp[r.w >> 16];
-                    const uint32_t old = sp[j];
-                    __builtin_amdgcn_sched_barrier(0);
-                    // Philox block (j, t, q, instance): rounds 0-1 split into the site's part
-                    // and the work-group's per-sweep words (uq, as in sqa_slices), then
-                    // round 2 and rounds 3-4
-                    const uint64_t pj = (uint64_t)0xD2511F53u * j;
-                    const uint32_t B = (uint32_t)(pj >> 32) ^ c3 ^ A.key1;
-                    const uint64_t pb = (uint64_t)0xCD9E8D57u * B;
-                    const uint32_t x0r = (uint32_t)(pb >> 32) ^ uq.x, x2r = (uint32_t)pj ^ uq.y;
-                    const uint64_t p0r = (uint64_t)0xD2511F53u * x0r;
-                    const uint64_t p1r = (uint64_t)0xCD9E8D57u * x2r;
-                    uint32_t x[4] = {xor3_vvs((uint32_t)(p1r >> 32), (uint32_t)pb,
-                                              A.key0 + 2u * 0x9E3779B9u),
-                                     (uint32_t)p1r, (uint32_t)(p0r >> 32) ^ uq.z, (uint32_t)p0r};
-                    uint32_t key[2] = {A.key0 + 3u * 0x9E3779B9u, A.key1 + 3u * 0xBB67AE85u};
-                    philox_rounds<3, 5>(x, key);
-                    __builtin_amdgcn_sched_barrier(0);
-                    // per byte (slot): number of present bonds whose J * s_neighbour = +1
-                    const uint32_t k4 = (nb0 ^ bytemask(jn & 1u)) + (nb1 ^ bytemask((jn >> 1) & 1u)) +
-                                        (nb2 ^ bytemask((jn >> 2) & 1u)) +
-                                        (nb3 ^ bytemask((jn >> 3) & 1u)) +
-                                        (nb4 ^ bytemask((jn >> 4) & 1u)) +
-                                        (nb5 ^ bytemask((jn >> 5) & 1u));
-                    // table index per slot byte: 2 k + h - d + imax (>= 0, <= 2 imax)
-                    const uint32_t base = ((r.x >> 25) & 63u) + (uint32_t)(A.imax - 32) -
-                                          ((r.x >> 16) & 7u);
-                    const uint32_t idx4 = (k4 << 1) + __builtin_amdgcn_perm(0u, base, 0u);   // base in every byte
-                    uint32_t o0, o1, o2, o3;
-                    if (SCALED) {
-                        const uint32_t off4 = (idx4 + soff4) << 2;
-                        o0 = off4 & 0xFFu;
-                        o1 = (off4 >> 8) & 0xFFu;
-                        o2 = (off4 >> 16) & 0xFFu;
-                        o3 = off4 >> 24;
-                    } else {
-                        o0 = (idx4 & 0xFFu) << 2;
-                        o1 = (((idx4 >> 8) & 0xFFu) + (uint32_t)ni) << 2;
-                        o2 = (((idx4 >> 16) & 0xFFu) + 2u * (uint32_t)ni) << 2;
-                        o3 = ((idx4 >> 24) + 3u * (uint32_t)ni) << 2;
-                    }
-                    const uint32_t T3 = lds_word(lut, o3), T2 = lds_word(lut, o2);
-                    const uint32_t T1 = lds_word(lut, o1), T0 = lds_word(lut, o0);
-                    __builtin_amdgcn_sched_barrier(0);
-                    philox_rounds<5, 10>(x, key);
-                    const uint4 u = make_uint4(x[0], x[1], x[2], x[3]);
-                    uint32_t acc = 0u;   // bit b: new state of slot b (Eq. 6)
-                    acc = shift_in_lt(acc, u.w, T3);
-                    acc = shift_in_lt(acc, u.z, T2);
-                    acc = shift_in_lt(acc, u.y, T1);
-                    acc = shift_in_lt(acc, u.x, T0);
-                    const uint32_t nw = __umul24(acc, 0x00204081u) & 0x01010101u;   // bit b -> byte b
-                    // Eq. (8): the update changes E by -(s_new - s_old) I_j = 2 (o - n) I_j,
-                    // with o, n the old and new states (0/1) and I_j = index - imax
-                    const uint32_t fl = old ^ nw;                    // flipped slots, bytes 0/1
-                    // byte 1 -> 0xFF, 0 -> 0x00 (two full-rate operations, no carries)
-                    const uint32_t mo = (old + 0x7F7F7F7Fu) ^ 0x7F7F7F7Fu;   // where o = 1
-                    const uint32_t mf = (fl + 0x7F7F7F7Fu) ^ 0x7F7F7F7Fu;    // where flipped
-                    const uint32_t v4 = (((idx4 ^ (rev4 - idx4)) & mo) ^ (rev4 - idx4)) & mf;
-                    V02 += v4 & 0x00FF00FFu;
-                    V13 += (v4 >> 8) & 0x00FF00FFu;
-                    C4 += fl;
-                    sp[j] = nw;
+                // two sites per pass, each with its own record register, so that the record
+                // of the next site loads while this one is updated
+                uint4 ra = (tid < cnt) ? rc[tid] : make_uint4(0u, 0u, 0u, 0u);
+                for (int i = tid; i < cnt; i += 2 * kQuadThreads) {
+                    const bool has_b = i + kQuadThreads < cnt;
+                    uint4 rb = make_uint4(0u, 0u, 0u, 0u);
+                    if (has_b) rb = rc[i + kQuadThreads];
+                    apt_site<SCALED, BOFF>(A, sp, lut, ra, uq, c3, soff4, rev4, V02, V13, C4);
+                    if (!has_b) break;
+                    if (i + 2 * kQuadThreads < cnt) ra = rc[i + 2 * kQuadThreads];
+                    apt_site<SCALED, BOFF>(A, sp, lut, rb, uq, c3, soff4, rev4, V02, V13, C4);
                 }
                 __syncthreads();
             }
@@ -2074,27 +2106,30 @@ static hipError_t allow_lds(const void *fn, size_t bytes)
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <bool SCALED, int W>
+template <bool SCALED, int W, bool BOFF>
 hipError_t launch_apt_quad_t(const AptArgs &a, size_t lds_bytes, hipStream_t s)
 {
-    hipError_t e = allow_lds((const void *)apt_quad_kernel<SCALED, W>, lds_bytes);
+    hipError_t e = allow_lds((const void *)apt_quad_kernel<SCALED, W, BOFF>, lds_bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((apt_quad_kernel<SCALED, W>), dim3(a.n_blocks), dim3(kQuadThreads), lds_bytes,
-                       s, a);
+    hipLaunchKernelGGL((apt_quad_kernel<SCALED, W, BOFF>), dim3(a.n_blocks), dim3(kQuadThreads),
+                       lds_bytes, s, a);
     return hipGetLastError();
 }
 
-template <bool SCALED>
+template <bool SCALED, bool BOFF>
 hipError_t launch_apt_quad_w(const AptArgs &a, size_t lds_bytes, hipStream_t s)
 {
-    if (a.waves == 8) return launch_apt_quad_t<SCALED, 8>(a, lds_bytes, s);
-    return launch_apt_quad_t<SCALED, 7>(a, lds_bytes, s);
+    if (a.waves == 8) return launch_apt_quad_t<SCALED, 8, BOFF>(a, lds_bytes, s);
+    return launch_apt_quad_t<SCALED, 7, BOFF>(a, lds_bytes, s);
 }
 
 hipError_t launch_apt_quad(const AptArgs &a, size_t lds_bytes, hipStream_t s)
 {
-    return a.ni <= 16 ? launch_apt_quad_w<true>(a, lds_bytes, s)
-                      : launch_apt_quad_w<false>(a, lds_bytes, s);
+    if (a.boff)
+        return a.ni <= 16 ? launch_apt_quad_w<true, true>(a, lds_bytes, s)
+                          : launch_apt_quad_w<false, true>(a, lds_bytes, s);
+    return a.ni <= 16 ? launch_apt_quad_w<true, false>(a, lds_bytes, s)
+                      : launch_apt_quad_w<false, false>(a, lds_bytes, s);
 }
 
 hipError_t launch_apt_swap(const SwapArgs &a, hipStream_t s)
