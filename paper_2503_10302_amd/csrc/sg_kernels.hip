@@ -931,7 +931,11 @@ __device__ __forceinline__ void apt_site(const AptArgs &A, uint32_t *sp, const u
     const uint64_t p1r = (uint64_t)0xCD9E8D57u * x2r;
     uint32_t x[4] = {xor3_vvs((uint32_t)(p1r >> 32), (uint32_t)pb, A.key0 + 2u * 0x9E3779B9u),
                      (uint32_t)p1r, (uint32_t)(p0r >> 32) ^ uq.z, (uint32_t)p0r};
-    uint32_t key[2] = {A.key0 + 3u * 0x9E3779B9u, A.key1 + 3u * 0xBB67AE85u};
+    // The round keys are derived afresh for every site (scalar additions), not held across
+    // the sweep: kept live, they crowd the scalar registers of the whole kernel.
+    uint32_t k0 = A.key0, k1 = A.key1;
+    asm volatile("" : "+s"(k0), "+s"(k1));
+    uint32_t key[2] = {k0 + 3u * 0x9E3779B9u, k1 + 3u * 0xBB67AE85u};
     philox_rounds<3, 5>(x, key);
     __builtin_amdgcn_sched_barrier(0);
     // per byte (slot): number of present bonds whose J * s_neighbour = +1
