@@ -104,6 +104,21 @@ __device__ __forceinline__ uint32_t shift_in_lt(uint32_t acc, uint32_t u, uint32
 
 __device__ __forceinline__ uint32_t bytemask(uint32_t bit) { return bit * 0x01010101u; }
 
+// 4 x 4 byte transpose: out[m] byte i = byte m of in[i] (eight byte permutes; v_perm_b32
+// picks each result byte from {S0, S1}, selectors 0-3 the bytes of S1 and 4-7 those of S0).
+__device__ __forceinline__ void transpose_bytes(uint32_t a, uint32_t b, uint32_t c, uint32_t d,
+                                                uint32_t out[4])
+{
+    const uint32_t ab_lo = __builtin_amdgcn_perm(b, a, 0x05010400u);   // a0 b0 a1 b1
+    const uint32_t ab_hi = __builtin_amdgcn_perm(b, a, 0x07030602u);   // a2 b2 a3 b3
+    const uint32_t cd_lo = __builtin_amdgcn_perm(d, c, 0x05010400u);
+    const uint32_t cd_hi = __builtin_amdgcn_perm(d, c, 0x07030602u);
+    out[0] = __builtin_amdgcn_perm(cd_lo, ab_lo, 0x05040100u);         // a0 b0 c0 d0
+    out[1] = __builtin_amdgcn_perm(cd_lo, ab_lo, 0x07060302u);
+    out[2] = __builtin_amdgcn_perm(cd_hi, ab_hi, 0x05040100u);
+    out[3] = __builtin_amdgcn_perm(cd_hi, ab_hi, 0x07060302u);
+}
+
 // Per byte (slot): number of present bonds whose J * s_neighbour = +1.
 __device__ __forceinline__ uint32_t aligned_count(const uint32_t *sp, const uint4 r)
 {
@@ -1046,12 +1061,10 @@ void apt_quad_kernel(AptArgs A)
             for (int h = 0; h < 2; ++h) {
                 if (h && !two) break;
                 const int g = h ? g1 : g0;
+                uint32_t o[4];
+                transpose_bytes(v[h][0], v[h][1], v[h][2], v[h][3], o);
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const int sh = 8 * m;
-                    sp[4 * g + m] = ((v[h][0] >> sh) & 0xFFu) | (((v[h][1] >> sh) & 0xFFu) << 8) |
-                                    (((v[h][2] >> sh) & 0xFFu) << 16) | (((v[h][3] >> sh) & 0xFFu) << 24);
-                }
+                for (int m = 0; m < 4; ++m) sp[4 * g + m] = o[m];
             }
         }
         if (tid < 4) sp[npad + tid] = 0u;
@@ -1220,15 +1233,8 @@ void apt_quad_kernel(AptArgs A)
         if (A.n_sweeps > 0 || A.do_icm) {
             uint8_t *gw = A.spins + I.spin_off;
             for (int g = tid; g < (npad >> 2); g += kQuadThreads) {
-                const uint32_t s0 = sp[4 * g], s1 = sp[4 * g + 1], s2 = sp[4 * g + 2],
-                               s3 = sp[4 * g + 3];
-                const uint32_t o[4] = {
-                    (s0 & 0xFFu) | ((s1 & 0xFFu) << 8) | ((s2 & 0xFFu) << 16) | ((s3 & 0xFFu) << 24),
-                    ((s0 >> 8) & 0xFFu) | (((s1 >> 8) & 0xFFu) << 8) | (((s2 >> 8) & 0xFFu) << 16) |
-                        (((s3 >> 8) & 0xFFu) << 24),
-                    ((s0 >> 16) & 0xFFu) | (((s1 >> 16) & 0xFFu) << 8) |
-                        (((s2 >> 16) & 0xFFu) << 16) | (((s3 >> 16) & 0xFFu) << 24),
-                    (s0 >> 24) | ((s1 >> 24) << 8) | ((s2 >> 24) << 16) | ((s3 >> 24) << 24)};
+                uint32_t o[4];
+                transpose_bytes(sp[4 * g], sp[4 * g + 1], sp[4 * g + 2], sp[4 * g + 3], o);
                 *(uint32_t *)(gw + b0 + 4 * g) = o[0];
                 *(uint32_t *)(gw + b1 + 4 * g) = o[1];
                 *(uint32_t *)(gw + b2 + 4 * g) = o[2];
