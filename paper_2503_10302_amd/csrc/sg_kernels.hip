@@ -606,15 +606,32 @@ __device__ void icm_pairs_planes(uint32_t *sp, const uint4 *rowA, const uint4 *r
     const uint32_t mA1 = 1u << (8 * ((pa >> 8) & 3u)), mB1 = 1u << (8 * ((pb >> 8) & 3u));
     uint32_t q0 = 0u, q1 = 0u, s0 = 0u, s1 = 0u;
     if (own) {
+        // The row's words (byte i = slot i, 0/1) folded four sites at a time: byte i of
+        // c[g] holds slot i at sites 4g..4g+3 in bits 0..3; then byte i of C[h] holds sites
+        // 8h..8h+7, and one byte permute per 16 sites gathers a slot's row bits.
         const uint32_t *row = sp + r * lx;
-#pragma unroll 4
-        for (int x = 0; x < lx; ++x) {
-            const uint32_t w = row[x];
-            q0 |= (uint32_t)(((w & mA0) != 0) != ((w & mB0) != 0)) << x;
-            q1 |= (uint32_t)(((w & mA1) != 0) != ((w & mB1) != 0)) << x;
-            s0 |= (uint32_t)((w & mA0) != 0) << x;
-            s1 |= (uint32_t)((w & mA1) != 0) << x;
+        uint32_t c[8];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            c[g] = 0u;
+            if (4 * g < lx) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (4 * g + t < lx) c[g] |= row[4 * g + t] << t;
+            }
         }
+        uint32_t C[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) C[h] = c[2 * h] | (c[2 * h + 1] << 4);
+        auto slot_row = [&](uint32_t slot) {
+            const uint32_t sel = slot | ((slot + 4u) << 8) | 0x0C0C0000u;   // 0x0C: zero byte
+            return __builtin_amdgcn_perm(C[1], C[0], sel) |
+                   (__builtin_amdgcn_perm(C[3], C[2], sel) << 16);
+        };
+        s0 = slot_row(pa & 3u);
+        q0 = s0 ^ slot_row(pb & 3u);
+        s1 = slot_row((pa >> 8) & 3u);
+        q1 = s1 ^ slot_row((pb >> 8) & 3u);
         Sr[r] = s0;
         if (np > 1) Sr[nrows + r] = s1;
         else q1 = 0u;
