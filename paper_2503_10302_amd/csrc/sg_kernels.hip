@@ -471,29 +471,47 @@ __device__ void icm_pairs_rows(uint32_t *sp, const uint4 *rowA, const uint4 *row
 // their boundary planes through LDS at a work-group barrier, until no wave gains a site.
 // The fill reaches the same connected component, so the cluster (and every result) is the
 // same as the search's.
-__device__ __forceinline__ uint32_t xfill(uint32_t V, uint32_t Q, uint32_t mr, uint32_t ml,
-                                          uint32_t hi)
+
+// Closure along x without iterating site by site.  A site y can take the cluster from y - 1
+// when y and y - 1 are both in Q and joined by a bond (mr bit y - 1); the runs of such
+// receivers (eu) are filled from the seeds by one addition, whose carry runs through a run of
+// ones and stops at its end.  The same on the bit-reversed row fills towards lower x (edr),
+// and a second pass continues a run through the wrap bond (bit lx - 1 to bit 0) from its other
+// end.  low: bit 0 of each row in the word (one row, or two rows of at most 16 sites packed at
+// bits 0 and 16).
+struct XMasks {
+    uint32_t eu;    // sites that can take the cluster from x - 1
+    uint32_t edr;   // bit-reversed: sites that can take it from x + 1
+    uint32_t w0;    // bit 0 of a row, reachable from bit lx - 1 through the wrap bond
+    uint32_t whi;   // bit lx - 1, reachable from bit 0
+};
+
+__device__ __forceinline__ XMasks x_masks(uint32_t Q, uint32_t mr, uint32_t hi, uint32_t low)
 {
-    while (true) {
-        const uint32_t right = (V >> 1) | (V << hi), left = (V << 1) | (V >> hi);
-        const uint32_t Vn = V | (((right & mr) | (left & ml)) & Q);
-        if (Vn == V) return V;
-        V = Vn;
-    }
+    XMasks m;
+    m.eu = Q & (Q << 1) & (mr << 1) & ~low;
+    m.edr = __builtin_bitreverse32(Q & (Q >> 1) & mr & ~(low << hi));
+    const uint32_t wb = (mr >> hi) & low;   // the wrap bond of each row, at its bit 0
+    m.w0 = wb & Q;
+    m.whi = (wb << hi) & Q;
+    return m;
 }
 
-// xfill on two rows of at most 16 sites packed in one word (bits 0..15 and 16..31):
-// shifts are masked so that nothing crosses between the halves.
-__device__ __forceinline__ uint32_t xfill2(uint32_t V, uint32_t Q, uint32_t mr, uint32_t ml,
-                                           uint32_t hi)
+__device__ __forceinline__ uint32_t xfill_linear(uint32_t V, const XMasks &m)
 {
-    while (true) {
-        const uint32_t right = ((V >> 1) & 0x7FFF7FFFu) | ((V & 0x00010001u) << hi);
-        const uint32_t left = ((V << 1) & 0xFFFEFFFEu) | ((V >> hi) & 0x00010001u);
-        const uint32_t Vn = V | (((right & mr) | (left & ml)) & Q);
-        if (Vn == V) return V;
-        V = Vn;
-    }
+    const uint32_t bu = (V << 1) & m.eu;
+    const uint32_t fu = (((m.eu + bu) ^ m.eu) | bu) & m.eu;
+    const uint32_t bd = (__builtin_bitreverse32(V) << 1) & m.edr;
+    const uint32_t fd = (((m.edr + bd) ^ m.edr) | bd) & m.edr;
+    return V | fu | __builtin_bitreverse32(fd);
+}
+
+// V (seeds, a subset of Q) grown to its connected part along x.
+__device__ __forceinline__ uint32_t xfill(uint32_t V, const XMasks &m, uint32_t hi)
+{
+    const uint32_t U = xfill_linear(V, m);
+    const uint32_t W = U | ((U >> hi) & m.w0) | ((U << hi) & m.whi);
+    return W != U ? xfill_linear(W, m) : U;
 }
 
 // The flood fill of icm_pairs_planes for both pairs (V0, V1: this lane's row of each
@@ -508,14 +526,15 @@ __device__ __forceinline__ void plane_fill(uint32_t &V0, uint32_t &V1, uint32_t 
 {
     if (PACK) {
         uint32_t W = V0 | (V1 << 16);
-        const uint32_t Qw = Q0 | (Q1 << 16), mr = a.x | (a.x << 16), ml = a.y | (a.y << 16);
+        const uint32_t Qw = Q0 | (Q1 << 16);
+        const XMasks xm = x_masks(Qw, a.x | (a.x << 16), hi, 0x00010001u);
         uint32_t mkw[4];
 #pragma unroll
         for (int d = 0; d < 4; ++d) mkw[d] = mk[d] | (mk[d] << 16);
         uint32_t X[2] = {0u, 0u};   // +z / -z rows from other waves
         while (true) {
             while (true) {   // closure inside the wave
-                W = xfill2(W, Qw, mr, ml, hi);
+                W = xfill(W, xm, hi);
                 uint32_t N = 0u;
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
@@ -547,11 +566,12 @@ __device__ __forceinline__ void plane_fill(uint32_t &V0, uint32_t &V1, uint32_t 
         V1 = W >> 16;
     } else {
         uint32_t X0[2] = {0u, 0u}, X1[2] = {0u, 0u};   // +z / -z rows from other waves
+        const XMasks xm0 = x_masks(Q0, a.x, hi, 1u), xm1 = x_masks(Q1, a.x, hi, 1u);
         while (true) {
             // closure inside the wave
             while (true) {
-                V0 = xfill(V0, Q0, a.x, a.y, hi);
-                V1 = xfill(V1, Q1, a.x, a.y, hi);
+                V0 = xfill(V0, xm0, hi);
+                V1 = xfill(V1, xm1, hi);
                 uint32_t N0 = 0u, N1 = 0u;
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
