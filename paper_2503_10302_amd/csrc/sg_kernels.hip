@@ -729,6 +729,12 @@ __device__ void icm_pairs_planes(uint32_t *sp, const uint4 *rowA, const uint4 *r
     // cluster flip of the first replica: crossing bonds change sign -> dE = 2 * sum
     dE01[0] = (m0 > 0 && 2 * tot[0] <= n) ? 2 * tot[2] : 0;
     dE01[1] = (np > 1 && m1 > 0 && 2 * tot[1] <= n) ? 2 * tot[3] : 0;
+    // The moves of both pairs touch different bytes of the site words, so they are made in
+    // one pass over this lane's row: pair p flips bytes Xf[p] at the sites of row bits F[p],
+    // the cluster in both replicas, or (a cluster of more than half the lattice) the whole
+    // lattice of one replica, which leaves the same pair of states up to a global flip.
+    uint32_t F[2] = {0u, 0u}, Xf[2] = {0u, 0u};
+    const uint32_t all = lx >= 32 ? 0xFFFFFFFFu : (1u << lx) - 1u;
     for (int p = 0; p < np; ++p) {
         const int32_t m = p ? m1 : m0, size = tot[p];
         const uint32_t mA = p ? mA1 : mA0, mB = p ? mB1 : mB0;
@@ -736,16 +742,12 @@ __device__ void icm_pairs_planes(uint32_t *sp, const uint4 *rowA, const uint4 *r
         int32_t branch = 0;
         if (m > 0) {
             if (2 * size > n) {
-                const uint32_t X = ((w1 >> 31) == 0u) ? mA : mB;
+                Xf[p] = ((w1 >> 31) == 0u) ? mA : mB;
                 branch = ((w1 >> 31) == 0u) ? 1 : 2;
-                for (int j = tid; j < n; j += kQuadThreads) sp[j] ^= X;
-            } else if (own) {
-                uint32_t bits = p ? V1 : V0;
-                while (bits) {
-                    const int x = __builtin_ctz(bits);
-                    sp[r * lx + x] ^= (mA | mB);
-                    bits &= bits - 1u;
-                }
+                F[p] = all;
+            } else {
+                Xf[p] = mA | mB;
+                F[p] = p ? V1 : V0;
             }
         }
         int32_t *o = p ? info1 : info0;
@@ -753,8 +755,28 @@ __device__ void icm_pairs_planes(uint32_t *sp, const uint4 *rowA, const uint4 *r
             if (m == 0) { o[0] = 0; o[1] = -1; o[2] = 0; o[3] = 0; }
             else { o[0] = m; o[1] = p ? seed1 : seed0; o[2] = size; o[3] = branch; }
         }
-        __syncthreads();
     }
+    if (own && (F[0] | F[1])) {
+        // every word of the row read first, then written: no load waits on a store
+        uint32_t *row = sp + r * lx;
+#pragma unroll
+        for (int x0 = 0; x0 < 32; x0 += 8) {
+            if (x0 >= lx) break;
+            uint32_t w[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                if (x0 + t < lx) w[t] = row[x0 + t];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (x0 + t < lx) {
+                    const uint32_t f0 = 0u - ((F[0] >> (x0 + t)) & 1u);
+                    const uint32_t f1 = 0u - ((F[1] >> (x0 + t)) & 1u);
+                    row[x0 + t] = w[t] ^ (f0 & Xf[0]) ^ (f1 & Xf[1]);
+                }
+            }
+        }
+    }
+    __syncthreads();
 }
 
 // Replica exchange (Eq. 4): the decision for temperature pair (b, b + 1), label l, at
