@@ -624,6 +624,14 @@ __device__ void icm_pairs_planes(uint32_t *sp, const uint4 *rowA, const uint4 *r
     const int r = own ? z * ly + y : 0;
     const uint32_t mA0 = 1u << (8 * (pa & 3u)), mB0 = 1u << (8 * (pb & 3u));
     const uint32_t mA1 = 1u << (8 * ((pa >> 8) & 3u)), mB1 = 1u << (8 * ((pb >> 8) & 3u));
+    // this lane's bond masks and neighbour rows, loaded first so that the row bitsets, the
+    // seed scan and its barriers cover their latency
+    uint4 a = make_uint4(0u, 0u, 0u, 0u), b = a, cc = a;
+    if (own) {
+        a = rowA[r];
+        b = rowB[r];
+        cc = rowC[r];
+    }
     uint32_t q0 = 0u, q1 = 0u, s0 = 0u, s1 = 0u;
     if (own) {
         // The row's words (byte i = slot i, 0/1) folded four sites at a time: byte i of
@@ -683,11 +691,6 @@ __device__ void icm_pairs_planes(uint32_t *sp, const uint4 *rowA, const uint4 *r
     const int32_t seed0 = m0 > 0 ? red[16] : -1;
     const int32_t seed1 = (np > 1 && m1 > 0) ? red[17] : -1;
     const uint32_t hi = (uint32_t)(lx - 1);
-    uint4 a = make_uint4(0u, 0u, 0u, 0u), b = a;
-    if (own) {
-        a = rowA[r];
-        b = rowB[r];
-    }
     // source lanes of the +y, -y, +z, -z neighbour rows inside this wave, -1 outside
     const int nbr[4] = {(int)(b.z & 0xFFFFu), (int)(b.z >> 16), (int)(b.w & 0xFFFFu),
                         (int)(b.w >> 16)};
@@ -708,7 +711,6 @@ __device__ void icm_pairs_planes(uint32_t *sp, const uint4 *rowA, const uint4 *r
     // bonds that cross the cluster boundary (counted once, along +x, +y, +z)
     int32_t tot[4] = {0, 0, 0, 0};
     if (own) {
-        const uint4 cc = rowC[r];
         for (int p = 0; p < np; ++p) {
             const uint32_t *Sp = Sr + p * nrows;
             // final cluster row idx of pair p (packed rows: half p of Vr[idx])
