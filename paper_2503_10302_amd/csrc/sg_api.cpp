@@ -392,7 +392,9 @@ void init_stream(sg_ctx *c, void *s)
 // than 32 sites) the visited bits and the queue.
 size_t apt_lds_bytes(int npad, int n_rows, int ni, bool queue)
 {
-    size_t words = (size_t)(npad + 4 + 4 * ni + 32 + 6 * n_rows);
+    // tile, threshold rows, reduction scratch; then the row scratch of the row-bitset cluster
+    // search, or in its place the visited bits and the queue of the breadth-first search
+    size_t words = (size_t)(npad + 4 + 4 * ni + 32) + (queue ? 0 : (size_t)6 * n_rows);
     size_t bytes = 16;
     if (queue) {
         words += (size_t)((npad + 31) / 32 + 1);

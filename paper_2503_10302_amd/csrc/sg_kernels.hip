@@ -1079,8 +1079,9 @@ void apt_quad_kernel(AptArgs A)
         int32_t *red = (int32_t *)(sp + npad + 4 + 4 * ni);    // 32
         uint32_t *Qr = (uint32_t *)(red + 32);           // 2 * n_rows
         uint32_t *Vr = Qr + 2 * I.n_rows;                // 2 * n_rows, then S rows 2 * n_rows
-        // queue search only (rows longer than 32 sites): allocated when some instance needs it
-        uint32_t *vis = Vr + 4 * I.n_rows;               // (npad + 31) / 32 + 1
+        // queue search only (no row tables: rows longer than 32 sites, or too many rows): in
+        // place of the row scratch, allocated when some instance needs it
+        uint32_t *vis = I.row_off >= 0 ? Vr + 4 * I.n_rows : Qr;   // (npad + 31) / 32 + 1
         uint16_t *queue = (uint16_t *)(vis + ((npad + 31) >> 5) + 1);   // npad
         const int q = D.quad;
         const int slot_off = D.inst * A.nb4;   // == I.slot_off, without waiting for I

@@ -385,6 +385,30 @@ def test_apt_queue_search_large_lattice():
     assert ctx.energy()[0].tolist() == [oracle.energy(_olat(insts[0]), s) for s in g[0, :, :16000]]
 
 
+def test_apt_byte_offset_record_limit():
+    """The sweep reads site records with neighbour byte offsets when every lattice of the
+    context has at most 16383 sites (4 x 16383 fills 16 bits; on open axes an absent neighbour
+    is the zero word after the last site, at offset 4 n), and site indices above that.  Each
+    side of the limit in a context of its own: a 3 x 43 x 127 open lattice (16383 sites) and a
+    32 x 32 x 16 periodic one (16384 sites), APT+ICM cycles against the oracle."""
+    for shape, periodic, seed in (((3, 43, 127), 0, 81), ((32, 32, 16), 7, 82)):
+        insts = [_inst(shape, periodic, seed)]
+        beta = geometric_ladder(4, 0.5, 3.0)
+        ctx = sg.apt(insts, beta, SEED, reps_per_beta=2)
+        trace = ctx.run_apt(4, 1, 0.5, record_every=2)
+        g = ctx.spins()
+        l = _olat(insts[0])
+        sp = oracle.apt_init(l, 0, 8, SEED)
+        ctr = np.zeros(3, np.uint32)
+        E = np.zeros(8, np.int64)
+        b = np.array([np.iinfo(np.int64).max], np.int64)
+        rc, otr, _ = oracle.apt_run(l, 0, beta, 2, SEED, 4, 1, 0.5, 2, ctr, sp, E, b)
+        assert rc == 0 and np.array_equal(g[0, :, :l.n], sp), shape
+        assert np.array_equal(trace[0], otr), shape
+        assert ctx.energy()[0].tolist() == [oracle.energy(l, s) for s in sp], shape
+        ctx.close()
+
+
 @pytest.mark.parametrize("reps", [2, 4])
 def test_apt_cluster_search_layouts(reps):
     """Row-bitset cluster search in both layouts: whole y-z planes per wave (wave-local fill:
