@@ -308,26 +308,122 @@ __device__ void icm_pair(uint32_t *sp, const uint4 *recj, int n, int ba, int bb,
     __syncthreads();
 }
 
-// Houdayer moves on up to two replica pairs at once, on rows of lx <= 32
-// sites (Algorithm S2, ICMop).  The overlap set Q and the cluster V of each
-// pair are bit rows; one propagation step adds every Q site next to V through
-// a bond with J != 0, until no row of either pair changes.  This reaches the
-// same connected component as a breadth-first search from the seed.  Each
-// thread owns consecutive rows; the bond masks of its first row stay in
-// registers.  LDS: Qr[2][n_rows], Vr[2][n_rows], red[>= 24].
-// Pair p uses bytes (pa >> 8p) & 3 and (pb >> 8p) & 3 of the site words.
+// Closure along x without iterating site by site.  A site y can take the cluster from y - 1
+// when y and y - 1 are both in Q and joined by a bond (mr bit y - 1); the runs of such
+// receivers (eu) are filled from the seeds by one addition, whose carry runs through a run of
+// ones and stops at its end.  The same on the bit-reversed row fills towards lower x (edr),
+// and a second pass continues a run through the wrap bond (bit lx - 1 to bit 0) from its other
+// end.  low: bit 0 of each row in the word (one row, or two rows of at most 16 sites packed at
+// bits 0 and 16).
+struct XMasks {
+    uint32_t eu;    // sites that can take the cluster from x - 1
+    uint32_t edr;   // bit-reversed: sites that can take it from x + 1
+    uint32_t w0;    // bit 0 of a row, reachable from bit lx - 1 through the wrap bond
+    uint32_t whi;   // bit lx - 1, reachable from bit 0
+};
 
+__device__ __forceinline__ XMasks x_masks(uint32_t Q, uint32_t mr, uint32_t hi, uint32_t low)
+{
+    XMasks m;
+    m.eu = Q & (Q << 1) & (mr << 1) & ~low;
+    m.edr = __builtin_bitreverse32(Q & (Q >> 1) & mr & ~(low << hi));
+    const uint32_t wb = (mr >> hi) & low;   // the wrap bond of each row, at its bit 0
+    m.w0 = wb & Q;
+    m.whi = (wb << hi) & Q;
+    return m;
+}
+
+__device__ __forceinline__ uint32_t xfill_linear(uint32_t V, const XMasks &m)
+{
+    const uint32_t bu = (V << 1) & m.eu;
+    const uint32_t fu = (((m.eu + bu) ^ m.eu) | bu) & m.eu;
+    const uint32_t bd = (__builtin_bitreverse32(V) << 1) & m.edr;
+    const uint32_t fd = (((m.edr + bd) ^ m.edr) | bd) & m.edr;
+    return V | fu | __builtin_bitreverse32(fd);
+}
+
+// V (seeds, a subset of Q) grown to its connected part along x.
+__device__ __forceinline__ uint32_t xfill(uint32_t V, const XMasks &m, uint32_t hi)
+{
+    const uint32_t U = xfill_linear(V, m);
+    const uint32_t W = U | ((U >> hi) & m.w0) | ((U << hi) & m.whi);
+    return W != U ? xfill_linear(W, m) : U;
+}
+
+// A lattice row's words (lx <= 32 sites; byte i = slot i, 0/1) folded four sites at a time:
+// byte i of c[g] holds slot i at sites 4g..4g+3 in bits 0..3, then byte i of C[h] holds sites
+// 8h..8h+7, so that one byte permute per 16 sites gathers a slot's row bits.
+struct RowFold {
+    uint32_t C[4];
+};
+
+__device__ __forceinline__ RowFold fold_row(const uint32_t *row, int lx)
+{
+    uint32_t c[8];
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+        c[g] = 0u;
+        if (4 * g < lx) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (4 * g + t < lx) c[g] |= row[4 * g + t] << t;
+        }
+    }
+    RowFold f;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) f.C[h] = c[2 * h] | (c[2 * h + 1] << 4);
+    return f;
+}
+
+// Bit x: the spin (1 = up) of the slot at site x of the folded row.
+__device__ __forceinline__ uint32_t slot_row(const RowFold &f, uint32_t slot)
+{
+    const uint32_t sel = slot | ((slot + 4u) << 8) | 0x0C0C0000u;   // 0x0C: zero byte
+    return __builtin_amdgcn_perm(f.C[1], f.C[0], sel) |
+           (__builtin_amdgcn_perm(f.C[3], f.C[2], sel) << 16);
+}
+
+// Flip bytes X0 at the sites of row bits F0 and bytes X1 at those of F1 (the two pairs of a
+// tile use different bytes); every word of the row is read before any is written.
+__device__ __forceinline__ void flip_row(uint32_t *row, int lx, uint32_t F0, uint32_t X0,
+                                         uint32_t F1, uint32_t X1)
+{
+#pragma unroll
+    for (int x0 = 0; x0 < 32; x0 += 8) {
+        if (x0 >= lx) break;
+        uint32_t w[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            if (x0 + t < lx) w[t] = row[x0 + t];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            if (x0 + t < lx) {
+                const uint32_t f0 = 0u - ((F0 >> (x0 + t)) & 1u);
+                const uint32_t f1 = 0u - ((F1 >> (x0 + t)) & 1u);
+                row[x0 + t] = w[t] ^ (f0 & X0) ^ (f1 & X1);
+            }
+        }
+    }
+}
+
+// One propagation step of a row: the Q sites next to the cluster in the +-y, +-z rows join,
+// then the row is closed along x.
 __device__ __forceinline__ uint32_t row_step(const uint32_t *Vp, int r, uint32_t hi, const uint4 a,
                                              const uint4 b, uint32_t Q)
 {
     const uint32_t V = Vp[r];
-    const uint32_t right = (V >> 1) | (V << hi);   // bit x <- site x+1 (mod lx)
-    const uint32_t left = (V << 1) | (V >> hi);    // bit x <- site x-1 (mod lx)
-    const uint32_t N = (right & a.x) | (left & a.y) | (Vp[b.z & 0xFFFFu] & a.z) |
-                       (Vp[b.z >> 16] & a.w) | (Vp[b.w & 0xFFFFu] & b.x) | (Vp[b.w >> 16] & b.y);
-    return V | (N & Q);
+    const uint32_t N = (Vp[b.z & 0xFFFFu] & a.z) | (Vp[b.z >> 16] & a.w) |
+                       (Vp[b.w & 0xFFFFu] & b.x) | (Vp[b.w >> 16] & b.y);
+    return xfill(V | (N & Q), x_masks(Q, a.x, hi, 1u), hi);
 }
 
+// Houdayer moves on up to two replica pairs at once, on rows of lx <= 32 sites (Algorithm S2,
+// ICMop).  The overlap set Q and the cluster V of each pair are bit rows; one propagation step
+// adds every Q site next to V through a bond with J != 0 along y or z and then closes the row
+// along x, until no row of either pair changes.  This reaches the same connected component as
+// a breadth-first search from the seed.  Each thread owns consecutive rows; the bond masks of
+// its first row stay in registers.  LDS: Qr[2][n_rows], Vr[2][n_rows], red[>= 24].  Pair p uses
+// bytes (pa >> 8p) & 3 and (pb >> 8p) & 3 of the site words.
 __device__ void icm_pairs_rows(uint32_t *sp, const uint4 *rowA, const uint4 *rowB,
                                const uint4 *rowC, int n, int lx, int nrows, int np, uint32_t pa,
                                uint32_t pb, uint4 w01, uint32_t *Qr, uint32_t *Vr, int32_t *red,
@@ -341,16 +437,9 @@ __device__ void icm_pairs_rows(uint32_t *sp, const uint4 *rowA, const uint4 *row
     const uint32_t mA1 = 1u << (8 * ((pa >> 8) & 3u)), mB1 = 1u << (8 * ((pb >> 8) & 3u));
     int32_t c0 = 0, c1 = 0;
     for (int r = r0; r < r1; ++r) {
-        uint32_t q0 = 0u, q1 = 0u;
-        const uint32_t *row = sp + r * lx;
-        uint32_t s0 = 0u, s1 = 0u;
-        for (int x = 0; x < lx; ++x) {
-            const uint32_t w = row[x];
-            q0 |= (uint32_t)(((w & mA0) != 0) != ((w & mB0) != 0)) << x;
-            q1 |= (uint32_t)(((w & mA1) != 0) != ((w & mB1) != 0)) << x;
-            s0 |= (uint32_t)((w & mA0) != 0) << x;
-            s1 |= (uint32_t)((w & mA1) != 0) << x;
-        }
+        const RowFold f = fold_row(sp + r * lx, lx);
+        const uint32_t s0 = slot_row(f, pa & 3u), q0 = s0 ^ slot_row(f, pb & 3u);
+        const uint32_t s1 = slot_row(f, (pa >> 8) & 3u), q1 = s1 ^ slot_row(f, (pb >> 8) & 3u);
         Qr[r] = q0;
         Vr[r] = 0u;
         Sr[r] = s0;
@@ -434,6 +523,12 @@ __device__ void icm_pairs_rows(uint32_t *sp, const uint4 *rowA, const uint4 *row
     // cluster flip of the first replica: crossing bonds change sign -> dE = 2 * sum
     dE01[0] = (m0 > 0 && 2 * tot[0] <= n) ? 2 * tot[2] : 0;
     dE01[1] = (np > 1 && m1 > 0 && 2 * tot[1] <= n) ? 2 * tot[3] : 0;
+    // both pairs' moves in one pass over the thread's rows (as in icm_pairs_planes): pair p
+    // flips bytes Xf[p] at its cluster, or, for a cluster of more than half the lattice, the
+    // whole lattice of one replica
+    bool whole[2] = {false, false};
+    uint32_t Xf[2] = {0u, 0u};
+    const uint32_t all = lx >= 32 ? 0xFFFFFFFFu : (1u << lx) - 1u;
     for (int p = 0; p < np; ++p) {
         const int32_t m = p ? m1 : m0, size = tot[p];
         const uint32_t mA = p ? mA1 : mA0, mB = p ? mB1 : mB0;
@@ -441,18 +536,11 @@ __device__ void icm_pairs_rows(uint32_t *sp, const uint4 *rowA, const uint4 *row
         int32_t branch = 0;
         if (m > 0) {
             if (2 * size > n) {
-                const uint32_t X = ((w1 >> 31) == 0u) ? mA : mB;
+                Xf[p] = ((w1 >> 31) == 0u) ? mA : mB;
                 branch = ((w1 >> 31) == 0u) ? 1 : 2;
-                for (int j = tid; j < n; j += kQuadThreads) sp[j] ^= X;
+                whole[p] = true;
             } else {
-                for (int r = r0; r < r1; ++r) {
-                    uint32_t bits = Vr[p * nrows + r];
-                    while (bits) {
-                        const int x = __builtin_ctz(bits);
-                        sp[r * lx + x] ^= (mA | mB);
-                        bits &= bits - 1u;
-                    }
-                }
+                Xf[p] = mA | mB;
             }
         }
         int32_t *o = p ? info1 : info0;
@@ -460,8 +548,13 @@ __device__ void icm_pairs_rows(uint32_t *sp, const uint4 *rowA, const uint4 *row
             if (m == 0) { o[0] = 0; o[1] = -1; o[2] = 0; o[3] = 0; }
             else { o[0] = m; o[1] = p ? seed1 : seed0; o[2] = size; o[3] = branch; }
         }
-        __syncthreads();
     }
+    for (int r = r0; r < r1; ++r) {
+        const uint32_t F0 = Xf[0] == 0u ? 0u : (whole[0] ? all : Vr[r]);
+        const uint32_t F1 = Xf[1] == 0u ? 0u : (whole[1] ? all : Vr[nrows + r]);
+        if (F0 | F1) flip_row(sp + r * lx, lx, F0, Xf[0], F1, Xf[1]);
+    }
+    __syncthreads();
 }
 
 // The same moves as icm_pairs_rows, for lattices whose x-rows fit one per lane with whole
@@ -471,48 +564,6 @@ __device__ void icm_pairs_rows(uint32_t *sp, const uint4 *rowA, const uint4 *row
 // their boundary planes through LDS at a work-group barrier, until no wave gains a site.
 // The fill reaches the same connected component, so the cluster (and every result) is the
 // same as the search's.
-
-// Closure along x without iterating site by site.  A site y can take the cluster from y - 1
-// when y and y - 1 are both in Q and joined by a bond (mr bit y - 1); the runs of such
-// receivers (eu) are filled from the seeds by one addition, whose carry runs through a run of
-// ones and stops at its end.  The same on the bit-reversed row fills towards lower x (edr),
-// and a second pass continues a run through the wrap bond (bit lx - 1 to bit 0) from its other
-// end.  low: bit 0 of each row in the word (one row, or two rows of at most 16 sites packed at
-// bits 0 and 16).
-struct XMasks {
-    uint32_t eu;    // sites that can take the cluster from x - 1
-    uint32_t edr;   // bit-reversed: sites that can take it from x + 1
-    uint32_t w0;    // bit 0 of a row, reachable from bit lx - 1 through the wrap bond
-    uint32_t whi;   // bit lx - 1, reachable from bit 0
-};
-
-__device__ __forceinline__ XMasks x_masks(uint32_t Q, uint32_t mr, uint32_t hi, uint32_t low)
-{
-    XMasks m;
-    m.eu = Q & (Q << 1) & (mr << 1) & ~low;
-    m.edr = __builtin_bitreverse32(Q & (Q >> 1) & mr & ~(low << hi));
-    const uint32_t wb = (mr >> hi) & low;   // the wrap bond of each row, at its bit 0
-    m.w0 = wb & Q;
-    m.whi = (wb << hi) & Q;
-    return m;
-}
-
-__device__ __forceinline__ uint32_t xfill_linear(uint32_t V, const XMasks &m)
-{
-    const uint32_t bu = (V << 1) & m.eu;
-    const uint32_t fu = (((m.eu + bu) ^ m.eu) | bu) & m.eu;
-    const uint32_t bd = (__builtin_bitreverse32(V) << 1) & m.edr;
-    const uint32_t fd = (((m.edr + bd) ^ m.edr) | bd) & m.edr;
-    return V | fu | __builtin_bitreverse32(fd);
-}
-
-// V (seeds, a subset of Q) grown to its connected part along x.
-__device__ __forceinline__ uint32_t xfill(uint32_t V, const XMasks &m, uint32_t hi)
-{
-    const uint32_t U = xfill_linear(V, m);
-    const uint32_t W = U | ((U >> hi) & m.w0) | ((U << hi) & m.whi);
-    return W != U ? xfill_linear(W, m) : U;
-}
 
 // The flood fill of icm_pairs_planes for both pairs (V0, V1: this lane's row of each
 // pair's cluster, seeds on entry).  PACK (rows of at most 16 sites): both pairs in one
@@ -634,32 +685,11 @@ __device__ void icm_pairs_planes(uint32_t *sp, const uint4 *rowA, const uint4 *r
     }
     uint32_t q0 = 0u, q1 = 0u, s0 = 0u, s1 = 0u;
     if (own) {
-        // The row's words (byte i = slot i, 0/1) folded four sites at a time: byte i of
-        // c[g] holds slot i at sites 4g..4g+3 in bits 0..3; then byte i of C[h] holds sites
-        // 8h..8h+7, and one byte permute per 16 sites gathers a slot's row bits.
-        const uint32_t *row = sp + r * lx;
-        uint32_t c[8];
-#pragma unroll
-        for (int g = 0; g < 8; ++g) {
-            c[g] = 0u;
-            if (4 * g < lx) {
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    if (4 * g + t < lx) c[g] |= row[4 * g + t] << t;
-            }
-        }
-        uint32_t C[4];
-#pragma unroll
-        for (int h = 0; h < 4; ++h) C[h] = c[2 * h] | (c[2 * h + 1] << 4);
-        auto slot_row = [&](uint32_t slot) {
-            const uint32_t sel = slot | ((slot + 4u) << 8) | 0x0C0C0000u;   // 0x0C: zero byte
-            return __builtin_amdgcn_perm(C[1], C[0], sel) |
-                   (__builtin_amdgcn_perm(C[3], C[2], sel) << 16);
-        };
-        s0 = slot_row(pa & 3u);
-        q0 = s0 ^ slot_row(pb & 3u);
-        s1 = slot_row((pa >> 8) & 3u);
-        q1 = s1 ^ slot_row((pb >> 8) & 3u);
+        const RowFold f = fold_row(sp + r * lx, lx);
+        s0 = slot_row(f, pa & 3u);
+        q0 = s0 ^ slot_row(f, pb & 3u);
+        s1 = slot_row(f, (pa >> 8) & 3u);
+        q1 = s1 ^ slot_row(f, (pb >> 8) & 3u);
         Sr[r] = s0;
         if (np > 1) Sr[nrows + r] = s1;
         else q1 = 0u;
@@ -758,26 +788,7 @@ __device__ void icm_pairs_planes(uint32_t *sp, const uint4 *rowA, const uint4 *r
             else { o[0] = m; o[1] = p ? seed1 : seed0; o[2] = size; o[3] = branch; }
         }
     }
-    if (own && (F[0] | F[1])) {
-        // every word of the row read first, then written: no load waits on a store
-        uint32_t *row = sp + r * lx;
-#pragma unroll
-        for (int x0 = 0; x0 < 32; x0 += 8) {
-            if (x0 >= lx) break;
-            uint32_t w[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t)
-                if (x0 + t < lx) w[t] = row[x0 + t];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                if (x0 + t < lx) {
-                    const uint32_t f0 = 0u - ((F[0] >> (x0 + t)) & 1u);
-                    const uint32_t f1 = 0u - ((F[1] >> (x0 + t)) & 1u);
-                    row[x0 + t] = w[t] ^ (f0 & Xf[0]) ^ (f1 & Xf[1]);
-                }
-            }
-        }
-    }
+    if (own && (F[0] | F[1])) flip_row(sp + r * lx, lx, F[0], Xf[0], F[1], Xf[1]);
     __syncthreads();
 }
 
