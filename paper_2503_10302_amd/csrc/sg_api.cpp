@@ -8,11 +8,13 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <limits>
 #include <map>
 #include <memory>
@@ -20,6 +22,7 @@
 #include <new>
 #include <set>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -44,6 +47,37 @@ struct Failure {
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     throw Failure{code, buf};
+}
+
+// f(0) .. f(n - 1) on up to 16 host threads (the calling one included), each index once.
+// After every thread has ended, the exception of the lowest failing index is rethrown, so
+// that the error reported does not depend on the threads' timing.
+template <class F>
+void parallel_for(int n, F f)
+{
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int nt = std::min({n, (int)hw, 16});
+    if (nt <= 1) {
+        for (int i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<int> next{0};
+    std::vector<std::exception_ptr> err((size_t)n);
+    auto work = [&] {
+        for (int i = next++; i < n; i = next++) {
+            try {
+                f(i);
+            } catch (...) {
+                err[(size_t)i] = std::current_exception();
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (int k = 1; k < nt; ++k) th.emplace_back(work);
+    work();
+    for (std::thread &t : th) t.join();
+    for (const std::exception_ptr &e : err)
+        if (e) std::rethrow_exception(e);
 }
 
 void hip_check(hipError_t e, const char *what)
@@ -112,19 +146,31 @@ struct Lat {
         return j / (Lx * Ly);
     }
     int stride(int a) const { return a == 0 ? 1 : (a == 1 ? Lx : Lx * Ly); }
-    // neighbour of j along axis a (dir = +1/-1) or -1
-    int nbr(int j, int a, int dir) const
+    // neighbours: nbt[6 j + 2 a + s], along axis a in direction +1 (s = 0) or -1 (s = 1),
+    // -1 where there is none (an open end, or an axis of one site)
+    std::vector<int32_t> nbt;
+    void build_neighbours()
     {
-        const int L = len(a);
-        if (L < 2) return -1;
-        const int c = coord(j, a);
-        int c2 = c + dir;
-        if (c2 < 0 || c2 >= L) {
-            if (!((periodic >> a) & 1u)) return -1;
-            c2 = (c2 + L) % L;
-        }
-        return j + (c2 - c) * stride(a);
+        nbt.assign((size_t)6 * n, -1);
+        for (int z = 0; z < Lz; ++z)
+            for (int y = 0; y < Ly; ++y)
+                for (int x = 0; x < Lx; ++x) {
+                    const int j = (z * Ly + y) * Lx + x;
+                    const int c[3] = {x, y, z};
+                    for (int a = 0; a < 3; ++a) {
+                        const int L = len(a), st = stride(a);
+                        if (L < 2) continue;
+                        const bool per = (periodic >> a) & 1u;
+                        int32_t *o = &nbt[(size_t)6 * j + 2 * a];
+                        if (c[a] + 1 < L) o[0] = j + st;
+                        else if (per) o[0] = j - (L - 1) * st;
+                        if (c[a] > 0) o[1] = j - st;
+                        else if (per) o[1] = j + (L - 1) * st;
+                    }
+                }
     }
+    // neighbour of j along axis a (dir = +1/-1) or -1
+    int nbr(int j, int a, int dir) const { return nbt[(size_t)6 * j + 2 * a + (dir < 0)]; }
     int coupling(int j, int a, int dir) const
     {
         const int nb = nbr(j, a, dir);
@@ -209,6 +255,7 @@ Lat copy_lattice(const sg_lattice &L, int idx)
         if (t.J[i] < -1 || t.J[i] > 1) fail(SG_EINVAL, "instance %d: J must be -1, 0 or +1", idx);
     for (int8_t v : t.h)
         if (v < -kMaxH || v > kMaxH) fail(SG_EINVAL, "instance %d: |h| must be <= %d", idx, kMaxH);
+    t.build_neighbours();
     // values stored across open boundaries are not bonds
     for (int j = 0; j < t.n; ++j)
         for (int a = 0; a < 3; ++a)
@@ -225,7 +272,7 @@ uint4 make_record(const Lat &L, int j, uint32_t parity)
         for (int s = 0; s < 2; ++s) {
             const int dir = s ? -1 : +1;
             const int v = L.nbr(j, a, dir);
-            const int c = L.coupling(j, a, dir);
+            const int c = v < 0 ? 0 : L.J[3 * (s ? v : j) + a];   // L.coupling(j, a, dir)
             const int slot = 2 * a + s;
             if (v < 0 || c == 0) {
                 nb[slot] = (uint32_t)L.n;
@@ -410,19 +457,25 @@ void apt_records(const Lat &L, std::vector<uint4> &rec, std::vector<uint4> &recj
     I.n_colours = C;
     I.rec_off = (int64_t)rec.size();
     I.recj_off = (int64_t)recj.size();
+    // the records in site order, then the colour classes in ascending site order (one stable
+    // bucket pass over the site colours)
+    std::vector<uint8_t> col(L.n);
+    int cnt[kMaxColours] = {};
+    for (int j = 0; j < L.n; ++j) {
+        recj.push_back(make_record(L, j, 0u));
+        col[j] = (uint8_t)L.colour(j);
+        ++cnt[col[j]];
+    }
     int off = 0;
+    int64_t pos[kMaxColours];
     for (int c = 0; c < kMaxColours; ++c) {
         I.col_off[c] = off;
-        I.col_cnt[c] = 0;
-        if (c >= C) continue;
-        for (int j = 0; j < L.n; ++j)
-            if (L.colour(j) == c) {
-                rec.push_back(make_record(L, j, 0u));
-                ++I.col_cnt[c];
-            }
+        I.col_cnt[c] = c < C ? cnt[c] : 0;
+        pos[c] = I.rec_off + off;
         off += I.col_cnt[c];
     }
-    for (int j = 0; j < L.n; ++j) recj.push_back(make_record(L, j, 0u));
+    rec.resize(rec.size() + (size_t)L.n);
+    for (int j = 0; j < L.n; ++j) rec[(size_t)pos[col[j]]++] = recj[(size_t)I.recj_off + j];
 }
 
 // Phases of the (d+1)-dimensional lattice with an even periodic Trotter ring:
@@ -513,7 +566,7 @@ void apt_rows(const Lat &L, std::vector<uint4> &rowA, std::vector<uint4> &rowB,
                 for (int s = 0; s < 2; ++s) {
                     const int dir = s ? -1 : +1;
                     const int v = L.nbr(j, a, dir);
-                    if (v < 0 || L.coupling(j, a, dir) == 0) continue;
+                    if (v < 0 || L.J[3 * (s ? v : j) + a] == 0) continue;   // L.coupling
                     m[2 * a + s] |= 1u << x;
                     if (a > 0) nbrow[2 * (a - 1) + s] = (uint32_t)(v / L.Lx);
                 }
@@ -614,10 +667,11 @@ void build_common(sg_ctx *c, const sg_config *cfg, const int8_t *const *colour =
 {
     if (cfg->n_inst < 1) fail(SG_EINVAL, "n_inst must be >= 1");
     if (!cfg->inst) fail(SG_EINVAL, "inst is NULL");
-    for (int i = 0; i < cfg->n_inst; ++i) {
-        c->lat.push_back(copy_lattice(cfg->inst[i], i));
-        if (colour && colour[i]) set_colour_map(c->lat.back(), colour[i], i);
-    }
+    c->lat.resize((size_t)cfg->n_inst);
+    parallel_for(cfg->n_inst, [&](int i) {
+        c->lat[i] = copy_lattice(cfg->inst[i], i);
+        if (colour && colour[i]) set_colour_map(c->lat[i], colour[i], i);
+    });
     c->n_inst = cfg->n_inst;
     for (auto &L : c->lat) {
         c->n_max = std::max(c->n_max, L.n);
@@ -650,21 +704,60 @@ void create_apt(sg_ctx *c, const sg_config *cfg, const int8_t *const *colour = n
     build_common(c, cfg, colour);
     const int nb4 = 4 * c->n_quads;   // physical buffers per instance (slots padded to a quad)
 
+    c->imax = 6 + c->hmax;
+    c->ni = 2 * c->imax + 1;
+    // Each instance's tables (site records, bond rows, heat-bath rows, swap tables) depend on
+    // that instance alone: they are built on several host threads, with offsets relative to
+    // the instance's own tables, then joined in instance order.
+    struct Tables {
+        InstDev I{};
+        std::vector<uint4> rec, recj, rowA, rowB, rowC;
+        std::vector<uint32_t> lut, tab;
+        std::vector<int32_t> tab_off, tab_len;
+    };
+    std::vector<Tables> per((size_t)c->n_inst);
+    parallel_for(c->n_inst, [&](int i) {
+        const Lat &L = c->lat[i];
+        Tables &T = per[i];
+        InstDev &I = T.I;
+        I.n = L.n;
+        I.npad = round_up(L.n, 16);
+        I.n_slots = c->n_slots;
+        apt_records(L, T.rec, T.recj, I);
+        I.n_bonds = L.bonds();
+        apt_rows(L, T.rowA, T.rowB, T.rowC, I);
+        const double *bt = &c->beta[(size_t)i * c->n_beta];
+        for (int b = 0; b < c->n_beta; ++b)
+            for (int I2 = -c->imax; I2 <= c->imax; ++I2) T.lut.push_back(heat_bath_threshold(bt[b], I2));
+        const int64_t gap = L.max_energy_gap();
+        for (int b = 0; b + 1 < c->n_beta; ++b) {
+            T.tab_off.push_back((int32_t)T.tab.size());
+            T.tab.push_back(0xFFFFFFFFu);   // d = 0 is always accepted and never looked up
+            int64_t d = 1;
+            for (; d <= gap; ++d) {
+                const uint32_t Tv = swap_threshold(bt[b], bt[b + 1], d);
+                if (Tv == 0u) break;
+                T.tab.push_back(Tv);
+            }
+            T.tab_len.push_back((int32_t)d);
+            if (T.tab.size() > (size_t)1 << 30) fail(SG_ENOMEM, "swap tables too large");
+        }
+    });
     std::vector<uint4> rec, recj, rowA, rowB, rowC;
     std::vector<int32_t> perm, slot_lut, tab_off, tab_len;
     std::vector<uint32_t> lut, tab;
     int64_t spin_bytes = 0;
-    c->imax = 6 + c->hmax;
-    c->ni = 2 * c->imax + 1;
     for (int i = 0; i < c->n_inst; ++i) {
-        const Lat &L = c->lat[i];
-        InstDev I{};
-        I.n = L.n;
-        I.npad = round_up(L.n, 16);
-        I.n_slots = c->n_slots;
-        apt_records(L, rec, recj, I);
-        I.n_bonds = L.bonds();
-        apt_rows(L, rowA, rowB, rowC, I);
+        Tables &T = per[i];
+        InstDev I = T.I;
+        I.rec_off += (int64_t)rec.size();
+        I.recj_off += (int64_t)recj.size();
+        if (I.row_off >= 0) I.row_off += (int32_t)rowA.size();
+        rec.insert(rec.end(), T.rec.begin(), T.rec.end());
+        recj.insert(recj.end(), T.recj.begin(), T.recj.end());
+        rowA.insert(rowA.end(), T.rowA.begin(), T.rowA.end());
+        rowB.insert(rowB.end(), T.rowB.begin(), T.rowB.end());
+        rowC.insert(rowC.end(), T.rowC.begin(), T.rowC.end());
         I.spin_off = spin_bytes;
         spin_bytes += (int64_t)nb4 * I.npad;
         I.slot_off = i * nb4;
@@ -674,23 +767,13 @@ void create_apt(sg_ctx *c, const sg_config *cfg, const int8_t *const *colour = n
             perm.push_back(s2);
             slot_lut.push_back(i * c->n_beta + std::min(s2, c->n_slots - 1) / c->reps);
         }
-        const double *bt = &c->beta[(size_t)i * c->n_beta];
-        for (int b = 0; b < c->n_beta; ++b)
-            for (int I2 = -c->imax; I2 <= c->imax; ++I2) lut.push_back(heat_bath_threshold(bt[b], I2));
-        const int64_t gap = L.max_energy_gap();
-        for (int b = 0; b + 1 < c->n_beta; ++b) {
-            tab_off.push_back((int32_t)tab.size());
-            tab.push_back(0xFFFFFFFFu);   // d = 0 is always accepted and never looked up
-            int64_t d = 1;
-            for (; d <= gap; ++d) {
-                const uint32_t T = swap_threshold(bt[b], bt[b + 1], d);
-                if (T == 0u) break;
-                tab.push_back(T);
-            }
-            tab_len.push_back((int32_t)d);
-            if (tab.size() > (size_t)1 << 30) fail(SG_ENOMEM, "swap tables too large");
-        }
+        lut.insert(lut.end(), T.lut.begin(), T.lut.end());
+        for (int32_t o : T.tab_off) tab_off.push_back((int32_t)tab.size() + o);
+        tab_len.insert(tab_len.end(), T.tab_len.begin(), T.tab_len.end());
+        tab.insert(tab.end(), T.tab.begin(), T.tab.end());
+        if (tab.size() > (size_t)1 << 30) fail(SG_ENOMEM, "swap tables too large");
         c->idev.push_back(I);
+        T = Tables{};   // release this instance's copies
     }
     // every host-side table is built before the first device call
     init_stream(c, cfg->hip_stream);
