@@ -54,6 +54,26 @@ def test_invalid_arguments_are_rejected_before_any_device_work():
     _expect(sg.SG_EINVAL, lambda: sg.sqa([(J, 7, None)], 8, 2, -1.0, 1))                 # beta <= 0
 
 
+def test_lowest_invalid_instance_is_reported():
+    """Instances are checked and their tables built on several host threads; with several
+    invalid instances the error names the lowest of them, whatever the threads' timing."""
+    beta = geometric_ladder(8)
+    insts = []
+    for i in range(64):
+        J, _ = ej_couplings(5, 7, seed=100 + i)
+        if i in (9, 23, 41, 60):
+            J = J.copy()
+            J[1, 2, 3, i % 3] = 2
+        insts.append((J, 7, None))
+    for _ in range(20):
+        with pytest.raises(sg.SGError) as e:
+            sg.apt(insts, beta, 1, 2)
+        assert e.value.code == sg.SG_EINVAL and "instance 9:" in str(e.value), str(e.value)
+        with pytest.raises(sg.SGError) as e:
+            sg.sqa(insts, 8, 2, 4.0, 1)
+        assert e.value.code == sg.SG_EINVAL and "instance 9:" in str(e.value), str(e.value)
+
+
 def test_no_silent_cpu_fallback():
     """Valid input on a machine without a GPU fails with SG_EHIP instead of computing elsewhere."""
     J, _ = ej_couplings(4, 7, seed=1)
