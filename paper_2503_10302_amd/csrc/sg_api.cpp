@@ -663,6 +663,13 @@ void set_colour_map(Lat &L, const int8_t *map, int idx)
     L.cmap_colours = C;
 }
 
+// The neighbour tables are needed only while the context's tables are built (24 bytes per
+// site): released before the first device call.
+void release_neighbours(sg_ctx *c)
+{
+    for (Lat &L : c->lat) std::vector<int32_t>().swap(L.nbt);
+}
+
 void build_common(sg_ctx *c, const sg_config *cfg, const int8_t *const *colour = nullptr)
 {
     if (cfg->n_inst < 1) fail(SG_EINVAL, "n_inst must be >= 1");
@@ -776,6 +783,7 @@ void create_apt(sg_ctx *c, const sg_config *cfg, const int8_t *const *colour = n
         T = Tables{};   // release this instance's copies
     }
     // every host-side table is built before the first device call
+    release_neighbours(c);
     init_stream(c, cfg->hip_stream);
     hipStream_t s = c->stream;
     c->d_inst.upload(c->idev, s, "instances");
@@ -990,6 +998,7 @@ void create_sqa(sg_ctx *c, const sg_config *cfg, const int8_t *const *colour = n
         c->idev.push_back(I);
     }
     // every host-side table is built before the first device call
+    release_neighbours(c);
     init_stream(c, cfg->hip_stream);
     hipStream_t s = c->stream;
     c->d_inst.upload(c->idev, s, "instances");
