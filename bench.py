@@ -707,8 +707,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs the whole hot path on one GPU; multi-GPU runs are not "
-              "part of it.", file=sys.stderr)
+        print("bench.py: libsg runs the whole hot path on one GPU; runs on several GPUs are not "
+              "supported (--gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     if args.apt_parts:
