@@ -22,6 +22,7 @@
 #include <new>
 #include <set>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <tuple>
 #include <vector>
@@ -73,7 +74,13 @@ void parallel_for(int n, F f)
         }
     };
     std::vector<std::thread> th;
-    for (int k = 1; k < nt; ++k) th.emplace_back(work);
+    for (int k = 1; k < nt; ++k) {
+        try {
+            th.emplace_back(work);
+        } catch (const std::system_error &) {
+            break;   // no more threads: the ones started and this one share the rest
+        }
+    }
     work();
     for (std::thread &t : th) t.join();
     for (const std::exception_ptr &e : err)
