@@ -377,6 +377,7 @@ double erfc_inv(double y)
 }
 
 constexpr int kRungs = 32, kPairs = kRungs - 1, kPilotReps = 2;
+constexpr int kPilotLaunchConfig = 1;   // APT launch configuration of the pilots
 // Pilot acceptances are clamped to [kAccEps, 1 - kAccEps] before they are turned into lengths.
 constexpr double kAccEps = 1e-3;
 
@@ -398,6 +399,15 @@ sg_status pilot_acceptance(const sg_lattice *inst, int n, const double *beta, co
     sg_ctx *c = nullptr;
     sg_status st = sg_create(&cfg, &c);
     if (st != SG_OK) return st;
+    // A fixed launch configuration (work-groups ordered by cost within each XCD, at least
+    // seven waves per SIMD): a pilot is short, and every configuration gives the same results,
+    // so timing the candidates on its fresh shape would cost more than it could save.
+    st = sg_set_launch_config(c, kPilotLaunchConfig);
+    if (st != SG_OK) {
+        set_global_error(sg_last_error(c));
+        sg_destroy(c);
+        return st;
+    }
     sg_apt_options opt{};
     opt.sweeps_per_swap = 1;
     opt.icm_pairs = 2;
