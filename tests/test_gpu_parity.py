@@ -385,6 +385,30 @@ def test_apt_queue_search_large_lattice():
     assert ctx.energy()[0].tolist() == [oracle.energy(_olat(insts[0]), s) for s in g[0, :, :16000]]
 
 
+def test_icm_rows_of_16_and_17_sites():
+    """The cluster fill along x at the packing limit: rows of 16 sites fill both halves of a
+    word with two pairs (the wrap bond at bit 15 and the boundary between the halves), open
+    and periodic in x, and rows of 17 sites take one word per pair; four labels (two pairs per
+    move) and two, cutoff low enough that most temperatures move."""
+    insts = [_inst((16, 4, 4), 7, 91), _inst((16, 3, 5), 6, 92), _inst((17, 4, 3), 7, 93),
+             _inst((16, 4, 3), 7, 94, p_absent=0.3)]
+    beta = geometric_ladder(6, 0.3, 2.5)
+    for reps in (4, 2):
+        ctx = sg.apt(insts, beta, SEED + reps, reps_per_beta=reps)
+        trace = ctx.run_apt(40, 1, 0.4, record_every=4)
+        g = ctx.spins()
+        for i, inst in enumerate(insts):
+            l = _olat(inst)
+            sp = oracle.apt_init(l, i, 6 * reps, SEED + reps)
+            ctr = np.zeros(3, np.uint32)
+            E = np.zeros(6 * reps, np.int64)
+            b = np.array([np.iinfo(np.int64).max], np.int64)
+            rc, otr, _ = oracle.apt_run(l, i, beta, reps, SEED + reps, 40, 1, 0.4, 4, ctr, sp, E, b)
+            assert rc == 0 and np.array_equal(g[i, :, :l.n], sp), (reps, i)
+            assert np.array_equal(trace[i], otr), (reps, i)
+        ctx.close()
+
+
 def test_apt_byte_offset_record_limit():
     """The sweep reads site records with neighbour byte offsets when every lattice of the
     context has at most 16383 sites (4 x 16383 fills 16 bits; on open axes an absent neighbour
