@@ -143,6 +143,28 @@ def test_apt_options_match_oracle(reps, pairs, S):
         assert np.array_equal(cnt[i], oacc)
 
 
+def test_apt_sweep_to_swap_ratio_516_matches_oracle():
+    """The ablation's largest sweep-to-swap ratio: 516 sweeps in each cycle's launch (the
+    packed energy sums flushed every sweep), then the cluster moves and the exchange, over
+    three cycles and two labels, against the oracle."""
+    insts = [_inst((5, 4, 3), 7, 97), _inst((4, 4, 4), 7, 98)]
+    beta = geometric_ladder(6, 0.3, 2.5)
+    ctx = sg.apt(insts, beta, SEED + 516, reps_per_beta=2)
+    trace = ctx.run_apt(3, 516, 1.0, record_every=1)
+    g = ctx.spins()
+    E = ctx.energy()
+    for i, inst in enumerate(insts):
+        l = _olat(inst)
+        sp = oracle.apt_init(l, i, 12, SEED + 516)
+        ctr = np.zeros(3, np.uint32)
+        Eo = np.zeros(12, np.int64)
+        b = np.array([np.iinfo(np.int64).max], np.int64)
+        rc, otr, _ = oracle.apt_run(l, i, beta, 2, SEED + 516, 3, 516, 1.0, 1, ctr, sp, Eo, b)
+        assert rc == 0 and np.array_equal(g[i, :, :l.n], sp), f"instance {i}"
+        assert np.array_equal(trace[i], otr), f"instance {i}"
+        assert E[i].tolist() == [oracle.energy(l, s_) for s_ in sp], f"instance {i}"
+
+
 def test_apt_every_launch_config_matches_oracle():
     """Every APT launch configuration (six work-group orders x 7 or 8 waves per SIMD) gives the
     oracle's spins, traces and swap counts, over a 32-cycle graph replay and a tail."""
