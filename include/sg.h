@@ -89,7 +89,9 @@ typedef struct {
 
 /* Validate, copy the instances, build colour classes and acceptance tables,
  * allocate device memory and draw the random initial spins (Algorithm S1 and
- * S2: "initialize all replicas to random states").  *out is NULL on error. */
+ * S2: random initial states for all replicas).  *out is NULL on error.  The
+ * per-instance tables are built on up to 16 host threads, all ended before the call
+ * returns; when several instances are invalid, the error names the lowest of them. */
 sg_status sg_create(const sg_config *cfg, sg_ctx **out);
 /* sg_create with a colour map per instance (Methods, "Graph Coloring": the p-bits of one
  * colour share no bond and are updated in parallel).  colour (nullable) [n_inst], colour[i]
