@@ -15,6 +15,7 @@
 
 #include "sg.h"
 #include "sg_internal.h"
+#include "sg_host.h"
 
 using namespace sg;
 
@@ -131,7 +132,12 @@ sg_status sg_instance_features(const sg_lattice *inst, int32_t n_inst, double *f
         const sg_lattice &L = inst[i];
         if (L.Lx < 1 || L.Ly < 1 || L.Lz < 1 || !L.J || (int64_t)L.Lx * L.Ly * L.Lz > kMaxN)
             return SG_EINVAL;
-        features_of(L, features + 4 * (size_t)i);
+    }
+    // one instance per host thread at a time: each instance's sums keep their site order
+    try {
+        parallel_for(n_inst, [&](int i) { features_of(inst[i], features + 4 * (size_t)i); });
+    } catch (const std::bad_alloc &) {
+        return SG_ENOMEM;
     }
     return SG_OK;
 }
