@@ -98,6 +98,17 @@ def apt_batched_workload(n_inst=256):
     return insts, geometric_ladder(32, 0.2, 3.0), sizes
 
 
+def apt_config_fields(code):
+    """An APT launch-configuration code spelled out: 1..12 = 1 + order + 6 * (8 waves), then
+    13..15 = order 0 at 7 waves with the work-groups in two launch groups on two streams
+    (the largest instances up to 65, 75 or 85 % of the sites, and the rest)."""
+    if code > 12:
+        return {"code": code, "order": 0, "waves_per_simd": 7, "launch_groups": 2,
+                "first_group_site_share": (0.65, 0.75, 0.85)[code - 13], "chosen_by": "autotuner"}
+    return {"code": code, "order": (code - 1) % 6, "waves_per_simd": 8 if code > 6 else 7,
+            "launch_groups": 1, "chosen_by": "autotuner"}
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -857,8 +868,7 @@ def main():
                "flips_per_ns": round(flips_per_ns(flips_cycle * args.apt_cycles, ms3), 3),
                "sweep_only_flips_per_ns": round(flips_per_ns(flips_cycle * 32, ms3s), 3),
                "graph_kernel_ms": round(k3, 3),
-               "launch_config": {"code": code, "order": (code - 1) % 6,
-                                 "waves_per_simd": 8 if code > 6 else 7, "chosen_by": "autotuner"}}
+               "launch_config": apt_config_fields(code)}
         apt["icm_swap_energy_share"] = round(1.0 - (ms3s / 32) / (ms3 / args.apt_cycles), 4)
         out["apt_batched"] = apt
         out["apt_plain"] = {"workload": "one L=8 periodic instance, 32 betas x 2 labels, ICM at beta >= 1",

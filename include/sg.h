@@ -220,9 +220,13 @@ sg_status sg_sqa_anneal_dev(sg_ctx *ctx, const double *gamma, int32_t n_steps, i
  * dispatch order of the replica kernel's work-groups (0-3: instances spread over the eight
  * XCDs, quads sorted by estimated cost with cluster-move weight 3, 1, 2, 4; 4: one global cost
  * sort; 5: instance-major), and at least 7 or 8 waves per SIMD (the kernel's register
- * budget).  The first sg_run_apt / sg_run_apt_ex of a context whose code is unset (0) times
- * all twelve on its own shape (sweeps per swap, cluster moves) and keeps the fastest, leaving
- * the context's state as it was; other calls use code 1 until then.
+ * budget).  Codes 13..15: order 0 at 7 waves, with the cycles of sg_run_apt / sg_run_apt_ex
+ * split into two launch groups that run side by side on the context's stream and a second
+ * stream the library creates (joined back before the call's later work): the largest
+ * instances up to 65, 75 or 85 % of all sites, and the rest (one group if that leaves the
+ * second empty).  The first sg_run_apt / sg_run_apt_ex of a context whose code is unset (0)
+ * times all fifteen on its own shape (sweeps per swap, cluster moves) and keeps the fastest,
+ * leaving the context's state as it was; other calls use code 1 until then.
  * Both tuners cache their pick per workload shape for the process and in the file named by
  * the environment variable SG_TUNE_CACHE (default ~/.cache/libsg_tune.txt; best effort).
  * get: 0 while unset.  set: 0 re-enables the autotuner; any other value outside the allowed

@@ -344,6 +344,14 @@ struct sg_ctx {
     DevBuf<uint4> d_rowA, d_rowB, d_rowC;
     int n_blocks = 0;
     size_t quad_lds = 0;
+    // two launch groups (a launch configuration): the graph's replica kernels of group 1 run
+    // on stream2, forked from and joined back into the context's stream
+    bool apt_split = false;
+    DevBuf<QuadDesc> d_desc_g[2];
+    int n_blocks_g[2] = {0, 0};
+    size_t lds_g[2] = {0, 0};
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int apt_config = 0;        // launch configuration asked for: 0 = the autotuner's on the next run
     int apt_config_used = 1;   // configuration of d_desc / apt_waves (1: order 0, 7 waves)
     int apt_waves = 7;
@@ -377,6 +385,9 @@ struct sg_ctx {
         if (timer.a) (void)hipEventDestroy(timer.a);
         if (timer.b) (void)hipEventDestroy(timer.b);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
+        if (stream2) (void)hipStreamDestroy(stream2);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
     }
 };
 
@@ -558,24 +569,30 @@ void apt_rows(const Lat &L, std::vector<uint4> &rowA, std::vector<uint4> &rowB,
 // estimated cost, largest first: sites, times w = 3, 1, 2 or 4 for quads holding a
 // temperature >= 1 (where the cluster moves usually run).  Order 4: one global cost sort
 // (w = 3), handed to the XCDs in turn.  Order 5: instance-major, quads ascending.
+// sel: the instances to include (all when null).
 constexpr int kAptOrders = 6;
-constexpr int kAptConfigs = 2 * kAptOrders;   // x {7, 8} waves per SIMD
+// Two-group configurations (order 0, 7 waves): the largest instances, up to this share of
+// all sites, in one launch and the rest in a second launch on a second stream; the two run
+// side by side, each with the LDS size of its own largest instance.
+constexpr double kAptSplitShare[3] = {0.65, 0.75, 0.85};
+constexpr int kAptConfigs = 2 * kAptOrders + 3;   // x {7, 8} waves per SIMD, then the splits
 
 std::vector<QuadDesc> make_quad_descs(const std::vector<Lat> &lat, int n_quads,
                                       const std::vector<double> &beta, int n_beta, int reps,
-                                      int order)
+                                      int order, const std::vector<char> *sel = nullptr)
 {
-    const int ni = (int)lat.size();
+    std::vector<int> idx;
+    for (int i = 0; i < (int)lat.size(); ++i)
+        if (!sel || (*sel)[(size_t)i]) idx.push_back(i);
+    const int ni = (int)idx.size();
     std::vector<QuadDesc> out;
     if (order == 5) {
-        for (int i = 0; i < ni; ++i)
+        for (int i : idx)
             for (int q = 0; q < n_quads; ++q) out.push_back({i, q});
         return out;
     }
     static const int kWeight[5] = {3, 1, 2, 4, 3};
     const int w = kWeight[order];
-    std::vector<int> idx(ni);
-    for (int i = 0; i < ni; ++i) idx[i] = i;
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return lat[a].n > lat[b].n; });
     auto cost = [&](const QuadDesc &d) {
         bool icm = false;
@@ -1165,13 +1182,56 @@ int sqa_threads_or_default(const sg_ctx *c) { return c->sqa_threads ? c->sqa_thr
 void apply_apt_config(sg_ctx *c, int code)
 {
     if (code == c->apt_config_used) return;
-    const int order = (code - 1) % kAptOrders;
+    const bool split_code = code > 2 * kAptOrders;
+    const int order = split_code ? 0 : (code - 1) % kAptOrders;
     std::vector<QuadDesc> d = make_quad_descs(c->lat, c->n_quads, c->beta, c->n_beta, c->reps, order);
-    // launches in flight still read the old task list
+    std::vector<char> in0((size_t)c->n_inst, 0);
+    int n0 = 0;
+    if (split_code) {
+        std::vector<int> idx((size_t)c->n_inst);
+        for (int i = 0; i < c->n_inst; ++i) idx[(size_t)i] = i;
+        std::stable_sort(idx.begin(), idx.end(),
+                         [&](int a, int b) { return c->lat[(size_t)a].n > c->lat[(size_t)b].n; });
+        int64_t total = 0, cum = 0;
+        for (const Lat &L : c->lat) total += L.n;
+        const double share = kAptSplitShare[code - 2 * kAptOrders - 1];
+        for (int i : idx) {
+            if (n0 > 0 && (double)(cum + c->lat[(size_t)i].n) > share * (double)total) break;
+            in0[(size_t)i] = 1;
+            cum += c->lat[(size_t)i].n;
+            ++n0;
+        }
+    }
+    // one group when the share leaves the second empty
+    const bool split = split_code && n0 < c->n_inst;
+    // launches in flight still read the old task lists
     hip_check(hipStreamSynchronize(c->stream), "launch config");
+    if (c->stream2) hip_check(hipStreamSynchronize(c->stream2), "launch config");
     c->d_desc.upload(d, c->stream, "tasks");
     c->n_blocks = (int)d.size();
-    c->apt_waves = (code - 1) / kAptOrders ? 8 : 7;
+    c->apt_split = split;
+    if (split) {
+        if (!c->stream2) {
+            hip_check(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking), "hipStreamCreate");
+            hip_check(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "event");
+            hip_check(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "event");
+        }
+        for (int g = 0; g < 2; ++g) {
+            std::vector<char> sel((size_t)c->n_inst);
+            for (size_t i = 0; i < sel.size(); ++i) sel[i] = (char)(in0[i] == (g == 0 ? 1 : 0));
+            const std::vector<QuadDesc> dg =
+                make_quad_descs(c->lat, c->n_quads, c->beta, c->n_beta, c->reps, 0, &sel);
+            c->d_desc_g[g].upload(dg, c->stream, "tasks");
+            c->n_blocks_g[g] = (int)dg.size();
+            c->lds_g[g] = 0;
+            for (int i = 0; i < c->n_inst; ++i) {
+                if (!sel[(size_t)i]) continue;
+                const InstDev &I = c->idev[(size_t)i];
+                c->lds_g[g] = std::max(c->lds_g[g], apt_lds_bytes(I.npad, I.n_rows, c->ni, I.row_off < 0));
+            }
+        }
+    }
+    c->apt_waves = !split_code && (code - 1) / kAptOrders ? 8 : 7;
     c->apt_config_used = code;
     if (c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);
@@ -1179,9 +1239,28 @@ void apply_apt_config(sg_ctx *c, int code)
     }
 }
 
+// body(stream, task list, work-groups, LDS bytes) launches replica kernels over one launch
+// group.  With two groups, group 1 goes to the second stream, forked from the context's
+// stream before and joined into it after, so that work queued after the call waits for both
+// (in a graph capture the groups become parallel branches).
+template <class F>
+hipError_t apt_on_groups(sg_ctx *c, F body)
+{
+    if (!c->apt_split) return body(c->stream, (const QuadDesc *)c->d_desc.p, c->n_blocks, c->quad_lds);
+    hipError_t e = hipEventRecord(c->ev_fork, c->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->stream2, c->ev_fork, 0);
+    if (e != hipSuccess) return e;
+    hipError_t eb = body(c->stream, (const QuadDesc *)c->d_desc_g[0].p, c->n_blocks_g[0], c->lds_g[0]);
+    if (eb == hipSuccess)
+        eb = body(c->stream2, (const QuadDesc *)c->d_desc_g[1].p, c->n_blocks_g[1], c->lds_g[1]);
+    hipError_t ej = hipEventRecord(c->ev_join, c->stream2);
+    if (ej == hipSuccess) ej = hipStreamWaitEvent(c->stream, c->ev_join, 0);
+    return eb != hipSuccess ? eb : ej;
+}
+
 std::string apt_tune_key(const sg_ctx *c, int S, bool icm, int pairs)
 {
-    std::string k = "apt/" + std::to_string(c->n_inst) + "/" + std::to_string(c->n_beta) + "/" +
+    std::string k = "apt2/" + std::to_string(c->n_inst) + "/" + std::to_string(c->n_beta) + "/" +
                     std::to_string(c->reps) + "/" + std::to_string(c->imax) + "/" + std::to_string(S) +
                     "/" + std::to_string((int)icm) + "/" + std::to_string(pairs);
     for (const InstDev &I : c->idev)
@@ -1194,10 +1273,10 @@ std::string apt_tune_key(const sg_ctx *c, int S, bool icm, int pairs)
 
 std::map<std::string, int> g_apt_tune_cache;   // guarded by g_tune_mu
 
-// Candidates: the six work-group orders x {7, 8} waves per SIMD, each timed over eight
-// replica-kernel launches of the run's shape (sweeps, cluster moves) twice; the state is
-// saved before and restored after, so the context is unchanged.  The pick is cached per
-// workload shape for the process and on disk.
+// Candidates: the six work-group orders x {7, 8} waves per SIMD and the three two-group
+// splits, each timed over sixteen replica-kernel launches of the run's shape (sweeps, cluster
+// moves), best of three; the state is saved before and restored after, so the context is
+// unchanged.  The pick is cached per workload shape for the process and on disk.
 void apt_autotune(sg_ctx *c, int S, bool icm, int pairs)
 {
     const std::string key = apt_tune_key(c, S, icm, pairs);
@@ -1237,13 +1316,21 @@ void apt_autotune(sg_ctx *c, int S, bool icm, int pairs)
         std::vector<float> best_ms(kAptConfigs + 1, std::numeric_limits<float>::infinity());
         hipError_t err = hipSuccess;
         try {
-            for (int rep = 0; rep < 2 && err == hipSuccess; ++rep)
+            for (int rep = 0; rep < 3 && err == hipSuccess; ++rep)
                 for (int code = 1; code <= kAptConfigs && err == hipSuccess; ++code) {
                     apply_apt_config(c, code);
                     AptArgs a = apt_args(c, S, icm ? 1 : 0);
                     a.icm_pairs = pairs;
                     err = hipEventRecord(e0, st);
-                    for (int k = 0; k < 8 && err == hipSuccess; ++k) err = launch_apt_quad(a, c->quad_lds, st);
+                    if (err == hipSuccess)
+                        err = apt_on_groups(c, [&](hipStream_t gs, const QuadDesc *desc, int nb, size_t lds) {
+                            AptArgs b = a;
+                            b.desc = desc;
+                            b.n_blocks = nb;
+                            hipError_t r = hipSuccess;
+                            for (int k = 0; k < 16 && r == hipSuccess; ++k) r = launch_apt_quad(b, lds, gs);
+                            return r;
+                        });
                     if (err == hipSuccess) err = hipEventRecord(e1, st);
                     if (err == hipSuccess) err = hipEventSynchronize(e1);
                     float ms = 0.f;
@@ -1572,22 +1659,28 @@ void run_apt(sg_ctx *c, int64_t n_cycles, int32_t sweeps_per_swap, const std::ve
             hip_check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "capture");
             hipError_t e = hipSuccess;
             int32_t *pa = c->d_perm.p, *pb = c->d_perm2.p, *ea = c->d_E.p, *eb = c->d_E2.p;
-            for (int k = 0; k < K && e == hipSuccess; ++k) {
-                AptArgs fa = qa;
-                fa.cyc_k = k;
-                if (k > 0) {
-                    const bool odd = (k & 1) != 0;
-                    fa.fused_swap = 1;
-                    fa.sw = sa;
-                    fa.sw.cyc_k = k - 1;
-                    fa.sw.perm_in = odd ? pa : pb;
-                    fa.sw.E_in = odd ? ea : eb;
-                    fa.sw.perm = odd ? pb : pa;
-                    fa.sw.E = fa.E = odd ? eb : ea;
-                    fa.perm = fa.sw.perm;
+            e = apt_on_groups(c, [&](hipStream_t gs, const QuadDesc *desc, int nb, size_t lds) {
+                hipError_t r = hipSuccess;
+                for (int k = 0; k < K && r == hipSuccess; ++k) {
+                    AptArgs fa = qa;
+                    fa.desc = desc;
+                    fa.n_blocks = nb;
+                    fa.cyc_k = k;
+                    if (k > 0) {
+                        const bool odd = (k & 1) != 0;
+                        fa.fused_swap = 1;
+                        fa.sw = sa;
+                        fa.sw.cyc_k = k - 1;
+                        fa.sw.perm_in = odd ? pa : pb;
+                        fa.sw.E_in = odd ? ea : eb;
+                        fa.sw.perm = odd ? pb : pa;
+                        fa.sw.E = fa.E = odd ? eb : ea;
+                        fa.perm = fa.sw.perm;
+                    }
+                    r = launch_apt_quad(fa, lds, gs);
                 }
-                e = launch_apt_quad(fa, c->quad_lds, c->stream);
-            }
+                return r;
+            });
             static_assert(K % 2 == 0, "the last replica kernel must write the second buffers");
             SwapArgs last = sa;
             last.cyc_k = K - 1;

@@ -324,7 +324,7 @@ class Context:
         return a
 
     def launch_config(self):
-        """DT-SQA work-group size, or APT configuration code (1..12); 0 until the autotuner
+        """DT-SQA work-group size, or APT configuration code (1..15); 0 until the autotuner
         has run."""
         t = C.c_int32(0)
         self._check(self.lib.sg_get_launch_config(self.h, C.byref(t)))

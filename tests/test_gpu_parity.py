@@ -166,8 +166,9 @@ def test_apt_sweep_to_swap_ratio_516_matches_oracle():
 
 
 def test_apt_every_launch_config_matches_oracle():
-    """Every APT launch configuration (six work-group orders x 7 or 8 waves per SIMD) gives the
-    oracle's spins, traces and swap counts, over a 32-cycle graph replay and a tail."""
+    """Every APT launch configuration (six work-group orders x 7 or 8 waves per SIMD, and the
+    three splits into two launch groups on two streams) gives the oracle's spins, traces and
+    swap counts, over a 32-cycle graph replay and a tail."""
     insts = [_inst(*m) for m in MIXED]
     beta = geometric_ladder(8, 0.2, 3.0)
     ref = []
@@ -180,7 +181,7 @@ def test_apt_every_launch_config_matches_oracle():
         rc, otr, oacc = oracle.apt_run(l, i, beta, 2, SEED + 5, 37, 1, 1.0, 1, ctr, sp, E, b)
         assert rc == 0
         ref.append((l.n, sp, otr, oacc))
-    for code in range(1, 13):
+    for code in range(1, 16):
         ctx = sg.apt(insts, beta, SEED + 5, reps_per_beta=2)
         ctx.set_launch_config(code)
         assert ctx.launch_config() == code
@@ -192,14 +193,14 @@ def test_apt_every_launch_config_matches_oracle():
             assert np.array_equal(tr[i], otr) and np.array_equal(cnt[i], oacc), f"config {code}"
         ctx.close()
     ctx = sg.apt(insts, beta, SEED + 5, reps_per_beta=2)
-    for bad in (-1, 13, 1000):
+    for bad in (-1, 16, 1000):
         with pytest.raises(sg.SGError) as e:
             ctx.set_launch_config(bad)
         assert e.value.code == sg.SG_EINVAL
 
 
 def test_apt_autotuner_keeps_state_and_caches(tmp_path, monkeypatch):
-    """The first run of a context with no configuration times the twelve candidates on a saved
+    """The first run of a context with no configuration times the fifteen candidates on a saved
     copy of the state and restores it: the run still matches the oracle; the pick is kept by
     the context, in the process cache and in the on-disk cache file."""
     cache = tmp_path / "tune.txt"
@@ -211,7 +212,7 @@ def test_apt_autotuner_keeps_state_and_caches(tmp_path, monkeypatch):
     ctx.sweep(3)
     tr = ctx.run_apt_ex(45, 1, 0.9, 1, record_every=3)
     code = ctx.launch_config()
-    assert 1 <= code <= 12
+    assert 1 <= code <= 15
     g = ctx.spins()
     for i, inst in enumerate(insts):
         l = _olat(inst)
@@ -743,6 +744,30 @@ def test_batched_apt_256_mixed_sampled_instances():
     # the range reader returns the same logical slots
     for i, first, count in ((4, 0, 64), (131, 17, 5), (255, 63, 1)):
         assert np.array_equal(ctx.spins_range(i, first, count), g[i, first:first + count, :insts[i][0][..., 0].size])
+
+
+@pytest.mark.parametrize("code", [13, 14, 15])
+def test_batched_apt_256_mixed_two_launch_groups(code):
+    """The 256-instance mixed batch with its replica kernels split into two launch groups on two
+    streams (largest instances up to 65, 75 or 85 % of the sites, then the rest), over one
+    32-cycle graph and a tail: sampled instances from both groups equal the oracle's."""
+    sizes = mixed_sizes(256)
+    insts = [(ej_couplings(L, 7, seed=10000 + i)[0], 7, None) for i, L in enumerate(sizes)]
+    beta = geometric_ladder(32, 0.2, 3.0)
+    ctx = sg.apt(insts, beta, 779, 2)
+    ctx.set_launch_config(code)
+    tr = ctx.run_apt(35, 1, 1.0, record_every=5)
+    g = ctx.spins()
+    cnt = ctx.swap_counts()
+    for i in (0, 1, 2, 3, 4, 128, 255):
+        l = oracle.Lattice(insts[i][0], 7)
+        sp = oracle.apt_init(l, i, 64, 779)
+        ctr = np.zeros(3, np.uint32)
+        E = np.zeros(64, np.int64)
+        b = np.array([np.iinfo(np.int64).max], np.int64)
+        _, otr, oacc = oracle.apt_run(l, i, beta, 2, 779, 35, 1, 1.0, 5, ctr, sp, E, b)
+        assert np.array_equal(g[i, :, :l.n], sp), f"config {code}, instance {i} (L={sizes[i]})"
+        assert np.array_equal(tr[i], otr) and np.array_equal(cnt[i], oacc), f"config {code}, instance {i}"
 
 
 def test_sqa_L10_M32_R64_sampled_replicas():
