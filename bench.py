@@ -98,15 +98,16 @@ def apt_batched_workload(n_inst=256):
     return insts, geometric_ladder(32, 0.2, 3.0), sizes
 
 
-def apt_config_fields(code):
+def apt_config_fields(code, forced=False):
     """An APT launch-configuration code spelled out: 1..12 = 1 + order + 6 * (8 waves), then
     13..15 = order 0 at 7 waves with the work-groups in two launch groups on two streams
     (the largest instances up to 65, 75 or 85 % of the sites, and the rest)."""
     if code > 12:
         return {"code": code, "order": 0, "waves_per_simd": 7, "launch_groups": 2,
-                "first_group_site_share": (0.65, 0.75, 0.85)[code - 13], "chosen_by": "autotuner"}
+                "first_group_site_share": (0.65, 0.75, 0.85)[code - 13],
+                "chosen_by": "--apt-launch-config" if forced else "autotuner"}
     return {"code": code, "order": (code - 1) % 6, "waves_per_simd": 8 if code > 6 else 7,
-            "launch_groups": 1, "chosen_by": "autotuner"}
+            "launch_groups": 1, "chosen_by": "--apt-launch-config" if forced else "autotuner"}
 
 
 def cpu_model():
@@ -677,6 +678,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--replicas", type=int, default=1024, help="R for the L=15 DT-SQA workload")
     ap.add_argument("--apt-cycles", type=int, default=256)
+    ap.add_argument("--apt-launch-config", type=int, default=0,
+                    help="APT launch configuration code for the batched APT line (0: the autotuner's)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["all", "sqa", "apt"], default="all")
@@ -839,6 +842,8 @@ def main():
         insts3, ladder, sizes = apt_batched_workload()
         flips_cycle = sum(L ** 3 for L in sizes) * 64
         c3 = sg.apt(insts3, ladder, seed=777, reps_per_beta=2)
+        if args.apt_launch_config:
+            c3.set_launch_config(args.apt_launch_config)
         c3.run_apt(64, 1, 1.0)
         c3.synchronize()
         c3.kernel_timing(True)
@@ -868,7 +873,7 @@ def main():
                "flips_per_ns": round(flips_per_ns(flips_cycle * args.apt_cycles, ms3), 3),
                "sweep_only_flips_per_ns": round(flips_per_ns(flips_cycle * 32, ms3s), 3),
                "graph_kernel_ms": round(k3, 3),
-               "launch_config": apt_config_fields(code)}
+               "launch_config": apt_config_fields(code, bool(args.apt_launch_config))}
         apt["icm_swap_energy_share"] = round(1.0 - (ms3s / 32) / (ms3 / args.apt_cycles), 4)
         out["apt_batched"] = apt
         out["apt_plain"] = {"workload": "one L=8 periodic instance, 32 betas x 2 labels, ICM at beta >= 1",
