@@ -1231,6 +1231,8 @@ void apply_apt_config(sg_ctx *c, int code)
             }
         }
     }
+    // the task lists are copied from host vectors that end with this call
+    hip_check(hipStreamSynchronize(c->stream), "launch config");
     c->apt_waves = !split_code && (code - 1) / kAptOrders ? 8 : 7;
     c->apt_config_used = code;
     if (c->gexec) {
