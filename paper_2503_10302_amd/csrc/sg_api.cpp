@@ -1504,6 +1504,7 @@ void sg_destroy(sg_ctx *c)
 {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->stream2) (void)hipStreamSynchronize(c->stream2);
     delete c;
 }
 
