@@ -192,6 +192,18 @@ def test_apt_every_launch_config_matches_oracle():
             assert np.array_equal(g[i, :, :n], sp), f"config {code}, instance {i}"
             assert np.array_equal(tr[i], otr) and np.array_equal(cnt[i], oacc), f"config {code}"
         ctx.close()
+    # a split that leaves the second group empty (one instance) runs as one group
+    one = sg.apt(insts[6:7], beta, SEED + 5, reps_per_beta=2)
+    one.set_launch_config(14)
+    tr = one.run_apt(37, 1, 1.0, record_every=1)
+    l6 = _olat(insts[6])
+    sp = oracle.apt_init(l6, 0, beta.size * 2, SEED + 5)
+    ctr = np.zeros(3, np.uint32)
+    E = np.zeros(beta.size * 2, np.int64)
+    b = np.array([np.iinfo(np.int64).max], np.int64)
+    rc, otr, _ = oracle.apt_run(l6, 0, beta, 2, SEED + 5, 37, 1, 1.0, 1, ctr, sp, E, b)
+    assert rc == 0 and np.array_equal(one.spins()[0, :, :l6.n], sp) and np.array_equal(tr[0], otr)
+    one.close()
     ctx = sg.apt(insts, beta, SEED + 5, reps_per_beta=2)
     for bad in (-1, 16, 1000):
         with pytest.raises(sg.SGError) as e:
