@@ -115,16 +115,20 @@ def test_apt_cycles_match_oracle(reps, S, cutoff):
     assert ctx.counters().tolist() == [n_cyc * S, n_cyc, n_cyc]
 
 
+@pytest.mark.parametrize("code", [0, 14])
 @pytest.mark.parametrize("reps,pairs,S", [(4, 1, 1), (4, 2, 10), (2, 1, 1)])
-def test_apt_options_match_oracle(reps, pairs, S):
+def test_apt_options_match_oracle(reps, pairs, S, code):
     """sg_run_apt_ex: one or two Houdayer moves per temperature per cycle (four labels), a
     sweep-to-swap ratio of 10, and a different ICM cutoff per instance, against the oracle
     (each instance run with its own cutoff): spins, best-energy traces, swap counts, over two
-    replays of the 32-cycle graph and a ragged tail."""
+    replays of the 32-cycle graph and a ragged tail; with the autotuner's launch configuration
+    and with two launch groups on two streams (code 14)."""
     insts = [_inst(*m) for m in MIXED[:6]]
     beta = geometric_ladder(10, 0.2, 3.0)
     cut = np.array([0.2, 1.0, 0.6, float("inf"), 1.5, 0.9])
     ctx = sg.apt(insts, beta, SEED + 7 * reps + pairs, reps_per_beta=reps)
+    if code:
+        ctx.set_launch_config(code)
     n_cyc = 70
     trace = ctx.run_apt_ex(n_cyc, S, cut, pairs, record_every=7)
     g = ctx.spins()
