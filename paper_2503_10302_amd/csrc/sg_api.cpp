@@ -1207,9 +1207,16 @@ void apply_apt_config(sg_ctx *c, int code)
     // launches in flight still read the old task lists
     hip_check(hipStreamSynchronize(c->stream), "launch config");
     if (c->stream2) hip_check(hipStreamSynchronize(c->stream2), "launch config");
+    // the cached cycle graph holds the old lists' addresses
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    // one group until every list of the new configuration is in place (a failure below leaves
+    // a consistent single-group context)
+    c->apt_split = false;
     c->d_desc.upload(d, c->stream, "tasks");
     c->n_blocks = (int)d.size();
-    c->apt_split = split;
     if (split) {
         if (!c->stream2) {
             hip_check(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking), "hipStreamCreate");
@@ -1233,12 +1240,9 @@ void apply_apt_config(sg_ctx *c, int code)
     }
     // the task lists are copied from host vectors that end with this call
     hip_check(hipStreamSynchronize(c->stream), "launch config");
+    c->apt_split = split;
     c->apt_waves = !split_code && (code - 1) / kAptOrders ? 8 : 7;
     c->apt_config_used = code;
-    if (c->gexec) {
-        (void)hipGraphExecDestroy(c->gexec);
-        c->gexec = nullptr;
-    }
 }
 
 // body(stream, task list, work-groups, LDS bytes) launches replica kernels over one launch
