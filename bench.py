@@ -844,7 +844,9 @@ def main():
         c3 = sg.apt(insts3, ladder, seed=777, reps_per_beta=2)
         if args.apt_launch_config:
             c3.set_launch_config(args.apt_launch_config)
-        c3.run_apt(64, 1, 1.0)
+        # untimed warm-up: the first few hundred cycles of a fresh context run a few per cent
+        # slower than the steady state that long runs see
+        c3.run_apt(512, 1, 1.0)
         c3.synchronize()
         c3.kernel_timing(True)
         c3.kernel_time()

@@ -1280,8 +1280,8 @@ std::string apt_tune_key(const sg_ctx *c, int S, bool icm, int pairs)
 std::map<std::string, int> g_apt_tune_cache;   // guarded by g_tune_mu
 
 // Candidates: the six work-group orders x {7, 8} waves per SIMD and the three two-group
-// splits, each timed over sixteen replica-kernel launches of the run's shape (sweeps, cluster
-// moves), best of three; the state is saved before and restored after, so the context is
+// splits, each timed over 32 replica-kernel launches of the run's shape (sweeps, cluster
+// moves), best of five; the state is saved before and restored after, so the context is
 // unchanged.  The pick is cached per workload shape for the process and on disk.
 void apt_autotune(sg_ctx *c, int S, bool icm, int pairs)
 {
@@ -1322,7 +1322,7 @@ void apt_autotune(sg_ctx *c, int S, bool icm, int pairs)
         std::vector<float> best_ms(kAptConfigs + 1, std::numeric_limits<float>::infinity());
         hipError_t err = hipSuccess;
         try {
-            for (int rep = 0; rep < 3 && err == hipSuccess; ++rep)
+            for (int rep = 0; rep < 5 && err == hipSuccess; ++rep)
                 for (int code = 1; code <= kAptConfigs && err == hipSuccess; ++code) {
                     apply_apt_config(c, code);
                     AptArgs a = apt_args(c, S, icm ? 1 : 0);
@@ -1334,7 +1334,7 @@ void apt_autotune(sg_ctx *c, int S, bool icm, int pairs)
                             b.desc = desc;
                             b.n_blocks = nb;
                             hipError_t r = hipSuccess;
-                            for (int k = 0; k < 16 && r == hipSuccess; ++k) r = launch_apt_quad(b, lds, gs);
+                            for (int k = 0; k < 32 && r == hipSuccess; ++k) r = launch_apt_quad(b, lds, gs);
                             return r;
                         });
                     if (err == hipSuccess) err = hipEventRecord(e1, st);
